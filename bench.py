@@ -1,0 +1,195 @@
+"""FastWalk throughput on one MI355X.
+
+Default workload: Barabasi-Albert graph, n = 1,000,000, 5 edges per new node (power-law
+degrees, unit weights), 10,000 rooted spanning trees sampled by Wilson's algorithm, RWC
+assembled in FP64.  One timed step is the whole hot path on device-resident inputs: CSR build
+(rwc_build_csr), sampling (rwc_sample_forests) and the pivot solve plus assembly
+(rwc_estimate).
+
+Prints one JSON line.  `value` is rooted trees per second for the whole step; walk steps/s,
+the dominant kernel's roofline and the CPU oracle's rate on the host cores ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rooted trees/s + walk steps/s at fixed RWC rel. error; plain vs batched; grad edges/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000"])
+    ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
+    ap.add_argument("--walkers", type=int, default=0, help="walkers per tree (0 = automatic)")
+    ap.add_argument("--tif", type=int, default=0, help="trees in flight (0 = automatic)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def workload(name):
+    import rwcgen
+    if name == "ba1m":
+        g = rwcgen.barabasi_albert(1_000_000, 5, 1002)
+        return g, 10_000, 2002, "BA(n=1e6, m=5) unit weights, 1e4 trees"
+    g = rwcgen.erdos_renyi_lcc(1000, 8, 1001)
+    return g, 2000, 2001, "ER(n=1000, d=8) LCC unit weights, 2000 trees"
+
+
+def walk_bytes(total_steps: int, trees: int, n: int, weighted: bool, mean_probe: float = 0.0) -> float:
+    """Algorithmic bytes of one walk launch: per walk step row_ptr[x], row_ptr[x+1] (8 B),
+    col[k] (4 B), the state word of the next node (8 B) and the store of x's state word (8 B)
+    (+ the CDF probes when weighted); per attached node the retrace reads and writes its state
+    word (16 B); per tree the start scan reads each node's state word once (8 B)."""
+    per_step = 28.0 + (8.0 * (1.0 + mean_probe) if weighted else 0.0)
+    return per_step * total_steps + trees * (16.0 * (n - 1) + 8.0 * n)
+
+
+def walk_accesses(total_steps: int, trees: int, n: int) -> float:
+    """Random memory accesses of one walk launch (row_ptr pair, col, state load, state store
+    per step; state load and store per attached node; one state load per scanned node)."""
+    return 4.0 * total_steps + trees * (2.0 * (n - 1) + n)
+
+
+def cpu_baseline(g, l, seed, seconds):
+    from oracle import wilson
+    o = wilson.OracleCSR(g.n, g.src, g.dst, g.w)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    one = wilson.fastwalk_sample(o, o.pivot, seed, 0, 0, 1)
+    t1 = time.perf_counter() - t0
+    per_thread = max(1, int(seconds / max(t1, 1e-6)))
+    nsamp = min(l, per_thread * threads)
+    t0 = time.perf_counter()
+    r = wilson.fastwalk_sample(o, o.pivot, seed, 0, 0, nsamp, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": nsamp / dt, "unit": "trees/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {nsamp} of the {l} trees (samples 0..{nsamp - 1}), serial Wilson "
+                      f"per thread, {threads} threads",
+            "walk_steps_per_s": float(r["steps"].sum()) / dt}, r
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler shards by "
+              "sample range with one all-reduce of the visit totals, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2510_20604_amd as P
+    from paper_2510_20604_amd import _lib
+
+    g, l, seed, desc = workload(args.config)
+    if args.trees:
+        l = args.trees
+    dev = torch.device("cuda:0")
+    src = torch.as_tensor(g.src).to(dev)
+    dst = torch.as_tensor(g.dst).to(dev)
+    ws = {"sample": None}
+
+    def step():
+        G = P.Graph(g.n, src, dst, None, dev)
+        s = P.sample_forests(G, l, seed, want_sq=True, want_hash=False, workspace=ws["sample"], timing=True,
+                             walkers_per_tree=args.walkers, trees_in_flight=args.tif)
+        ws["sample"] = s["workspace"]
+        e = P.estimate(G, s["counts"], l, counts_sq=s["counts_sq"], want_stderr=True)
+        return G, s, e
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walk_ms, reduce_ms, steps_total = [], [], 0
+    for _ in range(args.steps):
+        G, s, e = step()
+        walk_ms.append(s["walk_ms"])
+        reduce_ms.append(s["reduce_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_steps = int(P.as_uint64(s["total_steps"])[0])
+    trees_in_flight = min(l, ((l + 63) // 64) * 64)
+    launches = math.ceil(l / trees_in_flight)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps * l / elapsed
+
+    # roofline of the dominant kernel (the walk)
+    wms = float(np.mean(walk_ms)) / launches
+    bytes_launch = walk_bytes(total_steps, l, g.n, False) / launches
+    achieved = bytes_launch / (wms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "wilson_walk", "avg_launch_ms": round(wms, 3),
+            "algorithmic_bytes_per_launch": bytes_launch}
+
+    extra = {}
+    if not args.no_probe:
+        # measured random-gather roofline over the sampler's own state footprint
+        import ctypes
+        wsp = ws["sample"]
+        words = wsp.numel() // 8
+        lanes, chain = 256 * 2048, 64
+        sink = torch.empty(lanes, dtype=torch.int64, device=dev)
+        ms = ctypes.c_float()
+        lib = _lib.lib()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for seed_probe in (1, 2):   # the first call warms up
+            _lib.check(lib.rwc_probe_random_gather(ctypes.c_void_p(wsp.data_ptr()), words, lanes, chain,
+                                                   seed_probe, ctypes.c_void_p(sink.data_ptr()),
+                                                   ctypes.byref(ms), stream), "rwc_probe_random_gather")
+        peak_acc = lanes * chain / (ms.value * 1e-3)
+        acc = walk_accesses(total_steps, l, g.n) / launches / (wms * 1e-3)
+        extra["gather_roofline"] = {"probe": f"dependent random 8-byte gathers, {lanes} chains x {chain}, "
+                                             f"footprint {wsp.numel() / 2**30:.1f} GiB",
+                                    "peak_accesses_per_s": peak_acc, "walk_accesses_per_s": acc,
+                                    "frac": round(acc / peak_acc, 4)}
+
+    rel_se = (e["stderr"] / e["rwc"]).double()
+    mask = torch.ones(g.n, dtype=torch.bool, device=dev)
+    mask[G.pivot] = False
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "trees/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": g.n, "m": g.m, "trees": l, "trees_in_flight": trees_in_flight,
+                   "walkers_per_tree": 1, "launch": "plain"},
+        "walk_steps_per_s": round(args.steps * total_steps / elapsed, 1),
+        "walk_steps_per_tree": total_steps / l,
+        "sampler_trees_per_s": round(l / (np.mean(walk_ms) + np.mean(reduce_ms)) * 1e3, 3),
+        "rwc_rel_stderr_mean": float(rel_se[mask].mean()),
+        "pcg_iters": e["iters"],
+        "roofline": roof,
+    }
+    line.update(extra)
+    if not args.no_cpu_baseline:
+        cb, _ = cpu_baseline(g, l, seed, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * rwc.h -- C ABI of the MI355X FastWalk library: random walk centrality (RWC) from rooted
+ * spanning trees sampled with Wilson's algorithm (Liu, Xie, Zehmakan, Zhang, "Efficient
+ * Algorithms for Computing Random Walk Centrality", Section 5, Algorithm 3), assembled by
+ * the pivot reformulation of Theorem 3.1 / Algorithm 1 (AppRWC).
+ *
+ * Conventions shared by every entry point
+ *  - Every pointer argument named *_dev, and every pointer inside rwc_csr /
+ *    rwc_sample_outputs unless stated otherwise, is a DEVICE pointer owned by the caller.
+ *    The library never allocates device memory: each call that needs scratch space takes a
+ *    caller-owned workspace whose size is returned by the matching *_workspace query.
+ *    Workspaces must be 256-byte aligned.
+ *  - `stream` is a hipStream_t passed as void*; all device work is ordered on it.
+ *  - Return value: RWC_OK (0) or a negative rwc_status.  On an argument error no output is
+ *    touched.  No exception or abort crosses the ABI.  rwc_last_error() gives a
+ *    human-readable detail of the most recent failure on the calling thread.
+ *  - Graph semantics: undirected, no self-loops, no repeated edges, connected (the paper
+ *    works on the largest connected component of each graph, Section 6.1).  Edge weights,
+ *    when given, are float32 values in [0.5, 65536); the walk moves from u to a neighbour
+ *    with probability w_uv / d_u where d_u is the weighted degree (the paper's unweighted
+ *    walk of Section 2.3 is the case w = 1).
+ */
+#ifndef RWC_H
+#define RWC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rwc_status {
+    RWC_OK = 0,
+    RWC_ERR_INVALID_ARG = -1,      /* null pointer, negative size, bad flag combination      */
+    RWC_ERR_NODE_RANGE = -2,       /* an edge endpoint outside [0, n)                        */
+    RWC_ERR_SELF_LOOP = -3,        /* an edge (u, u)                                         */
+    RWC_ERR_DUP_EDGE = -4,         /* the same undirected edge listed twice                  */
+    RWC_ERR_WEIGHT_RANGE = -5,     /* a weight outside [0.5, 65536) or not finite            */
+    RWC_ERR_DISCONNECTED = -6,     /* more than one connected component (or an isolated node)*/
+    RWC_ERR_TOO_LARGE = -7,        /* n >= 2^31 - 1, 2m >= 2^31, or an index space overflow  */
+    RWC_ERR_WORKSPACE = -8,        /* workspace null, misaligned or smaller than required    */
+    RWC_ERR_STEP_LIMIT = -9,       /* a tree needed more walk steps than max_steps_per_tree  */
+    RWC_ERR_COUNT_OVERFLOW = -10,  /* a node departed 2^24 times within one tree             */
+    RWC_ERR_NOT_CONVERGED = -11,   /* the pivot/adjoint solve missed its tolerance           */
+    RWC_ERR_HIP = -12              /* a HIP runtime call failed                              */
+} rwc_status;
+
+/* A graph in device memory, produced by rwc_build_csr.  All pointers point into the
+ * workspace given to rwc_build_csr, which must outlive every use of the struct. */
+typedef struct rwc_csr {
+    int32_t n;             /* nodes                                                         */
+    int32_t pivot;         /* node of largest weighted degree, ties to the smallest id      */
+    int64_t m;             /* undirected edges (= input edges)                              */
+    int64_t nnz;           /* 2m directed CSR entries                                       */
+    int32_t weighted;      /* 1 if the graph was built with weights                         */
+    int32_t max_degree;    /* largest number of neighbours                                  */
+    double vol;            /* sum of weighted degrees (2m for unit weights)                 */
+    uint64_t vol_fixed;    /* vol * 2^24, exact                                             */
+    int32_t* row_ptr;      /* [n + 1] CSR offsets                                           */
+    int32_t* col;          /* [nnz] neighbour ids, ascending within each row                */
+    float* weight;         /* [nnz] weight of each entry (1 for unweighted graphs)          */
+    int32_t* edge_id;      /* [nnz] index of the input edge each entry came from            */
+    uint64_t* cdf;         /* [nnz] inclusive prefix sums within each row of the integer
+                              weights W_e = w_e * 2^24 (NULL for unweighted graphs)         */
+    double* strength;      /* [n] weighted degree d_u                                       */
+} rwc_csr;
+
+/* Bytes of workspace rwc_build_csr needs for n nodes and m edges (weighted != 0 if w will
+ * be given).  The first rwc_csr_persistent_bytes() of it hold the CSR and must be kept; the
+ * rest is scratch that is free again when rwc_build_csr returns. */
+int rwc_build_csr_workspace(int32_t n, int64_t m, int32_t weighted, size_t* bytes);
+int rwc_csr_persistent_bytes(int32_t n, int64_t m, int32_t weighted, size_t* bytes);
+
+/* Builds the symmetric CSR used by every other call: rows sorted by neighbour id, weighted
+ * degrees d, vol, the integer CDF rows that RandomNeighbor (Algorithm 3) samples from, and
+ * the pivot of Section 6.1 (largest degree).  Validates the input and checks connectivity.
+ *   src_dev, dst_dev  int32 [m] edge endpoints (device)
+ *   w_dev             float32 [m] weights (device) or NULL for unit weights
+ * Synchronises `stream` before returning (it reads back a status word and the scalars). */
+int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* dst_dev,
+                  const float* w_dev, void* ws, size_t ws_bytes, rwc_csr* out, void* stream);
+
+/* Sampling flags. */
+#define RWC_SAMPLE_ACCUMULATE    1u  /* add to counts / counts_sq / total_steps instead of
+                                        overwriting them                                    */
+#define RWC_SAMPLE_PERSISTENT    2u  /* batched: one persistent launch whose waves pop (graph,
+                                        tree block) work items from a device queue          */
+#define RWC_SAMPLE_GRAPH_CAPTURE 4u  /* record the launches in a hipGraph and replay it     */
+
+typedef struct rwc_sample_params {
+    uint64_t seed;               /* Philox key (seed mod 2^32, seed >> 32)                 */
+    int64_t sample_begin;        /* global index of the first sample                      */
+    int64_t num_samples;         /* trees per graph (l in Algorithm 3)                    */
+    int32_t root;                /* -1: each graph's pivot; otherwise the root (1 graph)   */
+    uint32_t flags;              /* RWC_SAMPLE_*                                          */
+    int32_t trees_in_flight;     /* trees resident at once per graph; 0 = automatic       */
+    int32_t walkers_per_tree;    /* 0 = automatic; 1 = one walker per tree                */
+    uint64_t max_steps_per_tree; /* guard; 0 = 2^20 + 4096 n                              */
+    uint32_t graph_index_base;   /* Philox graph word of graphs[0]; graph g uses base + g */
+    uint32_t reserved;
+} rwc_sample_params;
+
+typedef struct rwc_sample_outputs {
+    uint64_t* counts;            /* [sum n_g] visit totals: entry u of graph g is the sum
+                                    over the trees of Algorithm 3's visit count of u (t~_u
+                                    times l).  Graph g starts at offset sum_{h<g} n_h.     */
+    uint64_t* counts_sq;         /* [sum n_g] sum of squared per-tree visits, or NULL     */
+    uint64_t* total_steps;       /* [num_graphs] RandomNeighbor calls, or NULL            */
+    uint64_t* tree_hash;         /* [num_graphs * num_samples] per-tree checksum
+                                    sum_{u != root} splitmix64(u * 2^32 + parent(u)) mod 2^64,
+                                    or NULL                                               */
+    int32_t* parents;            /* [ndump * n] parent of each node in the dumped trees,
+                                    -1 at the root (single graph only), or NULL           */
+    const int64_t* dump_samples; /* HOST array [ndump] of absolute sample indices         */
+    int32_t ndump;               /* at most 64                                            */
+    int32_t reserved;
+    float* timing_ms;            /* HOST [2] or NULL: device time of the walk kernels and of
+                                    the reduction kernels, summed over batches (hipEvents on
+                                    `stream`; not available with RWC_SAMPLE_GRAPH_CAPTURE) */
+} rwc_sample_outputs;
+
+/* Workspace for rwc_sample_forests with these graphs and parameters. */
+int rwc_sample_forests_workspace(const rwc_csr* graphs, int32_t num_graphs,
+                                 const rwc_sample_params* p, size_t* bytes);
+
+/* Samples p->num_samples rooted spanning trees of each graph with Wilson's algorithm
+ * (Section 5; Algorithm 3 with its visit counting) and accumulates per-node visit totals.
+ * The k-th departure from node u in sample i of graph g takes RandomNeighbor(u) from
+ * Philox4x32-10 on the counter (k, u, i, g) under key `seed`, so the forest is a fixed
+ * function of (graph, seed, sample index) whatever the launch shape, the number of trees in
+ * flight, the walkers per tree, or plain versus batched launches.
+ *   graphs   HOST array [num_graphs] of graphs from rwc_build_csr
+ * Synchronises `stream` before returning and reports device-side errors
+ * (RWC_ERR_STEP_LIMIT, RWC_ERR_COUNT_OVERFLOW). */
+int rwc_sample_forests(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p,
+                       const rwc_sample_outputs* out, void* ws, size_t ws_bytes, void* stream);
+
+typedef struct rwc_solve_params {
+    double tol;        /* relative residual of the pivot solve; 0 = 1e-12                 */
+    int32_t max_iter;  /* 0 = 20000                                                       */
+    int32_t check_every; /* iterations between host convergence checks; 0 = 16            */
+} rwc_solve_params;
+
+int rwc_estimate_workspace(const rwc_csr* g, size_t* bytes);
+
+/* AppRWC (Algorithm 1) fed by the FastWalk estimate t~ = counts / l (Algorithm 3, last line).
+ * The pivot column of Algorithm 1 is obtained from the hitting times h_u = H_{u,pivot},
+ * which solve the grounded system L_v h = d_{-v} (Jacobi-preconditioned CG in FP64);
+ * Eq. (3) then reads RWC_u = vol t~_u / d_u - 2 h_u + RWC_v with RWC_v = sum_u d_u h_u / vol.
+ *   counts_dev     uint64 [n] visit totals from rwc_sample_forests (this graph's slice)
+ *   counts_sq_dev  uint64 [n] or NULL (needed for stderr_dev)
+ *   l              number of trees behind counts
+ *   rwc_dev        double [n] output RWC
+ *   hit_dev        double [n] output hitting times to the pivot, or NULL
+ *   stderr_dev     double [n] output standard error of rwc from the sample variance, or NULL
+ *   iters          HOST int32 output: CG iterations used, or NULL
+ * Synchronises `stream`. */
+int rwc_estimate(const rwc_csr* g, const uint64_t* counts_dev, const uint64_t* counts_sq_dev,
+                 int64_t l, const rwc_solve_params* sp, double* rwc_dev, double* hit_dev,
+                 double* stderr_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+const char* rwc_status_string(int status);
+/* Copies the calling thread's last error detail into buf (NUL-terminated); returns its
+ * length. */
+int rwc_last_error(char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RWC_H */

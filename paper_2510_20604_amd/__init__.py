@@ -1,0 +1,13 @@
+"""MI355X-native FastWalk: random walk centrality from rooted spanning trees sampled by
+Wilson's algorithm (Liu, Xie, Zehmakan, Zhang, Section 5), hand-written HIP for gfx950 behind
+the C ABI of include/rwc.h.
+
+The HIP library (librwc.so) must be built (``python paper_2510_20604_amd/build.py``); importing
+the package raises ImportError if it is missing.  There is no CPU fallback.
+"""
+from . import _lib
+
+_lib.lib()  # load librwc.so now: fail loudly at import, never later on a silent path
+
+from .api import Graph, as_uint64, estimate, random_walk_centrality, sample_forests  # noqa: F401,E402
+from ._lib import RWCError  # noqa: F401,E402

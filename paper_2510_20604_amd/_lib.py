@@ -1,0 +1,103 @@
+"""ctypes view of librwc.so (the C ABI declared in include/rwc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.  If the
+library has not been built this module raises on import; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librwc.so")
+
+c_i32, c_i64, c_u32, c_u64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                                 ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p,
+                                                 ctypes.c_size_t)
+
+RWC_SAMPLE_ACCUMULATE = 1
+RWC_SAMPLE_PERSISTENT = 2
+RWC_SAMPLE_GRAPH_CAPTURE = 4
+
+STATUS = {
+    0: "RWC_OK", -1: "RWC_ERR_INVALID_ARG", -2: "RWC_ERR_NODE_RANGE", -3: "RWC_ERR_SELF_LOOP",
+    -4: "RWC_ERR_DUP_EDGE", -5: "RWC_ERR_WEIGHT_RANGE", -6: "RWC_ERR_DISCONNECTED",
+    -7: "RWC_ERR_TOO_LARGE", -8: "RWC_ERR_WORKSPACE", -9: "RWC_ERR_STEP_LIMIT",
+    -10: "RWC_ERR_COUNT_OVERFLOW", -11: "RWC_ERR_NOT_CONVERGED", -12: "RWC_ERR_HIP",
+}
+
+
+class RwcCsr(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("pivot", c_i32), ("m", c_i64), ("nnz", c_i64), ("weighted", c_i32),
+                ("max_degree", c_i32), ("vol", c_dbl), ("vol_fixed", c_u64), ("row_ptr", c_vp),
+                ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp)]
+
+
+class SampleParams(ctypes.Structure):
+    _fields_ = [("seed", c_u64), ("sample_begin", c_i64), ("num_samples", c_i64), ("root", c_i32),
+                ("flags", c_u32), ("trees_in_flight", c_i32), ("walkers_per_tree", c_i32),
+                ("max_steps_per_tree", c_u64), ("graph_index_base", c_u32), ("reserved", c_u32)]
+
+
+class SampleOutputs(ctypes.Structure):
+    _fields_ = [("counts", c_vp), ("counts_sq", c_vp), ("total_steps", c_vp), ("tree_hash", c_vp),
+                ("parents", c_vp), ("dump_samples", c_vp), ("ndump", c_i32), ("reserved", c_i32),
+                ("timing_ms", c_vp)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("check_every", c_i32)]
+
+
+# (name, restype, argtypes) for every entry point declared in include/*.h
+SIGNATURES = [
+    ("rwc_build_csr_workspace", c_i32, [c_i32, c_i64, c_i32, ctypes.POINTER(c_sz)]),
+    ("rwc_csr_persistent_bytes", c_i32, [c_i32, c_i64, c_i32, ctypes.POINTER(c_sz)]),
+    ("rwc_build_csr", c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, ctypes.POINTER(RwcCsr), c_vp]),
+    ("rwc_sample_forests_workspace", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),
+                                             ctypes.POINTER(c_sz)]),
+    ("rwc_sample_forests", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),
+                                   ctypes.POINTER(SampleOutputs), c_vp, c_sz, c_vp]),
+    ("rwc_estimate_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
+    ("rwc_estimate", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_vp, c_i64, ctypes.POINTER(SolveParams), c_vp, c_vp,
+                             c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_status_string", ctypes.c_char_p, [c_i32]),
+    ("rwc_probe_random_gather", c_i32, [c_vp, c_u64, c_i64, c_i32, c_u32, c_vp, ctypes.POINTER(ctypes.c_float), c_vp]),
+    ("rwc_probe_copy", c_i32, [c_vp, c_vp, c_u64, ctypes.POINTER(ctypes.c_float), c_vp]),
+    ("rwc_last_error", c_i32, [ctypes.c_char_p, c_sz]),
+]
+
+
+class RWCError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({detail})")
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build the HIP library first "
+                          "(python paper_2510_20604_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def check(rc: int, where: str) -> None:
+    if rc != 0:
+        buf = ctypes.create_string_buffer(512)
+        lib().rwc_last_error(buf, 512)
+        raise RWCError(rc, where, buf.value.decode(errors="replace"))

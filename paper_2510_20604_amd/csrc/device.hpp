@@ -1,0 +1,119 @@
+// Device-side building blocks of the sampler: the counter-based generator, neighbour
+// selection, the per-(tree, node) state word and wave-level reductions.  gfx950, wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rwc {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 products
+// on counter words 0 and 2, key words added in each round and bumped by the Weyl
+// constants between rounds.  Only output words 0 and 1 are used; the compiler drops the
+// rest of the last round.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t philox_x64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return static_cast<uint64_t>(c0) | (static_cast<uint64_t>(c1) << 32);
+}
+
+// floor(a * b / 2^64)
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// RandomNeighbor: the position within the row of the chosen neighbour.
+//   unweighted: floor(x * deg / 2^64)
+//   weighted:   r = floor(x * S / 2^64), S = cdf[end-1]; the first k with r < cdf[beg+k]
+__device__ __forceinline__ int32_t select_unweighted(uint64_t x, int32_t deg) {
+    return static_cast<int32_t>(mulhi64(x, static_cast<uint64_t>(deg)));
+}
+
+__device__ __forceinline__ int32_t select_weighted(uint64_t x, const uint64_t* __restrict__ cdf,
+                                                   int32_t beg, int32_t deg) {
+    const uint64_t total = cdf[beg + deg - 1];
+    const uint64_t r = mulhi64(x, total);
+    int32_t lo = 0, hi = deg - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (r < cdf[beg + mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014): the tree checksum term.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-(tree, node) state word, 64 bits:
+//   [31:0]  next  -- the last neighbour chosen at a departure (Next[u] of Algorithm 3);
+//                    the parent once the node is in the tree
+//   [55:32] cnt   -- departures from the node in this tree (the Philox step word)
+//   [61:56] owner -- walker lane that holds the node on its current path (multi-walker)
+//   [62]    OWNED -- the node is on a live walker path
+//   [63]    INTREE
+// The all-zero word is a fresh node; the root starts as INTREE.
+// ---------------------------------------------------------------------------------------
+constexpr uint64_t kInTree = 1ull << 63;
+constexpr uint64_t kOwned = 1ull << 62;
+constexpr uint32_t kCntMax = (1u << 24) - 1;
+
+__device__ __forceinline__ uint32_t st_next(uint64_t w) { return static_cast<uint32_t>(w); }
+__device__ __forceinline__ uint32_t st_cnt(uint64_t w) {
+    return static_cast<uint32_t>(w >> 32) & 0xFFFFFFu;
+}
+__device__ __forceinline__ uint32_t st_owner(uint64_t w) {
+    return static_cast<uint32_t>(w >> 56) & 0x3Fu;
+}
+__device__ __forceinline__ uint64_t st_make(uint32_t next, uint32_t cnt) {
+    return static_cast<uint64_t>(next) | (static_cast<uint64_t>(cnt) << 32);
+}
+__device__ __forceinline__ uint64_t st_make_owned(uint32_t next, uint32_t cnt, uint32_t owner) {
+    return st_make(next, cnt) | kOwned | (static_cast<uint64_t>(owner) << 56);
+}
+
+// Square of a departure count as uint64.  The count is known to fit 24 bits; the empty asm
+// hides that from the optimiser, whose fold of a 24-bit multiply plus 64-bit add into
+// v_mad_u64_u32 drops the 24-bit mask (seen with the ROCm 7.2 compiler for gfx950) and would
+// square the raw word including the flag bits.  The asm holds no memory operation.
+__device__ __forceinline__ uint64_t square_count(uint32_t c) {
+    asm volatile("" : "+v"(c));
+    return static_cast<uint64_t>(c) * c;
+}
+
+// ---------------------------------------------------------------------------------------
+// Wave reductions (wave64, shuffles).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+}  // namespace rwc

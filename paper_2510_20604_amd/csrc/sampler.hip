@@ -1,0 +1,885 @@
+// rwc_sample_forests: Wilson's algorithm (Section 5, Algorithm 3) on the GPU, many trees at
+// once, with the visit counting of Algorithm 3 reduced into per-node totals.
+//
+// Layout.  Each graph g keeps T tree slots; slot t holds one 64-bit state word per node
+// (state[t * n_g + u], see device.hpp) -- the InTree flag, Next[u] and the departure count
+// of u in the slot's current tree.  A batch runs T trees (one per slot) to completion, then a
+// reduction pass folds the per-tree departure counts into the per-node totals, writes the
+// requested parent dumps and resets the slots for the next batch.
+//
+// One lane grows one tree.  The lane runs Algorithm 3's three loops -- pick the next start
+// node that is not yet in the tree, walk until the tree is hit, retrace the loop-erased path
+// -- as one flat state machine, so every iteration of the wave does one step of some lane's
+// work instead of parking lanes that finished a phase early.
+//
+// RandomNeighbor(u) at the k-th departure from u in sample i of graph word g is
+// Philox4x32-10((k, u, i, g), seed).  A node's successive choices are therefore fixed in
+// advance, which makes the tree and every count independent of the order in which walks are
+// run (cycle popping), so results match the serial order of Algorithm 3 exactly.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace rwc {
+namespace {
+
+struct GraphArgs {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const uint64_t* cdf;
+    uint64_t* state;        // [T][n]
+    int32_t n;
+    int32_t root;
+    uint32_t graph_word;
+    int32_t pad;
+};
+
+struct Item {
+    int32_t graph;
+    int32_t slot0;
+};
+
+constexpr int kMaxDump = 64;
+
+struct DumpArgs {
+    int32_t count;
+    int32_t slot[kMaxDump];
+    int32_t out[kMaxDump];
+};
+
+enum Phase : int { kScan = 0, kWalk = 1, kRetrace = 2, kDone = 3 };
+
+// Grows the tree of slot `slot` for absolute sample `sample` (one lane).
+__device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint64_t sample, uint64_t seed,
+                                          uint64_t max_steps, uint64_t& steps_out, uint64_t& hash_out,
+                                          uint32_t& err_out) {
+    const int32_t n = G.n;
+    const int32_t* __restrict__ row_ptr = G.row_ptr;
+    const int32_t* __restrict__ col = G.col;
+    const uint64_t* __restrict__ cdf = G.cdf;
+    uint64_t* __restrict__ st = G.state + static_cast<int64_t>(slot) * n;
+    const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+    const uint32_t sw = static_cast<uint32_t>(sample);
+    const uint32_t gw = G.graph_word;
+
+    uint32_t j = 0;      // next start candidate (ascending order, Algorithm 3)
+    uint32_t x = 0;      // walk position, or retrace cursor
+    uint32_t hit = 0;    // node at which the current walk met the tree
+    uint64_t wx = 0;     // state word of x while walking
+    uint64_t steps = 0, h = 0;
+    uint32_t retr = 0, err = 0;
+    int phase = kScan;
+    while (phase != kDone) {
+        if (phase == kScan) {
+            if (j >= static_cast<uint32_t>(n)) {
+                phase = kDone;
+            } else {
+                const uint64_t w = st[j];
+                if (w & kInTree) {
+                    ++j;
+                } else {
+                    x = j;
+                    wx = w;
+                    phase = kWalk;
+                }
+            }
+        } else if (phase == kWalk) {
+            const uint32_t k = st_cnt(wx);
+            const int32_t beg = row_ptr[x];
+            const int32_t deg = row_ptr[x + 1] - beg;
+            const uint64_t r = philox_x64(k, x, sw, gw, k0, k1);
+            const int32_t pick = cdf ? select_weighted(r, cdf, beg, deg) : select_unweighted(r, deg);
+            const uint32_t y = static_cast<uint32_t>(col[beg + pick]);
+            st[x] = st_make(y, k + 1);
+            const uint64_t wy = st[y];
+            ++steps;
+            if (k + 1 >= kCntMax) {
+                err |= kErrCountOverflow;
+                phase = kDone;
+            } else if (steps > max_steps) {
+                err |= kErrStepLimit;
+                phase = kDone;
+            } else if (wy & kInTree) {
+                hit = y;
+                x = j;
+                retr = 0;
+                phase = kRetrace;
+            } else {
+                x = y;
+                wx = wy;
+            }
+        } else {  // kRetrace: mark the loop-erased path j -> ... -> hit
+            if (x == hit) {
+                ++j;
+                phase = kScan;
+            } else {
+                const uint64_t w = st[x];
+                const uint32_t p = st_next(w);
+                st[x] = w | kInTree;
+                h += splitmix64((static_cast<uint64_t>(x) << 32) | p);
+                x = p;
+                if (++retr > static_cast<uint32_t>(n)) {
+                    err |= kErrRetrace;
+                    phase = kDone;
+                }
+            }
+        }
+    }
+    steps_out = steps;
+    hash_out = h;
+    err_out = err;
+}
+
+__device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t T,
+                                         int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
+                                         int64_t l, uint64_t seed, uint64_t max_steps,
+                                         uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
+                                         uint32_t* __restrict__ status) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t slot = it.slot0 + lane;
+    const int64_t sample = batch_sample0 + slot;
+    const GraphArgs G = graphs[it.graph];
+    uint64_t steps = 0, h = 0;
+    uint32_t err = 0;
+    const bool active = slot < T && sample < sample_end;
+    if (active) grow_tree(G, slot, static_cast<uint64_t>(sample), seed, max_steps, steps, h, err);
+    if (active) {
+        if (tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + (sample - sample_begin)] = h;
+        if (err) atomicOr(status, err);
+    }
+    const uint64_t wsteps = wave_sum(steps);
+    if (lane == 0 && total_steps && wsteps)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&total_steps[it.graph]),
+                  static_cast<unsigned long long>(wsteps));
+}
+
+// One wave per work item (a block of 64 tree slots of one graph).  Persistent mode: a grid
+// sized to the resident capacity pops items from `queue` until the list is exhausted.
+__global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                                     int32_t nitems, uint32_t* queue, int32_t T,
+                                                     int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
+                                                     int64_t l, uint64_t seed, uint64_t max_steps,
+                                                     uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    if (queue == nullptr) {
+        if (static_cast<int32_t>(blockIdx.x) < nitems)
+            run_item(graphs, items[blockIdx.x], T, batch_sample0, sample_end, sample_begin, l, seed, max_steps,
+                     tree_hash, total_steps, status);
+        return;
+    }
+    while (true) {
+        uint32_t idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
+        idx = __shfl(idx, 0, kWave);
+        if (idx >= static_cast<uint32_t>(nitems)) break;
+        run_item(graphs, items[idx], T, batch_sample0, sample_end, sample_begin, l, seed, max_steps, tree_hash,
+                 total_steps, status);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Several walkers per tree (a team of W lanes of one wave grows one tree).
+//
+// Wilson's algorithm is cycle popping on per-node stacks of random arrows: with the stack-keyed
+// generator, any procedure that reads arrows in stack order and pops only genuine cycles of
+// the current arrow configuration ends with the same tree and the same per-node departure
+// counts as Algorithm 3's serial order.  A team runs W such walks at once:
+//  * a walker owns the nodes of its current (loop-erased) path: state word OWNED + its team
+//    lane id; its head's arrow is read at each step (departure count incremented);
+//  * arrow into the tree       -> the path attaches (retrace from its start marking INTREE);
+//  * arrow into its own path   -> a cycle of its own arrows: the segment after the hit node is
+//                                 released (FREE, counts kept) and the hit node is the head;
+//  * arrow into a free node    -> claim it (compare-and-swap; the loser waits on the winner);
+//  * arrow into another walker's path -> wait.  Waiting walkers whose targets form a cycle of
+//    walkers hold a genuine arrow cycle: it is popped by every member releasing the segment
+//    after its junction (the node its cycle predecessor points at), which becomes its head.
+// Start nodes are handed out in ascending order; a start owned by another walker is waited
+// on until it is in the tree (skip) or free (claim).  Every iteration reads before it writes
+// and ends with a work-group fence, so all lanes see one consistent snapshot per iteration.
+// ---------------------------------------------------------------------------------------
+enum TeamMode : int { tIdle = 0, tStart = 1, tWalk = 2, tWait = 3, tRetrace = 4, tRelease = 5, tDone = 6 };
+
+__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool st_cas(uint64_t* p, uint64_t expected, uint64_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int W>
+__device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
+                          uint64_t max_iters, uint32_t* lds_pred, uint64_t& steps_out, uint64_t& hash_out,
+                          uint32_t& err_out) {
+    constexpr uint32_t kNone = 64;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int team = lane / W;
+    const uint32_t tl = static_cast<uint32_t>(lane % W);
+    const uint32_t team_base = static_cast<uint32_t>(team * W);
+    const uint64_t team_mask = (W == kWave) ? ~0ull : (((1ull << W) - 1ull) << team_base);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint32_t n = static_cast<uint32_t>(G.n);
+    const int32_t* __restrict__ row_ptr = G.row_ptr;
+    const int32_t* __restrict__ col = G.col;
+    const uint64_t* __restrict__ cdf = G.cdf;
+    uint64_t* st = G.state + static_cast<int64_t>(slot) * G.n;
+    const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+    const uint32_t sw = static_cast<uint32_t>(sample), gw = G.graph_word;
+
+    uint32_t next_start = 0;                 // uniform within the team
+    int mode = active ? tIdle : tDone;
+    uint32_t j = 0, h = 0, y = 0, c = 0, cend = 0, jn = 0;
+    uint64_t wh = 0, jw = 0;
+    uint64_t steps = 0, hsum = 0, iters = 0;
+    uint32_t err = 0;
+    while (true) {
+        // ---- hand out start nodes, ascending, to idle walkers of each team
+        const bool idle = (mode == tIdle);
+        const uint64_t bi = __ballot(idle);
+        if (idle) {
+            j = next_start + static_cast<uint32_t>(__popcll(bi & team_mask & lt_mask));
+            mode = (j < n) ? tStart : tDone;
+        }
+        next_start += static_cast<uint32_t>(__popcll(bi & team_mask));
+        if (__all(mode == tDone)) break;
+        if (++iters > max_iters) {
+            err |= kErrStepLimit;
+            break;
+        }
+
+        // ---- reads
+        uint32_t node = 0;
+        uint32_t ny = 0;
+        uint32_t k = 0;
+        if (mode == tWalk) {
+            k = st_cnt(wh);
+            const int32_t beg = row_ptr[h];
+            const int32_t deg = row_ptr[h + 1] - beg;
+            const uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
+            const int32_t pick = cdf ? select_weighted(r, cdf, beg, deg) : select_unweighted(r, deg);
+            ny = static_cast<uint32_t>(col[beg + pick]);
+            node = ny;
+        } else if (mode == tStart) {
+            node = j;
+        } else if (mode == tWait) {
+            node = y;
+        } else if (mode == tRetrace || mode == tRelease) {
+            node = c;
+        }
+        const bool reads = (mode != tDone) && (mode != tIdle);
+        const uint64_t w = reads ? st_load(&st[node]) : 0ull;
+        const bool w_tree = (w & kInTree) != 0;
+        const bool w_owned = (w & kOwned) != 0;
+        const bool w_mine = w_owned && st_owner(w) == tl;
+
+        // ---- decide
+        bool claim = false, depart = false, store = false, waiting = false;
+        uint64_t dep_word = 0, store_word = 0;
+        uint32_t dep_node = 0, claim_node = 0, store_node = 0;
+        if (mode == tWalk) {
+            depart = true;
+            dep_node = h;
+            dep_word = st_make_owned(ny, k + 1, tl);
+            ++steps;
+            if (k + 1 >= kCntMax) {
+                err |= kErrCountOverflow;
+                mode = tDone;
+            } else if (w_tree) {
+                mode = tRetrace;
+                c = j;
+            } else if (w_mine) {
+                // own cycle ny -> ... -> h -> ny: release the segment after ny; ny is the head
+                mode = tRelease;
+                c = st_next(w);
+                cend = h;
+                jn = ny;
+                jw = w;
+            } else if (w_owned) {
+                mode = tWait;
+                y = ny;
+                waiting = true;
+            } else {
+                claim = true;
+                claim_node = ny;
+            }
+        } else if (mode == tStart) {
+            if (w_tree) {
+                mode = tIdle;
+            } else if (!w_owned) {
+                claim = true;
+                claim_node = j;
+            }
+        } else if (mode == tWait) {
+            if (w_tree) {
+                mode = tRetrace;
+                c = j;
+            } else if (!w_owned) {
+                claim = true;
+                claim_node = y;
+            } else if (w_mine) {
+                err |= kErrProtocol;
+                mode = tDone;
+            } else {
+                waiting = true;
+            }
+        } else if (mode == tRetrace || mode == tRelease) {
+            if (!w_mine) {
+                err |= kErrProtocol;
+                mode = tDone;
+            } else if (mode == tRetrace) {
+                store = true;
+                store_node = c;
+                store_word = (w & ~(kOwned | (0x3Full << 56))) | kInTree;
+                hsum += splitmix64((static_cast<uint64_t>(c) << 32) | st_next(w));
+                if (c == h)
+                    mode = tIdle;
+                else
+                    c = st_next(w);
+            } else {
+                store = true;
+                store_node = c;
+                store_word = st_make(0u, st_cnt(w));
+                if (c == cend) {
+                    mode = tWalk;
+                    h = jn;
+                    wh = jw;
+                } else {
+                    c = st_next(w);
+                }
+            }
+        }
+
+        // ---- pop cycles of waiting walkers (team-local functional graph, pointer doubling:
+        // after 64 applications every chain has either left the waiting set or entered a
+        // cycle, so the image of the 64-fold map is exactly the set of cycle members)
+        if (__any(waiting)) {
+            const uint32_t wf = waiting ? team_base + (st_owner(w) & (W - 1)) : kNone;
+            uint32_t p = wf;
+#pragma unroll
+            for (int it = 0; it < 6; ++it) {
+                const uint32_t q = __shfl(p, static_cast<int>(p & (kWave - 1)), kWave);
+                p = (p == kNone) ? kNone : q;
+            }
+            uint64_t img = (p == kNone) ? 0ull : (1ull << p);
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) img |= __shfl_xor(img, off, kWave);
+            const bool on_cycle = waiting && ((img >> lane) & 1ull);
+            // each cycle member has exactly one predecessor on its cycle
+            if (on_cycle) lds_pred[wf] = static_cast<uint32_t>(lane);
+            __syncthreads();
+            const uint32_t pred = on_cycle ? lds_pred[lane] : static_cast<uint32_t>(lane);
+            const uint32_t py = __shfl(y, static_cast<int>(pred), kWave);
+            const uint64_t pw = __shfl(w, static_cast<int>(pred), kWave);
+            __syncthreads();
+            if (on_cycle) {
+                // the cycle enters my path at py: the arrows from py on are popped
+                jn = py;
+                jw = pw;
+                if (jn == h) {
+                    // my head's own arrow is popped; if I departed in this iteration the
+                    // snapshot the predecessor read predates my departure word
+                    mode = tWalk;
+                    wh = depart ? dep_word : jw;
+                } else {
+                    mode = tRelease;
+                    c = st_next(jw);
+                    cend = h;
+                }
+            }
+        }
+
+        // ---- writes
+        if (depart) st_store(&st[dep_node], dep_word);
+        if (store) st_store(&st[store_node], store_word);
+        if (claim) {
+            const uint64_t want = st_make_owned(st_next(w), st_cnt(w), tl);
+            if (st_cas(&st[claim_node], w, want)) {
+                h = claim_node;   // a start claim begins a path at j == claim_node
+                wh = want;
+                mode = tWalk;
+            } else if (mode == tWalk) {
+                mode = tWait;     // lost the race: the winner owns the node now
+                y = claim_node;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+    steps_out = steps;
+    hash_out = hsum;
+    err_out = err;
+}
+
+template <int W>
+__device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t T,
+                                              int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
+                                              int64_t l, uint64_t seed, uint64_t max_iters, uint32_t* lds_pred,
+                                              uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
+                                              uint32_t* __restrict__ status) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t slot = it.slot0 + lane / W;
+    const int64_t sample = batch_sample0 + slot;
+    const bool active = slot < T && sample < sample_end;
+    const GraphArgs G = graphs[it.graph];
+    uint64_t steps = 0, h = 0;
+    uint32_t err = 0;
+    grow_team<W>(G, active ? slot : 0, static_cast<uint64_t>(sample), active, seed, max_iters, lds_pred, steps, h,
+                 err);
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) {
+        steps += __shfl_xor(steps, off, kWave);
+        h += __shfl_xor(h, off, kWave);
+    }
+    const bool leader = (lane % W) == 0;
+    if (active && leader && tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + (sample - sample_begin)] = h;
+    if (err) atomicOr(status, err);
+    const uint64_t wsteps = wave_sum(leader ? steps : 0ull);
+    if (lane == 0 && total_steps && wsteps)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&total_steps[it.graph]),
+                  static_cast<unsigned long long>(wsteps));
+}
+
+// One wave per work item: 64 / W trees, W walkers each.
+template <int W>
+__global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                                     int32_t nitems, uint32_t* queue, int32_t T,
+                                                     int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
+                                                     int64_t l, uint64_t seed, uint64_t max_iters,
+                                                     uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    __shared__ uint32_t lds_pred[kWave];
+    if (queue == nullptr) {
+        if (static_cast<int32_t>(blockIdx.x) < nitems)
+            run_team_item<W>(graphs, items[blockIdx.x], T, batch_sample0, sample_end, sample_begin, l, seed, max_iters,
+                             lds_pred, tree_hash, total_steps, status);
+        return;
+    }
+    while (true) {
+        uint32_t idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
+        idx = __shfl(idx, 0, kWave);
+        if (idx >= static_cast<uint32_t>(nitems)) break;
+        run_team_item<W>(graphs, items[idx], T, batch_sample0, sample_end, sample_begin, l, seed, max_iters, lds_pred,
+                         tree_hash, total_steps, status);
+    }
+}
+
+using WalkKernel = void (*)(const GraphArgs*, const Item*, int32_t, uint32_t*, int32_t, int64_t, int64_t, int64_t,
+                            int64_t, uint64_t, uint64_t, uint64_t*, uint64_t*, uint32_t*);
+
+WalkKernel walk_kernel_for(int W) {
+    switch (W) {
+        case 2: return wilson_team<2>;
+        case 4: return wilson_team<4>;
+        case 8: return wilson_team<8>;
+        case 16: return wilson_team<16>;
+        case 32: return wilson_team<32>;
+        case 64: return wilson_team<64>;
+        default: return wilson_walk;
+    }
+}
+
+__device__ __forceinline__ int32_t graph_of(const int64_t* __restrict__ node_off, int32_t G, int64_t gx) {
+    int32_t lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (node_off[mid] <= gx)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Sets every slot of every graph to the fresh state (root in the tree, all else zero).
+__global__ void init_state(const GraphArgs* __restrict__ graphs, const int64_t* __restrict__ node_off, int32_t G,
+                           int64_t total_nodes, int32_t T) {
+    for (int64_t gx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; gx < total_nodes;
+         gx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t g = graph_of(node_off, G, gx);
+        const GraphArgs A = graphs[g];
+        const int64_t x = gx - node_off[g];
+        const uint64_t v = (x == A.root) ? kInTree : 0ull;
+        for (int32_t t = 0; t < T; ++t) A.state[static_cast<int64_t>(t) * A.n + x] = v;
+    }
+}
+
+__global__ void zero_outputs(uint64_t* counts, uint64_t* counts_sq, int64_t total_nodes, uint64_t* total_steps,
+                             int32_t G, uint32_t* status, uint32_t* queue) {
+    const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = tid; i < total_nodes; i += stride) {
+        if (counts) counts[i] = 0;
+        if (counts_sq) counts_sq[i] = 0;
+    }
+    for (int64_t i = tid; i < G; i += stride)
+        if (total_steps) total_steps[i] = 0;
+    if (tid == 0) {
+        *status = 0;
+        *queue = 0;
+    }
+}
+
+__global__ void reset_queue(uint32_t* queue) { *queue = 0; }
+
+// Folds the departure counts of the batch's trees into the per-node totals, writes the
+// parent dumps of this batch and resets the slots.  Thread per node, loop over slots: the
+// reads and writes of consecutive threads are consecutive words of one slot.
+__global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t* __restrict__ node_off, int32_t G,
+                             int64_t total_nodes, int32_t used_slots, uint64_t* __restrict__ counts,
+                             uint64_t* __restrict__ counts_sq, int32_t* __restrict__ parents, DumpArgs dumps) {
+    for (int64_t gx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; gx < total_nodes;
+         gx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t g = graph_of(node_off, G, gx);
+        const GraphArgs A = graphs[g];
+        const int64_t x = gx - node_off[g];
+        const int64_t n = A.n;
+        const bool is_root = (x == A.root);
+        for (int d = 0; d < dumps.count; ++d) {
+            const uint64_t w = A.state[static_cast<int64_t>(dumps.slot[d]) * n + x];
+            parents[static_cast<int64_t>(dumps.out[d]) * n + x] = is_root ? -1 : static_cast<int32_t>(st_next(w));
+        }
+        const uint64_t fresh = is_root ? kInTree : 0ull;
+        uint64_t c1 = 0, c2 = 0;
+        int32_t t = 0;
+        for (; t + 4 <= used_slots; t += 4) {
+            uint64_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] = A.state[static_cast<int64_t>(t + q) * n + x];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t c = st_cnt(w[q]);
+                c1 += c;
+                c2 += square_count(c);
+                A.state[static_cast<int64_t>(t + q) * n + x] = fresh;
+            }
+        }
+        for (; t < used_slots; ++t) {
+            const uint32_t c = st_cnt(A.state[static_cast<int64_t>(t) * n + x]);
+            c1 += c;
+            c2 += square_count(c);
+            A.state[static_cast<int64_t>(t) * n + x] = fresh;
+        }
+        if (counts) counts[gx] += c1;
+        if (counts_sq) counts_sq[gx] += c2;
+    }
+}
+
+// ---------------------------------------------------------------------- planning ------
+struct Plan {
+    int32_t T = 0;
+    int32_t W = 1;           // walkers per tree
+    int32_t S = kWave;       // trees per wave (64 / W)
+    int64_t total_nodes = 0;
+    std::vector<int64_t> node_off;
+};
+
+constexpr int64_t kDefaultStateBudget = 96ll << 30;  // bytes of slot state chosen automatically
+constexpr int64_t kTargetWalkers = 1 << 16;          // concurrent walkers aimed at with W > 1
+
+// Walkers per tree when the caller leaves it open: one per tree while all trees of a small
+// problem fit in flight with enough concurrency, otherwise a team per tree.
+int auto_walkers(int64_t total_nodes, int32_t G, int64_t l) {
+    if (total_nodes * l <= (int64_t(1) << 27) || l * G >= kTargetWalkers) return 1;
+    return 16;
+}
+
+int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan* plan) {
+    plan->node_off.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+        if (graphs[g].n < 2 || !graphs[g].row_ptr || !graphs[g].col)
+            return fail(RWC_ERR_INVALID_ARG, "graph %d is not a built CSR", g);
+        plan->node_off[g + 1] = plan->node_off[g] + graphs[g].n;
+    }
+    plan->total_nodes = plan->node_off[G];
+    const int64_t l = p->num_samples;
+    int W = p->walkers_per_tree;
+    if (W <= 0) W = auto_walkers(plan->total_nodes, G, l);
+    plan->W = W;
+    plan->S = kWave / W;
+    int64_t T = p->trees_in_flight;
+    if (T <= 0) {
+        // one walker per tree: every tree resident; several walkers: enough trees to give
+        // each graph about kTargetWalkers concurrent walkers
+        int64_t want = (W == 1) ? l : (kTargetWalkers / W + G - 1) / G;
+        if (want > l) want = l;
+        want = (want + plan->S - 1) / plan->S * plan->S;
+        int64_t cap = kDefaultStateBudget / (8 * plan->total_nodes) / plan->S * plan->S;
+        if (cap < plan->S) cap = plan->S;
+        T = want < cap ? want : cap;
+    }
+    if (T > (1 << 30)) return fail(RWC_ERR_TOO_LARGE, "trees_in_flight too large");
+    plan->T = static_cast<int32_t>(T);
+    return RWC_OK;
+}
+
+struct SampleLayout {
+    std::vector<uint64_t*> state;
+    GraphArgs* graphs;
+    int64_t* node_off;
+    Item* items;
+    uint32_t* queue;
+    uint32_t* status;
+    size_t total;
+};
+
+SampleLayout carve_sample(void* ws, const rwc_csr* graphs, int32_t G, const Plan& plan, int64_t max_items) {
+    Carver c(ws);
+    SampleLayout L{};
+    L.state.resize(G);
+    for (int32_t g = 0; g < G; ++g) L.state[g] = c.take<uint64_t>(static_cast<size_t>(plan.T) * graphs[g].n);
+    L.graphs = c.take<GraphArgs>(G);
+    L.node_off = c.take<int64_t>(G + 1);
+    L.items = c.take<Item>(max_items);
+    L.queue = c.take<uint32_t>(1);
+    L.status = c.take<uint32_t>(1);
+    L.total = c.used();
+    return L;
+}
+
+int64_t items_per_batch(int32_t G, const Plan& plan) {
+    return static_cast<int64_t>(G) * ((plan.T + plan.S - 1) / plan.S);
+}
+
+// hipEvents bracketing the walk and reduction launches of every batch.
+struct Timer {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    float walk_ms = 0.f, reduce_ms = 0.f;
+    int init() {
+        for (auto& e : ev) RWC_HIP(hipEventCreate(&e));
+        return RWC_OK;
+    }
+    ~Timer() {
+        for (auto& e : ev)
+            if (e) hipEventDestroy(e);
+    }
+};
+
+// Private stream for hipGraph capture: begin() orders it after the caller's stream;
+// end_and_launch() ends the capture, instantiates and launches the graph, and orders the
+// caller's stream after it.
+struct CaptureStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool capturing = false;
+
+    int begin(hipStream_t caller) {
+        RWC_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        RWC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        RWC_HIP(hipEventRecord(ev, caller));
+        RWC_HIP(hipStreamWaitEvent(stream, ev, 0));
+        RWC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        capturing = true;
+        return RWC_OK;
+    }
+    int end_and_launch(hipStream_t caller, int launch_rc) {
+        capturing = false;
+        const hipError_t e = hipStreamEndCapture(stream, &graph);
+        if (launch_rc != RWC_OK) return launch_rc;
+        if (e != hipSuccess) return fail(RWC_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        RWC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        RWC_HIP(hipGraphLaunch(exec, stream));
+        RWC_HIP(hipEventRecord(ev, stream));
+        RWC_HIP(hipStreamWaitEvent(caller, ev, 0));
+        return RWC_OK;
+    }
+    ~CaptureStream() {
+        if (capturing) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(stream, &g);
+            if (g) hipGraphDestroy(g);
+        }
+        if (stream) hipStreamSynchronize(stream);
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (ev) hipEventDestroy(ev);
+        if (stream) hipStreamDestroy(stream);
+    }
+};
+
+int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
+    if (!graphs || !p || G < 1) return fail(RWC_ERR_INVALID_ARG, "graphs/params missing or num_graphs < 1");
+    if (p->num_samples < 1) return fail(RWC_ERR_INVALID_ARG, "num_samples must be positive");
+    if (p->sample_begin < 0 || p->sample_begin + p->num_samples > (1ll << 32))
+        return fail(RWC_ERR_INVALID_ARG, "sample indices must lie in [0, 2^32)");
+    if (p->root >= 0 && G != 1) return fail(RWC_ERR_INVALID_ARG, "an explicit root needs a single graph");
+    if (p->root >= graphs[0].n) return fail(RWC_ERR_INVALID_ARG, "root out of range");
+    const int W = p->walkers_per_tree;
+    if (W < 0 || W > kWave || (W & (W - 1)) != 0)
+        return fail(RWC_ERR_INVALID_ARG, "walkers_per_tree must be 0 (automatic) or a power of two up to 64");
+    return RWC_OK;
+}
+
+}  // namespace
+}  // namespace rwc
+
+using namespace rwc;
+
+extern "C" int rwc_sample_forests_workspace(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p,
+                                            size_t* bytes) {
+    clear_error();
+    if (!bytes) return fail(RWC_ERR_INVALID_ARG, "bytes is null");
+    RWC_CHECK(validate(graphs, num_graphs, p));
+    Plan plan;
+    RWC_CHECK(make_plan(graphs, num_graphs, p, &plan));
+    *bytes = carve_sample(nullptr, graphs, num_graphs, plan, items_per_batch(num_graphs, plan)).total;
+    return RWC_OK;
+}
+
+extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p,
+                                  const rwc_sample_outputs* out, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    RWC_CHECK(validate(graphs, G, p));
+    if (!out || !out->counts) return fail(RWC_ERR_INVALID_ARG, "out->counts is required");
+    if (out->ndump < 0 || out->ndump > kMaxDump) return fail(RWC_ERR_INVALID_ARG, "ndump must be in [0, %d]", kMaxDump);
+    if (out->ndump > 0 && (G != 1 || !out->parents || !out->dump_samples))
+        return fail(RWC_ERR_INVALID_ARG, "parent dumps need a single graph, parents and dump_samples");
+    for (int d = 0; d < out->ndump; ++d)
+        if (out->dump_samples[d] < p->sample_begin || out->dump_samples[d] >= p->sample_begin + p->num_samples)
+            return fail(RWC_ERR_INVALID_ARG, "dump sample %lld is outside the sampled range",
+                        (long long)out->dump_samples[d]);
+    Plan plan;
+    RWC_CHECK(make_plan(graphs, G, p, &plan));
+    const int64_t max_items = items_per_batch(G, plan);
+    const size_t need = carve_sample(nullptr, graphs, G, plan, max_items).total;
+    RWC_CHECK(check_workspace(ws, ws_bytes, need));
+    SampleLayout L = carve_sample(ws, graphs, G, plan, max_items);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t T = plan.T;
+    const int64_t l = p->num_samples;
+
+    std::vector<GraphArgs> hg(G);
+    for (int32_t g = 0; g < G; ++g) {
+        hg[g].row_ptr = graphs[g].row_ptr;
+        hg[g].col = graphs[g].col;
+        hg[g].cdf = graphs[g].weighted ? graphs[g].cdf : nullptr;
+        hg[g].state = L.state[g];
+        hg[g].n = graphs[g].n;
+        hg[g].root = (p->root >= 0) ? p->root : graphs[g].pivot;
+        hg[g].graph_word = p->graph_index_base + static_cast<uint32_t>(g);
+        hg[g].pad = 0;
+    }
+    // Work items in decreasing graph size (longest trees first).
+    std::vector<int32_t> order(G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return graphs[a].n > graphs[b].n; });
+    std::vector<Item> items;
+    items.reserve(max_items);
+    for (int32_t g : order)
+        for (int32_t s0 = 0; s0 < T; s0 += plan.S) items.push_back(Item{g, s0});
+    RWC_HIP(hipMemcpyAsync(L.graphs, hg.data(), sizeof(GraphArgs) * G, hipMemcpyHostToDevice, s));
+    RWC_HIP(hipMemcpyAsync(L.node_off, plan.node_off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+    RWC_HIP(hipMemcpyAsync(L.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
+
+    const bool persistent = (p->flags & RWC_SAMPLE_PERSISTENT) != 0;
+    const WalkKernel walk = walk_kernel_for(plan.W);
+    int grid_persistent = 0;
+    if (persistent) {
+        int per_cu = 0;
+        RWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk, kWave, 0));
+        if (per_cu < 1) per_cu = 1;
+        grid_persistent = per_cu * device_cu_count();
+    }
+    uint64_t max_steps = p->max_steps_per_tree;
+
+    const bool capture = (p->flags & RWC_SAMPLE_GRAPH_CAPTURE) != 0;
+    if (capture && out->timing_ms)
+        return fail(RWC_ERR_INVALID_ARG, "timing_ms is not available with RWC_SAMPLE_GRAPH_CAPTURE");
+    Timer timer;
+    if (out->timing_ms) RWC_CHECK(timer.init());
+    // A capture runs on a private stream (the caller's may be the legacy default stream,
+    // which cannot be captured), ordered after and before the caller's stream by events.
+    CaptureStream cap;
+    if (capture) RWC_CHECK(cap.begin(s));
+    const hipStream_t ls = capture ? cap.stream : s;
+
+    auto launches = [&]() -> int {
+        const unsigned node_blocks = blocks_for(plan.total_nodes, 256) < 8192 ? blocks_for(plan.total_nodes, 256) : 8192;
+        const bool accumulate = (p->flags & RWC_SAMPLE_ACCUMULATE) != 0;
+        hipLaunchKernelGGL(zero_outputs, dim3(node_blocks), dim3(256), 0, ls, accumulate ? nullptr : out->counts,
+                           accumulate ? nullptr : out->counts_sq, plan.total_nodes,
+                           accumulate ? nullptr : out->total_steps, G, L.status, L.queue);
+        hipLaunchKernelGGL(init_state, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G, plan.total_nodes,
+                           T);
+        for (int64_t b0 = 0; b0 < l; b0 += T) {
+            const int32_t used = static_cast<int32_t>((l - b0) < T ? (l - b0) : T);
+            // A short last batch reuses the full item list: slots at or beyond `used` map to
+            // samples >= sample_end, which the kernel leaves idle.
+            const Item* item_ptr = L.items;
+            const int32_t nit = static_cast<int32_t>(items.size());
+            const int64_t batch_sample0 = p->sample_begin + b0;
+            const int64_t sample_end = p->sample_begin + l;
+            const uint64_t guard = max_steps;
+            if (out->timing_ms) RWC_HIP(hipEventRecord(timer.ev[0], ls));
+            if (persistent) {
+                hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, ls, L.queue);
+                const int grid = grid_persistent < nit ? grid_persistent : nit;
+                hipLaunchKernelGGL(walk, dim3(grid), dim3(kWave), 0, ls, L.graphs, item_ptr, nit, L.queue, T,
+                                   batch_sample0, sample_end, p->sample_begin, l, p->seed, guard, out->tree_hash,
+                                   out->total_steps, L.status);
+            } else {
+                hipLaunchKernelGGL(walk, dim3(nit), dim3(kWave), 0, ls, L.graphs, item_ptr, nit, nullptr, T,
+                                   batch_sample0, sample_end, p->sample_begin, l, p->seed, guard, out->tree_hash,
+                                   out->total_steps, L.status);
+            }
+            DumpArgs dumps{};
+            for (int d = 0; d < out->ndump; ++d) {
+                const int64_t rel = out->dump_samples[d] - batch_sample0;
+                if (rel >= 0 && rel < used) {
+                    dumps.slot[dumps.count] = static_cast<int32_t>(rel);
+                    dumps.out[dumps.count] = d;
+                    ++dumps.count;
+                }
+            }
+            if (out->timing_ms) RWC_HIP(hipEventRecord(timer.ev[1], ls));
+            hipLaunchKernelGGL(reduce_batch, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G,
+                               plan.total_nodes, used, out->counts, out->counts_sq, out->parents, dumps);
+            if (out->timing_ms) {
+                RWC_HIP(hipEventRecord(timer.ev[2], ls));
+                RWC_HIP(hipEventSynchronize(timer.ev[2]));
+                float a = 0.f, b = 0.f;
+                RWC_HIP(hipEventElapsedTime(&a, timer.ev[0], timer.ev[1]));
+                RWC_HIP(hipEventElapsedTime(&b, timer.ev[1], timer.ev[2]));
+                timer.walk_ms += a;
+                timer.reduce_ms += b;
+            }
+        }
+        RWC_HIP(hipGetLastError());
+        return RWC_OK;
+    };
+
+    if (max_steps == 0) {
+        // default guard: far above the expected walk length of any graph we accept, and
+        // small enough that a runaway tree ends with an error instead of a hang
+        int64_t maxn = 0;
+        for (int32_t g = 0; g < G; ++g) maxn = graphs[g].n > maxn ? graphs[g].n : maxn;
+        max_steps = (1ull << 20) + 4096ull * static_cast<uint64_t>(maxn);
+    }
+    if (plan.W > 1) {
+        // a team's iterations: every step, retrace, release and start check of the tree
+        // takes at most one iteration of some walker, and waits end by cycle pops
+        int64_t maxn = 0;
+        for (int32_t g = 0; g < G; ++g) maxn = graphs[g].n > maxn ? graphs[g].n : maxn;
+        max_steps = 4ull * max_steps + 8ull * static_cast<uint64_t>(maxn) + 1024ull;
+    }
+    int rc = launches();
+    if (capture) {
+        const int rc2 = cap.end_and_launch(s, rc);
+        RWC_CHECK(rc);
+        RWC_CHECK(rc2);
+    }
+    RWC_CHECK(rc);
+    uint32_t status = 0;
+    RWC_HIP(hipMemcpyAsync(&status, L.status, sizeof(status), hipMemcpyDeviceToHost, s));
+    RWC_HIP(hipStreamSynchronize(s));
+    if (out->timing_ms) {
+        out->timing_ms[0] = timer.walk_ms;
+        out->timing_ms[1] = timer.reduce_ms;
+    }
+    return device_error_to_status(status);
+}

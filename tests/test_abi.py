@@ -1,0 +1,74 @@
+"""The C-ABI library loads, exports every entry point declared in include/rwc.h, and its
+host-only paths (workspace queries, argument validation) behave -- no GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(rwc_\w+)\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    names = _declared()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert set(names) <= bound
+
+
+def test_workspace_queries_and_argument_errors():
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    size = ctypes.c_size_t()
+    assert lib.rwc_build_csr_workspace(1000, 4000, 0, ctypes.byref(size)) == 0
+    small = size.value
+    assert lib.rwc_build_csr_workspace(1000, 4000, 1, ctypes.byref(size)) == 0
+    assert size.value > small
+    pers = ctypes.c_size_t()
+    assert lib.rwc_csr_persistent_bytes(1000, 4000, 1, ctypes.byref(pers)) == 0
+    assert 0 < pers.value < size.value
+    assert lib.rwc_build_csr_workspace(1, 1, 0, ctypes.byref(size)) == -1      # n < 2
+    assert lib.rwc_build_csr_workspace(10, 0, 0, ctypes.byref(size)) == -1     # m < 1
+    assert lib.rwc_build_csr_workspace(10, 1 << 31, 0, ctypes.byref(size)) == -7
+    # null inputs are rejected before any device work
+    csr = _lib.RwcCsr()
+    assert lib.rwc_build_csr(10, 5, None, None, None, None, 0, ctypes.byref(csr), None) == -1
+    buf = ctypes.create_string_buffer(256)
+    assert lib.rwc_last_error(buf, 256) > 0
+    assert lib.rwc_status_string(-6) == b"graph is not connected"
+
+
+def test_sample_workspace_scales_with_trees_in_flight():
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8)
+    p = _lib.SampleParams(seed=1, sample_begin=0, num_samples=500, root=-1, trees_in_flight=64)
+    a = ctypes.c_size_t()
+    assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(a)) == 0
+    p.trees_in_flight = 128
+    b = ctypes.c_size_t()
+    assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(b)) == 0
+    assert b.value - a.value >= 64 * 1000 * 8
+    p.walkers_per_tree = 0
+    p.num_samples = 0
+    assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(b)) == -1
+
+
+def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2510_20604_amd import _lib
+    with pytest.raises(ImportError):
+        _lib.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,235 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer outputs (CSR, visit totals, squared visits, step totals, tree checksums, parent
+arrays) must be bit-identical.  Floating-point outputs follow tolerances derived in the tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import rwcgen as G
+from oracle import exact as E
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2510_20604_amd")
+
+
+def _case(name):
+    if name == "er1000":
+        return G.erdos_renyi_lcc(1000, 8, 1001)
+    if name == "er1000_w":
+        g = G.erdos_renyi_lcc(1000, 8, 1001)
+        return g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 3))
+    if name == "ba3000_w":
+        g = G.barabasi_albert(3000, 3, 5)
+        return g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 6))
+    if name == "grid_w":
+        g = G.grid_with_deletions(2500, 0.1, 7)
+        return g.with_weights(G.uniform_weights(g.m, 1.0, 4.0, 8))
+    if name == "star":
+        return G.star_graph(65)
+    if name == "path":
+        return G.path_graph(130)
+    if name == "k2":
+        return G.complete_graph(2)
+    raise KeyError(name)
+
+
+CASES = ["er1000", "er1000_w", "ba3000_w", "grid_w", "star", "path", "k2"]
+
+
+def _u64(t):
+    return P.as_uint64(t)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_csr_matches_oracle(name):
+    g = _case(name)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+    np.testing.assert_array_equal(Gd.row_ptr().cpu().numpy(), o.row_ptr)
+    np.testing.assert_array_equal(Gd.col().cpu().numpy(), o.col)
+    np.testing.assert_array_equal(Gd.strength().cpu().numpy(), o.strength)
+    assert Gd.pivot == o.pivot
+    assert Gd.vol == o.vol
+    if g.w is not None:
+        np.testing.assert_array_equal(_u64(Gd.cdf()), o.cdf)
+        np.testing.assert_array_equal(Gd.weight().cpu().numpy().astype(np.float64), o.weight)
+    # edge_id maps every entry back to an input edge with matching endpoints
+    eid = Gd.edge_id().cpu().numpy()
+    rows = np.repeat(np.arange(g.n), np.diff(o.row_ptr))
+    a, b = g.src[eid], g.dst[eid]
+    assert np.all(((a == rows) & (b == o.col)) | ((b == rows) & (a == o.col)))
+
+
+@pytest.mark.parametrize("bad,code", [("self_loop", -3), ("dup", -4), ("range", -2), ("weight", -5),
+                                      ("disconnected", -6), ("nan", -5)])
+def test_csr_rejects_bad_input(bad, code):
+    src = np.array([0, 1, 2, 3], dtype=np.int32)
+    dst = np.array([1, 2, 3, 0], dtype=np.int32)
+    w = None
+    n = 4
+    if bad == "self_loop":
+        dst[1] = 1
+    elif bad == "dup":
+        src[3], dst[3] = 1, 0
+    elif bad == "range":
+        dst[2] = 7
+    elif bad == "weight":
+        w = np.array([1.0, 0.25, 1.0, 1.0], dtype=np.float32)
+    elif bad == "nan":
+        w = np.array([1.0, np.nan, 1.0, 1.0], dtype=np.float32)
+    elif bad == "disconnected":
+        n = 6
+    with pytest.raises(P.RWCError) as ei:
+        P.Graph(n, src, dst, w)
+    assert ei.value.status == code
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    cache = {}
+
+    def get(name, l, seed, graph=0, sample_begin=0):
+        key = (name, l, seed, graph, sample_begin)
+        if key not in cache:
+            g = _case(name)
+            o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+            cache[key] = (g, o, W.fastwalk_sample(o, o.pivot, seed, graph, sample_begin, l,
+                                                  want_parents=True, threads=8))
+        return cache[key]
+
+    return get
+
+
+@pytest.mark.parametrize("name,l", [("er1000", 2000), ("er1000_w", 300), ("ba3000_w", 200), ("grid_w", 100),
+                                    ("star", 50), ("path", 70), ("k2", 10)])
+def test_forest_bit_exact(name, l, oracle_runs):
+    g, o, ref = oracle_runs(name, l, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    dump = list(range(min(16, l)))
+    s = P.sample_forests(Gd, l, 2001, dump=dump)
+    np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(_u64(s["counts_sq"]), ref["visits_sq"])
+    np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
+    np.testing.assert_array_equal(s["parents"].cpu().numpy(), ref["parents"][dump])
+    assert int(_u64(s["total_steps"])[0]) == int(ref["steps"].sum())
+
+
+@pytest.mark.parametrize("tif,persistent,capture", [(64, False, False), (128, True, False), (192, False, True),
+                                                    (64, True, True)])
+def test_launch_shape_does_not_change_the_forest(tif, persistent, capture, oracle_runs):
+    g, o, ref = oracle_runs("er1000_w", 300, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    s = P.sample_forests(Gd, 300, 2001, trees_in_flight=tif, persistent=persistent, capture=capture, dump=[0, 299])
+    np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(_u64(s["counts_sq"]), ref["visits_sq"])
+    np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
+    np.testing.assert_array_equal(s["parents"].cpu().numpy(), ref["parents"][[0, 299]])
+
+
+@pytest.mark.parametrize("walkers", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("name,l", [("er1000", 150), ("er1000_w", 100), ("ba3000_w", 70), ("grid_w", 40),
+                                    ("star", 20), ("path", 30), ("k2", 8)])
+def test_walker_teams_are_bit_exact(walkers, name, l, oracle_runs):
+    """Several walkers per tree pop the same cycles as the serial order of Algorithm 3."""
+    g, o, ref = oracle_runs(name, l, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    dump = [0, l - 1]
+    s = P.sample_forests(Gd, l, 2001, walkers_per_tree=walkers, dump=dump)
+    np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
+    np.testing.assert_array_equal(s["parents"].cpu().numpy(), ref["parents"][dump])
+    np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(_u64(s["counts_sq"]), ref["visits_sq"])
+    assert int(_u64(s["total_steps"])[0]) == int(ref["steps"].sum())
+
+
+@pytest.mark.parametrize("walkers,tif,persistent", [(8, 16, True), (16, 4, False), (64, 3, True)])
+def test_walker_teams_launch_shapes(walkers, tif, persistent, oracle_runs):
+    g, o, ref = oracle_runs("ba3000_w", 200, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=walkers, trees_in_flight=tif, persistent=persistent)
+    np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
+
+
+def test_sample_range_chunks_accumulate(oracle_runs):
+    g, o, ref = oracle_runs("ba3000_w", 200, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    a = P.sample_forests(Gd, 70, 2001, sample_begin=0)
+    b = P.sample_forests(Gd, 130, 2001, sample_begin=70, accumulate={k: a[k] for k in
+                                                                    ("counts", "counts_sq", "total_steps")})
+    np.testing.assert_array_equal(_u64(b["counts"]), ref["visits"])
+    np.testing.assert_array_equal(_u64(b["counts_sq"]), ref["visits_sq"])
+    np.testing.assert_array_equal(_u64(b["tree_hash"][0]), ref["hash"][70:])
+
+
+def test_batched_graphs_match_per_graph_oracle():
+    graphs = G.batch_mix(6, 300, 3000, seed=41)
+    dev = [P.Graph(g.n, g.src, g.dst, g.w) for g in graphs]
+    l, seed, base = 64 + 17, 77, 5
+    s = P.sample_forests(dev, l, seed, persistent=True, capture=True, graph_index_base=base)
+    counts = _u64(s["counts"])
+    off = 0
+    for i, g in enumerate(graphs):
+        o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+        ref = W.fastwalk_sample(o, o.pivot, seed, base + i, 0, l, threads=8)
+        np.testing.assert_array_equal(counts[off:off + g.n], ref["visits"])
+        np.testing.assert_array_equal(_u64(s["tree_hash"][i]), ref["hash"])
+        off += g.n
+    # plain per-graph launches give the same bits
+    for i, gd in enumerate(dev[:2]):
+        p = P.sample_forests(gd, l, seed, graph_index_base=base + i)
+        np.testing.assert_array_equal(_u64(p["tree_hash"][0]), _u64(s["tree_hash"][i]))
+
+
+def test_explicit_root(oracle_runs):
+    g = _case("er1000_w")
+    o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+    ref = W.fastwalk_sample(o, 17, 5, 0, 0, 40)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    s = P.sample_forests(Gd, 40, 5, root=17)
+    np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
+
+
+def test_step_guard_reports_an_error():
+    g = _case("grid_w")
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    with pytest.raises(P.RWCError) as ei:
+        P.sample_forests(Gd, 8, 1, max_steps_per_tree=100)
+    assert ei.value.status == -9
+
+
+# ----------------------------------------------------------------------- estimate -----
+@pytest.mark.parametrize("name,l", [("er1000", 2000), ("er1000_w", 300), ("ba3000_w", 200), ("grid_w", 100)])
+def test_estimate_matches_oracle_assembly(name, l, oracle_runs):
+    """rwc_estimate on the same visit totals reproduces Algorithm 1 evaluated with a dense FP64
+    solve.  The CG stops at relative residual 1e-12 of L_v h = d; the error this leaves in h is
+    at most cond(L_v) * 1e-12 relative, which the test bounds with cond <= 1e3 for these graphs
+    (plus rounding), hence 1e-9."""
+    g, o, ref = oracle_runs(name, l, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    counts = torch.as_tensor(ref["visits"].view(np.int64)).cuda()
+    counts_sq = torch.as_tensor(ref["visits_sq"].view(np.int64)).cuda()
+    est = P.estimate(Gd, counts, l, counts_sq=counts_sq, want_stderr=True)
+    want = E.fastwalk_estimate(g.n, g.src, g.dst, g.w, o.pivot, ref["visits"], l)
+    got = est["rwc"].cpu().numpy()
+    np.testing.assert_allclose(got, want, rtol=1e-9)
+    hit = E.hitting_times_to(g.n, g.src, g.dst, g.w, o.pivot)
+    np.testing.assert_allclose(est["hit"].cpu().numpy(), hit, rtol=1e-9, atol=1e-9 * hit.max())
+    # the estimate is within its own error bars of the exact RWC for most nodes
+    exact = E.rwc_laplacian_pinv(g.n, g.src, g.dst, g.w)
+    se = est["stderr"].cpu().numpy()
+    mask = se > 0
+    z = np.abs(got[mask] - exact[mask]) / se[mask]
+    assert np.mean(z > 4) < 0.01
+
+
+def test_end_to_end_er1000_accuracy():
+    g = _case("er1000")
+    rwc = P.random_walk_centrality(g.n, g.src, g.dst, None, l=2000, seed=2001).cpu().numpy()
+    exact = E.rwc_laplacian_pinv(g.n, g.src, g.dst, None)
+    mre = E.mean_relative_error(exact, rwc)
+    assert mre < 0.03
