@@ -64,6 +64,9 @@ typedef struct rwc_csr {
     uint64_t* cdf;         /* [nnz] inclusive prefix sums within each row of the integer
                               weights W_e = w_e * 2^24 (NULL for unweighted graphs)         */
     double* strength;      /* [n] weighted degree d_u                                       */
+    uint32_t* rec;         /* [16 n] 64-byte node records: degree, row offset, then the first
+                              14 neighbour ids (unweighted) or the first 4 ids in words 2..5
+                              and their CDF values in words 8..15 (weighted)               */
 } rwc_csr;
 
 /* Bytes of workspace rwc_build_csr needs for n nodes and m edges (weighted != 0 if w will
@@ -159,6 +162,40 @@ int rwc_estimate_workspace(const rwc_csr* g, size_t* bytes);
 int rwc_estimate(const rwc_csr* g, const uint64_t* counts_dev, const uint64_t* counts_sq_dev,
                  int64_t l, const rwc_solve_params* sp, double* rwc_dev, double* hit_dev,
                  double* stderr_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+typedef struct rwc_backward_params {
+    int32_t k;           /* Rademacher probes per sign class of g; 0 = exact (one column per
+                            target)                                                       */
+    int32_t max_iter;    /* 0 = 20000                                                      */
+    uint64_t seed;       /* probe key: the sign of probe i at node u is bit 0 of word 0 of
+                            Philox4x32-10 on the counter (i, u, 0, 2^32 - 1); probes of the
+                            negative class are numbered k .. 2k-1                          */
+    double tol;          /* relative residual of every solve column; 0 = 1e-10            */
+    int32_t check_every; /* iterations between host convergence checks; 0 = 16            */
+    int32_t reserved;
+} rwc_backward_params;
+
+/* Workspace for rwc_backward with this target list (its size depends on the number of
+ * solve columns, hence on the targets and the signs of their g values). */
+int rwc_backward_workspace(const rwc_csr* g, int32_t num_targets, const int32_t* targets,
+                           const double* gvals, const rwc_backward_params* bp, size_t* bytes);
+
+/* Gradient of l(w) = sum_j g_j RWC_j (exact RWC, Eq. (2)) with respect to every edge weight.
+ * The paper does not differentiate RWC; this is the adjoint of its quantity, with the
+ * derivative of L^+ through the incidence form L = B^T B of Section 2.2:
+ *   dl/dw_e = 2 trGL - vol Q_e + 2 D_A D_B - 2 S_A + G ((2 S_B - D_B^2)/vol - 2 d^T B/vol^2)
+ * A = L^+ g, B = L^+ d, G = sum g, trGL = sum_j g_j L^+_jj, Q_e = sum_j g_j (L^+ b_e)_j^2,
+ * D_X = X_a - X_b, S_X = X_a + X_b for e = (a, b).  Q_e and trGL are exact (k = 0) or a
+ * Johnson-Lindenstrauss / Hutchinson sketch with k probes per sign class of g.  All solves
+ * run together as one batched Jacobi-preconditioned CG on the grounded Laplacian (FP32
+ * search directions, FP64 iterate, residual and dot products).
+ *   targets, gvals  HOST arrays [num_targets]: the nodes with g_j != 0 and their g_j
+ *   grad_w_dev      double [m] output in input-edge order (device)
+ *   iters           HOST int32 output: CG iterations used, or NULL
+ * Synchronises `stream`. */
+int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t* targets, const double* gvals,
+                 const rwc_backward_params* bp, double* grad_w_dev, int32_t* iters, void* ws,
+                 size_t ws_bytes, void* stream);
 
 const char* rwc_status_string(int status);
 /* Copies the calling thread's last error detail into buf (NUL-terminated); returns its

@@ -102,3 +102,98 @@ def grad_autograd(n: int, src, dst, w, g) -> np.ndarray:
     lval = (torch.as_tensor(np.asarray(g, dtype=np.float64)) * H).sum()
     lval.backward()
     return wt.grad.detach().numpy().copy()
+
+
+# ---------------------------------------------------------------------------------------
+# Probe columns shared by the exact and sketched forms, and a sparse evaluation at sampled
+# edges for graphs too large for dense matrices.
+# ---------------------------------------------------------------------------------------
+def probe_columns(n: int, targets, gvals, k: int, seed: int):
+    """Columns (c_i, y_i) with Q_e ~ sum_i c_i (b_e^T L^+ y_i)^2 and trGL ~ sum_i c_i y_i^T L^+ y_i.
+
+    k = 0: y = sqrt|g_j| e_j, c = sign(g_j) for every target (exact).
+    k > 0: for each sign class of g present (positive first), k Rademacher probes
+    y_i = sqrt(|g|) r_i restricted to that class, c_i = +-1/k.  The sign of probe i at node u is
+    bit 0 of word 0 of Philox4x32-10 on the counter (i, u, 0, 2^32 - 1) with key `seed`;
+    probes of the negative class are numbered k .. 2k - 1.
+    """
+    from .wilson import philox4x32_10
+    targets = np.asarray(targets, dtype=np.int64)
+    gvals = np.asarray(gvals, dtype=np.float64)
+    cols = []
+    if k == 0:
+        for t, gv in zip(targets, gvals):
+            y = np.zeros(n)
+            y[t] = np.sqrt(abs(gv))
+            cols.append((float(np.sign(gv)), y))
+        return cols
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    for cls in (0, 1):
+        sel = gvals > 0 if cls == 0 else gvals < 0
+        if not np.any(sel):
+            continue
+        for i in range(k):
+            probe = cls * k + i
+            y = np.zeros(n)
+            for t, gv in zip(targets[sel], gvals[sel]):
+                o0 = philox4x32_10([probe, int(t), 0, 0xFFFFFFFF], key)[0]
+                y[t] = (-1.0 if (o0 & 1) else 1.0) * np.sqrt(abs(gv))
+            cols.append(((1.0 if cls == 0 else -1.0) / k, y))
+    return cols
+
+
+def grad_from_probes(n: int, src, dst, w, g, cols) -> np.ndarray:
+    """Dense gradient with Q_e and trGL taken from the probe columns."""
+    d, vol, Lp, g, A, B, a, b = _edge_terms(n, src, dst, w, g)
+    Q = np.zeros(len(a))
+    trGL = 0.0
+    for c, y in cols:
+        z = Lp @ y
+        dz = z[a] - z[b]
+        Q += c * dz * dz
+        trGL += c * float(y @ z)
+    return _assemble(vol, g, A, B, a, b, Q, trGL, float(d @ B))
+
+
+def grad_at_edges_sparse(n: int, src, dst, w, targets, gvals, edges, cols=None) -> np.ndarray:
+    """dl/dw_e for the input edges `edges` from sparse conjugate-gradient solves (SciPy), for
+    graphs too large for dense matrices.  cols=None evaluates Q_e and trGL exactly (one solve
+    per sampled edge and per target); otherwise from the given probe columns."""
+    from .exact import _sparse_laplacian, lap_solve
+    L, d = _sparse_laplacian(n, src, dst, w)
+    vol = d.sum()
+    targets = np.asarray(targets, dtype=np.int64)
+    gvals = np.asarray(gvals, dtype=np.float64)
+    g = np.zeros(n)
+    g[targets] = gvals
+
+    def pinv(y):
+        yc = y - y.mean()
+        z = lap_solve(n, src, dst, w, yc, "sparse_cg")
+        return z - z.mean()
+
+    A = pinv(g)
+    B = pinv(d)
+    a = np.asarray(src, dtype=np.int64)[edges]
+    b = np.asarray(dst, dtype=np.int64)[edges]
+    if cols is None:
+        trGL = 0.0
+        for t, gv in zip(targets, gvals):
+            e = np.zeros(n)
+            e[t] = 1.0
+            trGL += gv * pinv(e)[t]
+        Q = np.zeros(len(edges))
+        for i, (ai, bi) in enumerate(zip(a, b)):
+            be = np.zeros(n)
+            be[ai], be[bi] = 1.0, -1.0
+            y = pinv(be)
+            Q[i] = float(g @ (y * y))
+    else:
+        Q = np.zeros(len(edges))
+        trGL = 0.0
+        for c, y in cols:
+            z = pinv(y)
+            dz = z[a] - z[b]
+            Q += c * dz * dz
+            trGL += c * float(y @ z)
+    return _assemble(vol, g, A, B, a, b, Q, trGL, float(d @ B))

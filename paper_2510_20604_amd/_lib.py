@@ -30,7 +30,8 @@ STATUS = {
 class RwcCsr(ctypes.Structure):
     _fields_ = [("n", c_i32), ("pivot", c_i32), ("m", c_i64), ("nnz", c_i64), ("weighted", c_i32),
                 ("max_degree", c_i32), ("vol", c_dbl), ("vol_fixed", c_u64), ("row_ptr", c_vp),
-                ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp)]
+                ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp),
+                ("rec", c_vp)]
 
 
 class SampleParams(ctypes.Structure):
@@ -49,6 +50,11 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("check_every", c_i32)]
 
 
+class BackwardParams(ctypes.Structure):
+    _fields_ = [("k", c_i32), ("max_iter", c_i32), ("seed", c_u64), ("tol", c_dbl), ("check_every", c_i32),
+                ("reserved", c_i32)]
+
+
 # (name, restype, argtypes) for every entry point declared in include/*.h
 SIGNATURES = [
     ("rwc_build_csr_workspace", c_i32, [c_i32, c_i64, c_i32, ctypes.POINTER(c_sz)]),
@@ -61,6 +67,10 @@ SIGNATURES = [
     ("rwc_estimate_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
     ("rwc_estimate", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_vp, c_i64, ctypes.POINTER(SolveParams), c_vp, c_vp,
                              c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_backward_workspace", c_i32, [ctypes.POINTER(RwcCsr), c_i32, c_vp, c_vp, ctypes.POINTER(BackwardParams),
+                                       ctypes.POINTER(c_sz)]),
+    ("rwc_backward", c_i32, [ctypes.POINTER(RwcCsr), c_i32, c_vp, c_vp, ctypes.POINTER(BackwardParams), c_vp,
+                             ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
     ("rwc_status_string", ctypes.c_char_p, [c_i32]),
     ("rwc_probe_random_gather", c_i32, [c_vp, c_u64, c_i64, c_i32, c_u32, c_vp, ctypes.POINTER(ctypes.c_float), c_vp]),
     ("rwc_probe_copy", c_i32, [c_vp, c_vp, c_u64, ctypes.POINTER(ctypes.c_float), c_vp]),

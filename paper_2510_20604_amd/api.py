@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import RwcCsr, SampleOutputs, SampleParams, SolveParams, check
+from ._lib import BackwardParams, RwcCsr, SampleOutputs, SampleParams, SolveParams, check
 
 
 def _stream() -> ctypes.c_void_p:
@@ -92,6 +92,9 @@ class Graph:
 
     def strength(self) -> torch.Tensor:
         return self._view(self.csr.strength, self.n, torch.float64)
+
+    def rec(self) -> torch.Tensor:
+        return self._view(self.csr.rec, 16 * self.n, torch.int32)
 
 
 def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int, sample_begin: int = 0,
@@ -173,6 +176,62 @@ def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor
                          _ptr(rwc), _ptr(hit), _ptr(se), ctypes.byref(iters), _ptr(ws), ws.numel(), _stream()),
           "rwc_estimate")
     return {"rwc": rwc, "hit": hit, "stderr": se, "iters": iters.value}
+
+
+def backward(graph: Graph, targets, gvals, k: int = 0, seed: int = 0, tol: float = 1e-10,
+             max_iter: int = 0) -> dict:
+    """Gradient of sum_j g_j RWC_j with respect to the edge weights (rwc_backward).
+
+    targets / gvals: the nodes with nonzero g and their values (host arrays).  k = 0 solves
+    one column per target (exact); k > 0 uses k Rademacher probes per sign class of g.
+    Returns grad_w (float64 [m] on the device, input-edge order) and the CG iterations."""
+    L = _lib.lib()
+    t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    gv = np.ascontiguousarray(np.asarray(gvals, dtype=np.float64))
+    if t.shape != gv.shape or t.ndim != 1 or t.size == 0:
+        raise ValueError("targets and gvals must be matching non-empty 1-D arrays")
+    bp = BackwardParams(k=k, max_iter=max_iter, seed=seed, tol=tol, check_every=0)
+    tp = t.ctypes.data_as(ctypes.c_void_p)
+    gp = gv.ctypes.data_as(ctypes.c_void_p)
+    size = ctypes.c_size_t()
+    check(L.rwc_backward_workspace(ctypes.byref(graph.csr), t.size, tp, gp, ctypes.byref(bp), ctypes.byref(size)),
+          "rwc_backward_workspace")
+    ws = _workspace(size.value, graph.device)
+    grad = torch.empty(graph.m, dtype=torch.float64, device=graph.device)
+    iters = ctypes.c_int32()
+    check(L.rwc_backward(ctypes.byref(graph.csr), t.size, tp, gp, ctypes.byref(bp), _ptr(grad), ctypes.byref(iters),
+                         _ptr(ws), ws.numel(), _stream()), "rwc_backward")
+    return {"grad_w": grad, "iters": iters.value}
+
+
+class RWCFunction(torch.autograd.Function):
+    """RWC as a differentiable function of the edge weights.
+
+    forward:  FastWalk estimate (Algorithm 3: l Wilson trees rooted at the pivot, then AppRWC);
+    backward: the analytic gradient of the exact RWC (rwc_backward).  The Monte Carlo
+    estimator itself is piecewise constant in w, so its own derivative is useless; the
+    backward pass differentiates the quantity it estimates.
+
+    apply(w, n, src, dst, l, seed, k=0, probe_seed=0) with w a float32 CUDA tensor [m]."""
+
+    @staticmethod
+    def forward(ctx, w, n, src, dst, l, seed, k=0, probe_seed=0):
+        g = Graph(n, src, dst, w.detach().to(torch.float32), w.device)
+        s = sample_forests(g, l, seed, want_sq=False, want_hash=False)
+        rwc = estimate(g, s["counts"], l, want_hit=False)["rwc"]
+        ctx.graph, ctx.k, ctx.probe_seed, ctx.wdtype = g, k, probe_seed, w.dtype
+        return rwc
+
+    @staticmethod
+    def backward(ctx, grad_rwc):
+        gr = grad_rwc.detach().to(torch.float64)
+        nz = torch.nonzero(gr).flatten()
+        if nz.numel() == 0:
+            gw = torch.zeros(ctx.graph.m, dtype=ctx.wdtype, device=gr.device)
+        else:
+            res = backward(ctx.graph, nz.cpu().numpy(), gr[nz].cpu().numpy(), k=ctx.k, seed=ctx.probe_seed)
+            gw = res["grad_w"].to(ctx.wdtype)
+        return gw, None, None, None, None, None, None, None
 
 
 def random_walk_centrality(n: int, src, dst, w=None, l: int = 2000, seed: int = 0,

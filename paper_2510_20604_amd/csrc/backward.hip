@@ -1,0 +1,472 @@
+// rwc_backward: gradient of l(w) = sum_j g_j RWC_j with respect to the edge weights.
+//
+// RWC_j = vol L^+_jj - 2 (L^+ d)_j + d^T L^+ d / vol (Eq. (2) with the pseudo-inverse
+// identity of Section 3).  With dL/dw_e = b_e b_e^T (b_e from the incidence matrix of
+// Section 2.2), dL^+/dw_e = -L^+ b_e b_e^T L^+, dd/dw_e = e_a + e_b and dvol/dw_e = 2:
+//   dl/dw_e = 2 trGL - vol Q_e + 2 D_A D_B - 2 S_A + G ((2 S_B - D_B^2)/vol - 2 dLd/vol^2)
+// with A = L^+ g, B = L^+ d, G = sum g, trGL = sum_j g_j L^+_jj, dLd = d^T B,
+// Q_e = sum_j g_j (L^+ b_e)_j^2, D_X = X_a - X_b, S_X = X_a + X_b for e = (a, b).
+//
+// Q_e and trGL are carried by probe columns y_i with coefficients c_i:
+//   Q_e ~ sum_i c_i (b_e^T L^+ y_i)^2,   trGL ~ sum_i c_i y_i^T L^+ y_i.
+// Exact mode: one column per target j, y = sqrt|g_j| e_j, c = sign(g_j).  Sketch mode (a
+// Johnson-Lindenstrauss / Hutchinson estimate): k Rademacher columns per sign class of g,
+// y_i = sqrt(|g|) r_i on the targets of that class, c_i = +-1/k.  The same columns give Q^ and
+// trGL^, which keeps sum_e w_e dl/dw_e = 0 exactly.
+//
+// All columns [g, d, y_1..y_P] are centred and solved together on the grounded Laplacian L_v
+// (row and column of the pivot removed) by a batched Jacobi-preconditioned conjugate gradient:
+// FP64 iterate and residual, FP32 search directions (the SpMM gathers half the bytes), FP64
+// accumulation of every product and dot.  Because the stored FP32 direction is exactly what
+// the operator is applied to, x and r stay consistent; the step and direction updates use the
+// residual-based (flexible) formulas alpha = r.p / p.Ap and beta = z'.(r' - r) / z.r, which
+// tolerate the rounded directions.  Solutions are centred at the end (L^+ y = z - mean(z)).
+// This file is compiled without FMA contraction.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace rwc {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxWaves = 4096;
+
+struct ColScalars {
+    double alpha, beta, zr, rr, rr0, zr_new, zro, rp, pap;
+    int32_t done;
+    int32_t pad;
+};
+
+// ----------------------------------------------------------------- RHS ---------------
+// Column 0: g (sparse, added below), column 1: d; all columns then get -mean.
+__global__ void rhs_dense(int32_t n, int32_t R, const double* __restrict__ d, const double* __restrict__ colmean,
+                          double* __restrict__ Y) {
+    const int64_t total = static_cast<int64_t>(n) * R;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t u = i / R;
+        const int32_t c = static_cast<int32_t>(i - u * R);
+        double v = -colmean[c];
+        if (c == 1) v += d[u];
+        Y[i] = v;
+    }
+}
+
+struct Entry {
+    int32_t node;
+    int32_t col;
+    double val;
+};
+
+__global__ void rhs_scatter(int32_t count, const Entry* __restrict__ e, int32_t R, double* __restrict__ Y) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) Y[static_cast<int64_t>(e[i].node) * R + e[i].col] += e[i].val;
+}
+
+// ------------------------------------------------------------ batched PCG ------------
+// One wave per row (grid-stride), lanes over columns.
+__global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restrict__ d, double* __restrict__ Y,
+                          double* __restrict__ X, float* __restrict__ P32, double* __restrict__ part) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+    for (int32_t c0 = 0; c0 < R; c0 += kWave) {
+        const int32_t c = c0 + lane;
+        double zr = 0.0, rr = 0.0;
+        for (int64_t u = wave; u < n; u += nw) {
+            if (c >= R) continue;
+            const int64_t i = u * R + c;
+            const double r = (u == v) ? 0.0 : Y[i];
+            const double z = (u == v) ? 0.0 : r / d[u];
+            Y[i] = r;   // Y becomes the residual
+            X[i] = 0.0;
+            P32[i] = static_cast<float>(z);
+            zr += z * r;
+            rr += r * r;
+        }
+        if (c < R) {
+            part[(wave * R + c) * 2] = zr;
+            part[(wave * R + c) * 2 + 1] = rr;
+        }
+    }
+}
+
+// AP = L_v P (FP32 P promoted, FP64 sums); partial dots r.P and P.AP per column.
+__global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __restrict__ row_ptr,
+                          const int32_t* __restrict__ col, const float* __restrict__ weight,
+                          const double* __restrict__ d, const float* __restrict__ P32, const double* __restrict__ Rr,
+                          double* __restrict__ AP, double* __restrict__ part) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+    for (int32_t c0 = 0; c0 < R; c0 += kWave) {
+        const int32_t c = c0 + lane;
+        double rp = 0.0, pap = 0.0;
+        for (int64_t u = wave; u < n; u += nw) {
+            if (c >= R) continue;
+            const int64_t i = u * R + c;
+            double y = 0.0;
+            const double pu = static_cast<double>(P32[i]);
+            if (u != v) {
+                double s = 0.0;
+                const int32_t end = row_ptr[u + 1];
+                for (int32_t k = row_ptr[u]; k < end; ++k) {
+                    const int32_t w = col[k];
+                    if (w == v) continue;
+                    s += static_cast<double>(weight[k]) * static_cast<double>(P32[static_cast<int64_t>(w) * R + c]);
+                }
+                y = d[u] * pu - s;
+            }
+            AP[i] = y;
+            rp += Rr[i] * pu;
+            pap += pu * y;
+        }
+        if (c < R) {
+            part[(wave * R + c) * 2] = rp;
+            part[(wave * R + c) * 2 + 1] = pap;
+        }
+    }
+}
+
+__global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
+                            const double* __restrict__ d, double* __restrict__ X, double* __restrict__ Rr,
+                            const float* __restrict__ P32, const double* __restrict__ AP, double* __restrict__ part) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+    for (int32_t c0 = 0; c0 < R; c0 += kWave) {
+        const int32_t c = c0 + lane;
+        double zr = 0.0, zro = 0.0, rr = 0.0;
+        const double alpha = (c < R) ? sc[c].alpha : 0.0;
+        for (int64_t u = wave; u < n; u += nw) {
+            if (c >= R || u == v) continue;
+            const int64_t i = u * R + c;
+            const double p = static_cast<double>(P32[i]);
+            X[i] = X[i] + alpha * p;
+            const double r_old = Rr[i];
+            const double r = r_old - alpha * AP[i];
+            Rr[i] = r;
+            const double z = r / d[u];
+            zr += z * r;
+            zro += z * r_old;
+            rr += r * r;
+        }
+        if (c < R) {
+            part[(wave * R + c) * 3] = zr;
+            part[(wave * R + c) * 3 + 1] = zro;
+            part[(wave * R + c) * 3 + 2] = rr;
+        }
+    }
+}
+
+__global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
+                               const double* __restrict__ d, const double* __restrict__ Rr, float* __restrict__ P32) {
+    const int64_t total = static_cast<int64_t>(n) * R;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t u = i / R;
+        if (u == v) continue;
+        const int32_t c = static_cast<int32_t>(i - u * R);
+        const double z = Rr[i] / d[u];
+        P32[i] = static_cast<float>(z + sc[c].beta * static_cast<double>(P32[i]));
+    }
+}
+
+// Per-column scalar steps; one thread per column sums the per-wave partials in order.
+//   mode 0: after init (zr, rr0)   mode 1: after spmm (alpha)   mode 2: after update (beta)
+__global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict__ part, ColScalars* sc, int mode,
+                             double tol2) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= R) return;
+    const int stride = (mode == 2) ? 3 : 2;
+    double a = 0.0, b = 0.0, e = 0.0;
+    for (int32_t w = 0; w < nwaves; ++w) {
+        const double* q = part + (static_cast<int64_t>(w) * R + c) * stride;
+        a += q[0];
+        b += q[1];
+        if (stride == 3) e += q[2];
+    }
+    ColScalars s = sc[c];
+    if (mode == 0) {
+        s.zr = a;
+        s.rr0 = b;
+        s.rr = b;
+        s.done = (b == 0.0) ? 1 : 0;
+        s.alpha = 0.0;
+        s.beta = 0.0;
+    } else if (mode == 1) {
+        s.rp = a;
+        s.pap = b;
+        s.alpha = (s.done || b == 0.0) ? 0.0 : a / b;
+    } else {
+        s.rr = e;
+        s.beta = (s.done || s.zr == 0.0) ? 0.0 : (a - b) / s.zr;
+        s.zr = a;
+        if (e <= tol2 * s.rr0) s.done = 1;
+    }
+    sc[c] = s;
+}
+
+// Column sums (for centring), one thread per column over rows, fixed order.
+__global__ void column_sums(int32_t n, int32_t R, const double* __restrict__ M, double* __restrict__ out,
+                            double scale) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= R) return;
+    double s = 0.0;
+    for (int64_t u = 0; u < n; ++u) s += M[u * R + c];
+    out[c] = s * scale;
+}
+
+__global__ void center_columns(int32_t n, int32_t R, const double* __restrict__ mean, double* __restrict__ M) {
+    const int64_t total = static_cast<int64_t>(n) * R;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        M[i] = M[i] - mean[i % R];
+}
+
+struct EdgeScalars {
+    double trgl;
+    double dld;
+};
+
+// trGL^ = sum_i c_i y_i^T L^+ y_i over the probe entries; dLd = d^T B.
+__global__ void edge_scalars(int32_t n, int32_t R, int32_t count, const Entry* __restrict__ e,
+                             const double* __restrict__ coef, const double* __restrict__ Z, const double* __restrict__ d,
+                             EdgeScalars* out) {
+    __shared__ double lds[kBlock];
+    double t = 0.0, q = 0.0;
+    for (int32_t i = threadIdx.x; i < count; i += blockDim.x)
+        if (e[i].col >= 2) t += coef[e[i].col] * e[i].val * Z[static_cast<int64_t>(e[i].node) * R + e[i].col];
+    for (int64_t u = threadIdx.x; u < n; u += blockDim.x) q += d[u] * Z[u * R + 1];
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kBlock; ++i) s += lds[i];
+        out->trgl = s;
+    }
+    __syncthreads();
+    lds[threadIdx.x] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kBlock; ++i) s += lds[i];
+        out->dld = s;
+    }
+}
+
+// One thread per CSR row; every entry (u, w) with u < w is one undirected edge.
+__global__ void edge_gradient(int32_t n, int32_t R, const int32_t* __restrict__ row_ptr,
+                              const int32_t* __restrict__ col, const int32_t* __restrict__ edge_id,
+                              const double* __restrict__ Z, const double* __restrict__ coef,
+                              const EdgeScalars* __restrict__ es, double G, double vol, double* __restrict__ grad) {
+    const double trgl = es->trgl, dld = es->dld;
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double* za = Z + u * R;
+        for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+            const int64_t w = col[k];
+            if (w < u) continue;
+            const double* zb = Z + w * R;
+            const double dA = za[0] - zb[0], sA = za[0] + zb[0];
+            const double dB = za[1] - zb[1], sB = za[1] + zb[1];
+            double q = 0.0;
+            for (int32_t c = 2; c < R; ++c) {
+                const double t = za[c] - zb[c];
+                q += coef[c] * (t * t);
+            }
+            const double term_g = (2.0 * sB - dB * dB) / vol - (2.0 * dld) / (vol * vol);
+            grad[edge_id[k]] = ((2.0 * trgl - vol * q) + (2.0 * dA * dB - 2.0 * sA)) + G * term_g;
+        }
+    }
+}
+
+struct BwdLayout {
+    double *Y, *X, *AP, *part, *colmean, *coef;
+    float* P32;
+    ColScalars* sc;
+    EdgeScalars* es;
+    Entry* entries;
+    size_t total;
+};
+
+BwdLayout carve_bwd(void* ws, int32_t n, int32_t R, int32_t nentries) {
+    Carver c(ws);
+    BwdLayout L{};
+    const size_t nr = static_cast<size_t>(n) * R;
+    L.Y = c.take<double>(nr);
+    L.X = c.take<double>(nr);
+    L.AP = c.take<double>(nr);
+    L.P32 = c.take<float>(nr);
+    L.part = c.take<double>(static_cast<size_t>(kMaxWaves) * R * 3);
+    L.colmean = c.take<double>(R);
+    L.coef = c.take<double>(R);
+    L.sc = c.take<ColScalars>(R);
+    L.es = c.take<EdgeScalars>(1);
+    L.entries = c.take<Entry>(nentries > 0 ? nentries : 1);
+    L.total = c.used();
+    return L;
+}
+
+// Probe layout decided on the host from the target list: number of columns and entries.
+struct Probes {
+    int32_t R = 2;
+    std::vector<Entry> entries;      // sparse part of the RHS (g column and probe columns)
+    std::vector<double> colmean;     // mean of each RHS column before centring
+    std::vector<double> coef;        // c_i (0 for the g and d columns)
+    double G = 0.0;
+};
+
+int plan_probes(const rwc_csr* g, int32_t T, const int32_t* targets, const double* gvals,
+                const rwc_backward_params* bp, Probes* pr) {
+    const int32_t n = g->n;
+    const int32_t k = bp ? bp->k : 0;
+    bool pos = false, neg = false;
+    for (int32_t t = 0; t < T; ++t) {
+        if (targets[t] < 0 || targets[t] >= n) return fail(RWC_ERR_INVALID_ARG, "target %d out of range", targets[t]);
+        if (!std::isfinite(gvals[t])) return fail(RWC_ERR_INVALID_ARG, "g value of target %d is not finite", t);
+        pos |= gvals[t] > 0.0;
+        neg |= gvals[t] < 0.0;
+        pr->G += gvals[t];
+    }
+    const int32_t P = (k == 0) ? T : k * ((pos ? 1 : 0) + (neg ? 1 : 0));
+    pr->R = 2 + P;
+    pr->coef.assign(pr->R, 0.0);
+    pr->colmean.assign(pr->R, 0.0);
+    pr->colmean[1] = g->vol / n;
+    for (int32_t t = 0; t < T; ++t) {
+        pr->entries.push_back(Entry{targets[t], 0, gvals[t]});
+        pr->colmean[0] += gvals[t] / n;
+    }
+    const uint32_t s0 = bp ? static_cast<uint32_t>(bp->seed) : 0u;
+    const uint32_t s1 = bp ? static_cast<uint32_t>(bp->seed >> 32) : 0u;
+    if (k == 0) {
+        for (int32_t t = 0; t < T; ++t) {
+            const int32_t c = 2 + t;
+            const double a = std::fabs(gvals[t]);
+            pr->coef[c] = (gvals[t] > 0) ? 1.0 : (gvals[t] < 0 ? -1.0 : 0.0);
+            pr->entries.push_back(Entry{targets[t], c, std::sqrt(a)});
+            pr->colmean[c] = std::sqrt(a) / n;
+        }
+    } else {
+        int32_t c = 2;
+        for (int cls = 0; cls < 2; ++cls) {
+            const bool use = (cls == 0) ? pos : neg;
+            if (!use) continue;
+            for (int32_t i = 0; i < k; ++i, ++c) {
+                const uint32_t probe = static_cast<uint32_t>(cls * k + i);
+                pr->coef[c] = (cls == 0 ? 1.0 : -1.0) / k;
+                for (int32_t t = 0; t < T; ++t) {
+                    const double gv = gvals[t];
+                    if ((cls == 0 && gv <= 0) || (cls == 1 && gv >= 0)) continue;
+                    // Rademacher sign of probe i at node targets[t]: bit 0 of Philox word 0 on
+                    // the counter (probe, node, 0, 2^32 - 1) under the probe key
+                    const uint64_t x = philox_x64(probe, static_cast<uint32_t>(targets[t]), 0u, 0xFFFFFFFFu, s0, s1);
+                    const double sgn = (x & 1ull) ? -1.0 : 1.0;
+                    const double val = sgn * std::sqrt(std::fabs(gv));
+                    pr->entries.push_back(Entry{targets[t], c, val});
+                    pr->colmean[c] += val / n;
+                }
+            }
+        }
+    }
+    return RWC_OK;
+}
+
+}  // namespace
+}  // namespace rwc
+
+using namespace rwc;
+
+extern "C" int rwc_backward_workspace(const rwc_csr* g, int32_t num_targets, const int32_t* targets,
+                                      const double* gvals, const rwc_backward_params* bp, size_t* bytes) {
+    clear_error();
+    if (!g || !bytes || num_targets < 1 || !targets || !gvals)
+        return fail(RWC_ERR_INVALID_ARG, "g, targets, gvals and bytes are required");
+    Probes pr;
+    RWC_CHECK(plan_probes(g, num_targets, targets, gvals, bp, &pr));
+    *bytes = carve_bwd(nullptr, g->n, pr.R, static_cast<int32_t>(pr.entries.size())).total;
+    return RWC_OK;
+}
+
+extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t* targets, const double* gvals,
+                            const rwc_backward_params* bp, double* grad_w, int32_t* iters, void* ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    if (!g || !grad_w || num_targets < 1 || !targets || !gvals)
+        return fail(RWC_ERR_INVALID_ARG, "g, targets, gvals and grad_w are required");
+    if (bp && bp->k < 0) return fail(RWC_ERR_INVALID_ARG, "k must be >= 0");
+    Probes pr;
+    RWC_CHECK(plan_probes(g, num_targets, targets, gvals, bp, &pr));
+    const int32_t n = g->n, R = pr.R, v = g->pivot;
+    const int32_t nent = static_cast<int32_t>(pr.entries.size());
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, R, nent).total));
+    BwdLayout L = carve_bwd(ws, n, R, nent);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double tol = (bp && bp->tol > 0) ? bp->tol : 1e-10;
+    const int max_iter = (bp && bp->max_iter > 0) ? bp->max_iter : 20000;
+    const int check = (bp && bp->check_every > 0) ? bp->check_every : 16;
+
+    RWC_HIP(hipMemcpyAsync(L.entries, pr.entries.data(), sizeof(Entry) * nent, hipMemcpyHostToDevice, s));
+    RWC_HIP(hipMemcpyAsync(L.colmean, pr.colmean.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    RWC_HIP(hipMemcpyAsync(L.coef, pr.coef.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    const int64_t nr = static_cast<int64_t>(n) * R;
+    const unsigned flat = blocks_for(nr, kBlock) < 8192 ? blocks_for(nr, kBlock) : 8192;
+    hipLaunchKernelGGL(rhs_dense, dim3(flat), dim3(kBlock), 0, s, n, R, g->strength, L.colmean, L.Y);
+    hipLaunchKernelGGL(rhs_scatter, dim3(blocks_for(nent, kBlock)), dim3(kBlock), 0, s, nent, L.entries, R, L.Y);
+
+    int64_t nwaves = n;
+    if (nwaves > kMaxWaves) nwaves = kMaxWaves;
+    const unsigned wave_blocks = static_cast<unsigned>((nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
+    nwaves = static_cast<int64_t>(wave_blocks) * kWavesPerBlock;
+    const int32_t nw = static_cast<int32_t>(nwaves);
+    const unsigned col_blocks = blocks_for(R, 64);
+    const double tol2 = tol * tol;
+    hipLaunchKernelGGL(bpcg_init, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
+                       L.part);
+    hipLaunchKernelGGL(bpcg_scalars, dim3(col_blocks), dim3(64), 0, s, R, nw, L.part, L.sc, 0, tol2);
+    RWC_HIP(hipGetLastError());
+    std::vector<ColScalars> host(R);
+    int it = 0;
+    bool converged = false;
+    while (!converged && it < max_iter) {
+        const int chunk = (max_iter - it) < check ? (max_iter - it) : check;
+        for (int c = 0; c < chunk; ++c) {
+            hipLaunchKernelGGL(bpcg_spmm, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->row_ptr, g->col,
+                               g->weight, g->strength, L.P32, L.Y, L.AP, L.part);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(col_blocks), dim3(64), 0, s, R, nw, L.part, L.sc, 1, tol2);
+            hipLaunchKernelGGL(bpcg_update, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
+                               L.Y, L.P32, L.AP, L.part);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(col_blocks), dim3(64), 0, s, R, nw, L.part, L.sc, 2, tol2);
+            hipLaunchKernelGGL(bpcg_direction, dim3(flat), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y, L.P32);
+        }
+        RWC_HIP(hipGetLastError());
+        it += chunk;
+        RWC_HIP(hipMemcpyAsync(host.data(), L.sc, sizeof(ColScalars) * R, hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipStreamSynchronize(s));
+        converged = true;
+        for (int32_t c = 0; c < R; ++c) converged = converged && host[c].done;
+    }
+    if (iters) *iters = it;
+    if (!converged) {
+        double worst = 0.0;
+        for (int32_t c = 0; c < R; ++c)
+            if (host[c].rr0 > 0) worst = std::fmax(worst, std::sqrt(host[c].rr / host[c].rr0));
+        return fail(RWC_ERR_NOT_CONVERGED, "adjoint solves: worst relative residual %.3e after %d iterations", worst, it);
+    }
+    // L^+ y = z - mean(z)
+    hipLaunchKernelGGL(column_sums, dim3(col_blocks), dim3(64), 0, s, n, R, L.X, L.colmean, 1.0 / n);
+    hipLaunchKernelGGL(center_columns, dim3(flat), dim3(kBlock), 0, s, n, R, L.colmean, L.X);
+    hipLaunchKernelGGL(edge_scalars, dim3(1), dim3(kBlock), 0, s, n, R, nent, L.entries, L.coef, L.X, g->strength,
+                       L.es);
+    hipLaunchKernelGGL(edge_gradient, dim3(blocks_for(n, kBlock) < 8192 ? blocks_for(n, kBlock) : 8192),
+                       dim3(kBlock), 0, s, n, R, g->row_ptr, g->col, g->edge_id, L.X, L.coef, L.es, pr.G, g->vol,
+                       grad_w);
+    RWC_HIP(hipGetLastError());
+    RWC_HIP(hipStreamSynchronize(s));
+    return RWC_OK;
+}

@@ -308,6 +308,34 @@ __global__ void row_pass(int32_t n, const int32_t* __restrict__ row_ptr, const f
     }
 }
 
+// 64-byte node records: one aligned load gives a walker the degree, the row offset and, for
+// low-degree rows, the neighbours themselves (and their CDF values when weighted).
+__global__ void build_records(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                              const uint64_t* __restrict__ cdf, uint32_t* __restrict__ rec) {
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t beg = row_ptr[u], deg = row_ptr[u + 1] - beg;
+        uint32_t r[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = 0;
+        r[0] = static_cast<uint32_t>(deg);
+        r[1] = static_cast<uint32_t>(beg);
+        if (cdf) {
+            for (int i = 0; i < kRecInlineWeighted && i < deg; ++i) {
+                r[2 + i] = static_cast<uint32_t>(col[beg + i]);
+                const uint64_t c = cdf[beg + i];
+                r[8 + 2 * i] = static_cast<uint32_t>(c);
+                r[9 + 2 * i] = static_cast<uint32_t>(c >> 32);
+            }
+        } else {
+            for (int i = 0; i < kRecInline && i < deg; ++i) r[2 + i] = static_cast<uint32_t>(col[beg + i]);
+        }
+        uint4* out = reinterpret_cast<uint4*>(rec + 16 * u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_uint4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+    }
+}
+
 __global__ void pick_pivot(int32_t n, const uint64_t* __restrict__ sfix, BuildScalars* sc) {
     const uint64_t target = sc->max_s;
     int32_t best = 0x7FFFFFFF;
@@ -378,6 +406,7 @@ struct BuildLayout {
     int32_t* edge_id;
     uint64_t* cdf;
     double* strength;
+    uint32_t* rec;
     uint64_t* sfix;
     BuildScalars* scalars;
     size_t persistent;
@@ -402,6 +431,7 @@ BuildLayout carve_build(void* ws, int32_t n, int64_t m, bool weighted) {
     L.edge_id = c.take<int32_t>(nnz);
     L.cdf = weighted ? c.take<uint64_t>(nnz) : nullptr;
     L.strength = c.take<double>(n);
+    L.rec = c.take<uint32_t>(static_cast<size_t>(16) * n);
     L.sfix = c.take<uint64_t>(n);
     L.scalars = c.take<BuildScalars>(1);
     L.persistent = c.used();
@@ -508,6 +538,8 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
                                           ? blocks_for(static_cast<int64_t>(n) * kWave, kBlock)
                                           : gs),
                        dim3(kBlock), 0, s, n, L.row_ptr, L.weight, L.cdf, L.strength, L.sfix, L.scalars);
+    hipLaunchKernelGGL(build_records, dim3(blocks_for(n, kBlock) < gs ? blocks_for(n, kBlock) : gs), dim3(kBlock), 0,
+                       s, n, L.row_ptr, L.col, L.cdf, L.rec);
     hipLaunchKernelGGL(pick_pivot, dim3(blocks_for(n, kBlock) < gs ? blocks_for(n, kBlock) : gs), dim3(kBlock), 0, s,
                        n, L.sfix, L.scalars);
     hipLaunchKernelGGL(uf_init, dim3(blocks_for(n, kBlock) < gs ? blocks_for(n, kBlock) : gs), dim3(kBlock), 0, s, n,
@@ -538,6 +570,7 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     g.edge_id = L.edge_id;
     g.cdf = L.cdf;
     g.strength = L.strength;
+    g.rec = L.rec;
     *out = g;
     return RWC_OK;
 }

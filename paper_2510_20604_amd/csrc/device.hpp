@@ -16,14 +16,14 @@ constexpr int kWave = 64;
 // constants between rounds.  Only output words 0 and 1 are used; the compiler drops the
 // rest of the last round.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t philox_x64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+__host__ __device__ __forceinline__ uint64_t philox_x64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                        uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;   // v_mul_lo/hi_u32 on the GPU
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t lo0 = static_cast<uint32_t>(p0), hi0 = static_cast<uint32_t>(p0 >> 32);
+        const uint32_t lo1 = static_cast<uint32_t>(p1), hi1 = static_cast<uint32_t>(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -60,6 +60,10 @@ __device__ __forceinline__ int32_t select_weighted(uint64_t x, const uint64_t* _
     }
     return lo;
 }
+
+// Node records (rwc_csr::rec): 16 x uint32 per node.
+constexpr int kRecInline = 14;          // neighbours stored inline for unweighted rows
+constexpr int kRecInlineWeighted = 4;   // (id, cdf) pairs stored inline for weighted rows
 
 // SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014): the tree checksum term.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {

@@ -30,6 +30,7 @@ struct GraphArgs {
     const int32_t* row_ptr;
     const int32_t* col;
     const uint64_t* cdf;
+    const uint4* rec;       // 64-byte node records (4 x uint4 per node)
     uint64_t* state;        // [T][n]
     int32_t n;
     int32_t root;
@@ -212,6 +213,27 @@ __device__ __forceinline__ bool st_cas(uint64_t* p, uint64_t expected, uint64_t 
                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Word i (0..15) of a node record held in four uint4 registers.
+__device__ __forceinline__ uint32_t rec_word(const uint4& a, const uint4& b, const uint4& c, const uint4& d,
+                                             uint32_t i) {
+    const uint4 q = (i < 4) ? a : (i < 8) ? b : (i < 12) ? c : d;
+    const uint32_t s = i & 3u;
+    return s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
+}
+
+// RandomNeighbor from a weighted record with deg <= kRecInlineWeighted inline (id, cdf) pairs.
+__device__ __forceinline__ uint32_t rec_pick_weighted(const uint4& a, const uint4& b, const uint4& c,
+                                                      const uint4& d, uint64_t x, uint32_t deg) {
+    const uint64_t c0 = c.x | (static_cast<uint64_t>(c.y) << 32);
+    const uint64_t c1 = c.z | (static_cast<uint64_t>(c.w) << 32);
+    const uint64_t c2 = d.x | (static_cast<uint64_t>(d.y) << 32);
+    const uint64_t c3 = d.z | (static_cast<uint64_t>(d.w) << 32);
+    const uint64_t total = deg == 1 ? c0 : (deg == 2 ? c1 : (deg == 3 ? c2 : c3));
+    const uint64_t r = mulhi64(x, total);
+    const uint32_t k = (r < c0) ? 0u : ((r < c1) ? 1u : ((r < c2) ? 2u : 3u));
+    return rec_word(a, b, c, d, 2u + k);
+}
+
 template <int W>
 __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
                           uint64_t max_iters, uint32_t* lds_pred, uint64_t& steps_out, uint64_t& hash_out,
@@ -227,7 +249,12 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     const int32_t* __restrict__ row_ptr = G.row_ptr;
     const int32_t* __restrict__ col = G.col;
     const uint64_t* __restrict__ cdf = G.cdf;
+    const uint4* __restrict__ rec = G.rec;
     uint64_t* st = G.state + static_cast<int64_t>(slot) * G.n;
+    // record of node rh_node, loaded alongside that node's state word so that a step from a
+    // fresh head needs no dependent load for low-degree rows
+    uint4 ra = make_uint4(0, 0, 0, 0), rb = ra, rc = ra, rd = ra;
+    uint32_t rh_node = 0xFFFFFFFFu;
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     const uint32_t sw = static_cast<uint32_t>(sample), gw = G.graph_word;
 
@@ -257,12 +284,27 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         uint32_t ny = 0;
         uint32_t k = 0;
         if (mode == tWalk) {
+            if (rh_node != h) {
+                const uint4* q = rec + 4 * static_cast<int64_t>(h);
+                ra = q[0];
+                rb = q[1];
+                rc = q[2];
+                rd = q[3];
+                rh_node = h;
+            }
             k = st_cnt(wh);
-            const int32_t beg = row_ptr[h];
-            const int32_t deg = row_ptr[h + 1] - beg;
+            const uint32_t deg = ra.x;
+            const int32_t beg = static_cast<int32_t>(ra.y);
             const uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
-            const int32_t pick = cdf ? select_weighted(r, cdf, beg, deg) : select_unweighted(r, deg);
-            ny = static_cast<uint32_t>(col[beg + pick]);
+            if (cdf == nullptr) {
+                const int32_t pick = select_unweighted(r, static_cast<int32_t>(deg));
+                ny = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_word(ra, rb, rc, rd, 2u + pick)
+                                                                 : static_cast<uint32_t>(col[beg + pick]);
+            } else if (deg <= static_cast<uint32_t>(kRecInlineWeighted)) {
+                ny = rec_pick_weighted(ra, rb, rc, rd, r, deg);
+            } else {
+                ny = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
+            }
             node = ny;
         } else if (mode == tStart) {
             node = j;
@@ -273,6 +315,15 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         }
         const bool reads = (mode != tDone) && (mode != tIdle);
         const uint64_t w = reads ? st_load(&st[node]) : 0ull;
+        if (mode == tWalk || mode == tStart || mode == tWait) {
+            // the node may become this walker's head
+            const uint4* q = rec + 4 * static_cast<int64_t>(node);
+            ra = q[0];
+            rb = q[1];
+            rc = q[2];
+            rd = q[3];
+            rh_node = node;
+        }
         const bool w_tree = (w & kInTree) != 0;
         const bool w_owned = (w & kOwned) != 0;
         const bool w_mine = w_owned && st_owner(w) == tl;
@@ -578,13 +629,17 @@ struct Plan {
 };
 
 constexpr int64_t kDefaultStateBudget = 96ll << 30;  // bytes of slot state chosen automatically
-constexpr int64_t kTargetWalkers = 1 << 16;          // concurrent walkers aimed at with W > 1
+constexpr int64_t kTargetWalkers = 1 << 17;          // concurrent walkers aimed at with W > 1
 
-// Walkers per tree when the caller leaves it open: one per tree while all trees of a small
-// problem fit in flight with enough concurrency, otherwise a team per tree.
+// Walkers per tree when the caller leaves it open.  Throughput is set by the number of
+// concurrent walkers and by the state footprint they touch (measured: 64 walkers x 2048 trees
+// beats 16 x 10^4 trees on BA(10^6)), so large graphs get full-wave teams and few trees in
+// flight; when one walker per tree already gives enough concurrency, one per tree.
 int auto_walkers(int64_t total_nodes, int32_t G, int64_t l) {
-    if (total_nodes * l <= (int64_t(1) << 27) || l * G >= kTargetWalkers) return 1;
-    return 16;
+    if (l * G >= kTargetWalkers || total_nodes * l <= (int64_t(1) << 22)) return 1;
+    int W = 64;
+    while (W > 2 && W * 16 > total_nodes / G) W >>= 1;
+    return W;
 }
 
 int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan* plan) {
@@ -758,6 +813,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         hg[g].row_ptr = graphs[g].row_ptr;
         hg[g].col = graphs[g].col;
         hg[g].cdf = graphs[g].weighted ? graphs[g].cdf : nullptr;
+        hg[g].rec = reinterpret_cast<const uint4*>(graphs[g].rec);
         hg[g].state = L.state[g];
         hg[g].n = graphs[g].n;
         hg[g].root = (p->root >= 0) ? p->root : graphs[g].pivot;

@@ -57,6 +57,18 @@ def test_csr_matches_oracle(name):
     if g.w is not None:
         np.testing.assert_array_equal(_u64(Gd.cdf()), o.cdf)
         np.testing.assert_array_equal(Gd.weight().cpu().numpy().astype(np.float64), o.weight)
+    # 64-byte node records: degree, row offset, inline neighbours (and CDF values)
+    rec = Gd.rec().cpu().numpy().reshape(g.n, 16).view(np.uint32)
+    deg = np.diff(o.row_ptr)
+    np.testing.assert_array_equal(rec[:, 0], deg)
+    np.testing.assert_array_equal(rec[:, 1], o.row_ptr[:-1])
+    inline = 4 if g.w is not None else 14
+    for u in range(0, g.n, max(1, g.n // 200)):
+        b, k = o.row_ptr[u], min(deg[u], inline)
+        np.testing.assert_array_equal(rec[u, 2:2 + k], o.col[b:b + k])
+        if g.w is not None:
+            c = rec[u, 8:8 + 2 * k].astype(np.uint64)
+            np.testing.assert_array_equal(c[0::2] | (c[1::2] << np.uint64(32)), o.cdf[b:b + k])
     # edge_id maps every entry back to an input edge with matching endpoints
     eid = Gd.edge_id().cpu().numpy()
     rows = np.repeat(np.arange(g.n), np.diff(o.row_ptr))
