@@ -13,7 +13,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -32,13 +31,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000"])
+    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000", "batch256"])
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
     ap.add_argument("--walkers", type=int, default=0, help="walkers per tree (0 = automatic)")
     ap.add_argument("--tif", type=int, default=0, help="trees in flight (0 = automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB streaming copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -84,8 +85,71 @@ def cpu_baseline(g, l, seed, seconds):
             "walk_steps_per_s": float(r["steps"].sum()) / dt}, r
 
 
+def batch_main(args):
+    """256 uneven graphs, 1000 trees each: one persistent hipGraph-captured launch against one
+    plain launch per graph (same outputs, bit for bit)."""
+    import torch
+    import paper_2510_20604_amd as P
+    import rwcgen
+    t0 = time.perf_counter()
+    gl = rwcgen.batch_mix(256, 1e3, 1e5, seed=1003)
+    print(f"generated {len(gl)} graphs, sum n = {sum(g.n for g in gl)} in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    l, seed = args.trees or 1000, 2003
+    dev = [P.Graph(g.n, g.src, g.dst, g.w, "cuda:0") for g in gl]
+    torch.cuda.synchronize()
+
+    def batched():
+        return P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=False)
+
+    def plain():
+        out = []
+        for i, G in enumerate(dev):
+            out.append(P.sample_forests(G, l, seed, graph_index_base=i, want_sq=False))
+            if i % 32 == 31:
+                print(f"plain: {i + 1} graphs done", file=sys.stderr, flush=True)
+        return out
+
+    for _ in range(args.warmup):
+        batched()
+    times_b, times_p = [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sb = batched()
+        torch.cuda.synchronize()
+        times_b.append(time.perf_counter() - t)
+        print(f"batched step {time.perf_counter() - t:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sp = plain()
+    torch.cuda.synchronize()
+    times_p.append(time.perf_counter() - t)
+    print(f"plain pass {times_p[-1]:.3f}s", file=sys.stderr, flush=True)
+    same = all(torch.equal(sb["tree_hash"][i], r["tree_hash"][0]) for i, r in enumerate(sp))
+    steps = int(P.as_uint64(sb["total_steps"]).sum())
+    tb, tp = float(np.mean(times_b)), float(np.mean(times_p))
+    line = {
+        "metric": METRIC, "value": round(len(gl) * l / tb, 3), "unit": "trees/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * tb, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "256 graphs: 128 BA(m=3) + 128 grids with 10% edges deleted, n log-uniform "
+                               "[1e3, 1e5], w ~ U[0.5, 2], 1000 trees each", "sum_n": int(sum(g.n for g in gl)),
+                   "trees": len(gl) * l, "launch": "batched persistent + hipGraph"},
+        "walk_steps_per_s": round(steps / tb, 1),
+        "plain_trees_per_s": round(len(gl) * l / tp, 3), "plain_ms": round(1e3 * tp, 3),
+        "batched_over_plain": round(tp / tb, 3), "bit_identical": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
+    if args.config == "batch256":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return batch_main(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler shards by "
               "sample range with one all-reduce of the visit totals, which this build does not run.",
@@ -123,8 +187,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     total_steps = int(P.as_uint64(s["total_steps"])[0])
-    trees_in_flight = min(l, ((l + 63) // 64) * 64)
-    launches = math.ceil(l / trees_in_flight)
+    trees_in_flight = s["trees_in_flight"]
+    launches = s["batches"]
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps * l / elapsed
 
@@ -159,6 +223,19 @@ def main():
                                     "peak_accesses_per_s": peak_acc, "walk_accesses_per_s": acc,
                                     "frac": round(acc / peak_acc, 4)}
 
+    if args.copy_probe:
+        import ctypes
+        words = (1 << 30) // 8
+        a = torch.zeros(words, dtype=torch.int64, device=dev)
+        b = torch.empty(words, dtype=torch.int64, device=dev)
+        ms = ctypes.c_float()
+        _lib.check(_lib.lib().rwc_probe_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), words,
+                                             ctypes.byref(ms), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                   "rwc_probe_copy")
+        extra["copy_probe"] = {"bytes_read": words * 8, "bytes_written": words * 8, "ms": ms.value,
+                               "GB_per_s": 2 * words * 8 / (ms.value * 1e-3) / 1e9}
+        del a, b
+
     rel_se = (e["stderr"] / e["rwc"]).double()
     mask = torch.ones(g.n, dtype=torch.bool, device=dev)
     mask[G.pivot] = False
@@ -176,7 +253,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m": g.m, "trees": l, "trees_in_flight": trees_in_flight,
-                   "walkers_per_tree": 1, "launch": "plain"},
+                   "walkers_per_tree": s["walkers_per_tree"], "walk_launches": launches, "launch": "plain"},
         "walk_steps_per_s": round(args.steps * total_steps / elapsed, 1),
         "walk_steps_per_tree": total_steps / l,
         "sampler_trees_per_s": round(l / (np.mean(walk_ms) + np.mean(reduce_ms)) * 1e3, 3),

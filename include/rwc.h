@@ -67,6 +67,8 @@ typedef struct rwc_csr {
     uint32_t* rec;         /* [16 n] 64-byte node records: degree, row offset, then the first
                               14 neighbour ids (unweighted) or the first 4 ids in words 2..5
                               and their CDF values in words 8..15 (weighted)               */
+    int32_t* bfs_order;    /* [n] nodes in breadth-first order from the pivot: the order in
+                              which walker teams take start nodes                          */
 } rwc_csr;
 
 /* Bytes of workspace rwc_build_csr needs for n nodes and m edges (weighted != 0 if w will
@@ -90,6 +92,8 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
 #define RWC_SAMPLE_PERSISTENT    2u  /* batched: one persistent launch whose waves pop (graph,
                                         tree block) work items from a device queue          */
 #define RWC_SAMPLE_GRAPH_CAPTURE 4u  /* record the launches in a hipGraph and replay it     */
+#define RWC_SAMPLE_BFS_STARTS    8u  /* walker teams take start nodes in breadth-first order
+                                        from the root instead of ascending ids (same forest) */
 
 typedef struct rwc_sample_params {
     uint64_t seed;               /* Philox key (seed mod 2^32, seed >> 32)                 */
@@ -121,6 +125,8 @@ typedef struct rwc_sample_outputs {
     float* timing_ms;            /* HOST [2] or NULL: device time of the walk kernels and of
                                     the reduction kernels, summed over batches (hipEvents on
                                     `stream`; not available with RWC_SAMPLE_GRAPH_CAPTURE) */
+    int32_t* plan;               /* HOST [3] or NULL: walkers per tree, trees in flight per
+                                    graph and number of batches actually used             */
 } rwc_sample_outputs;
 
 /* Workspace for rwc_sample_forests with these graphs and parameters. */
@@ -138,6 +144,30 @@ int rwc_sample_forests_workspace(const rwc_csr* graphs, int32_t num_graphs,
  * (RWC_ERR_STEP_LIMIT, RWC_ERR_COUNT_OVERFLOW). */
 int rwc_sample_forests(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p,
                        const rwc_sample_outputs* out, void* ws, size_t ws_bytes, void* stream);
+
+typedef struct rwc_tune_result {
+    int32_t walkers_per_tree;    /* the winning walkers per tree                            */
+    int32_t trees_in_flight;     /* the winning trees in flight                              */
+    double steps_per_s;          /* walk steps per second of the winning probe               */
+    int32_t candidates;          /* probes run (0 when served from the cache)                */
+    int32_t cached;              /* 1 if the result came from the per-process cache          */
+} rwc_tune_result;
+
+/* Workspace for rwc_autotune_sampler: room for the largest candidate whose slot state fits
+ * `budget_bytes`, plus one graph's counts. */
+int rwc_autotune_workspace(const rwc_csr* g, const rwc_sample_params* p, int64_t budget_bytes,
+                           size_t* bytes);
+
+/* Chooses walkers_per_tree and trees_in_flight for sampling `g` with parameters `p` by timing
+ * one batch of each candidate (1, 8, 16, 32 or 64 walkers per tree; about 2^16, 2^17 or 2^18
+ * concurrent walkers; slot state within budget_bytes) on the real sample range, and caches
+ * the winner per graph class (log2 n, mean degree, weighted, log2 l) for the process.  The
+ * forest does not depend on the choice, only the speed.  Synchronises `stream`. */
+int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p, int64_t budget_bytes,
+                         rwc_tune_result* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Forgets every cached tuning result. */
+void rwc_autotune_clear_cache(void);
 
 typedef struct rwc_solve_params {
     double tol;        /* relative residual of the pivot solve; 0 = 1e-12                 */

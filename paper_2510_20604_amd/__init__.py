@@ -9,6 +9,6 @@ from . import _lib
 
 _lib.lib()  # load librwc.so now: fail loudly at import, never later on a silent path
 
-from .api import (Graph, RWCFunction, as_uint64, backward, estimate, random_walk_centrality,  # noqa: F401,E402
-                  sample_forests)
+from .api import (Graph, RWCFunction, as_uint64, autotune, backward, estimate,  # noqa: F401,E402
+                  random_walk_centrality, sample_forests)
 from ._lib import RWCError  # noqa: F401,E402

@@ -18,6 +18,7 @@ c_i32, c_i64, c_u32, c_u64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64,
 RWC_SAMPLE_ACCUMULATE = 1
 RWC_SAMPLE_PERSISTENT = 2
 RWC_SAMPLE_GRAPH_CAPTURE = 4
+RWC_SAMPLE_BFS_STARTS = 8
 
 STATUS = {
     0: "RWC_OK", -1: "RWC_ERR_INVALID_ARG", -2: "RWC_ERR_NODE_RANGE", -3: "RWC_ERR_SELF_LOOP",
@@ -31,7 +32,7 @@ class RwcCsr(ctypes.Structure):
     _fields_ = [("n", c_i32), ("pivot", c_i32), ("m", c_i64), ("nnz", c_i64), ("weighted", c_i32),
                 ("max_degree", c_i32), ("vol", c_dbl), ("vol_fixed", c_u64), ("row_ptr", c_vp),
                 ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp),
-                ("rec", c_vp)]
+                ("rec", c_vp), ("bfs_order", c_vp)]
 
 
 class SampleParams(ctypes.Structure):
@@ -43,11 +44,16 @@ class SampleParams(ctypes.Structure):
 class SampleOutputs(ctypes.Structure):
     _fields_ = [("counts", c_vp), ("counts_sq", c_vp), ("total_steps", c_vp), ("tree_hash", c_vp),
                 ("parents", c_vp), ("dump_samples", c_vp), ("ndump", c_i32), ("reserved", c_i32),
-                ("timing_ms", c_vp)]
+                ("timing_ms", c_vp), ("plan", c_vp)]
 
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("check_every", c_i32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("walkers_per_tree", c_i32), ("trees_in_flight", c_i32), ("steps_per_s", c_dbl),
+                ("candidates", c_i32), ("cached", c_i32)]
 
 
 class BackwardParams(ctypes.Structure):
@@ -71,6 +77,11 @@ SIGNATURES = [
                                        ctypes.POINTER(c_sz)]),
     ("rwc_backward", c_i32, [ctypes.POINTER(RwcCsr), c_i32, c_vp, c_vp, ctypes.POINTER(BackwardParams), c_vp,
                              ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_autotune_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(SampleParams), c_i64,
+                                       ctypes.POINTER(c_sz)]),
+    ("rwc_autotune_sampler", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(SampleParams), c_i64,
+                                     ctypes.POINTER(TuneResult), c_vp, c_sz, c_vp]),
+    ("rwc_autotune_clear_cache", None, []),
     ("rwc_status_string", ctypes.c_char_p, [c_i32]),
     ("rwc_probe_random_gather", c_i32, [c_vp, c_u64, c_i64, c_i32, c_u32, c_vp, ctypes.POINTER(ctypes.c_float), c_vp]),
     ("rwc_probe_copy", c_i32, [c_vp, c_vp, c_u64, ctypes.POINTER(ctypes.c_float), c_vp]),

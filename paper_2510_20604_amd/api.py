@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BackwardParams, RwcCsr, SampleOutputs, SampleParams, SolveParams, check
+from ._lib import BackwardParams, RwcCsr, SampleOutputs, SampleParams, SolveParams, TuneResult, check
 
 
 def _stream() -> ctypes.c_void_p:
@@ -93,6 +93,9 @@ class Graph:
     def strength(self) -> torch.Tensor:
         return self._view(self.csr.strength, self.n, torch.float64)
 
+    def bfs_order(self) -> torch.Tensor:
+        return self._view(self.csr.bfs_order, self.n, torch.int32)
+
     def rec(self) -> torch.Tensor:
         return self._view(self.csr.rec, 16 * self.n, torch.int32)
 
@@ -102,7 +105,8 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
                    persistent: bool = False, capture: bool = False, want_sq: bool = True,
                    want_hash: bool = True, dump: Sequence[int] = (), max_steps_per_tree: int = 0,
                    graph_index_base: int = 0, accumulate: dict | None = None,
-                   workspace: torch.Tensor | None = None, timing: bool = False) -> dict:
+                   workspace: torch.Tensor | None = None, timing: bool = False,
+                   bfs_starts: bool = False) -> dict:
     """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
 
     Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
@@ -121,6 +125,8 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
         flags |= _lib.RWC_SAMPLE_GRAPH_CAPTURE
     if accumulate is not None:
         flags |= _lib.RWC_SAMPLE_ACCUMULATE
+    if bfs_starts:
+        flags |= _lib.RWC_SAMPLE_BFS_STARTS
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=root, flags=flags,
                      trees_in_flight=trees_in_flight, walkers_per_tree=walkers_per_tree,
                      max_steps_per_tree=max_steps_per_tree, graph_index_base=graph_index_base)
@@ -150,12 +156,32 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     tms = (ctypes.c_float * 2)()
     if timing:
         out.timing_ms = ctypes.cast(tms, ctypes.c_void_p)
+    plan = (ctypes.c_int32 * 3)()
+    out.plan = ctypes.cast(plan, ctypes.c_void_p)
     check(L.rwc_sample_forests(arr, G, ctypes.byref(p), ctypes.byref(out), _ptr(workspace), workspace.numel(),
                                _stream()), "rwc_sample_forests")
     res["workspace"] = workspace
+    res["walkers_per_tree"], res["trees_in_flight"], res["batches"] = int(plan[0]), int(plan[1]), int(plan[2])
     if timing:
         res["walk_ms"], res["reduce_ms"] = float(tms[0]), float(tms[1])
     return res
+
+
+def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
+             budget_bytes: int = 64 << 30) -> dict:
+    """Times one batch of each candidate (walkers per tree, trees in flight) and returns the
+    fastest (rwc_autotune_sampler); cached per graph class for the process."""
+    L = _lib.lib()
+    p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=-1)
+    size = ctypes.c_size_t()
+    check(L.rwc_autotune_workspace(ctypes.byref(graph.csr), ctypes.byref(p), int(budget_bytes), ctypes.byref(size)),
+          "rwc_autotune_workspace")
+    ws = _workspace(size.value, graph.device)
+    r = TuneResult()
+    check(L.rwc_autotune_sampler(ctypes.byref(graph.csr), ctypes.byref(p), int(budget_bytes), ctypes.byref(r),
+                                 _ptr(ws), ws.numel(), _stream()), "rwc_autotune_sampler")
+    return {"walkers_per_tree": r.walkers_per_tree, "trees_in_flight": r.trees_in_flight,
+            "steps_per_s": r.steps_per_s, "candidates": r.candidates, "cached": bool(r.cached)}
 
 
 def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor | None = None,

@@ -350,6 +350,34 @@ __global__ void pick_pivot(int32_t n, const uint64_t* __restrict__ sfix, BuildSc
     if ((threadIdx.x & (kWave - 1)) == 0 && best != 0x7FFFFFFF) atomicMin(&sc->pivot, best);
 }
 
+// Breadth-first order from the pivot, built in place: order[0..tail) is the queue; each level
+// expands order[lo, hi) and appends newly reached nodes.  The order within a level follows
+// the atomics and is not reproducible; nothing that depends on it is observable except speed
+// (any start order yields the same forest).
+__global__ void bfs_init(int32_t n, int32_t pivot, int32_t* __restrict__ dist, int32_t* __restrict__ order,
+                         uint32_t* __restrict__ tail) {
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dist[u] = (u == pivot) ? 0 : -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        order[0] = pivot;
+        *tail = 1;
+    }
+}
+
+__global__ void bfs_level(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t lo,
+                          int32_t hi, int32_t level, int32_t* __restrict__ dist, int32_t* __restrict__ order,
+                          uint32_t* __restrict__ tail) {
+    for (int64_t i = lo + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < hi;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t u = order[i];
+        for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+            const int32_t w = col[k];
+            if (dist[w] == -1 && atomicCAS(&dist[w], -1, level + 1) == -1) order[atomicAdd(tail, 1u)] = w;
+        }
+    }
+}
+
 // Union-find with parent[x] <= x: find walks down to a root with path halving.
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
     int32_t p = parent[x];
@@ -407,6 +435,7 @@ struct BuildLayout {
     uint64_t* cdf;
     double* strength;
     uint32_t* rec;
+    int32_t* bfs_order;
     uint64_t* sfix;
     BuildScalars* scalars;
     size_t persistent;
@@ -418,6 +447,7 @@ struct BuildLayout {
     uint32_t* hist;
     uint32_t* sums;
     int32_t* parent;
+    uint32_t* tail;
     size_t total;
 };
 
@@ -432,6 +462,7 @@ BuildLayout carve_build(void* ws, int32_t n, int64_t m, bool weighted) {
     L.cdf = weighted ? c.take<uint64_t>(nnz) : nullptr;
     L.strength = c.take<double>(n);
     L.rec = c.take<uint32_t>(static_cast<size_t>(16) * n);
+    L.bfs_order = c.take<int32_t>(n);
     L.sfix = c.take<uint64_t>(n);
     L.scalars = c.take<BuildScalars>(1);
     L.persistent = c.used();
@@ -444,6 +475,7 @@ BuildLayout carve_build(void* ws, int32_t n, int64_t m, bool weighted) {
     const int64_t scan_len = (256 * nb > n + 1) ? 256 * nb : n + 1;
     L.sums = c.take<uint32_t>(blocks_for(scan_len, kTile) + 1);
     L.parent = c.take<int32_t>(n);
+    L.tail = c.take<uint32_t>(1);
     L.total = c.used();
     return L;
 }
@@ -555,6 +587,25 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     if (host.nroots != 1)
         return fail(RWC_ERR_DISCONNECTED, "the graph has %d connected components", host.nroots);
 
+    // breadth-first start order from the pivot (the union-find scratch holds the distances)
+    hipLaunchKernelGGL(bfs_init, dim3(blocks_for(n, kBlock) < gs ? blocks_for(n, kBlock) : gs), dim3(kBlock), 0, s, n,
+                       host.pivot, L.parent, L.bfs_order, L.tail);
+    RWC_HIP(hipGetLastError());
+    uint32_t lo = 0, hi = 1;
+    for (int32_t level = 0; hi < static_cast<uint32_t>(n); ++level) {
+        const int64_t width = hi - lo;
+        hipLaunchKernelGGL(bfs_level, dim3(blocks_for(width, kBlock) < gs ? blocks_for(width, kBlock) : gs),
+                           dim3(kBlock), 0, s, L.row_ptr, L.col, static_cast<int32_t>(lo), static_cast<int32_t>(hi),
+                           level, L.parent, L.bfs_order, L.tail);
+        RWC_HIP(hipGetLastError());
+        uint32_t t = 0;
+        RWC_HIP(hipMemcpyAsync(&t, L.tail, sizeof(t), hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipStreamSynchronize(s));
+        if (t == hi) return fail(RWC_ERR_DISCONNECTED, "breadth-first search stopped at %u of %d nodes", t, n);
+        lo = hi;
+        hi = t;
+    }
+
     rwc_csr g{};
     g.n = n;
     g.pivot = host.pivot;
@@ -571,6 +622,7 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     g.cdf = L.cdf;
     g.strength = L.strength;
     g.rec = L.rec;
+    g.bfs_order = L.bfs_order;
     *out = g;
     return RWC_OK;
 }

@@ -66,23 +66,31 @@ __global__ void pcg_init(int32_t n, int32_t v, const double* __restrict__ d, dou
     }
 }
 
-// y = L_v p on the grounded system (row and column v removed, p_v kept at zero).
+// y = L_v p on the grounded system (row and column v removed, p_v kept at zero).  Eight
+// lanes share a row (strided over its entries, then a shuffle reduction), so hub rows of
+// power-law graphs are split and short rows still read their entries contiguously.
+constexpr int kRowLanes = 8;
+
 __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                          const float* __restrict__ weight, const double* __restrict__ d, const double* __restrict__ p,
                          double* __restrict__ ap, double* __restrict__ part) {
     __shared__ double lds[kBlock / kWave];
+    const int sub = threadIdx.x & (kRowLanes - 1);
+    const int64_t group = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kRowLanes;
+    const int64_t ngroups = static_cast<int64_t>(gridDim.x) * blockDim.x / kRowLanes;
     double acc = 0.0;
-    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
-         u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        double y = 0.0;
-        if (u != v) {
-            double s = 0.0;
-            for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k)
-                s += static_cast<double>(weight[k]) * p[col[k]];
-            y = d[u] * p[u] - s;
+    for (int64_t u = group; u < n; u += ngroups) {
+        double s = 0.0;
+        const int32_t end = row_ptr[u + 1];
+        for (int32_t k = row_ptr[u] + sub; k < end; k += kRowLanes)
+            s += static_cast<double>(weight[k]) * p[col[k]];
+#pragma unroll
+        for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (sub == 0) {
+            const double y = (u == v) ? 0.0 : d[u] * p[u] - s;
+            ap[u] = y;
+            acc += p[u] * y;
         }
-        ap[u] = y;
-        acc += p[u] * y;
     }
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) part[2 * blockIdx.x] = acc;
@@ -241,6 +249,8 @@ extern "C" int rwc_estimate(const rwc_csr* g, const uint64_t* counts, const uint
     const int check = (sp && sp->check_every > 0) ? sp->check_every : 16;
     const int v = g->pivot;
     const unsigned nb = blocks_for(n, kBlock) < kMaxBlocks ? blocks_for(n, kBlock) : kMaxBlocks;
+    const int64_t spmv_threads = static_cast<int64_t>(n) * kRowLanes;
+    const unsigned nb_spmv = blocks_for(spmv_threads, kBlock) < kMaxBlocks ? blocks_for(spmv_threads, kBlock) : kMaxBlocks;
 
     hipLaunchKernelGGL(pcg_init, dim3(nb), dim3(kBlock), 0, s, n, v, g->strength, L.x, L.r, L.z, L.p, L.part);
     hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 0, g->vol);
@@ -254,9 +264,10 @@ extern "C" int rwc_estimate(const rwc_csr* g, const uint64_t* counts, const uint
     while (!converged && it < max_iter) {
         const int chunk = (max_iter - it) < check ? (max_iter - it) : check;
         for (int c = 0; c < chunk; ++c) {
-            hipLaunchKernelGGL(spmv_dot, dim3(nb), dim3(kBlock), 0, s, n, v, g->row_ptr, g->col, g->weight,
+            hipLaunchKernelGGL(spmv_dot, dim3(nb_spmv), dim3(kBlock), 0, s, n, v, g->row_ptr, g->col, g->weight,
                                g->strength, L.p, L.ap, L.part);
-            hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 1, g->vol);
+            hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb_spmv), L.sc, 1,
+                               g->vol);
             hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kBlock), 0, s, n, v, L.sc, g->strength, L.x, L.r, L.z, L.p,
                                L.ap, L.part);
             hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 2, g->vol);

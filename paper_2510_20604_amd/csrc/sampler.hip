@@ -31,10 +31,15 @@ struct GraphArgs {
     const int32_t* col;
     const uint64_t* cdf;
     const uint4* rec;       // 64-byte node records (4 x uint4 per node)
-    uint64_t* state;        // [T][n]
+    const int32_t* order;   // start order of walker teams (breadth-first from the pivot)
+    uint64_t* state;        // [T][stride]
+    int64_t stride;         // words per tree slot (n rounded up to a multiple of 8)
+    uint64_t guard;         // per-tree step guard (one walker) or iteration guard (team)
     int32_t n;
     int32_t root;
     uint32_t graph_word;
+    int32_t T;              // tree slots (trees in flight) of this graph
+    int32_t W;              // walkers per tree
     int32_t pad;
 };
 
@@ -55,13 +60,13 @@ enum Phase : int { kScan = 0, kWalk = 1, kRetrace = 2, kDone = 3 };
 
 // Grows the tree of slot `slot` for absolute sample `sample` (one lane).
 __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint64_t sample, uint64_t seed,
-                                          uint64_t max_steps, uint64_t& steps_out, uint64_t& hash_out,
-                                          uint32_t& err_out) {
+                                          uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
+    const uint64_t max_steps = G.guard;
     const int32_t n = G.n;
     const int32_t* __restrict__ row_ptr = G.row_ptr;
     const int32_t* __restrict__ col = G.col;
     const uint64_t* __restrict__ cdf = G.cdf;
-    uint64_t* __restrict__ st = G.state + static_cast<int64_t>(slot) * n;
+    uint64_t* __restrict__ st = G.state + static_cast<int64_t>(slot) * G.stride;
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     const uint32_t sw = static_cast<uint32_t>(sample);
     const uint32_t gw = G.graph_word;
@@ -134,21 +139,21 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
     err_out = err;
 }
 
-__device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t T,
-                                         int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
-                                         int64_t l, uint64_t seed, uint64_t max_steps,
+// Batch b of graph g covers samples sample_begin + b*T_g + slot for slot in [0, T_g).
+__device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t batch,
+                                         int64_t sample_begin, int64_t l, uint64_t seed,
                                          uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
                                          uint32_t* __restrict__ status) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t slot = it.slot0 + lane;
-    const int64_t sample = batch_sample0 + slot;
     const GraphArgs G = graphs[it.graph];
+    const int32_t slot = it.slot0 + lane;
+    const int64_t rel = static_cast<int64_t>(batch) * G.T + slot;   // sample index within the call
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    const bool active = slot < T && sample < sample_end;
-    if (active) grow_tree(G, slot, static_cast<uint64_t>(sample), seed, max_steps, steps, h, err);
+    const bool active = slot < G.T && rel < l;
+    if (active) grow_tree(G, slot, static_cast<uint64_t>(sample_begin + rel), seed, steps, h, err);
     if (active) {
-        if (tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + (sample - sample_begin)] = h;
+        if (tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + rel] = h;
         if (err) atomicOr(status, err);
     }
     const uint64_t wsteps = wave_sum(steps);
@@ -160,14 +165,12 @@ __device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, c
 // One wave per work item (a block of 64 tree slots of one graph).  Persistent mode: a grid
 // sized to the resident capacity pops items from `queue` until the list is exhausted.
 __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
-                                                     int32_t nitems, uint32_t* queue, int32_t T,
-                                                     int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
-                                                     int64_t l, uint64_t seed, uint64_t max_steps,
+                                                     int32_t nitems, uint32_t* queue, int32_t batch,
+                                                     int64_t sample_begin, int64_t l, uint64_t seed,
                                                      uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
     if (queue == nullptr) {
         if (static_cast<int32_t>(blockIdx.x) < nitems)
-            run_item(graphs, items[blockIdx.x], T, batch_sample0, sample_end, sample_begin, l, seed, max_steps,
-                     tree_hash, total_steps, status);
+            run_item(graphs, items[blockIdx.x], batch, sample_begin, l, seed, tree_hash, total_steps, status);
         return;
     }
     while (true) {
@@ -175,8 +178,7 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
         if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
         idx = __shfl(idx, 0, kWave);
         if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_item(graphs, items[idx], T, batch_sample0, sample_end, sample_begin, l, seed, max_steps, tree_hash,
-                 total_steps, status);
+        run_item(graphs, items[idx], batch, sample_begin, l, seed, tree_hash, total_steps, status);
     }
 }
 
@@ -234,14 +236,14 @@ __device__ __forceinline__ uint32_t rec_pick_weighted(const uint4& a, const uint
     return rec_word(a, b, c, d, 2u + k);
 }
 
-template <int W>
 __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
-                          uint64_t max_iters, uint32_t* lds_pred, uint64_t& steps_out, uint64_t& hash_out,
-                          uint32_t& err_out) {
+                          uint32_t* lds_pred, uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
     constexpr uint32_t kNone = 64;
+    const int W = G.W;                       // walkers per tree, a power of two <= 64
+    const uint64_t max_iters = G.guard;
     const int lane = threadIdx.x & (kWave - 1);
     const int team = lane / W;
-    const uint32_t tl = static_cast<uint32_t>(lane % W);
+    const uint32_t tl = static_cast<uint32_t>(lane & (W - 1));
     const uint32_t team_base = static_cast<uint32_t>(team * W);
     const uint64_t team_mask = (W == kWave) ? ~0ull : (((1ull << W) - 1ull) << team_base);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
@@ -250,7 +252,8 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     const int32_t* __restrict__ col = G.col;
     const uint64_t* __restrict__ cdf = G.cdf;
     const uint4* __restrict__ rec = G.rec;
-    uint64_t* st = G.state + static_cast<int64_t>(slot) * G.n;
+    const int32_t* __restrict__ order = G.order;
+    uint64_t* st = G.state + static_cast<int64_t>(slot) * G.stride;
     // record of node rh_node, loaded alongside that node's state word so that a step from a
     // fresh head needs no dependent load for low-degree rows
     uint4 ra = make_uint4(0, 0, 0, 0), rb = ra, rc = ra, rd = ra;
@@ -269,8 +272,11 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         const bool idle = (mode == tIdle);
         const uint64_t bi = __ballot(idle);
         if (idle) {
-            j = next_start + static_cast<uint32_t>(__popcll(bi & team_mask & lt_mask));
-            mode = (j < n) ? tStart : tDone;
+            // starts in ascending order, or breadth-first from the root on request (any
+            // order gives the same forest; it only changes how walks overlap in time)
+            const uint32_t idx = next_start + static_cast<uint32_t>(__popcll(bi & team_mask & lt_mask));
+            mode = (idx < n) ? tStart : tDone;
+            if (idx < n) j = order ? static_cast<uint32_t>(order[idx]) : idx;
         }
         next_start += static_cast<uint32_t>(__popcll(bi & team_mask));
         if (__all(mode == tDone)) break;
@@ -465,28 +471,25 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     err_out = err;
 }
 
-template <int W>
-__device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t T,
-                                              int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
-                                              int64_t l, uint64_t seed, uint64_t max_iters, uint32_t* lds_pred,
+__device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t batch,
+                                              int64_t sample_begin, int64_t l, uint64_t seed, uint32_t* lds_pred,
                                               uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
                                               uint32_t* __restrict__ status) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t slot = it.slot0 + lane / W;
-    const int64_t sample = batch_sample0 + slot;
-    const bool active = slot < T && sample < sample_end;
     const GraphArgs G = graphs[it.graph];
+    const int W = G.W;
+    const int32_t slot = it.slot0 + lane / W;
+    const int64_t rel = static_cast<int64_t>(batch) * G.T + slot;
+    const bool active = slot < G.T && rel < l;
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    grow_team<W>(G, active ? slot : 0, static_cast<uint64_t>(sample), active, seed, max_iters, lds_pred, steps, h,
-                 err);
-#pragma unroll
+    grow_team(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_pred, steps, h, err);
     for (int off = W / 2; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off, kWave);
         h += __shfl_xor(h, off, kWave);
     }
-    const bool leader = (lane % W) == 0;
-    if (active && leader && tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + (sample - sample_begin)] = h;
+    const bool leader = (lane & (W - 1)) == 0;
+    if (active && leader && tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + rel] = h;
     if (err) atomicOr(status, err);
     const uint64_t wsteps = wave_sum(leader ? steps : 0ull);
     if (lane == 0 && total_steps && wsteps)
@@ -494,18 +497,16 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
                   static_cast<unsigned long long>(wsteps));
 }
 
-// One wave per work item: 64 / W trees, W walkers each.
-template <int W>
+// One wave per work item: 64 / W trees of one graph, W walkers each (W from the graph).
 __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
-                                                     int32_t nitems, uint32_t* queue, int32_t T,
-                                                     int64_t batch_sample0, int64_t sample_end, int64_t sample_begin,
-                                                     int64_t l, uint64_t seed, uint64_t max_iters,
+                                                     int32_t nitems, uint32_t* queue, int32_t batch,
+                                                     int64_t sample_begin, int64_t l, uint64_t seed,
                                                      uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
     __shared__ uint32_t lds_pred[kWave];
     if (queue == nullptr) {
         if (static_cast<int32_t>(blockIdx.x) < nitems)
-            run_team_item<W>(graphs, items[blockIdx.x], T, batch_sample0, sample_end, sample_begin, l, seed, max_iters,
-                             lds_pred, tree_hash, total_steps, status);
+            run_team_item(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_pred, tree_hash, total_steps,
+                          status);
         return;
     }
     while (true) {
@@ -513,25 +514,12 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
         if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
         idx = __shfl(idx, 0, kWave);
         if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_team_item<W>(graphs, items[idx], T, batch_sample0, sample_end, sample_begin, l, seed, max_iters, lds_pred,
-                         tree_hash, total_steps, status);
+        run_team_item(graphs, items[idx], batch, sample_begin, l, seed, lds_pred, tree_hash, total_steps, status);
     }
 }
 
-using WalkKernel = void (*)(const GraphArgs*, const Item*, int32_t, uint32_t*, int32_t, int64_t, int64_t, int64_t,
-                            int64_t, uint64_t, uint64_t, uint64_t*, uint64_t*, uint32_t*);
-
-WalkKernel walk_kernel_for(int W) {
-    switch (W) {
-        case 2: return wilson_team<2>;
-        case 4: return wilson_team<4>;
-        case 8: return wilson_team<8>;
-        case 16: return wilson_team<16>;
-        case 32: return wilson_team<32>;
-        case 64: return wilson_team<64>;
-        default: return wilson_walk;
-    }
-}
+using WalkKernel = void (*)(const GraphArgs*, const Item*, int32_t, uint32_t*, int32_t, int64_t, int64_t, uint64_t,
+                            uint64_t*, uint64_t*, uint32_t*);
 
 __device__ __forceinline__ int32_t graph_of(const int64_t* __restrict__ node_off, int32_t G, int64_t gx) {
     int32_t lo = 0, hi = G - 1;
@@ -547,14 +535,14 @@ __device__ __forceinline__ int32_t graph_of(const int64_t* __restrict__ node_off
 
 // Sets every slot of every graph to the fresh state (root in the tree, all else zero).
 __global__ void init_state(const GraphArgs* __restrict__ graphs, const int64_t* __restrict__ node_off, int32_t G,
-                           int64_t total_nodes, int32_t T) {
+                           int64_t total_nodes) {
     for (int64_t gx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; gx < total_nodes;
          gx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int32_t g = graph_of(node_off, G, gx);
         const GraphArgs A = graphs[g];
         const int64_t x = gx - node_off[g];
         const uint64_t v = (x == A.root) ? kInTree : 0ull;
-        for (int32_t t = 0; t < T; ++t) A.state[static_cast<int64_t>(t) * A.n + x] = v;
+        for (int32_t t = 0; t < A.T; ++t) A.state[static_cast<int64_t>(t) * A.stride + x] = v;
     }
 }
 
@@ -576,43 +564,44 @@ __global__ void zero_outputs(uint64_t* counts, uint64_t* counts_sq, int64_t tota
 
 __global__ void reset_queue(uint32_t* queue) { *queue = 0; }
 
-// Folds the departure counts of the batch's trees into the per-node totals, writes the
-// parent dumps of this batch and resets the slots.  Thread per node, loop over slots: the
-// reads and writes of consecutive threads are consecutive words of one slot.
+// Folds the departure counts of batch `batch` into the per-node totals, writes the parent
+// dumps of this batch and resets the slots.  Thread per node, loop over slots: the reads and
+// writes of consecutive threads are consecutive words of one slot.
 __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t* __restrict__ node_off, int32_t G,
-                             int64_t total_nodes, int32_t used_slots, uint64_t* __restrict__ counts,
+                             int64_t total_nodes, int32_t batch, int64_t l, uint64_t* __restrict__ counts,
                              uint64_t* __restrict__ counts_sq, int32_t* __restrict__ parents, DumpArgs dumps) {
     for (int64_t gx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; gx < total_nodes;
          gx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int32_t g = graph_of(node_off, G, gx);
         const GraphArgs A = graphs[g];
         const int64_t x = gx - node_off[g];
-        const int64_t n = A.n;
+        const int64_t first = static_cast<int64_t>(batch) * A.T;
+        const int32_t used = static_cast<int32_t>(first >= l ? 0 : ((l - first) < A.T ? (l - first) : A.T));
         const bool is_root = (x == A.root);
         for (int d = 0; d < dumps.count; ++d) {
-            const uint64_t w = A.state[static_cast<int64_t>(dumps.slot[d]) * n + x];
-            parents[static_cast<int64_t>(dumps.out[d]) * n + x] = is_root ? -1 : static_cast<int32_t>(st_next(w));
+            const uint64_t w = A.state[static_cast<int64_t>(dumps.slot[d]) * A.stride + x];
+            parents[static_cast<int64_t>(dumps.out[d]) * A.n + x] = is_root ? -1 : static_cast<int32_t>(st_next(w));
         }
         const uint64_t fresh = is_root ? kInTree : 0ull;
         uint64_t c1 = 0, c2 = 0;
         int32_t t = 0;
-        for (; t + 4 <= used_slots; t += 4) {
+        for (; t + 4 <= used; t += 4) {
             uint64_t w[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) w[q] = A.state[static_cast<int64_t>(t + q) * n + x];
+            for (int q = 0; q < 4; ++q) w[q] = A.state[static_cast<int64_t>(t + q) * A.stride + x];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t c = st_cnt(w[q]);
                 c1 += c;
                 c2 += square_count(c);
-                A.state[static_cast<int64_t>(t + q) * n + x] = fresh;
+                A.state[static_cast<int64_t>(t + q) * A.stride + x] = fresh;
             }
         }
-        for (; t < used_slots; ++t) {
-            const uint32_t c = st_cnt(A.state[static_cast<int64_t>(t) * n + x]);
+        for (; t < used; ++t) {
+            const uint32_t c = st_cnt(A.state[static_cast<int64_t>(t) * A.stride + x]);
             c1 += c;
             c2 += square_count(c);
-            A.state[static_cast<int64_t>(t) * n + x] = fresh;
+            A.state[static_cast<int64_t>(t) * A.stride + x] = fresh;
         }
         if (counts) counts[gx] += c1;
         if (counts_sq) counts_sq[gx] += c2;
@@ -621,53 +610,82 @@ __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t
 
 // ---------------------------------------------------------------------- planning ------
 struct Plan {
-    int32_t T = 0;
-    int32_t W = 1;           // walkers per tree
-    int32_t S = kWave;       // trees per wave (64 / W)
-    int64_t total_nodes = 0;
+    std::vector<int32_t> W, T, S;     // per graph: walkers per tree, tree slots, trees per wave
+    std::vector<int64_t> stride;      // per graph: words per slot
     std::vector<int64_t> node_off;
+    int64_t total_nodes = 0;
+    int32_t batches = 1;
+    bool team = false;                // some graph uses more than one walker per tree
 };
 
 constexpr int64_t kDefaultStateBudget = 96ll << 30;  // bytes of slot state chosen automatically
-constexpr int64_t kTargetWalkers = 1 << 17;          // concurrent walkers aimed at with W > 1
+constexpr int64_t kTargetWalkers = 1 << 17;          // concurrent walkers aimed at
 
 // Walkers per tree when the caller leaves it open.  Throughput is set by the number of
-// concurrent walkers and by the state footprint they touch (measured: 64 walkers x 2048 trees
-// beats 16 x 10^4 trees on BA(10^6)), so large graphs get full-wave teams and few trees in
-// flight; when one walker per tree already gives enough concurrency, one per tree.
-int auto_walkers(int64_t total_nodes, int32_t G, int64_t l) {
-    if (l * G >= kTargetWalkers || total_nodes * l <= (int64_t(1) << 22)) return 1;
-    int W = 64;
-    while (W > 2 && W * 16 > total_nodes / G) W >>= 1;
+// concurrent walkers and by the state footprint they touch (measured on BA(10^6): 64 walkers x
+// 2048 trees beats 16 walkers x 10^4 trees), so a single large graph gets full-wave teams and
+// few trees in flight.  In a batch every tree is in flight and a graph's team width grows with
+// its size, which bounds the longest tree's walk time.
+int auto_walkers(int64_t n, int32_t G, int64_t l) {
+    int W = 1;
+    if (G == 1) {
+        if (l >= kTargetWalkers || n * l <= (int64_t(1) << 22)) return 1;
+        W = 64;
+        while (W > 2 && W * 16 > n) W >>= 1;
+        return W;
+    }
+    while (W < 64 && static_cast<int64_t>(W) * 2 * 4096 <= n) W <<= 1;
     return W;
 }
 
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
 int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan* plan) {
     plan->node_off.assign(G + 1, 0);
+    plan->W.assign(G, 1);
+    plan->T.assign(G, 1);
+    plan->S.assign(G, kWave);
+    plan->stride.assign(G, 0);
     for (int32_t g = 0; g < G; ++g) {
-        if (graphs[g].n < 2 || !graphs[g].row_ptr || !graphs[g].col)
+        if (graphs[g].n < 2 || !graphs[g].row_ptr || !graphs[g].col || !graphs[g].rec || !graphs[g].bfs_order)
             return fail(RWC_ERR_INVALID_ARG, "graph %d is not a built CSR", g);
         plan->node_off[g + 1] = plan->node_off[g] + graphs[g].n;
     }
     plan->total_nodes = plan->node_off[G];
     const int64_t l = p->num_samples;
-    int W = p->walkers_per_tree;
-    if (W <= 0) W = auto_walkers(plan->total_nodes, G, l);
-    plan->W = W;
-    plan->S = kWave / W;
-    int64_t T = p->trees_in_flight;
-    if (T <= 0) {
-        // one walker per tree: every tree resident; several walkers: enough trees to give
-        // each graph about kTargetWalkers concurrent walkers
-        int64_t want = (W == 1) ? l : (kTargetWalkers / W + G - 1) / G;
-        if (want > l) want = l;
-        want = (want + plan->S - 1) / plan->S * plan->S;
-        int64_t cap = kDefaultStateBudget / (8 * plan->total_nodes) / plan->S * plan->S;
-        if (cap < plan->S) cap = plan->S;
-        T = want < cap ? want : cap;
+    int64_t state_words = 0;
+    for (int32_t g = 0; g < G; ++g) {
+        const int64_t n = graphs[g].n;
+        const int W = (p->walkers_per_tree > 0) ? p->walkers_per_tree : auto_walkers(n, G, l);
+        const int S = kWave / W;
+        int64_t T = p->trees_in_flight;
+        if (T <= 0) {
+            int64_t want = l;
+            if (G == 1 && W > 1) want = kTargetWalkers / W < l ? kTargetWalkers / W : l;
+            T = round_up(want, S);
+        }
+        if (T > (1 << 30)) return fail(RWC_ERR_TOO_LARGE, "trees_in_flight too large");
+        plan->W[g] = W;
+        plan->S[g] = S;
+        plan->T[g] = static_cast<int32_t>(T);
+        plan->stride[g] = round_up(n, 8);
+        plan->team = plan->team || W > 1;
+        state_words += T * plan->stride[g];
     }
-    if (T > (1 << 30)) return fail(RWC_ERR_TOO_LARGE, "trees_in_flight too large");
-    plan->T = static_cast<int32_t>(T);
+    if (p->trees_in_flight <= 0 && state_words * 8 > kDefaultStateBudget) {
+        // shrink every graph's slots by the same factor to fit the automatic budget
+        const double f = static_cast<double>(kDefaultStateBudget) / (8.0 * static_cast<double>(state_words));
+        for (int32_t g = 0; g < G; ++g) {
+            int64_t T = static_cast<int64_t>(plan->T[g] * f) / plan->S[g] * plan->S[g];
+            plan->T[g] = static_cast<int32_t>(T < plan->S[g] ? plan->S[g] : T);
+        }
+    }
+    int32_t batches = 1;
+    for (int32_t g = 0; g < G; ++g) {
+        const int64_t b = (l + plan->T[g] - 1) / plan->T[g];
+        batches = b > batches ? static_cast<int32_t>(b) : batches;
+    }
+    plan->batches = batches;
     return RWC_OK;
 }
 
@@ -681,22 +699,24 @@ struct SampleLayout {
     size_t total;
 };
 
-SampleLayout carve_sample(void* ws, const rwc_csr* graphs, int32_t G, const Plan& plan, int64_t max_items) {
+int64_t max_items(int32_t G, const Plan& plan) {
+    int64_t k = 0;
+    for (int32_t g = 0; g < G; ++g) k += (plan.T[g] + plan.S[g] - 1) / plan.S[g];
+    return k;
+}
+
+SampleLayout carve_sample(void* ws, int32_t G, const Plan& plan) {
     Carver c(ws);
     SampleLayout L{};
     L.state.resize(G);
-    for (int32_t g = 0; g < G; ++g) L.state[g] = c.take<uint64_t>(static_cast<size_t>(plan.T) * graphs[g].n);
+    for (int32_t g = 0; g < G; ++g) L.state[g] = c.take<uint64_t>(static_cast<size_t>(plan.T[g]) * plan.stride[g]);
     L.graphs = c.take<GraphArgs>(G);
     L.node_off = c.take<int64_t>(G + 1);
-    L.items = c.take<Item>(max_items);
+    L.items = c.take<Item>(max_items(G, plan));
     L.queue = c.take<uint32_t>(1);
     L.status = c.take<uint32_t>(1);
     L.total = c.used();
     return L;
-}
-
-int64_t items_per_batch(int32_t G, const Plan& plan) {
-    return static_cast<int64_t>(G) * ((plan.T + plan.S - 1) / plan.S);
 }
 
 // hipEvents bracketing the walk and reduction launches of every batch.
@@ -782,7 +802,7 @@ extern "C" int rwc_sample_forests_workspace(const rwc_csr* graphs, int32_t num_g
     RWC_CHECK(validate(graphs, num_graphs, p));
     Plan plan;
     RWC_CHECK(make_plan(graphs, num_graphs, p, &plan));
-    *bytes = carve_sample(nullptr, graphs, num_graphs, plan, items_per_batch(num_graphs, plan)).total;
+    *bytes = carve_sample(nullptr, num_graphs, plan).total;
     return RWC_OK;
 }
 
@@ -798,42 +818,56 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         if (out->dump_samples[d] < p->sample_begin || out->dump_samples[d] >= p->sample_begin + p->num_samples)
             return fail(RWC_ERR_INVALID_ARG, "dump sample %lld is outside the sampled range",
                         (long long)out->dump_samples[d]);
+    const bool capture = (p->flags & RWC_SAMPLE_GRAPH_CAPTURE) != 0;
+    if (capture && out->timing_ms)
+        return fail(RWC_ERR_INVALID_ARG, "timing_ms is not available with RWC_SAMPLE_GRAPH_CAPTURE");
     Plan plan;
     RWC_CHECK(make_plan(graphs, G, p, &plan));
-    const int64_t max_items = items_per_batch(G, plan);
-    const size_t need = carve_sample(nullptr, graphs, G, plan, max_items).total;
-    RWC_CHECK(check_workspace(ws, ws_bytes, need));
-    SampleLayout L = carve_sample(ws, graphs, G, plan, max_items);
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_sample(nullptr, G, plan).total));
+    SampleLayout L = carve_sample(ws, G, plan);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int32_t T = plan.T;
     const int64_t l = p->num_samples;
 
     std::vector<GraphArgs> hg(G);
     for (int32_t g = 0; g < G; ++g) {
+        const uint64_t n = static_cast<uint64_t>(graphs[g].n);
+        // default step guard: far above the expected walk length of any graph we accept,
+        // small enough that a runaway tree ends with an error instead of a hang
+        uint64_t steps = p->max_steps_per_tree ? p->max_steps_per_tree : (1ull << 20) + 4096ull * n;
+        // a team's iterations: every step, retrace, release and start check of a tree takes
+        // at most one iteration of some walker, and waits end by cycle pops
+        if (plan.W[g] > 1) steps = 4ull * steps + 8ull * n + 1024ull;
         hg[g].row_ptr = graphs[g].row_ptr;
         hg[g].col = graphs[g].col;
         hg[g].cdf = graphs[g].weighted ? graphs[g].cdf : nullptr;
         hg[g].rec = reinterpret_cast<const uint4*>(graphs[g].rec);
+        hg[g].order = (p->flags & RWC_SAMPLE_BFS_STARTS) ? graphs[g].bfs_order : nullptr;
         hg[g].state = L.state[g];
+        hg[g].stride = plan.stride[g];
+        hg[g].guard = steps;
         hg[g].n = graphs[g].n;
         hg[g].root = (p->root >= 0) ? p->root : graphs[g].pivot;
         hg[g].graph_word = p->graph_index_base + static_cast<uint32_t>(g);
+        hg[g].T = plan.T[g];
+        hg[g].W = plan.W[g];
         hg[g].pad = 0;
     }
-    // Work items in decreasing graph size (longest trees first).
+    // Work items with the longest trees first: a tree's time grows with n / W.
     std::vector<int32_t> order(G);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return graphs[a].n > graphs[b].n; });
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return static_cast<int64_t>(graphs[a].n) * plan.W[b] > static_cast<int64_t>(graphs[b].n) * plan.W[a];
+    });
     std::vector<Item> items;
-    items.reserve(max_items);
+    items.reserve(max_items(G, plan));
     for (int32_t g : order)
-        for (int32_t s0 = 0; s0 < T; s0 += plan.S) items.push_back(Item{g, s0});
+        for (int32_t s0 = 0; s0 < plan.T[g]; s0 += plan.S[g]) items.push_back(Item{g, s0});
     RWC_HIP(hipMemcpyAsync(L.graphs, hg.data(), sizeof(GraphArgs) * G, hipMemcpyHostToDevice, s));
     RWC_HIP(hipMemcpyAsync(L.node_off, plan.node_off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
     RWC_HIP(hipMemcpyAsync(L.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
 
     const bool persistent = (p->flags & RWC_SAMPLE_PERSISTENT) != 0;
-    const WalkKernel walk = walk_kernel_for(plan.W);
+    const WalkKernel walk = plan.team ? static_cast<WalkKernel>(wilson_team) : static_cast<WalkKernel>(wilson_walk);
     int grid_persistent = 0;
     if (persistent) {
         int per_cu = 0;
@@ -841,11 +875,6 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         if (per_cu < 1) per_cu = 1;
         grid_persistent = per_cu * device_cu_count();
     }
-    uint64_t max_steps = p->max_steps_per_tree;
-
-    const bool capture = (p->flags & RWC_SAMPLE_GRAPH_CAPTURE) != 0;
-    if (capture && out->timing_ms)
-        return fail(RWC_ERR_INVALID_ARG, "timing_ms is not available with RWC_SAMPLE_GRAPH_CAPTURE");
     Timer timer;
     if (out->timing_ms) RWC_CHECK(timer.init());
     // A capture runs on a private stream (the caller's may be the legacy default stream,
@@ -853,6 +882,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     CaptureStream cap;
     if (capture) RWC_CHECK(cap.begin(s));
     const hipStream_t ls = capture ? cap.stream : s;
+    const int32_t nit = static_cast<int32_t>(items.size());
 
     auto launches = [&]() -> int {
         const unsigned node_blocks = blocks_for(plan.total_nodes, 256) < 8192 ? blocks_for(plan.total_nodes, 256) : 8192;
@@ -860,33 +890,23 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         hipLaunchKernelGGL(zero_outputs, dim3(node_blocks), dim3(256), 0, ls, accumulate ? nullptr : out->counts,
                            accumulate ? nullptr : out->counts_sq, plan.total_nodes,
                            accumulate ? nullptr : out->total_steps, G, L.status, L.queue);
-        hipLaunchKernelGGL(init_state, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G, plan.total_nodes,
-                           T);
-        for (int64_t b0 = 0; b0 < l; b0 += T) {
-            const int32_t used = static_cast<int32_t>((l - b0) < T ? (l - b0) : T);
-            // A short last batch reuses the full item list: slots at or beyond `used` map to
-            // samples >= sample_end, which the kernel leaves idle.
-            const Item* item_ptr = L.items;
-            const int32_t nit = static_cast<int32_t>(items.size());
-            const int64_t batch_sample0 = p->sample_begin + b0;
-            const int64_t sample_end = p->sample_begin + l;
-            const uint64_t guard = max_steps;
+        hipLaunchKernelGGL(init_state, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G, plan.total_nodes);
+        for (int32_t b = 0; b < plan.batches; ++b) {
+            // every graph runs its samples [b*T_g, (b+1)*T_g); graphs with fewer batches idle
             if (out->timing_ms) RWC_HIP(hipEventRecord(timer.ev[0], ls));
             if (persistent) {
                 hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, ls, L.queue);
                 const int grid = grid_persistent < nit ? grid_persistent : nit;
-                hipLaunchKernelGGL(walk, dim3(grid), dim3(kWave), 0, ls, L.graphs, item_ptr, nit, L.queue, T,
-                                   batch_sample0, sample_end, p->sample_begin, l, p->seed, guard, out->tree_hash,
-                                   out->total_steps, L.status);
+                hipLaunchKernelGGL(walk, dim3(grid), dim3(kWave), 0, ls, L.graphs, L.items, nit, L.queue, b,
+                                   p->sample_begin, l, p->seed, out->tree_hash, out->total_steps, L.status);
             } else {
-                hipLaunchKernelGGL(walk, dim3(nit), dim3(kWave), 0, ls, L.graphs, item_ptr, nit, nullptr, T,
-                                   batch_sample0, sample_end, p->sample_begin, l, p->seed, guard, out->tree_hash,
-                                   out->total_steps, L.status);
+                hipLaunchKernelGGL(walk, dim3(nit), dim3(kWave), 0, ls, L.graphs, L.items, nit, nullptr, b,
+                                   p->sample_begin, l, p->seed, out->tree_hash, out->total_steps, L.status);
             }
             DumpArgs dumps{};
             for (int d = 0; d < out->ndump; ++d) {
-                const int64_t rel = out->dump_samples[d] - batch_sample0;
-                if (rel >= 0 && rel < used) {
+                const int64_t rel = out->dump_samples[d] - p->sample_begin - static_cast<int64_t>(b) * plan.T[0];
+                if (rel >= 0 && rel < plan.T[0]) {
                     dumps.slot[dumps.count] = static_cast<int32_t>(rel);
                     dumps.out[dumps.count] = d;
                     ++dumps.count;
@@ -894,35 +914,21 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
             }
             if (out->timing_ms) RWC_HIP(hipEventRecord(timer.ev[1], ls));
             hipLaunchKernelGGL(reduce_batch, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G,
-                               plan.total_nodes, used, out->counts, out->counts_sq, out->parents, dumps);
+                               plan.total_nodes, b, l, out->counts, out->counts_sq, out->parents, dumps);
             if (out->timing_ms) {
                 RWC_HIP(hipEventRecord(timer.ev[2], ls));
                 RWC_HIP(hipEventSynchronize(timer.ev[2]));
-                float a = 0.f, b = 0.f;
+                float a = 0.f, c = 0.f;
                 RWC_HIP(hipEventElapsedTime(&a, timer.ev[0], timer.ev[1]));
-                RWC_HIP(hipEventElapsedTime(&b, timer.ev[1], timer.ev[2]));
+                RWC_HIP(hipEventElapsedTime(&c, timer.ev[1], timer.ev[2]));
                 timer.walk_ms += a;
-                timer.reduce_ms += b;
+                timer.reduce_ms += c;
             }
         }
         RWC_HIP(hipGetLastError());
         return RWC_OK;
     };
 
-    if (max_steps == 0) {
-        // default guard: far above the expected walk length of any graph we accept, and
-        // small enough that a runaway tree ends with an error instead of a hang
-        int64_t maxn = 0;
-        for (int32_t g = 0; g < G; ++g) maxn = graphs[g].n > maxn ? graphs[g].n : maxn;
-        max_steps = (1ull << 20) + 4096ull * static_cast<uint64_t>(maxn);
-    }
-    if (plan.W > 1) {
-        // a team's iterations: every step, retrace, release and start check of the tree
-        // takes at most one iteration of some walker, and waits end by cycle pops
-        int64_t maxn = 0;
-        for (int32_t g = 0; g < G; ++g) maxn = graphs[g].n > maxn ? graphs[g].n : maxn;
-        max_steps = 4ull * max_steps + 8ull * static_cast<uint64_t>(maxn) + 1024ull;
-    }
     int rc = launches();
     if (capture) {
         const int rc2 = cap.end_and_launch(s, rc);
@@ -936,6 +942,12 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     if (out->timing_ms) {
         out->timing_ms[0] = timer.walk_ms;
         out->timing_ms[1] = timer.reduce_ms;
+    }
+    if (out->plan) {
+        // graph 0's plan (every graph's plan is the same unless chosen automatically)
+        out->plan[0] = plan.W[0];
+        out->plan[1] = plan.T[0];
+        out->plan[2] = plan.batches;
     }
     return device_error_to_status(status);
 }

@@ -55,7 +55,7 @@ def test_workspace_queries_and_argument_errors():
 def test_sample_workspace_scales_with_trees_in_flight():
     from paper_2510_20604_amd import _lib
     lib = _lib.load()
-    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8)
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8, rec=8, bfs_order=8)
     p = _lib.SampleParams(seed=1, sample_begin=0, num_samples=500, root=-1, trees_in_flight=64)
     a = ctypes.c_size_t()
     assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(a)) == 0

@@ -69,6 +69,15 @@ def test_csr_matches_oracle(name):
         if g.w is not None:
             c = rec[u, 8:8 + 2 * k].astype(np.uint64)
             np.testing.assert_array_equal(c[0::2] | (c[1::2] << np.uint64(32)), o.cdf[b:b + k])
+    # breadth-first start order: a permutation starting at the pivot, distances non-decreasing
+    order = Gd.bfs_order().cpu().numpy()
+    np.testing.assert_array_equal(np.sort(order), np.arange(g.n))
+    assert order[0] == o.pivot
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as csg
+    A = sp.csr_matrix((np.ones(o.col.shape[0]), o.col, o.row_ptr), shape=(g.n, g.n))
+    dist = csg.shortest_path(A, unweighted=True, indices=o.pivot)
+    assert np.all(np.diff(dist[order]) >= 0)
     # edge_id maps every entry back to an input edge with matching endpoints
     eid = Gd.edge_id().cpu().numpy()
     rows = np.repeat(np.arange(g.n), np.diff(o.row_ptr))
@@ -197,6 +206,29 @@ def test_batched_graphs_match_per_graph_oracle():
         np.testing.assert_array_equal(_u64(p["tree_hash"][0]), _u64(s["tree_hash"][i]))
 
 
+def test_batched_mixed_team_widths_match_oracle():
+    """A batch whose graphs get different walkers per tree (1, 2 and 4 by size) in one
+    persistent launch reproduces each graph's serial forest."""
+    gs = [G.barabasi_albert(300, 3, 51), G.grid_with_deletions(9000, 0.1, 52), G.barabasi_albert(20000, 3, 53),
+          G.grid_with_deletions(600, 0.1, 54)]
+    gs = [g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 60 + i)) for i, g in enumerate(gs)]
+    dev = [P.Graph(g.n, g.src, g.dst, g.w) for g in gs]
+    l, seed = 40, 91
+    s = P.sample_forests(dev, l, seed, persistent=True)
+    counts = _u64(s["counts"])
+    off = 0
+    for i, g in enumerate(gs):
+        o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+        ref = W.fastwalk_sample(o, o.pivot, seed, i, 0, l, threads=8)
+        np.testing.assert_array_equal(counts[off:off + g.n], ref["visits"])
+        np.testing.assert_array_equal(_u64(s["tree_hash"][i]), ref["hash"])
+        off += g.n
+    # and with a forced small number of trees in flight (several batches, all graphs)
+    s2 = P.sample_forests(dev, l, seed, persistent=True, trees_in_flight=16)
+    np.testing.assert_array_equal(_u64(s2["counts"]), counts)
+    np.testing.assert_array_equal(_u64(s2["tree_hash"]), _u64(s["tree_hash"]))
+
+
 def test_explicit_root(oracle_runs):
     g = _case("er1000_w")
     o = W.OracleCSR(g.n, g.src, g.dst, g.w)
@@ -245,3 +277,19 @@ def test_end_to_end_er1000_accuracy():
     exact = E.rwc_laplacian_pinv(g.n, g.src, g.dst, None)
     mre = E.mean_relative_error(exact, rwc)
     assert mre < 0.03
+
+
+def test_autotuner_choice_does_not_change_the_forest(oracle_runs):
+    g, o, ref = oracle_runs("ba3000_w", 200, 2001)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    from paper_2510_20604_amd import _lib
+    _lib.lib().rwc_autotune_clear_cache()
+    t = P.autotune(Gd, 200, 2001)
+    assert t["candidates"] >= 2 and not t["cached"]
+    assert t["walkers_per_tree"] in (1, 8, 16, 32, 64) and t["trees_in_flight"] >= 1
+    s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=t["walkers_per_tree"],
+                         trees_in_flight=t["trees_in_flight"])
+    np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
+    again = P.autotune(Gd, 200, 2001)
+    assert again["cached"] and again["walkers_per_tree"] == t["walkers_per_tree"]
