@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000", "batch256"])
+    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000", "batch256", "grad100k"])
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
     ap.add_argument("--walkers", type=int, default=0, help="walkers per tree (0 = automatic)")
     ap.add_argument("--tif", type=int, default=0, help="trees in flight (0 = automatic)")
@@ -143,8 +143,37 @@ def batch_main(args):
     print(json.dumps(line), flush=True)
 
 
+def grad_main(args):
+    """Adjoint throughput: BA(1e5, 4), w ~ U[0.5, 2], loss = sum of RWC over 100 random
+    targets, JL sketch with k = 64 (rwc_backward)."""
+    import torch
+    import paper_2510_20604_amd as P
+    import rwcgen
+    g = rwcgen.barabasi_albert(100_000, 4, 1004)
+    g = g.with_weights(rwcgen.uniform_weights(g.m, 0.5, 2.0, 1005))
+    t = np.random.default_rng(6).choice(g.n, size=100, replace=False).astype(np.int32)
+    gv = np.ones(100)
+    G = P.Graph(g.n, g.src, g.dst, g.w, "cuda:0")
+    for _ in range(args.warmup):
+        P.backward(G, t, gv, k=64, seed=2004, tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = P.backward(G, t, gv, k=64, seed=2004, tol=1e-8)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    line = {"metric": METRIC, "value": round(g.m / el, 1), "unit": "grad edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(1e3 * el, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+            "config": {"workload": "BA(n=1e5, m=4), w ~ U[0.5, 2], 100 targets, JL sketch k = 64", "n": g.n,
+                       "m": g.m, "solve_columns": 66, "pcg_iters": r["iters"], "tol": 1e-8}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
+    if args.config == "grad100k":
+        return grad_main(args)
     if args.config == "batch256":
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)

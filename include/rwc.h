@@ -69,6 +69,8 @@ typedef struct rwc_csr {
                               and their CDF values in words 8..15 (weighted)               */
     int32_t* bfs_order;    /* [n] nodes in breadth-first order from the pivot: the order in
                               which walker teams take start nodes                          */
+    int32_t bfs_depth;     /* largest hop distance from the pivot (its eccentricity)       */
+    int32_t reserved;
 } rwc_csr;
 
 /* Bytes of workspace rwc_build_csr needs for n nodes and m edges (weighted != 0 if w will
@@ -94,6 +96,18 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
 #define RWC_SAMPLE_GRAPH_CAPTURE 4u  /* record the launches in a hipGraph and replay it     */
 #define RWC_SAMPLE_BFS_STARTS    8u  /* walker teams take start nodes in breadth-first order
                                         from the root instead of ascending ids (same forest) */
+#define RWC_SAMPLE_SPREAD_STARTS 16u /* each walker of a team takes start nodes from its own
+                                        contiguous range of the start order (same forest)   */
+#define RWC_SAMPLE_SHARED_STARTS 32u /* a team's walkers take consecutive start positions.
+                                        With neither this nor SPREAD, each graph gets spread
+                                        starts if its bfs_depth exceeds 32 (long walks, e.g.
+                                        meshes), shared starts otherwise                    */
+#define RWC_SAMPLE_PATH_RING     64u /* team kernel keeps each walker's newest path nodes in
+                                        LDS so loop erasure and attachment of them are single
+                                        atomic flips (same forest)                          */
+#define RWC_SAMPLE_NO_PATH_RING 128u /* team kernel without that ring.  With neither, the
+                                        ring is used iff some graph of the call has spread
+                                        starts                                              */
 
 typedef struct rwc_sample_params {
     uint64_t seed;               /* Philox key (seed mod 2^32, seed >> 32)                 */

@@ -19,6 +19,10 @@ RWC_SAMPLE_ACCUMULATE = 1
 RWC_SAMPLE_PERSISTENT = 2
 RWC_SAMPLE_GRAPH_CAPTURE = 4
 RWC_SAMPLE_BFS_STARTS = 8
+RWC_SAMPLE_SPREAD_STARTS = 16
+RWC_SAMPLE_SHARED_STARTS = 32
+RWC_SAMPLE_PATH_RING = 64
+RWC_SAMPLE_NO_PATH_RING = 128
 
 STATUS = {
     0: "RWC_OK", -1: "RWC_ERR_INVALID_ARG", -2: "RWC_ERR_NODE_RANGE", -3: "RWC_ERR_SELF_LOOP",
@@ -32,7 +36,8 @@ class RwcCsr(ctypes.Structure):
     _fields_ = [("n", c_i32), ("pivot", c_i32), ("m", c_i64), ("nnz", c_i64), ("weighted", c_i32),
                 ("max_degree", c_i32), ("vol", c_dbl), ("vol_fixed", c_u64), ("row_ptr", c_vp),
                 ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp),
-                ("rec", c_vp), ("bfs_order", c_vp)]
+                ("rec", c_vp), ("bfs_order", c_vp), ("bfs_depth", c_i32),
+                ("reserved", c_i32)]
 
 
 class SampleParams(ctypes.Structure):

@@ -106,13 +106,15 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
                    want_hash: bool = True, dump: Sequence[int] = (), max_steps_per_tree: int = 0,
                    graph_index_base: int = 0, accumulate: dict | None = None,
                    workspace: torch.Tensor | None = None, timing: bool = False,
-                   bfs_starts: bool = False) -> dict:
+                   bfs_starts: bool = False, starts: str = "auto", path_ring: bool | None = None) -> dict:
     """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
 
     Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
     total_steps [G], tree_hash [G, num_samples], parents [len(dump), n] and the workspace
     used (pass it back as `workspace` to reuse it).  With timing=True also walk_ms and
-    reduce_ms: device time of the walk and reduction kernels (hipEvents on the stream)."""
+    reduce_ms: device time of the walk and reduction kernels (hipEvents on the stream).
+    `starts` ("auto", "shared", "spread") and `path_ring` (None = automatic) pick how walker
+    teams schedule their walks; the forest does not depend on them."""
     L = _lib.lib()
     gl = [graphs] if isinstance(graphs, Graph) else list(graphs)
     G = len(gl)
@@ -127,6 +129,14 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
         flags |= _lib.RWC_SAMPLE_ACCUMULATE
     if bfs_starts:
         flags |= _lib.RWC_SAMPLE_BFS_STARTS
+    if starts == "spread":
+        flags |= _lib.RWC_SAMPLE_SPREAD_STARTS
+    elif starts == "shared":
+        flags |= _lib.RWC_SAMPLE_SHARED_STARTS
+    elif starts != "auto":
+        raise ValueError(f"starts must be 'auto', 'shared' or 'spread', not {starts!r}")
+    if path_ring is not None:
+        flags |= _lib.RWC_SAMPLE_PATH_RING if path_ring else _lib.RWC_SAMPLE_NO_PATH_RING
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=root, flags=flags,
                      trees_in_flight=trees_in_flight, walkers_per_tree=walkers_per_tree,
                      max_steps_per_tree=max_steps_per_tree, graph_index_base=graph_index_base)

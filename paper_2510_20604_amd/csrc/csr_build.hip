@@ -592,6 +592,7 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
                        host.pivot, L.parent, L.bfs_order, L.tail);
     RWC_HIP(hipGetLastError());
     uint32_t lo = 0, hi = 1;
+    int32_t depth = 0;
     for (int32_t level = 0; hi < static_cast<uint32_t>(n); ++level) {
         const int64_t width = hi - lo;
         hipLaunchKernelGGL(bfs_level, dim3(blocks_for(width, kBlock) < gs ? blocks_for(width, kBlock) : gs),
@@ -604,6 +605,7 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
         if (t == hi) return fail(RWC_ERR_DISCONNECTED, "breadth-first search stopped at %u of %d nodes", t, n);
         lo = hi;
         hi = t;
+        depth = level + 1;
     }
 
     rwc_csr g{};
@@ -623,6 +625,7 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     g.strength = L.strength;
     g.rec = L.rec;
     g.bfs_order = L.bfs_order;
+    g.bfs_depth = depth;
     *out = g;
     return RWC_OK;
 }

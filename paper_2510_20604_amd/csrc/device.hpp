@@ -10,6 +10,25 @@ namespace rwc {
 
 constexpr int kWave = 64;
 
+// Pointers the hot loops dereference, retagged as global memory: loaded from argument
+// structs they are generic, which makes every access a flat instruction (64-bit addresses,
+// and counted with LDS traffic so that waits for LDS also wait for HBM).
+#define RWC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RWC_GLOBAL T* global_ptr(T* p) {
+    return (RWC_GLOBAL T*)p;
+}
+#define RWC_LDS __attribute__((address_space(3)))
+// Waits until every vector memory operation of this wave has completed, including copies
+// from memory into LDS, which the compiler does not track (s_waitcnt vmcnt(0)).
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// 16-byte load through such a pointer (HIP's vector types only bind generic references)
+__device__ __forceinline__ uint4 load_u4(const RWC_GLOBAL uint4* p) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = *reinterpret_cast<const RWC_GLOBAL u32x4*>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 products
 // on counter words 0 and 2, key words added in each round and bumped by the Weyl
@@ -46,8 +65,8 @@ __device__ __forceinline__ int32_t select_unweighted(uint64_t x, int32_t deg) {
     return static_cast<int32_t>(mulhi64(x, static_cast<uint64_t>(deg)));
 }
 
-__device__ __forceinline__ int32_t select_weighted(uint64_t x, const uint64_t* __restrict__ cdf,
-                                                   int32_t beg, int32_t deg) {
+template <class CdfPtr>
+__device__ __forceinline__ int32_t select_weighted(uint64_t x, CdfPtr cdf, int32_t beg, int32_t deg) {
     const uint64_t total = cdf[beg + deg - 1];
     const uint64_t r = mulhi64(x, total);
     int32_t lo = 0, hi = deg - 1;

@@ -40,7 +40,7 @@ struct GraphArgs {
     uint32_t graph_word;
     int32_t T;              // tree slots (trees in flight) of this graph
     int32_t W;              // walkers per tree
-    int32_t pad;
+    int32_t spread;         // each walker of a team takes starts from its own range
 };
 
 struct Item {
@@ -58,18 +58,43 @@ struct DumpArgs {
 
 enum Phase : int { kScan = 0, kWalk = 1, kRetrace = 2, kDone = 3 };
 
+// Word i (0..15) of a node record held in four uint4 registers.
+__device__ __forceinline__ uint32_t rec_word(const uint4& a, const uint4& b, const uint4& c, const uint4& d,
+                                             uint32_t i) {
+    const uint4 q = (i < 4) ? a : (i < 8) ? b : (i < 12) ? c : d;
+    const uint32_t s = i & 3u;
+    return s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
+}
+
+// RandomNeighbor from a weighted record with deg <= kRecInlineWeighted inline (id, cdf) pairs:
+// the position k of the chosen pair (its id is record word 2 + k).  c and d are record
+// words 8..15, the four CDF values.
+__device__ __forceinline__ uint32_t rec_weighted_slot(const uint4& c, const uint4& d, uint64_t x, uint32_t deg) {
+    const uint64_t c0 = c.x | (static_cast<uint64_t>(c.y) << 32);
+    const uint64_t c1 = c.z | (static_cast<uint64_t>(c.w) << 32);
+    const uint64_t c2 = d.x | (static_cast<uint64_t>(d.y) << 32);
+    const uint64_t c3 = d.z | (static_cast<uint64_t>(d.w) << 32);
+    const uint64_t total = deg == 1 ? c0 : (deg == 2 ? c1 : (deg == 3 ? c2 : c3));
+    const uint64_t r = mulhi64(x, total);
+    return (r < c0) ? 0u : ((r < c1) ? 1u : ((r < c2) ? 2u : 3u));
+}
+
 // Grows the tree of slot `slot` for absolute sample `sample` (one lane).
 __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint64_t sample, uint64_t seed,
                                           uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
     const uint64_t max_steps = G.guard;
     const int32_t n = G.n;
-    const int32_t* __restrict__ row_ptr = G.row_ptr;
-    const int32_t* __restrict__ col = G.col;
-    const uint64_t* __restrict__ cdf = G.cdf;
-    uint64_t* __restrict__ st = G.state + static_cast<int64_t>(slot) * G.stride;
+    const auto row_ptr = global_ptr(G.row_ptr);
+    const auto col = global_ptr(G.col);
+    const auto cdf = global_ptr(G.cdf);
+    const auto rec = global_ptr(G.rec);
+    const auto st = global_ptr(G.state + static_cast<int64_t>(slot) * G.stride);
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     const uint32_t sw = static_cast<uint32_t>(sample);
     const uint32_t gw = G.graph_word;
+    // record of node rh_node, loaded with that node's state word when the walk arrives
+    uint4 ra = make_uint4(0, 0, 0, 0), rb = ra, rc = ra, rd = ra;
+    uint32_t rh_node = 0xFFFFFFFFu;
 
     uint32_t j = 0;      // next start candidate (ascending order, Algorithm 3)
     uint32_t x = 0;      // walk position, or retrace cursor
@@ -94,13 +119,37 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
             }
         } else if (phase == kWalk) {
             const uint32_t k = st_cnt(wx);
-            const int32_t beg = row_ptr[x];
-            const int32_t deg = row_ptr[x + 1] - beg;
+            if (rh_node != x) {
+                const auto q = rec + 4 * static_cast<int64_t>(x);
+                ra = load_u4(q + 0);
+                rb = load_u4(q + 1);
+                rc = load_u4(q + 2);
+                rd = load_u4(q + 3);
+                rh_node = x;
+            }
+            const uint32_t deg = ra.x;
+            const int32_t beg = static_cast<int32_t>(ra.y);
             const uint64_t r = philox_x64(k, x, sw, gw, k0, k1);
-            const int32_t pick = cdf ? select_weighted(r, cdf, beg, deg) : select_unweighted(r, deg);
-            const uint32_t y = static_cast<uint32_t>(col[beg + pick]);
+            uint32_t y;
+            if (cdf == nullptr) {
+                const int32_t pick = select_unweighted(r, static_cast<int32_t>(deg));
+                y = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_word(ra, rb, rc, rd, 2u + pick)
+                                                                : static_cast<uint32_t>(col[beg + pick]);
+            } else if (deg <= static_cast<uint32_t>(kRecInlineWeighted)) {
+                y = rec_word(ra, rb, rc, rd, 2u + rec_weighted_slot(rc, rd, r, deg));
+            } else {
+                y = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
+            }
             st[x] = st_make(y, k + 1);
             const uint64_t wy = st[y];
+            {
+                const auto q = rec + 4 * static_cast<int64_t>(y);   // y is the next position
+                ra = load_u4(q + 0);
+                rb = load_u4(q + 1);
+                rc = load_u4(q + 2);
+                rd = load_u4(q + 3);
+                rh_node = y;
+            }
             ++steps;
             if (k + 1 >= kCntMax) {
                 err |= kErrCountOverflow;
@@ -202,42 +251,25 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
 // on until it is in the tree (skip) or free (claim).  Every iteration reads before it writes
 // and ends with a work-group fence, so all lanes see one consistent snapshot per iteration.
 // ---------------------------------------------------------------------------------------
+constexpr uint32_t kPathBuf = 16;   // newest path nodes kept per walker (power of two)
+
 enum TeamMode : int { tIdle = 0, tStart = 1, tWalk = 2, tWait = 3, tRetrace = 4, tRelease = 5, tDone = 6 };
 
-__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+__device__ __forceinline__ uint64_t st_load(const RWC_GLOBAL uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ void st_store(RWC_GLOBAL uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ bool st_cas(uint64_t* p, uint64_t expected, uint64_t desired) {
+__device__ __forceinline__ bool st_cas(RWC_GLOBAL uint64_t* p, uint64_t expected, uint64_t desired) {
     return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Word i (0..15) of a node record held in four uint4 registers.
-__device__ __forceinline__ uint32_t rec_word(const uint4& a, const uint4& b, const uint4& c, const uint4& d,
-                                             uint32_t i) {
-    const uint4 q = (i < 4) ? a : (i < 8) ? b : (i < 12) ? c : d;
-    const uint32_t s = i & 3u;
-    return s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
-}
-
-// RandomNeighbor from a weighted record with deg <= kRecInlineWeighted inline (id, cdf) pairs.
-__device__ __forceinline__ uint32_t rec_pick_weighted(const uint4& a, const uint4& b, const uint4& c,
-                                                      const uint4& d, uint64_t x, uint32_t deg) {
-    const uint64_t c0 = c.x | (static_cast<uint64_t>(c.y) << 32);
-    const uint64_t c1 = c.z | (static_cast<uint64_t>(c.w) << 32);
-    const uint64_t c2 = d.x | (static_cast<uint64_t>(d.y) << 32);
-    const uint64_t c3 = d.z | (static_cast<uint64_t>(d.w) << 32);
-    const uint64_t total = deg == 1 ? c0 : (deg == 2 ? c1 : (deg == 3 ? c2 : c3));
-    const uint64_t r = mulhi64(x, total);
-    const uint32_t k = (r < c0) ? 0u : ((r < c1) ? 1u : ((r < c2) ? 2u : 3u));
-    return rec_word(a, b, c, d, 2u + k);
-}
-
+template <bool kRing>
 __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
-                          uint32_t* lds_pred, uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
+                          uint32_t* lds_pred, uint32_t (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
+                          uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
     constexpr uint32_t kNone = 64;
     const int W = G.W;                       // walkers per tree, a power of two <= 64
     const uint64_t max_iters = G.guard;
@@ -245,40 +277,81 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     const int team = lane / W;
     const uint32_t tl = static_cast<uint32_t>(lane & (W - 1));
     const uint32_t team_base = static_cast<uint32_t>(team * W);
-    const uint64_t team_mask = (W == kWave) ? ~0ull : (((1ull << W) - 1ull) << team_base);
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const uint32_t n = static_cast<uint32_t>(G.n);
-    const int32_t* __restrict__ row_ptr = G.row_ptr;
-    const int32_t* __restrict__ col = G.col;
-    const uint64_t* __restrict__ cdf = G.cdf;
-    const uint4* __restrict__ rec = G.rec;
-    const int32_t* __restrict__ order = G.order;
-    uint64_t* st = G.state + static_cast<int64_t>(slot) * G.stride;
+    const auto row_ptr = global_ptr(G.row_ptr);
+    const auto col = global_ptr(G.col);
+    const auto cdf = global_ptr(G.cdf);
+    const auto rec = global_ptr(G.rec);
+    const auto order = global_ptr(G.order);
+    const auto st = global_ptr(G.state + static_cast<int64_t>(slot) * G.stride);
     // record of node rh_node, loaded alongside that node's state word so that a step from a
-    // fresh head needs no dependent load for low-degree rows
-    uint4 ra = make_uint4(0, 0, 0, 0), rb = ra, rc = ra, rd = ra;
+    // fresh head needs no dependent load for low-degree rows.  It is copied straight from
+    // memory into LDS (lane's column of lds_rec) without passing through registers; reads of
+    // it wait for the copy with wait_vm().
     uint32_t rh_node = 0xFFFFFFFFu;
+    auto keep_record = [&](uint32_t v) {
+        const auto q = rec + 4 * static_cast<int64_t>(v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((const RWC_GLOBAL void*)(q + i),
+                                             (RWC_LDS void*)(&lds_rec[i][0]), 16, 0, 0);
+        rh_node = v;
+    };
+    auto rec_at = [&](uint32_t i) -> uint32_t {
+        return reinterpret_cast<const uint32_t*>(&lds_rec[i >> 2][lane])[i & 3u];
+    };
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     const uint32_t sw = static_cast<uint32_t>(sample), gw = G.graph_word;
 
     uint32_t next_start = 0;                 // uniform within the team
+    // spread starts: walker tl owns the start positions [tl*chunk, (tl+1)*chunk) of the order
+    const uint32_t chunk = (n + static_cast<uint32_t>(W) - 1) / static_cast<uint32_t>(W);
+    uint32_t my_next = tl * chunk;
     int mode = active ? tIdle : tDone;
     uint32_t j = 0, h = 0, y = 0, c = 0, cend = 0, jn = 0;
     uint64_t wh = 0, jw = 0;
+    // ring of the newest nodes of this walker's path in LDS: entry 0 is the head and the
+    // entries form a contiguous suffix of the path ending at it (nbuf >= 1 while walking)
+    uint32_t nbuf = 0, bhead = 0;
+    uint32_t cstop = 0;                  // a retrace chase stops before this (buffered) node
+    auto buf = [&](uint32_t d) -> uint32_t { return lds_path[(bhead - d) & (kPathBuf - 1)][lane]; };
+    auto push = [&](uint32_t v) {
+        if constexpr (kRing) {
+            bhead = (bhead + 1) & (kPathBuf - 1);
+            lds_path[bhead][lane] = v;
+            nbuf = nbuf < kPathBuf ? nbuf + 1 : kPathBuf;
+        }
+    };
+    auto find = [&](uint32_t v) -> uint32_t {   // offset of v among entries 1..nbuf-1, 0 if absent
+        if constexpr (kRing) {
+            for (uint32_t d = 1; d < nbuf; ++d)
+                if (buf(d) == v) return d;
+        }
+        return 0u;
+    };
     uint64_t steps = 0, hsum = 0, iters = 0;
     uint32_t err = 0;
     while (true) {
         // ---- hand out start nodes, ascending, to idle walkers of each team
         const bool idle = (mode == tIdle);
         const uint64_t bi = __ballot(idle);
+        // idle walkers of my team (bit t = team lane t)
+        const uint64_t tbits = (W == kWave) ? bi : ((bi >> team_base) & ((1ull << W) - 1ull));
         if (idle) {
-            // starts in ascending order, or breadth-first from the root on request (any
-            // order gives the same forest; it only changes how walks overlap in time)
-            const uint32_t idx = next_start + static_cast<uint32_t>(__popcll(bi & team_mask & lt_mask));
+            // starts in ascending order, or breadth-first from the root on request; shared
+            // (the team takes consecutive positions) or spread (each walker its own range).
+            // Any order gives the same forest; it only changes how walks overlap in time.
+            uint32_t idx;
+            if (G.spread) {
+                const uint32_t my_end = (tl + 1) * chunk < n ? (tl + 1) * chunk : n;
+                idx = my_next < my_end ? my_next++ : n;
+            } else {
+                idx = next_start + static_cast<uint32_t>(__popcll(tbits & ((1ull << tl) - 1ull)));
+            }
             mode = (idx < n) ? tStart : tDone;
             if (idx < n) j = order ? static_cast<uint32_t>(order[idx]) : idx;
         }
-        next_start += static_cast<uint32_t>(__popcll(bi & team_mask));
+        next_start += static_cast<uint32_t>(__popcll(tbits));
         if (__all(mode == tDone)) break;
         if (++iters > max_iters) {
             err |= kErrStepLimit;
@@ -290,24 +363,19 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         uint32_t ny = 0;
         uint32_t k = 0;
         if (mode == tWalk) {
-            if (rh_node != h) {
-                const uint4* q = rec + 4 * static_cast<int64_t>(h);
-                ra = q[0];
-                rb = q[1];
-                rc = q[2];
-                rd = q[3];
-                rh_node = h;
-            }
+            if (rh_node != h) keep_record(h);
+            wait_vm();
             k = st_cnt(wh);
-            const uint32_t deg = ra.x;
-            const int32_t beg = static_cast<int32_t>(ra.y);
+            const uint2 db = *reinterpret_cast<const uint2*>(&lds_rec[0][lane]);
+            const uint32_t deg = db.x;
+            const int32_t beg = static_cast<int32_t>(db.y);
             const uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
             if (cdf == nullptr) {
                 const int32_t pick = select_unweighted(r, static_cast<int32_t>(deg));
-                ny = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_word(ra, rb, rc, rd, 2u + pick)
+                ny = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_at(2u + static_cast<uint32_t>(pick))
                                                                  : static_cast<uint32_t>(col[beg + pick]);
             } else if (deg <= static_cast<uint32_t>(kRecInlineWeighted)) {
-                ny = rec_pick_weighted(ra, rb, rc, rd, r, deg);
+                ny = rec_at(2u + rec_weighted_slot(lds_rec[2][lane], lds_rec[3][lane], r, deg));
             } else {
                 ny = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
             }
@@ -321,15 +389,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         }
         const bool reads = (mode != tDone) && (mode != tIdle);
         const uint64_t w = reads ? st_load(&st[node]) : 0ull;
-        if (mode == tWalk || mode == tStart || mode == tWait) {
-            // the node may become this walker's head
-            const uint4* q = rec + 4 * static_cast<int64_t>(node);
-            ra = q[0];
-            rb = q[1];
-            rc = q[2];
-            rd = q[3];
-            rh_node = node;
-        }
+        if (mode == tWalk || mode == tStart || mode == tWait) keep_record(node);   // may become the head
         const bool w_tree = (w & kInTree) != 0;
         const bool w_owned = (w & kOwned) != 0;
         const bool w_mine = w_owned && st_owner(w) == tl;
@@ -338,6 +398,54 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         bool claim = false, depart = false, store = false, waiting = false;
         uint64_t dep_word = 0, store_word = 0;
         uint32_t dep_node = 0, claim_node = 0, store_node = 0;
+        uint32_t xor_cnt = 0, xor_head = 0;   // atomically flip the xor_cnt newest path entries
+        uint64_t xor_mask = 0;
+        // attach the path (its head points at the tree node `hit`): the buffered suffix flips
+        // to INTREE in this iteration, an older prefix is chased from the start afterwards
+        auto attach = [&](uint32_t hit) {
+            if (kRing && nbuf > 0) {
+                xor_cnt = nbuf;
+                xor_head = bhead;
+                xor_mask = kOwned | kInTree | (static_cast<uint64_t>(tl) << 56);
+                for (uint32_t d = 0; d < nbuf; ++d)
+                    hsum += splitmix64((static_cast<uint64_t>(buf(d)) << 32) | (d == 0 ? hit : buf(d - 1)));
+                const uint32_t oldest = buf(nbuf - 1);
+                if (oldest == j) {
+                    mode = tIdle;
+                } else {
+                    mode = tRetrace;
+                    c = j;
+                    cstop = oldest;
+                }
+            } else {
+                // chase the whole path; only the head points at the tree node
+                mode = tRetrace;
+                c = j;
+                cstop = hit;
+            }
+        };
+        // pop the path back to node v (v on the path, older than the head): release what is
+        // newer than v, from the ring if v is buffered, else by chasing from v's successor
+        auto pop_to = [&](uint32_t v, uint64_t vw) {
+            const uint32_t d = find(v);
+            if (d > 0) {
+                xor_cnt = d;
+                xor_head = bhead;
+                xor_mask = kOwned | (static_cast<uint64_t>(tl) << 56);
+                bhead = (bhead - d) & (kPathBuf - 1);
+                nbuf -= d;
+                mode = tWalk;
+                h = v;
+                wh = vw;
+            } else {
+                mode = tRelease;
+                c = st_next(vw);
+                cend = h;
+                jn = v;
+                jw = vw;
+                nbuf = 0;
+            }
+        };
         if (mode == tWalk) {
             depart = true;
             dep_node = h;
@@ -347,15 +455,10 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 err |= kErrCountOverflow;
                 mode = tDone;
             } else if (w_tree) {
-                mode = tRetrace;
-                c = j;
+                attach(ny);
             } else if (w_mine) {
                 // own cycle ny -> ... -> h -> ny: release the segment after ny; ny is the head
-                mode = tRelease;
-                c = st_next(w);
-                cend = h;
-                jn = ny;
-                jw = w;
+                pop_to(ny, w);
             } else if (w_owned) {
                 mode = tWait;
                 y = ny;
@@ -373,8 +476,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             }
         } else if (mode == tWait) {
             if (w_tree) {
-                mode = tRetrace;
-                c = j;
+                attach(y);
             } else if (!w_owned) {
                 claim = true;
                 claim_node = y;
@@ -389,11 +491,12 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 err |= kErrProtocol;
                 mode = tDone;
             } else if (mode == tRetrace) {
+                // chase of the path prefix older than the ring
                 store = true;
                 store_node = c;
                 store_word = (w & ~(kOwned | (0x3Full << 56))) | kInTree;
                 hsum += splitmix64((static_cast<uint64_t>(c) << 32) | st_next(w));
-                if (c == h)
+                if (st_next(w) == cstop)
                     mode = tIdle;
                 else
                     c = st_next(w);
@@ -405,6 +508,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                     mode = tWalk;
                     h = jn;
                     wh = jw;
+                    push(jn);
                 } else {
                     c = st_next(w);
                 }
@@ -435,30 +539,34 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             __syncthreads();
             if (on_cycle) {
                 // the cycle enters my path at py: the arrows from py on are popped
-                jn = py;
-                jw = pw;
-                if (jn == h) {
+                if (py == h) {
                     // my head's own arrow is popped; if I departed in this iteration the
                     // snapshot the predecessor read predates my departure word
                     mode = tWalk;
-                    wh = depart ? dep_word : jw;
+                    wh = depart ? dep_word : pw;
                 } else {
-                    mode = tRelease;
-                    c = st_next(jw);
-                    cend = h;
+                    pop_to(py, pw);
                 }
             }
         }
 
-        // ---- writes
+        // ---- writes (a lane that flips ring entries does not claim in the same iteration)
         if (depart) st_store(&st[dep_node], dep_word);
         if (store) st_store(&st[store_node], store_word);
+        if constexpr (kRing) {
+            for (uint32_t d = 0; d < xor_cnt; ++d) {
+                const uint32_t v = lds_path[(xor_head - d) & (kPathBuf - 1)][lane];
+                __hip_atomic_fetch_xor(&st[v], xor_mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
         if (claim) {
             const uint64_t want = st_make_owned(st_next(w), st_cnt(w), tl);
             if (st_cas(&st[claim_node], w, want)) {
-                h = claim_node;   // a start claim begins a path at j == claim_node
+                if (mode == tStart) nbuf = 0;   // a start claim begins a new path at j
+                h = claim_node;
                 wh = want;
                 mode = tWalk;
+                push(claim_node);
             } else if (mode == tWalk) {
                 mode = tWait;     // lost the race: the winner owns the node now
                 y = claim_node;
@@ -471,8 +579,10 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     err_out = err;
 }
 
+template <bool kRing>
 __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t batch,
                                               int64_t sample_begin, int64_t l, uint64_t seed, uint32_t* lds_pred,
+                                              uint32_t (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
                                               uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
                                               uint32_t* __restrict__ status) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -483,7 +593,8 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
     const bool active = slot < G.T && rel < l;
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    grow_team(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_pred, steps, h, err);
+    grow_team<kRing>(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_pred,
+                     lds_path, lds_rec, steps, h, err);
     for (int off = W / 2; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off, kWave);
         h += __shfl_xor(h, off, kWave);
@@ -498,15 +609,18 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
 }
 
 // One wave per work item: 64 / W trees of one graph, W walkers each (W from the graph).
+template <bool kRing>
 __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
                                                      int32_t nitems, uint32_t* queue, int32_t batch,
                                                      int64_t sample_begin, int64_t l, uint64_t seed,
                                                      uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
     __shared__ uint32_t lds_pred[kWave];
+    __shared__ uint32_t lds_path[kRing ? kPathBuf : 1][kWave];
+    __shared__ uint4 lds_rec[4][kWave];
     if (queue == nullptr) {
         if (static_cast<int32_t>(blockIdx.x) < nitems)
-            run_team_item(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_pred, tree_hash, total_steps,
-                          status);
+            run_team_item<kRing>(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_pred, lds_path,
+                                 lds_rec, tree_hash, total_steps, status);
         return;
     }
     while (true) {
@@ -514,8 +628,21 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
         if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
         idx = __shfl(idx, 0, kWave);
         if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_team_item(graphs, items[idx], batch, sample_begin, l, seed, lds_pred, tree_hash, total_steps, status);
+        run_team_item<kRing>(graphs, items[idx], batch, sample_begin, l, seed, lds_pred, lds_path, lds_rec,
+                             tree_hash, total_steps, status);
     }
+}
+
+// Start positions for a team: spread when asked, shared when asked, otherwise spread for
+// graphs whose pivot eccentricity marks them as long-walk (mesh-like) graphs.  On such graphs
+// consecutive starts lie next to each other and a team's walkers keep blocking one another;
+// on small-world graphs consecutive starts keep the team inside a hot region of the graph.
+constexpr int32_t kLongWalkDepth = 32;
+
+bool spread_starts(const rwc_csr& g, uint32_t flags) {
+    if (flags & RWC_SAMPLE_SPREAD_STARTS) return true;
+    if (flags & RWC_SAMPLE_SHARED_STARTS) return false;
+    return g.bfs_depth > kLongWalkDepth;
 }
 
 using WalkKernel = void (*)(const GraphArgs*, const Item*, int32_t, uint32_t*, int32_t, int64_t, int64_t, uint64_t,
@@ -787,6 +914,10 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
     const int W = p->walkers_per_tree;
     if (W < 0 || W > kWave || (W & (W - 1)) != 0)
         return fail(RWC_ERR_INVALID_ARG, "walkers_per_tree must be 0 (automatic) or a power of two up to 64");
+    if ((p->flags & RWC_SAMPLE_SPREAD_STARTS) && (p->flags & RWC_SAMPLE_SHARED_STARTS))
+        return fail(RWC_ERR_INVALID_ARG, "spread and shared starts are exclusive");
+    if ((p->flags & RWC_SAMPLE_PATH_RING) && (p->flags & RWC_SAMPLE_NO_PATH_RING))
+        return fail(RWC_ERR_INVALID_ARG, "path ring and no path ring are exclusive");
     return RWC_OK;
 }
 
@@ -829,6 +960,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     const int64_t l = p->num_samples;
 
     std::vector<GraphArgs> hg(G);
+    bool any_spread = false;
     for (int32_t g = 0; g < G; ++g) {
         const uint64_t n = static_cast<uint64_t>(graphs[g].n);
         // default step guard: far above the expected walk length of any graph we accept,
@@ -850,8 +982,12 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         hg[g].graph_word = p->graph_index_base + static_cast<uint32_t>(g);
         hg[g].T = plan.T[g];
         hg[g].W = plan.W[g];
-        hg[g].pad = 0;
+        hg[g].spread = spread_starts(graphs[g], p->flags) ? 1 : 0;
+        any_spread = any_spread || (plan.W[g] > 1 && hg[g].spread);
     }
+    const bool ring = (p->flags & RWC_SAMPLE_PATH_RING) ? true
+                      : (p->flags & RWC_SAMPLE_NO_PATH_RING) ? false
+                                                              : any_spread;
     // Work items with the longest trees first: a tree's time grows with n / W.
     std::vector<int32_t> order(G);
     std::iota(order.begin(), order.end(), 0);
@@ -867,7 +1003,9 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     RWC_HIP(hipMemcpyAsync(L.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
 
     const bool persistent = (p->flags & RWC_SAMPLE_PERSISTENT) != 0;
-    const WalkKernel walk = plan.team ? static_cast<WalkKernel>(wilson_team) : static_cast<WalkKernel>(wilson_walk);
+    const WalkKernel walk = !plan.team ? static_cast<WalkKernel>(wilson_walk)
+                            : ring     ? static_cast<WalkKernel>(wilson_team<true>)
+                                       : static_cast<WalkKernel>(wilson_team<false>);
     int grid_persistent = 0;
     if (persistent) {
         int per_cu = 0;

@@ -72,3 +72,25 @@ def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_2510_20604_amd import _lib
     with pytest.raises(ImportError):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_flag_constants_match_the_header():
+    from paper_2510_20604_amd import _lib
+    txt = open(os.path.join(ROOT, "include", "rwc.h")).read()
+    defs = dict(re.findall(r"#define\s+(RWC_SAMPLE_\w+)\s+(\d+)u", txt))
+    assert len(defs) >= 8
+    for name, val in defs.items():
+        assert getattr(_lib, name) == int(val), name
+
+
+def test_exclusive_schedule_flags_are_rejected():
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8, rec=8, bfs_order=8)
+    size = ctypes.c_size_t()
+    for bad in (_lib.RWC_SAMPLE_SPREAD_STARTS | _lib.RWC_SAMPLE_SHARED_STARTS,
+                _lib.RWC_SAMPLE_PATH_RING | _lib.RWC_SAMPLE_NO_PATH_RING):
+        p = _lib.SampleParams(seed=1, num_samples=10, root=-1, flags=bad)
+        assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(size)) == -1
+    p = _lib.SampleParams(seed=1, num_samples=10, root=-1, flags=_lib.RWC_SAMPLE_SPREAD_STARTS | _lib.RWC_SAMPLE_PATH_RING)
+    assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(size)) == 0

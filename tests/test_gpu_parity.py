@@ -78,6 +78,7 @@ def test_csr_matches_oracle(name):
     A = sp.csr_matrix((np.ones(o.col.shape[0]), o.col, o.row_ptr), shape=(g.n, g.n))
     dist = csg.shortest_path(A, unweighted=True, indices=o.pivot)
     assert np.all(np.diff(dist[order]) >= 0)
+    assert Gd.csr.bfs_depth == int(dist.max())        # the pivot's eccentricity
     # edge_id maps every entry back to an input edge with matching endpoints
     eid = Gd.edge_id().cpu().numpy()
     rows = np.repeat(np.arange(g.n), np.diff(o.row_ptr))
@@ -167,11 +168,19 @@ def test_walker_teams_are_bit_exact(walkers, name, l, oracle_runs):
     assert int(_u64(s["total_steps"])[0]) == int(ref["steps"].sum())
 
 
-@pytest.mark.parametrize("walkers,tif,persistent", [(8, 16, True), (16, 4, False), (64, 3, True)])
-def test_walker_teams_launch_shapes(walkers, tif, persistent, oracle_runs):
-    g, o, ref = oracle_runs("ba3000_w", 200, 2001)
+@pytest.mark.parametrize("walkers,tif,persistent,bfs,starts,ring", [
+    (8, 16, True, False, "shared", False), (16, 4, False, True, "shared", None),
+    (64, 3, True, False, "spread", None), (4, 32, False, True, "spread", False),
+    (64, 200, False, False, "shared", True), (32, 7, True, True, "auto", True),
+    (2, 64, False, False, "spread", True), (64, 64, True, False, "auto", None)])
+@pytest.mark.parametrize("name", ["ba3000_w", "grid_w", "path"])
+def test_walker_teams_launch_shapes(walkers, tif, persistent, bfs, starts, ring, name, oracle_runs):
+    """Start order, start sharing, the LDS path ring and the launch shape only change the
+    schedule: the forest and the visit counts stay those of the serial order."""
+    g, o, ref = oracle_runs(name, 200, 2001)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=walkers, trees_in_flight=tif, persistent=persistent)
+    s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=walkers, trees_in_flight=tif, persistent=persistent,
+                         bfs_starts=bfs, starts=starts, path_ring=ring)
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
 
