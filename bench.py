@@ -24,6 +24,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rooted trees/s + walk steps/s at fixed RWC rel. error; plain vs batched; grad edges/s"
 HBM_PEAK_GBS = 8000.0
+# HBM byte counters of the walk kernel on the default workload, taken with rocprofv3 (FETCH_SIZE
+# and WRITE_SIZE runs, scaled by the same counters on a plain copy kernel); valid only for the
+# sampler sources they were taken on, which the file records by SHA-256.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_team_ba1m_traffic.json")
+SAMPLER_SOURCES = ("paper_2510_20604_amd/csrc/sampler.hip", "paper_2510_20604_amd/csrc/device.hpp")
+
+
+def sampler_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SAMPLER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, trees: int, trees_in_flight: int):
+    """HBM bytes per walk launch from the committed counter summary, or None when the summary
+    is missing or was taken on other sources, another kernel or another plan."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("sources_sha256") != sampler_sha256() or t.get("kernel") != kernel or t.get("trees") != trees
+            or t.get("trees_in_flight") != trees_in_flight):
+        return None
+    return t.get("traffic_bytes_per_launch")
 
 
 def parse():
@@ -226,9 +254,10 @@ def main():
     bytes_launch = walk_bytes(total_steps, l, g.n, False) / launches
     achieved = bytes_launch / (wms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": "wilson_walk", "avg_launch_ms": round(wms, 3),
-            "algorithmic_bytes_per_launch": bytes_launch}
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": measured_traffic(s["walk_kernel"], l, trees_in_flight),
+            "kernel": s["walk_kernel"], "avg_launch_ms": round(wms, 3),
+            "algorithmic_bytes_per_launch": bytes_launch, "traffic_unit": "HBM bytes per launch"}
 
     extra = {}
     if not args.no_probe:
@@ -282,7 +311,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m": g.m, "trees": l, "trees_in_flight": trees_in_flight,
-                   "walkers_per_tree": s["walkers_per_tree"], "walk_launches": launches, "launch": "plain"},
+                   "walkers_per_tree": s["walkers_per_tree"], "starts": s["starts"], "walk_launches": launches,
+                   "launch": "plain"},
         "walk_steps_per_s": round(args.steps * total_steps / elapsed, 1),
         "walk_steps_per_tree": total_steps / l,
         "sampler_trees_per_s": round(l / (np.mean(walk_ms) + np.mean(reduce_ms)) * 1e3, 3),

@@ -139,8 +139,10 @@ typedef struct rwc_sample_outputs {
     float* timing_ms;            /* HOST [2] or NULL: device time of the walk kernels and of
                                     the reduction kernels, summed over batches (hipEvents on
                                     `stream`; not available with RWC_SAMPLE_GRAPH_CAPTURE) */
-    int32_t* plan;               /* HOST [3] or NULL: walkers per tree, trees in flight per
-                                    graph and number of batches actually used             */
+    int32_t* plan;               /* HOST [5] or NULL, as used for graph 0: walkers per tree,
+                                    trees in flight, number of batches, walk kernel (0 one
+                                    walker per tree, 1 walker teams, 2 walker teams with the
+                                    LDS path ring), spread starts (0/1)                   */
 } rwc_sample_outputs;
 
 /* Workspace for rwc_sample_forests with these graphs and parameters. */

@@ -104,6 +104,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build the HIP library first "
                           "(python paper_2510_20604_amd/build.py)")
+    # PyTorch ships its own HIP runtime and loads it by path.  Importing torch first makes
+    # librwc.so bind to that same runtime (by soname); loaded the other way round, the process
+    # would hold two HIP runtimes and only one of them could open the GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)

@@ -166,12 +166,14 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     tms = (ctypes.c_float * 2)()
     if timing:
         out.timing_ms = ctypes.cast(tms, ctypes.c_void_p)
-    plan = (ctypes.c_int32 * 3)()
+    plan = (ctypes.c_int32 * 5)()
     out.plan = ctypes.cast(plan, ctypes.c_void_p)
     check(L.rwc_sample_forests(arr, G, ctypes.byref(p), ctypes.byref(out), _ptr(workspace), workspace.numel(),
                                _stream()), "rwc_sample_forests")
     res["workspace"] = workspace
     res["walkers_per_tree"], res["trees_in_flight"], res["batches"] = int(plan[0]), int(plan[1]), int(plan[2])
+    res["walk_kernel"] = ("wilson_walk", "wilson_team<false>", "wilson_team<true>")[int(plan[3])]
+    res["starts"] = "spread" if plan[4] else "shared"
     if timing:
         res["walk_ms"], res["reduce_ms"] = float(tms[0]), float(tms[1])
     return res

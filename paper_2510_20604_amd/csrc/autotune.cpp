@@ -35,25 +35,30 @@ ClassKey class_of(const rwc_csr* g, int64_t l) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// One walker per tree with every tree in flight, and teams of 8 to 64 walkers with one or two
+// device-fulls of resident waves or every tree in flight (the last avoids batch tails), all
+// capped by the state budget.
 std::vector<Candidate> candidates(const rwc_csr* g, int64_t l, int64_t budget_bytes) {
     std::vector<Candidate> out;
     const int64_t stride = round_up(g->n, 8);
     const int64_t cap = budget_bytes / (8 * stride);
-    const int widths[] = {1, 8, 16, 32, 64};
-    const int64_t walkers[] = {int64_t(1) << 16, int64_t(1) << 17, int64_t(1) << 18};
-    for (int W : widths) {
+    auto add = [&](int W, int64_t T) {
         const int64_t S = 64 / W;
-        for (int64_t K : walkers) {
-            int64_t T = (W == 1) ? l : K / W;
-            if (T > l) T = l;
-            T = round_up(T, S);
-            if (T > cap) T = cap / S * S;
-            if (T < S) continue;
-            bool dup = false;
-            for (const Candidate& c : out) dup = dup || (c.W == W && c.T == T);
-            if (!dup) out.push_back({W, T});
-            if (W == 1) break;
-        }
+        if (T > l) T = l;
+        T = round_up(T, S);
+        if (T > cap) T = cap / S * S;
+        if (T < S) return;
+        for (const Candidate& c : out)
+            if (c.W == W && c.T == T) return;
+        out.push_back({W, T});
+    };
+    add(1, l);
+    const int64_t resident = team_resident_waves(g->bfs_depth > 32);
+    for (int W : {8, 16, 32, 64}) {
+        const int64_t S = 64 / W;
+        add(W, resident * S);
+        add(W, 2 * resident * S);
+        add(W, l);
     }
     return out;
 }

@@ -95,39 +95,126 @@ __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restr
     }
 }
 
-// AP = L_v P (FP32 P promoted, FP64 sums); partial dots r.P and P.AP per column.
+// AP = L_v P (FP32 P promoted, FP64 sums); partial dots r.P and P.AP per column.  Block b
+// owns rows b, b + nb, b + 2 nb, ... (nb blocks), so the hub rows of a power-law graph, which
+// cluster at small ids, land in different blocks; each wave takes one row at a time and a lane
+// holds up to kColPass columns (lane + 64 j), so one pass over a row's entries serves up to
+// 256 columns.  Rows longer than kLongRow are skipped there and then taken, in order, by all
+// waves of the block, which split the entries and add their sums in LDS in wave order.  Row v
+// of P is zero, so its column entries need no test.
+constexpr int kColPass = 4;
+constexpr int kLongRow = 4 * kWave;
+
+// sum[j] += w_k * P[col_k, c_j] over entries k = beg, beg + step, ... < end, in that order,
+// with the loads of four entries issued before their products are added.
+__device__ __forceinline__ void gather_rows(int32_t beg, int32_t end, int32_t step, const int32_t* __restrict__ col,
+                                            const float* __restrict__ weight, const float* __restrict__ P32,
+                                            int32_t R, int32_t cbase, double* sum) {
+    int32_t k = beg;
+    for (; k + 3 * step < end; k += 4 * step) {
+        const int64_t w0 = col[k], w1 = col[k + step], w2 = col[k + 2 * step], w3 = col[k + 3 * step];
+        const double t0 = weight[k], t1 = weight[k + step], t2 = weight[k + 2 * step], t3 = weight[k + 3 * step];
+#pragma unroll
+        for (int j = 0; j < kColPass; ++j) {
+            const int32_t c = cbase + j * kWave;
+            if (c < R) {
+                const float a0 = P32[w0 * R + c], a1 = P32[w1 * R + c], a2 = P32[w2 * R + c], a3 = P32[w3 * R + c];
+                sum[j] += t0 * static_cast<double>(a0);
+                sum[j] += t1 * static_cast<double>(a1);
+                sum[j] += t2 * static_cast<double>(a2);
+                sum[j] += t3 * static_cast<double>(a3);
+            }
+        }
+    }
+    for (; k < end; k += step) {
+        const int64_t w0 = col[k];
+        const double t0 = weight[k];
+#pragma unroll
+        for (int j = 0; j < kColPass; ++j) {
+            const int32_t c = cbase + j * kWave;
+            if (c < R) sum[j] += t0 * static_cast<double>(P32[w0 * R + c]);
+        }
+    }
+}
+
 __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __restrict__ row_ptr,
                           const int32_t* __restrict__ col, const float* __restrict__ weight,
                           const double* __restrict__ d, const float* __restrict__ P32, const double* __restrict__ Rr,
                           double* __restrict__ AP, double* __restrict__ part) {
+    __shared__ double lds[kWavesPerBlock][kColPass * kWave];
+    __shared__ uint64_t long_mask[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-    for (int32_t c0 = 0; c0 < R; c0 += kWave) {
-        const int32_t c = c0 + lane;
-        double rp = 0.0, pap = 0.0;
-        for (int64_t u = wave; u < n; u += nw) {
-            if (c >= R) continue;
-            const int64_t i = u * R + c;
-            double y = 0.0;
-            const double pu = static_cast<double>(P32[i]);
-            if (u != v) {
-                double s = 0.0;
-                const int32_t end = row_ptr[u + 1];
-                for (int32_t k = row_ptr[u]; k < end; ++k) {
-                    const int32_t w = col[k];
-                    if (w == v) continue;
-                    s += static_cast<double>(weight[k]) * static_cast<double>(P32[static_cast<int64_t>(w) * R + c]);
-                }
-                y = d[u] * pu - s;
+    const int wib = threadIdx.x / kWave;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib;
+    const int64_t b = blockIdx.x, nb = gridDim.x;
+    for (int32_t c0 = 0; c0 < R; c0 += kColPass * kWave) {
+        double rp[kColPass], pap[kColPass];
+#pragma unroll
+        for (int j = 0; j < kColPass; ++j) rp[j] = pap[j] = 0.0;
+        // finishes row u from its neighbour sums (one lane, its columns)
+        auto finish = [&](int64_t u, const double* sum) {
+#pragma unroll
+            for (int j = 0; j < kColPass; ++j) {
+                const int32_t c = c0 + lane + j * kWave;
+                if (c >= R) continue;
+                const int64_t i = u * R + c;
+                const double pu = static_cast<double>(P32[i]);
+                const double y = (u == v) ? 0.0 : d[u] * pu - sum[j];
+                AP[i] = y;
+                rp[j] += Rr[i] * pu;
+                pap[j] += pu * y;
             }
-            AP[i] = y;
-            rp += Rr[i] * pu;
-            pap += pu * y;
+        };
+        for (int64_t u = b + wib * nb; u < n; u += kWavesPerBlock * nb) {
+            const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+            if (end - beg > kLongRow) continue;
+            double sum[kColPass];
+#pragma unroll
+            for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
+            gather_rows(beg, end, 1, col, weight, P32, R, c0 + lane, sum);
+            finish(u, sum);
         }
-        if (c < R) {
-            part[(wave * R + c) * 2] = rp;
-            part[(wave * R + c) * 2 + 1] = pap;
+        for (int64_t base = b; base < n; base += kBlock * nb) {
+            const int64_t u = base + threadIdx.x * nb;
+            const bool is_long = u < n && row_ptr[u + 1] - row_ptr[u] > kLongRow;
+            const uint64_t m = __ballot(is_long);
+            if (lane == 0) long_mask[wib] = m;
+            __syncthreads();
+            for (int wv = 0; wv < kWavesPerBlock; ++wv) {
+                uint64_t bits = long_mask[wv];
+                while (bits) {
+                    const int bit = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const int64_t r = base + (wv * kWave + bit) * nb;
+                    const int32_t beg = row_ptr[r], end = row_ptr[r + 1];
+                    double sum[kColPass];
+#pragma unroll
+                    for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
+                    gather_rows(beg + wib, end, kWavesPerBlock, col, weight, P32, R, c0 + lane, sum);
+#pragma unroll
+                    for (int j = 0; j < kColPass; ++j) lds[wib][lane + j * kWave] = sum[j];
+                    __syncthreads();
+                    if (wib == 0) {
+#pragma unroll
+                        for (int j = 0; j < kColPass; ++j) {
+                            double t = 0.0;
+                            for (int q = 0; q < kWavesPerBlock; ++q) t += lds[q][lane + j * kWave];
+                            sum[j] = t;
+                        }
+                        finish(r, sum);
+                    }
+                    __syncthreads();
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < kColPass; ++j) {
+            const int32_t c = c0 + lane + j * kWave;
+            if (c < R) {
+                part[(wave * R + c) * 2] = rp[j];
+                part[(wave * R + c) * 2 + 1] = pap[j];
+            }
         }
     }
 }
@@ -176,20 +263,37 @@ __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars
     }
 }
 
-// Per-column scalar steps; one thread per column sums the per-wave partials in order.
+// Per-column scalar steps; block c sums column c's per-wave partials (thread t takes waves
+// t, t + 256, ...; then a fixed tree over the threads).
 //   mode 0: after init (zr, rr0)   mode 1: after spmm (alpha)   mode 2: after update (beta)
 __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict__ part, ColScalars* sc, int mode,
                              double tol2) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= R) return;
+    __shared__ double la[kBlock], lb[kBlock], le[kBlock];
+    const int32_t c = blockIdx.x;
     const int stride = (mode == 2) ? 3 : 2;
     double a = 0.0, b = 0.0, e = 0.0;
-    for (int32_t w = 0; w < nwaves; ++w) {
+    for (int32_t w = threadIdx.x; w < nwaves; w += kBlock) {
         const double* q = part + (static_cast<int64_t>(w) * R + c) * stride;
         a += q[0];
         b += q[1];
         if (stride == 3) e += q[2];
     }
+    la[threadIdx.x] = a;
+    lb[threadIdx.x] = b;
+    le[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) {
+            la[threadIdx.x] += la[threadIdx.x + h];
+            lb[threadIdx.x] += lb[threadIdx.x + h];
+            le[threadIdx.x] += le[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    a = la[0];
+    b = lb[0];
+    e = le[0];
     ColScalars s = sc[c];
     if (mode == 0) {
         s.zr = a;
@@ -211,13 +315,26 @@ __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict
     sc[c] = s;
 }
 
-// Column sums (for centring), one thread per column over rows, fixed order.
-__global__ void column_sums(int32_t n, int32_t R, const double* __restrict__ M, double* __restrict__ out,
-                            double scale) {
+// Column sums (for centring) in two fixed-order stages: block b sums its contiguous range of
+// rows per column (threads over columns, so the reads are coalesced), then one thread per
+// column adds the block partials in block order.
+__global__ void column_partials(int32_t n, int32_t R, int32_t rows_per_block, const double* __restrict__ M,
+                                double* __restrict__ part) {
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+    const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
+    for (int32_t c = threadIdx.x; c < R; c += blockDim.x) {
+        double s = 0.0;
+        for (int64_t u = lo; u < hi; ++u) s += M[u * R + c];
+        part[static_cast<int64_t>(blockIdx.x) * R + c] = s;
+    }
+}
+
+__global__ void column_finish(int32_t R, int32_t nparts, const double* __restrict__ part, double* __restrict__ out,
+                              double scale) {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= R) return;
     double s = 0.0;
-    for (int64_t u = 0; u < n; ++u) s += M[u * R + c];
+    for (int32_t b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * R + c];
     out[c] = s * scale;
 }
 
@@ -234,54 +351,74 @@ struct EdgeScalars {
 };
 
 // trGL^ = sum_i c_i y_i^T L^+ y_i over the probe entries; dLd = d^T B.
-__global__ void edge_scalars(int32_t n, int32_t R, int32_t count, const Entry* __restrict__ e,
-                             const double* __restrict__ coef, const double* __restrict__ Z, const double* __restrict__ d,
+// d^T B over row ranges (column 1 of Z), one partial per block.
+__global__ void dld_partials(int32_t n, int32_t R, int32_t rows_per_block, const double* __restrict__ Z,
+                             const double* __restrict__ d, double* __restrict__ part) {
+    __shared__ double lds[kBlock];
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+    const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
+    double q = 0.0;
+    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) q += d[u] * Z[u * R + 1];
+    lds[threadIdx.x] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kBlock; ++i) s += lds[i];
+        part[blockIdx.x] = s;
+    }
+}
+
+// trGL from the probe entries and dLd from the block partials (one block, fixed order).
+__global__ void edge_scalars(int32_t R, int32_t count, const Entry* __restrict__ e, const double* __restrict__ coef,
+                             const double* __restrict__ Z, int32_t nparts, const double* __restrict__ part,
                              EdgeScalars* out) {
     __shared__ double lds[kBlock];
-    double t = 0.0, q = 0.0;
+    double t = 0.0;
     for (int32_t i = threadIdx.x; i < count; i += blockDim.x)
         if (e[i].col >= 2) t += coef[e[i].col] * e[i].val * Z[static_cast<int64_t>(e[i].node) * R + e[i].col];
-    for (int64_t u = threadIdx.x; u < n; u += blockDim.x) q += d[u] * Z[u * R + 1];
     lds[threadIdx.x] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int i = 0; i < kBlock; ++i) s += lds[i];
         out->trgl = s;
-    }
-    __syncthreads();
-    lds[threadIdx.x] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < kBlock; ++i) s += lds[i];
-        out->dld = s;
+        double q = 0.0;
+        for (int32_t b = 0; b < nparts; ++b) q += part[b];
+        out->dld = q;
     }
 }
 
-// One thread per CSR row; every entry (u, w) with u < w is one undirected edge.
-__global__ void edge_gradient(int32_t n, int32_t R, const int32_t* __restrict__ row_ptr,
+// One thread per CSR entry (u, w) with u < w, i.e. per undirected edge; the row u of entry
+// k is found by binary search, so hub rows spread over the whole grid.
+__global__ void edge_gradient(int32_t n, int64_t nnz, int32_t R, const int32_t* __restrict__ row_ptr,
                               const int32_t* __restrict__ col, const int32_t* __restrict__ edge_id,
                               const double* __restrict__ Z, const double* __restrict__ coef,
                               const EdgeScalars* __restrict__ es, double G, double vol, double* __restrict__ grad) {
     const double trgl = es->trgl, dld = es->dld;
-    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
-         u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const double* za = Z + u * R;
-        for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
-            const int64_t w = col[k];
-            if (w < u) continue;
-            const double* zb = Z + w * R;
-            const double dA = za[0] - zb[0], sA = za[0] + zb[0];
-            const double dB = za[1] - zb[1], sB = za[1] + zb[1];
-            double q = 0.0;
-            for (int32_t c = 2; c < R; ++c) {
-                const double t = za[c] - zb[c];
-                q += coef[c] * (t * t);
-            }
-            const double term_g = (2.0 * sB - dB * dB) / vol - (2.0 * dld) / (vol * vol);
-            grad[edge_id[k]] = ((2.0 * trgl - vol * q) + (2.0 * dA * dB - 2.0 * sA)) + G * term_g;
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < nnz;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t w = col[k];
+        int32_t lo = 0, hi = n - 1;     // largest u with row_ptr[u] <= k
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (row_ptr[mid] <= k)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
+        const int64_t u = lo;
+        if (w < u) continue;
+        const double* za = Z + u * R;
+        const double* zb = Z + w * R;
+        const double dA = za[0] - zb[0], sA = za[0] + zb[0];
+        const double dB = za[1] - zb[1], sB = za[1] + zb[1];
+        double q = 0.0;
+        for (int32_t c = 2; c < R; ++c) {
+            const double t = za[c] - zb[c];
+            q += coef[c] * (t * t);
+        }
+        const double term_g = (2.0 * sB - dB * dB) / vol - (2.0 * dld) / (vol * vol);
+        grad[edge_id[k]] = ((2.0 * trgl - vol * q) + (2.0 * dA * dB - 2.0 * sA)) + G * term_g;
     }
 }
 
@@ -424,11 +561,12 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
     const unsigned wave_blocks = static_cast<unsigned>((nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
     nwaves = static_cast<int64_t>(wave_blocks) * kWavesPerBlock;
     const int32_t nw = static_cast<int32_t>(nwaves);
+    const int32_t rows_per_block = static_cast<int32_t>((static_cast<int64_t>(n) + wave_blocks - 1) / wave_blocks);
     const unsigned col_blocks = blocks_for(R, 64);
     const double tol2 = tol * tol;
     hipLaunchKernelGGL(bpcg_init, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
                        L.part);
-    hipLaunchKernelGGL(bpcg_scalars, dim3(col_blocks), dim3(64), 0, s, R, nw, L.part, L.sc, 0, tol2);
+    hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 0, tol2);
     RWC_HIP(hipGetLastError());
     std::vector<ColScalars> host(R);
     int it = 0;
@@ -438,10 +576,10 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
         for (int c = 0; c < chunk; ++c) {
             hipLaunchKernelGGL(bpcg_spmm, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->row_ptr, g->col,
                                g->weight, g->strength, L.P32, L.Y, L.AP, L.part);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(col_blocks), dim3(64), 0, s, R, nw, L.part, L.sc, 1, tol2);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 1, tol2);
             hipLaunchKernelGGL(bpcg_update, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
                                L.Y, L.P32, L.AP, L.part);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(col_blocks), dim3(64), 0, s, R, nw, L.part, L.sc, 2, tol2);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 2, tol2);
             hipLaunchKernelGGL(bpcg_direction, dim3(flat), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y, L.P32);
         }
         RWC_HIP(hipGetLastError());
@@ -459,13 +597,18 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
         return fail(RWC_ERR_NOT_CONVERGED, "adjoint solves: worst relative residual %.3e after %d iterations", worst, it);
     }
     // L^+ y = z - mean(z)
-    hipLaunchKernelGGL(column_sums, dim3(col_blocks), dim3(64), 0, s, n, R, L.X, L.colmean, 1.0 / n);
+    // (the partial arrays reuse the PCG partials: kMaxWaves * R * 3 doubles >= wave_blocks * R)
+    hipLaunchKernelGGL(column_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.X, L.part);
+    hipLaunchKernelGGL(column_finish, dim3(col_blocks), dim3(64), 0, s, R, static_cast<int32_t>(wave_blocks), L.part,
+                       L.colmean, 1.0 / n);
     hipLaunchKernelGGL(center_columns, dim3(flat), dim3(kBlock), 0, s, n, R, L.colmean, L.X);
-    hipLaunchKernelGGL(edge_scalars, dim3(1), dim3(kBlock), 0, s, n, R, nent, L.entries, L.coef, L.X, g->strength,
-                       L.es);
-    hipLaunchKernelGGL(edge_gradient, dim3(blocks_for(n, kBlock) < 8192 ? blocks_for(n, kBlock) : 8192),
-                       dim3(kBlock), 0, s, n, R, g->row_ptr, g->col, g->edge_id, L.X, L.coef, L.es, pr.G, g->vol,
-                       grad_w);
+    hipLaunchKernelGGL(dld_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.X, g->strength,
+                       L.part);
+    hipLaunchKernelGGL(edge_scalars, dim3(1), dim3(kBlock), 0, s, R, nent, L.entries, L.coef, L.X,
+                       static_cast<int32_t>(wave_blocks), L.part, L.es);
+    const unsigned edge_blocks = blocks_for(g->nnz, kBlock) < 16384 ? blocks_for(g->nnz, kBlock) : 16384;
+    hipLaunchKernelGGL(edge_gradient, dim3(edge_blocks), dim3(kBlock), 0, s, n, g->nnz, R, g->row_ptr, g->col,
+                       g->edge_id, L.X, L.coef, L.es, pr.G, g->vol, grad_w);
     RWC_HIP(hipGetLastError());
     RWC_HIP(hipStreamSynchronize(s));
     return RWC_OK;

@@ -22,7 +22,12 @@ int fail(int status, const char* fmt, ...) {
     return status;
 }
 
-void clear_error() { g_last_error.clear(); }
+void clear_error() {
+    g_last_error.clear();
+    // drop an error state left by earlier HIP calls of other code in this thread, so that the
+    // launch checks of this call report only its own failures
+    (void)hipGetLastError();
+}
 
 int device_error_to_status(uint32_t bits) {
     if (bits == 0) return RWC_OK;

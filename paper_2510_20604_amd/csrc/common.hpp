@@ -84,5 +84,8 @@ int device_error_to_status(uint32_t bits);
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
+// Waves of the walker-team kernel (with or without the LDS path ring) resident on the whole
+// device at once (occupancy x compute units); defined with the kernels.
+int team_resident_waves(bool ring);
 
 }  // namespace rwc

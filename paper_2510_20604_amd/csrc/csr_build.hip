@@ -365,13 +365,17 @@ __global__ void bfs_init(int32_t n, int32_t pivot, int32_t* __restrict__ dist, i
     }
 }
 
+// One wave per frontier node, lanes over its neighbours (hub rows do not serialise a lane).
 __global__ void bfs_level(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t lo,
                           int32_t hi, int32_t level, int32_t* __restrict__ dist, int32_t* __restrict__ order,
                           uint32_t* __restrict__ tail) {
-    for (int64_t i = lo + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < hi;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+    for (int64_t i = lo + wave; i < hi; i += nw) {
         const int32_t u = order[i];
-        for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+        const int32_t end = row_ptr[u + 1];
+        for (int32_t k = row_ptr[u] + lane; k < end; k += kWave) {
             const int32_t w = col[k];
             if (dist[w] == -1 && atomicCAS(&dist[w], -1, level + 1) == -1) order[atomicAdd(tail, 1u)] = w;
         }
@@ -594,9 +598,8 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     uint32_t lo = 0, hi = 1;
     int32_t depth = 0;
     for (int32_t level = 0; hi < static_cast<uint32_t>(n); ++level) {
-        const int64_t width = hi - lo;
-        hipLaunchKernelGGL(bfs_level, dim3(blocks_for(width, kBlock) < gs ? blocks_for(width, kBlock) : gs),
-                           dim3(kBlock), 0, s, L.row_ptr, L.col, static_cast<int32_t>(lo), static_cast<int32_t>(hi),
+        const unsigned wb = blocks_for(static_cast<int64_t>(hi - lo) * kWave, kBlock);
+        hipLaunchKernelGGL(bfs_level, dim3(wb < gs ? wb : gs), dim3(kBlock), 0, s, L.row_ptr, L.col, static_cast<int32_t>(lo), static_cast<int32_t>(hi),
                            level, L.parent, L.bfs_order, L.tail);
         RWC_HIP(hipGetLastError());
         uint32_t t = 0;

@@ -66,24 +66,29 @@ __global__ void pcg_init(int32_t n, int32_t v, const double* __restrict__ d, dou
     }
 }
 
-// y = L_v p on the grounded system (row and column v removed, p_v kept at zero).  Eight
-// lanes share a row (strided over its entries, then a shuffle reduction), so hub rows of
-// power-law graphs are split and short rows still read their entries contiguously.
+// y = L_v p on the grounded system (row and column v removed, p_v kept at zero).  Block b owns
+// rows b, b + nb, b + 2 nb, ... (nb blocks), so hub rows, which cluster at small ids in
+// power-law graphs, land in different blocks.  Eight lanes share a short row (strided over its
+// entries, then a shuffle reduction); rows longer than kLongRow are left out of that pass and
+// then taken one at a time, in order, by the whole block.
 constexpr int kRowLanes = 8;
+constexpr int kLongRow = 16 * kRowLanes;
 
 __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                          const float* __restrict__ weight, const double* __restrict__ d, const double* __restrict__ p,
                          double* __restrict__ ap, double* __restrict__ part) {
     __shared__ double lds[kBlock / kWave];
+    __shared__ uint64_t long_mask[kBlock / kWave];
     const int sub = threadIdx.x & (kRowLanes - 1);
-    const int64_t group = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kRowLanes;
-    const int64_t ngroups = static_cast<int64_t>(gridDim.x) * blockDim.x / kRowLanes;
+    const int group = threadIdx.x / kRowLanes;
+    constexpr int kGroups = kBlock / kRowLanes;
+    const int64_t b = blockIdx.x, nb = gridDim.x;
     double acc = 0.0;
-    for (int64_t u = group; u < n; u += ngroups) {
+    for (int64_t u = b + group * nb; u < n; u += kGroups * nb) {
+        const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+        if (end - beg > kLongRow) continue;
         double s = 0.0;
-        const int32_t end = row_ptr[u + 1];
-        for (int32_t k = row_ptr[u] + sub; k < end; k += kRowLanes)
-            s += static_cast<double>(weight[k]) * p[col[k]];
+        for (int32_t k = beg + sub; k < end; k += kRowLanes) s += static_cast<double>(weight[k]) * p[col[k]];
 #pragma unroll
         for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
         if (sub == 0) {
@@ -91,6 +96,32 @@ __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_p
             ap[u] = y;
             acc += p[u] * y;
         }
+    }
+    for (int64_t base = b; base < n; base += kBlock * nb) {
+        const int64_t u = base + threadIdx.x * nb;
+        const bool is_long = u < n && row_ptr[u + 1] - row_ptr[u] > kLongRow;
+        const uint64_t m = __ballot(is_long);
+        if ((threadIdx.x & (kWave - 1)) == 0) long_mask[threadIdx.x / kWave] = m;
+        __syncthreads();
+        for (int wv = 0; wv < kBlock / kWave; ++wv) {
+            uint64_t bits = long_mask[wv];
+            while (bits) {
+                const int bit = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                const int64_t r = base + (wv * kWave + bit) * nb;
+                const int32_t beg = row_ptr[r], end = row_ptr[r + 1];
+                double s = 0.0;
+                for (int32_t k = beg + static_cast<int32_t>(threadIdx.x); k < end; k += kBlock)
+                    s += static_cast<double>(weight[k]) * p[col[k]];
+                s = block_sum(s, lds);
+                if (threadIdx.x == 0) {
+                    const double y = (r == v) ? 0.0 : d[r] * p[r] - s;
+                    ap[r] = y;
+                    acc += p[r] * y;
+                }
+            }
+        }
+        __syncthreads();
     }
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) part[2 * blockIdx.x] = acc;

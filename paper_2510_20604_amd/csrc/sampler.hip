@@ -633,6 +633,18 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
     }
 }
 
+}  // namespace
+
+int team_resident_waves(bool ring) {
+    int per_cu = 0;
+    const hipError_t e = ring ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_team<true>, kWave, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_team<false>, kWave, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * device_cu_count();
+}
+
+namespace {
+
 // Start positions for a team: spread when asked, shared when asked, otherwise spread for
 // graphs whose pivot eccentricity marks them as long-walk (mesh-like) graphs.  On such graphs
 // consecutive starts lie next to each other and a team's walkers keep blocking one another;
@@ -692,11 +704,12 @@ __global__ void zero_outputs(uint64_t* counts, uint64_t* counts_sq, int64_t tota
 __global__ void reset_queue(uint32_t* queue) { *queue = 0; }
 
 // Folds the departure counts of batch `batch` into the per-node totals, writes the parent
-// dumps of this batch and resets the slots.  Thread per node, loop over slots: the reads and
+// dumps of this batch and, unless it is the last batch, resets the slots for the next one.  Thread per node, loop over slots: the reads and
 // writes of consecutive threads are consecutive words of one slot.
 __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t* __restrict__ node_off, int32_t G,
-                             int64_t total_nodes, int32_t batch, int64_t l, uint64_t* __restrict__ counts,
-                             uint64_t* __restrict__ counts_sq, int32_t* __restrict__ parents, DumpArgs dumps) {
+                             int64_t total_nodes, int32_t batch, int64_t l, bool reset,
+                             uint64_t* __restrict__ counts, uint64_t* __restrict__ counts_sq,
+                             int32_t* __restrict__ parents, DumpArgs dumps) {
     for (int64_t gx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; gx < total_nodes;
          gx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int32_t g = graph_of(node_off, G, gx);
@@ -721,14 +734,14 @@ __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t
                 const uint32_t c = st_cnt(w[q]);
                 c1 += c;
                 c2 += square_count(c);
-                A.state[static_cast<int64_t>(t + q) * A.stride + x] = fresh;
+                if (reset) A.state[static_cast<int64_t>(t + q) * A.stride + x] = fresh;
             }
         }
         for (; t < used; ++t) {
             const uint32_t c = st_cnt(A.state[static_cast<int64_t>(t) * A.stride + x]);
             c1 += c;
             c2 += square_count(c);
-            A.state[static_cast<int64_t>(t) * A.stride + x] = fresh;
+            if (reset) A.state[static_cast<int64_t>(t) * A.stride + x] = fresh;
         }
         if (counts) counts[gx] += c1;
         if (counts_sq) counts_sq[gx] += c2;
@@ -746,13 +759,12 @@ struct Plan {
 };
 
 constexpr int64_t kDefaultStateBudget = 96ll << 30;  // bytes of slot state chosen automatically
-constexpr int64_t kTargetWalkers = 1 << 17;          // concurrent walkers aimed at
+constexpr int64_t kTargetWalkers = 1 << 17;          // one walker per tree from this many trees on
 
-// Walkers per tree when the caller leaves it open.  Throughput is set by the number of
-// concurrent walkers and by the state footprint they touch (measured on BA(10^6): 64 walkers x
-// 2048 trees beats 16 walkers x 10^4 trees), so a single large graph gets full-wave teams and
-// few trees in flight.  In a batch every tree is in flight and a graph's team width grows with
-// its size, which bounds the longest tree's walk time.
+// Walkers per tree when the caller leaves it open.  A single large graph gets full-wave teams
+// (on BA(10^6), 10^4 trees: 64 walkers beat 32, and one batch of all trees beats batches of
+// 2048 to 5120 by 4 to 14%, since every batch ends in a tail of slow trees).  In a batch a
+// graph's team width grows with its size, which bounds the longest tree's walk time.
 int auto_walkers(int64_t n, int32_t G, int64_t l) {
     int W = 1;
     if (G == 1) {
@@ -787,9 +799,7 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
         const int S = kWave / W;
         int64_t T = p->trees_in_flight;
         if (T <= 0) {
-            int64_t want = l;
-            if (G == 1 && W > 1) want = kTargetWalkers / W < l ? kTargetWalkers / W : l;
-            T = round_up(want, S);
+            T = round_up(l, S);     // all trees at once; the state budget below may cut it
         }
         if (T > (1 << 30)) return fail(RWC_ERR_TOO_LARGE, "trees_in_flight too large");
         plan->W[g] = W;
@@ -1052,7 +1062,8 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
             }
             if (out->timing_ms) RWC_HIP(hipEventRecord(timer.ev[1], ls));
             hipLaunchKernelGGL(reduce_batch, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G,
-                               plan.total_nodes, b, l, out->counts, out->counts_sq, out->parents, dumps);
+                               plan.total_nodes, b, l, b + 1 < plan.batches, out->counts, out->counts_sq,
+                               out->parents, dumps);
             if (out->timing_ms) {
                 RWC_HIP(hipEventRecord(timer.ev[2], ls));
                 RWC_HIP(hipEventSynchronize(timer.ev[2]));
@@ -1086,6 +1097,8 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         out->plan[0] = plan.W[0];
         out->plan[1] = plan.T[0];
         out->plan[2] = plan.batches;
+        out->plan[3] = !plan.team ? 0 : (ring ? 2 : 1);
+        out->plan[4] = hg[0].spread;
     }
     return device_error_to_status(status);
 }

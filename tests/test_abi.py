@@ -94,3 +94,17 @@ def test_exclusive_schedule_flags_are_rejected():
         assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(size)) == -1
     p = _lib.SampleParams(seed=1, num_samples=10, root=-1, flags=_lib.RWC_SAMPLE_SPREAD_STARTS | _lib.RWC_SAMPLE_PATH_RING)
     assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(size)) == 0
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Importing the package (without importing torch first) must leave one HIP runtime in the
+    process: a second copy could not open the GPU that torch's copy holds."""
+    import subprocess
+    import sys
+    code = ("import paper_2510_20604_amd\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -39,7 +39,7 @@ def test_ba1m_bench_configuration_sampled_trees():
     Gd = P.Graph(g.n, g.src, g.dst)
     dump = [0, 9_999]
     s = P.sample_forests(Gd, l, seed, dump=dump)
-    assert s["walkers_per_tree"] > 1 and s["batches"] > 1     # the bench's team plan
+    assert s["walkers_per_tree"] == 64 and s["trees_in_flight"] == l     # the bench's team plan
     _check_sampled_trees(g, s, l, seed, [0, 1, 2047, 2048, 5001, 9_999], dump)
 
 
