@@ -142,7 +142,7 @@ typedef struct rwc_sample_outputs {
     int32_t* plan;               /* HOST [5] or NULL, as used for graph 0: walkers per tree,
                                     trees in flight, number of batches, walk kernel (0 one
                                     walker per tree, 1 walker teams, 2 walker teams with the
-                                    LDS path ring), spread starts (0/1)                   */
+                                    LDS path ring), team starts (0 shared, 1 spread)      */
 } rwc_sample_outputs;
 
 /* Workspace for rwc_sample_forests with these graphs and parameters. */

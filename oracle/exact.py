@@ -89,6 +89,28 @@ def rwc_laplacian_pinv(n: int, src, dst, w=None) -> np.ndarray:
     return vol * np.diag(Lp) - 2.0 * Ld + (d @ Ld) / vol
 
 
+def rwc_laplacian_pinv_cholesky(n: int, src, dst, w=None) -> np.ndarray:
+    """The same formula as rwc_laplacian_pinv for larger n (tens of thousands of nodes):
+    M = L + J/n is symmetric positive definite, so with M = C C^T (Cholesky) the diagonal of
+    M^{-1} is the column sums of squares of C^{-1}, and L^+ = M^{-1} - J/n gives
+    L^+_uu = (M^{-1})_uu - 1/n and L^+ d = M^{-1} d - (sum d / n) 1."""
+    import scipy.linalg as sla
+    A = adjacency(n, src, dst, w)
+    d = A.sum(axis=1)
+    vol = d.sum()
+    M = laplacian(A)
+    del A
+    M += 1.0 / n
+    C = sla.cholesky(M, lower=True, overwrite_a=True, check_finite=False)
+    Ci, info = sla.lapack.dtrtri(C, lower=1, overwrite_c=1)
+    if info != 0:
+        raise np.linalg.LinAlgError(f"dtrtri failed ({info})")
+    diag = np.einsum("ij,ij->j", Ci, Ci) - 1.0 / n
+    Md = Ci.T @ (Ci @ d)
+    Ld = Md - vol / n
+    return vol * diag - 2.0 * Ld + (d @ Ld) / vol
+
+
 def kemeny_from_spectrum(n: int, src, dst, w=None) -> float:
     """Trace of calL^+ = sum over the non-zero eigenvalues of calL of 1 / lambda."""
     A = adjacency(n, src, dst, w)

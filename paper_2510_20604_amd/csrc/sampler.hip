@@ -81,7 +81,8 @@ __device__ __forceinline__ uint32_t rec_weighted_slot(const uint4& c, const uint
 
 // Grows the tree of slot `slot` for absolute sample `sample` (one lane).
 __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint64_t sample, uint64_t seed,
-                                          uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
+                                          bool want_hash, uint64_t& steps_out, uint64_t& hash_out,
+                                          uint32_t& err_out) {
     const uint64_t max_steps = G.guard;
     const int32_t n = G.n;
     const auto row_ptr = global_ptr(G.row_ptr);
@@ -174,7 +175,7 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
                 const uint64_t w = st[x];
                 const uint32_t p = st_next(w);
                 st[x] = w | kInTree;
-                h += splitmix64((static_cast<uint64_t>(x) << 32) | p);
+                if (want_hash) h += splitmix64((static_cast<uint64_t>(x) << 32) | p);
                 x = p;
                 if (++retr > static_cast<uint32_t>(n)) {
                     err |= kErrRetrace;
@@ -200,7 +201,7 @@ __device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, c
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
     const bool active = slot < G.T && rel < l;
-    if (active) grow_tree(G, slot, static_cast<uint64_t>(sample_begin + rel), seed, steps, h, err);
+    if (active) grow_tree(G, slot, static_cast<uint64_t>(sample_begin + rel), seed, tree_hash != nullptr, steps, h, err);
     if (active) {
         if (tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + rel] = h;
         if (err) atomicOr(status, err);
@@ -269,8 +270,9 @@ __device__ __forceinline__ bool st_cas(RWC_GLOBAL uint64_t* p, uint64_t expected
 template <bool kRing>
 __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
                           uint32_t* lds_pred, uint32_t (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
-                          uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
+                          bool want_hash, uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
     constexpr uint32_t kNone = 64;
+    constexpr uint32_t kNoNode = 0xFFFFFFFFu;
     const int W = G.W;                       // walkers per tree, a power of two <= 64
     const uint64_t max_iters = G.guard;
     const int lane = threadIdx.x & (kWave - 1);
@@ -278,7 +280,6 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     const uint32_t tl = static_cast<uint32_t>(lane & (W - 1));
     const uint32_t team_base = static_cast<uint32_t>(team * W);
     const uint32_t n = static_cast<uint32_t>(G.n);
-    const auto row_ptr = global_ptr(G.row_ptr);
     const auto col = global_ptr(G.col);
     const auto cdf = global_ptr(G.cdf);
     const auto rec = global_ptr(G.rec);
@@ -288,7 +289,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     // fresh head needs no dependent load for low-degree rows.  It is copied straight from
     // memory into LDS (lane's column of lds_rec) without passing through registers; reads of
     // it wait for the copy with wait_vm().
-    uint32_t rh_node = 0xFFFFFFFFu;
+    uint32_t rh_node = kNoNode;
     auto keep_record = [&](uint32_t v) {
         const auto q = rec + 4 * static_cast<int64_t>(v);
 #pragma unroll
@@ -308,12 +309,15 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     const uint32_t chunk = (n + static_cast<uint32_t>(W) - 1) / static_cast<uint32_t>(W);
     uint32_t my_next = tl * chunk;
     int mode = active ? tIdle : tDone;
-    uint32_t j = 0, h = 0, y = 0, c = 0, cend = 0, jn = 0;
-    uint64_t wh = 0, jw = 0;
+    uint32_t j = 0;       // start of the current path
+    uint32_t h = 0;       // head of the current path
+    uint32_t hk = 0;      // departures from the head so far (its next arrow's index)
+    uint32_t c = 0;       // node waited on (tWait) or chase cursor (tRetrace, tRelease)
+    uint32_t cstop = 0;   // retrace: stop once the next node is cstop; release: stop after cstop
+    uint32_t jn = 0, jk = 0;   // release: the node that becomes the head afterwards, its count
     // ring of the newest nodes of this walker's path in LDS: entry 0 is the head and the
     // entries form a contiguous suffix of the path ending at it (nbuf >= 1 while walking)
     uint32_t nbuf = 0, bhead = 0;
-    uint32_t cstop = 0;                  // a retrace chase stops before this (buffered) node
     auto buf = [&](uint32_t d) -> uint32_t { return lds_path[(bhead - d) & (kPathBuf - 1)][lane]; };
     auto push = [&](uint32_t v) {
         if constexpr (kRing) {
@@ -332,7 +336,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     uint64_t steps = 0, hsum = 0, iters = 0;
     uint32_t err = 0;
     while (true) {
-        // ---- hand out start nodes, ascending, to idle walkers of each team
+        // ---- hand out start nodes to idle walkers of each team
         const bool idle = (mode == tIdle);
         const uint64_t bi = __ballot(idle);
         // idle walkers of my team (bit t = team lane t)
@@ -358,33 +362,30 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             break;
         }
 
-        // ---- reads
+        // ---- reads: the node this walker looks at in this iteration and its state word
+        // (one load for all lanes, issued after the walk's neighbour choice)
         uint32_t node = 0;
-        uint32_t ny = 0;
         uint32_t k = 0;
         if (mode == tWalk) {
             if (rh_node != h) keep_record(h);
             wait_vm();
-            k = st_cnt(wh);
+            k = hk;
             const uint2 db = *reinterpret_cast<const uint2*>(&lds_rec[0][lane]);
             const uint32_t deg = db.x;
             const int32_t beg = static_cast<int32_t>(db.y);
             const uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
             if (cdf == nullptr) {
                 const int32_t pick = select_unweighted(r, static_cast<int32_t>(deg));
-                ny = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_at(2u + static_cast<uint32_t>(pick))
-                                                                 : static_cast<uint32_t>(col[beg + pick]);
+                node = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_at(2u + static_cast<uint32_t>(pick))
+                                                                   : static_cast<uint32_t>(col[beg + pick]);
             } else if (deg <= static_cast<uint32_t>(kRecInlineWeighted)) {
-                ny = rec_at(2u + rec_weighted_slot(lds_rec[2][lane], lds_rec[3][lane], r, deg));
+                node = rec_at(2u + rec_weighted_slot(lds_rec[2][lane], lds_rec[3][lane], r, deg));
             } else {
-                ny = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
+                node = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
             }
-            node = ny;
         } else if (mode == tStart) {
             node = j;
-        } else if (mode == tWait) {
-            node = y;
-        } else if (mode == tRetrace || mode == tRelease) {
+        } else if (mode == tWait || mode == tRetrace || mode == tRelease) {
             node = c;
         }
         const bool reads = (mode != tDone) && (mode != tIdle);
@@ -394,92 +395,53 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         const bool w_owned = (w & kOwned) != 0;
         const bool w_mine = w_owned && st_owner(w) == tl;
 
-        // ---- decide
-        bool claim = false, depart = false, store = false, waiting = false;
-        uint64_t dep_word = 0, store_word = 0;
-        uint32_t dep_node = 0, claim_node = 0, store_node = 0;
-        uint32_t xor_cnt = 0, xor_head = 0;   // atomically flip the xor_cnt newest path entries
-        uint64_t xor_mask = 0;
-        // attach the path (its head points at the tree node `hit`): the buffered suffix flips
-        // to INTREE in this iteration, an older prefix is chased from the start afterwards
-        auto attach = [&](uint32_t hit) {
-            if (kRing && nbuf > 0) {
-                xor_cnt = nbuf;
-                xor_head = bhead;
-                xor_mask = kOwned | kInTree | (static_cast<uint64_t>(tl) << 56);
-                for (uint32_t d = 0; d < nbuf; ++d)
-                    hsum += splitmix64((static_cast<uint64_t>(buf(d)) << 32) | (d == 0 ? hit : buf(d - 1)));
-                const uint32_t oldest = buf(nbuf - 1);
-                if (oldest == j) {
-                    mode = tIdle;
-                } else {
-                    mode = tRetrace;
-                    c = j;
-                    cstop = oldest;
-                }
-            } else {
-                // chase the whole path; only the head points at the tree node
-                mode = tRetrace;
-                c = j;
-                cstop = hit;
-            }
-        };
-        // pop the path back to node v (v on the path, older than the head): release what is
-        // newer than v, from the ring if v is buffered, else by chasing from v's successor
-        auto pop_to = [&](uint32_t v, uint64_t vw) {
-            const uint32_t d = find(v);
-            if (d > 0) {
-                xor_cnt = d;
-                xor_head = bhead;
-                xor_mask = kOwned | (static_cast<uint64_t>(tl) << 56);
-                bhead = (bhead - d) & (kPathBuf - 1);
-                nbuf -= d;
-                mode = tWalk;
-                h = v;
-                wh = vw;
-            } else {
-                mode = tRelease;
-                c = st_next(vw);
-                cend = h;
-                jn = v;
-                jw = vw;
-                nbuf = 0;
-            }
-        };
+        // ---- decide.  Writes of this iteration: the departure word of the head, issued as
+        // soon as it is known (no lane reads state words again before the iteration's fence,
+        // and issuing it early lets it drain while the rest of the iteration runs; measured
+        // faster than issuing it with the other writes), or one chase store; then either a
+        // batch of atomic flips of ring entries or one compare-and-swap claim of `node`.
+        bool departed = false;
+        uint32_t st_node = kNoNode;
+        uint64_t st_word = 0;
+        bool claim = false, waiting = false;
+        constexpr int kActNone = 0, kActAttach = 1, kActPop = 2;
+        int act = kActNone;
+        uint32_t act_v = 0, act_k = 0, act_next = 0;   // attach: tree node hit; pop: kept node
         if (mode == tWalk) {
-            depart = true;
-            dep_node = h;
-            dep_word = st_make_owned(ny, k + 1, tl);
+            // departure from the head along arrow k
+            st_store(&st[h], st_make_owned(node, k + 1, tl));
+            departed = true;
             ++steps;
             if (k + 1 >= kCntMax) {
                 err |= kErrCountOverflow;
                 mode = tDone;
             } else if (w_tree) {
-                attach(ny);
+                act = kActAttach;
+                act_v = node;
             } else if (w_mine) {
-                // own cycle ny -> ... -> h -> ny: release the segment after ny; ny is the head
-                pop_to(ny, w);
+                // own cycle node -> ... -> h -> node: keep node as the head, release the rest
+                act = kActPop;
+                act_v = node;
+                act_k = st_cnt(w);
+                act_next = st_next(w);
             } else if (w_owned) {
                 mode = tWait;
-                y = ny;
+                c = node;
                 waiting = true;
             } else {
                 claim = true;
-                claim_node = ny;
             }
         } else if (mode == tStart) {
-            if (w_tree) {
+            if (w_tree)
                 mode = tIdle;
-            } else if (!w_owned) {
+            else if (!w_owned)
                 claim = true;
-                claim_node = j;
-            }
         } else if (mode == tWait) {
             if (w_tree) {
-                attach(y);
+                act = kActAttach;
+                act_v = c;
             } else if (!w_owned) {
                 claim = true;
-                claim_node = y;
             } else if (w_mine) {
                 err |= kErrProtocol;
                 mode = tDone;
@@ -491,23 +453,22 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 err |= kErrProtocol;
                 mode = tDone;
             } else if (mode == tRetrace) {
-                // chase of the path prefix older than the ring
-                store = true;
-                store_node = c;
-                store_word = (w & ~(kOwned | (0x3Full << 56))) | kInTree;
-                hsum += splitmix64((static_cast<uint64_t>(c) << 32) | st_next(w));
+                // chase of the path prefix older than the ring: mark it INTREE
+                st_node = c;
+                st_word = (w & ~(kOwned | (0x3Full << 56))) | kInTree;
+                if (want_hash) hsum += splitmix64((static_cast<uint64_t>(c) << 32) | st_next(w));
                 if (st_next(w) == cstop)
                     mode = tIdle;
                 else
                     c = st_next(w);
             } else {
-                store = true;
-                store_node = c;
-                store_word = st_make(0u, st_cnt(w));
-                if (c == cend) {
+                // chase release of a popped segment: FREE, departure count kept
+                st_node = c;
+                st_word = st_make(0u, st_cnt(w));
+                if (c == cstop) {
                     mode = tWalk;
                     h = jn;
-                    wh = jw;
+                    hk = jk;
                     push(jn);
                 } else {
                     c = st_next(w);
@@ -517,8 +478,9 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
 
         // ---- pop cycles of waiting walkers (team-local functional graph, pointer doubling:
         // after 64 applications every chain has either left the waiting set or entered a
-        // cycle, so the image of the 64-fold map is exactly the set of cycle members)
-        if (__any(waiting)) {
+        // cycle, so the image of the 64-fold map is exactly the set of cycle members).  A
+        // cycle stays until it is popped, so looking every fourth iteration only delays pops.
+        if ((iters & 3u) == 0 && __any(waiting)) {
             const uint32_t wf = waiting ? team_base + (st_owner(w) & (W - 1)) : kNone;
             uint32_t p = wf;
 #pragma unroll
@@ -534,42 +496,88 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             if (on_cycle) lds_pred[wf] = static_cast<uint32_t>(lane);
             __syncthreads();
             const uint32_t pred = on_cycle ? lds_pred[lane] : static_cast<uint32_t>(lane);
-            const uint32_t py = __shfl(y, static_cast<int>(pred), kWave);
+            const uint32_t py = __shfl(c, static_cast<int>(pred), kWave);
             const uint64_t pw = __shfl(w, static_cast<int>(pred), kWave);
             __syncthreads();
             if (on_cycle) {
                 // the cycle enters my path at py: the arrows from py on are popped
                 if (py == h) {
-                    // my head's own arrow is popped; if I departed in this iteration the
-                    // snapshot the predecessor read predates my departure word
+                    // only my head's arrow is popped; if I departed in this iteration the
+                    // snapshot the predecessor read predates my departure
                     mode = tWalk;
-                    wh = depart ? dep_word : pw;
+                    hk = departed ? k + 1 : st_cnt(pw);
                 } else {
-                    pop_to(py, pw);
+                    act = kActPop;
+                    act_v = py;
+                    act_k = st_cnt(pw);
+                    act_next = st_next(pw);
                 }
             }
         }
 
+        // ---- the two path actions
+        uint32_t xor_cnt = 0, xor_head = 0;   // atomically flip the xor_cnt newest ring entries
+        uint64_t xor_mask = 0;
+        if (act == kActAttach) {
+            // the path attaches at tree node act_v: the buffered suffix flips to INTREE now,
+            // an older prefix is chased from the start afterwards
+            mode = tRetrace;
+            c = j;
+            cstop = act_v;   // without a ring: the chase runs up to the head
+            if (kRing && nbuf > 0) {
+                xor_cnt = nbuf;
+                xor_head = bhead;
+                xor_mask = kOwned | kInTree | (static_cast<uint64_t>(tl) << 56);
+                if (want_hash)
+                    for (uint32_t d = 0; d < nbuf; ++d)
+                        hsum += splitmix64((static_cast<uint64_t>(buf(d)) << 32) | (d == 0 ? act_v : buf(d - 1)));
+                cstop = buf(nbuf - 1);
+                if (cstop == j) mode = tIdle;
+            }
+        } else if (act == kActPop) {
+            // keep act_v (on the path, older than the head) as the head and release what is
+            // newer: from the ring if act_v is buffered, else by a chase from its successor
+            const uint32_t d = find(act_v);
+            mode = tWalk;
+            if (d > 0) {
+                xor_cnt = d;
+                xor_head = bhead;
+                xor_mask = kOwned | (static_cast<uint64_t>(tl) << 56);
+                bhead = (bhead - d) & (kPathBuf - 1);
+                nbuf -= d;
+                h = act_v;
+                hk = act_k;
+            } else {
+                mode = tRelease;
+                c = act_next;
+                cstop = h;
+                jn = act_v;
+                jk = act_k;
+                nbuf = 0;
+            }
+        }
+
         // ---- writes (a lane that flips ring entries does not claim in the same iteration)
-        if (depart) st_store(&st[dep_node], dep_word);
-        if (store) st_store(&st[store_node], store_word);
+        if (st_node != kNoNode) st_store(&st[st_node], st_word);
         if constexpr (kRing) {
             for (uint32_t d = 0; d < xor_cnt; ++d) {
                 const uint32_t v = lds_path[(xor_head - d) & (kPathBuf - 1)][lane];
                 __hip_atomic_fetch_xor(&st[v], xor_mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
+        // keep the chase store ahead of the claim, so that both are in flight together
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (claim) {
             const uint64_t want = st_make_owned(st_next(w), st_cnt(w), tl);
-            if (st_cas(&st[claim_node], w, want)) {
+            if (st_cas(&st[node], w, want)) {
                 if (mode == tStart) nbuf = 0;   // a start claim begins a new path at j
-                h = claim_node;
-                wh = want;
+                h = node;
+                hk = st_cnt(w);
                 mode = tWalk;
-                push(claim_node);
+                push(node);
             } else if (mode == tWalk) {
                 mode = tWait;     // lost the race: the winner owns the node now
-                y = claim_node;
+                c = node;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -594,7 +602,7 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
     grow_team<kRing>(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_pred,
-                     lds_path, lds_rec, steps, h, err);
+                     lds_path, lds_rec, tree_hash != nullptr, steps, h, err);
     for (int off = W / 2; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off, kWave);
         h += __shfl_xor(h, off, kWave);
@@ -645,10 +653,10 @@ int team_resident_waves(bool ring) {
 
 namespace {
 
-// Start positions for a team: spread when asked, shared when asked, otherwise spread for
-// graphs whose pivot eccentricity marks them as long-walk (mesh-like) graphs.  On such graphs
-// consecutive starts lie next to each other and a team's walkers keep blocking one another;
-// on small-world graphs consecutive starts keep the team inside a hot region of the graph.
+// Start positions for a team: spread or shared as asked, otherwise spread for graphs whose
+// pivot eccentricity marks them as long-walk (mesh-like) graphs.  On such graphs consecutive starts lie next to
+// each other and a team's walkers keep blocking one another; on small-world graphs
+// consecutive starts keep the team inside a hot region of the graph.
 constexpr int32_t kLongWalkDepth = 32;
 
 bool spread_starts(const rwc_csr& g, uint32_t flags) {

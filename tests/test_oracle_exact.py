@@ -32,6 +32,9 @@ def test_three_characterisations_agree(g):
     h_pinv = E.rwc_laplacian_pinv(g.n, g.src, g.dst, g.w)
     np.testing.assert_allclose(h_eq2, h_def, rtol=1e-11)
     np.testing.assert_allclose(h_pinv, h_def, rtol=1e-11)
+    # the Cholesky route used for the larger exact checks
+    h_chol = E.rwc_laplacian_pinv_cholesky(g.n, g.src, g.dst, g.w)
+    np.testing.assert_allclose(h_chol, h_def, rtol=1e-10)
 
 
 def _closed_forms():
@@ -161,3 +164,26 @@ def test_error_measures():
     assert E.mean_relative_error(x, x * 1.1) == pytest.approx(0.1)
     assert E.kendall_tau_a(x, x) == 1.0
     assert E.kendall_tau_a(x, -x) == -1.0
+
+
+def test_ba20k_fixture_matches_the_hitting_time_definition():
+    """The stored exact RWC of BA(20 000, 5) (dense Cholesky route) against the definition
+    H_u = sum_i pi_i H_iu, each H_.u from one sparse grounded solve (L_u h = d_{-u})."""
+    import scipy.sparse.linalg as spla
+    rows = []
+    with open(os.path.join(GOLDEN, "ba20k_exact_rwc.txt")) as f:
+        for line in f:
+            if not line.startswith("#"):
+                u, val = line.split("|")
+                rows.append((int(u), float(val)))
+    assert len(rows) >= 2000
+    g = G.barabasi_albert(20_000, 5, 1002)
+    L, d = E._sparse_laplacian(g.n, g.src, g.dst, g.w)
+    for u, val in [rows[0], rows[len(rows) // 2], rows[-1]]:
+        keep = np.ones(g.n, dtype=bool)
+        keep[u] = False
+        Lu = L[keep][:, keep].tocsr()
+        h, info = spla.cg(Lu, d[keep], rtol=1e-14, atol=0.0, maxiter=5000,
+                          M=spla.LinearOperator(Lu.shape, matvec=lambda x: x / d[keep]))
+        assert info == 0
+        assert abs(d[keep] @ h / d.sum() - val) <= 1e-9 * val
