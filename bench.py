@@ -40,8 +40,8 @@ def sampler_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, trees: int, trees_in_flight: int):
-    """HBM bytes per walk launch from the committed counter summary, or None when the summary
+def measured_counters(kernel: str, trees: int, trees_in_flight: int):
+    """The committed counter summary of the walk launch (HBM bytes, L2 misses), or None when it
     is missing or was taken on other sources, another kernel or another plan."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -51,7 +51,7 @@ def measured_traffic(kernel: str, trees: int, trees_in_flight: int):
     if (t.get("sources_sha256") != sampler_sha256() or t.get("kernel") != kernel or t.get("trees") != trees
             or t.get("trees_in_flight") != trees_in_flight):
         return None
-    return t.get("traffic_bytes_per_launch")
+    return t
 
 
 def parse():
@@ -253,9 +253,10 @@ def main():
     wms = float(np.mean(walk_ms)) / launches
     bytes_launch = walk_bytes(total_steps, l, g.n, False) / launches
     achieved = bytes_launch / (wms * 1e-3) / 1e9
+    counters = measured_counters(s["walk_kernel"], l, trees_in_flight)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": measured_traffic(s["walk_kernel"], l, trees_in_flight),
+            "traffic": counters["traffic_bytes_per_launch"] if counters else None,
             "kernel": s["walk_kernel"], "avg_launch_ms": round(wms, 3),
             "algorithmic_bytes_per_launch": bytes_launch, "traffic_unit": "HBM bytes per launch"}
 
@@ -275,11 +276,17 @@ def main():
                                                    seed_probe, ctypes.c_void_p(sink.data_ptr()),
                                                    ctypes.byref(ms), stream), "rwc_probe_random_gather")
         peak_acc = lanes * chain / (ms.value * 1e-3)
-        acc = walk_accesses(total_steps, l, g.n) / launches / (wms * 1e-3)
-        extra["gather_roofline"] = {"probe": f"dependent random 8-byte gathers, {lanes} chains x {chain}, "
-                                             f"footprint {wsp.numel() / 2**30:.1f} GiB",
-                                    "peak_accesses_per_s": peak_acc, "walk_accesses_per_s": acc,
-                                    "frac": round(acc / peak_acc, 4)}
+        gr = {"probe": f"dependent random 8-byte gathers, {lanes} chains x {chain}, "
+                       f"footprint {wsp.numel() / 2**30:.1f} GiB", "peak_accesses_per_s": peak_acc,
+              "walk_algorithmic_accesses_per_s": walk_accesses(total_steps, l, g.n) / launches / (wms * 1e-3)}
+        if counters:
+            # every L2 miss of the walk is one random line access to the fabric, the quantity the
+            # probe saturates (its own accesses all miss)
+            miss = counters["tcc_miss_per_dispatch"] / (wms * 1e-3)
+            gr.update({"walk_l2_misses_per_s": miss, "frac": round(miss / peak_acc, 4)})
+        else:
+            gr["frac"] = None
+        extra["gather_roofline"] = gr
 
     if args.copy_probe:
         import ctypes
