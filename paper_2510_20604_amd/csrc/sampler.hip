@@ -769,19 +769,15 @@ struct Plan {
 constexpr int64_t kDefaultStateBudget = 96ll << 30;  // bytes of slot state chosen automatically
 constexpr int64_t kTargetWalkers = 1 << 17;          // one walker per tree from this many trees on
 
-// Walkers per tree when the caller leaves it open.  A single large graph gets full-wave teams
-// (on BA(10^6), 10^4 trees: 64 walkers beat 32, and one batch of all trees beats batches of
-// 2048 to 5120 by 4 to 14%, since every batch ends in a tail of slow trees).  In a batch a
-// graph's team width grows with its size, which bounds the longest tree's walk time.
+// Walkers per tree when the caller leaves it open.  Full-wave teams, narrowed only for tiny
+// graphs (at least 16 nodes per walker): on BA(10^6), 10^4 trees, 64 walkers beat 32, and on
+// the 256-graph batch (BA and meshes, 10^3..10^5 nodes) 64 walkers for every graph beat widths
+// growing with n by 3-5%.  A single graph whose trees are too many (>= 2^17) or too small
+// (n * l <= 2^22 node-trees) for teams to matter gets one walker per tree.
 int auto_walkers(int64_t n, int32_t G, int64_t l) {
-    int W = 1;
-    if (G == 1) {
-        if (l >= kTargetWalkers || n * l <= (int64_t(1) << 22)) return 1;
-        W = 64;
-        while (W > 2 && W * 16 > n) W >>= 1;
-        return W;
-    }
-    while (W < 64 && static_cast<int64_t>(W) * 2 * 4096 <= n) W <<= 1;
+    if (G == 1 && (l >= kTargetWalkers || n * l <= (int64_t(1) << 22))) return 1;
+    int W = 64;
+    while (W > 2 && W * 16 > n) W >>= 1;
     return W;
 }
 

@@ -213,11 +213,17 @@ def test_batched_graphs_match_per_graph_oracle():
     for i, gd in enumerate(dev[:2]):
         p = P.sample_forests(gd, l, seed, graph_index_base=base + i)
         np.testing.assert_array_equal(_u64(p["tree_hash"][0]), _u64(s["tree_hash"][i]))
+    # and so does the batch with one walker per tree (the single-lane kernel, persistent)
+    s1 = P.sample_forests(dev, l, seed, persistent=True, graph_index_base=base, walkers_per_tree=1)
+    assert s1["walk_kernel"] == "wilson_walk"
+    np.testing.assert_array_equal(_u64(s1["counts"]), counts)
+    np.testing.assert_array_equal(_u64(s1["tree_hash"]), _u64(s["tree_hash"]))
 
 
 def test_batched_mixed_team_widths_match_oracle():
-    """A batch whose graphs get different walkers per tree (1, 2 and 4 by size) in one
-    persistent launch reproduces each graph's serial forest."""
+    """A batch whose graphs get different walkers per tree (16, 32 and 64 by size) and different
+    start modes (shared for BA, spread for the meshes) in one persistent launch reproduces each
+    graph's serial forest."""
     gs = [G.barabasi_albert(300, 3, 51), G.grid_with_deletions(9000, 0.1, 52), G.barabasi_albert(20000, 3, 53),
           G.grid_with_deletions(600, 0.1, 54)]
     gs = [g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 60 + i)) for i, g in enumerate(gs)]
