@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000", "batch256", "grad100k"])
+    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000", "batch256", "grad100k", "rmat23"])
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
     ap.add_argument("--walkers", type=int, default=0, help="walkers per tree (0 = automatic)")
     ap.add_argument("--tif", type=int, default=0, help="trees in flight (0 = automatic)")
@@ -198,20 +198,90 @@ def grad_main(args):
     print(json.dumps(line), flush=True)
 
 
+def rmat_main(args):
+    """Scale: R-MAT scale 23 (a, b, c) = (.57, .19, .19), 5 edge draws per node, largest
+    component, w ~ U[1, 4]; one step = CSR build + 5000 trees in a persistent launch + pivot
+    solve and assembly + the adjoint of the RWC sum over 1000 targets (k = 64)."""
+    import torch
+    import paper_2510_20604_amd as P
+    import rwcgen
+    t0 = time.perf_counter()
+    g = rwcgen.rmat_lcc(23, 5, 0.57, 0.19, 0.19, 1005)
+    g = g.with_weights(rwcgen.uniform_weights(g.m, 1.0, 4.0, 1006))
+    print(f"generated R-MAT LCC n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    l, seed = args.trees or 5000, 2005
+    targets = np.random.default_rng(7).choice(g.n, size=1000, replace=False).astype(np.int32)
+    gv = np.ones(1000)
+    dev = torch.device("cuda:0")
+    src, dst = torch.as_tensor(g.src).to(dev), torch.as_tensor(g.dst).to(dev)
+    w = torch.as_tensor(g.w).to(dev)
+    ws = {"sample": None}
+
+    def step():
+        G = P.Graph(g.n, src, dst, w, dev)
+        s = P.sample_forests(G, l, seed, persistent=True, want_sq=True, want_hash=False, workspace=ws["sample"],
+                             timing=True)
+        ws["sample"] = s["workspace"]
+        e = P.estimate(G, s["counts"], l, counts_sq=s["counts_sq"], want_stderr=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        r = P.backward(G, targets, gv, k=64, seed=2006, tol=1e-8)
+        torch.cuda.synchronize()
+        return G, s, e, r, time.perf_counter() - tb
+
+    for _ in range(args.warmup):
+        step()
+        print("warmup step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walk_ms, back_s = [], []
+    for _ in range(args.steps):
+        G, s, e, r, tb = step()
+        walk_ms.append(s["walk_ms"])
+        back_s.append(tb)
+        print("timed step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    total_steps = int(P.as_uint64(s["total_steps"])[0])
+    wms = float(np.mean(walk_ms)) / s["batches"]
+    bytes_launch = walk_bytes(total_steps, l, g.n, True) / s["batches"]
+    achieved = bytes_launch / (wms * 1e-3) / 1e9
+    rel_se = (e["stderr"] / e["rwc"]).double()
+    line = {
+        "metric": METRIC, "value": round(l / elapsed, 3), "unit": "trees/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64/f64", "data": "synthetic",
+        "config": {"workload": "R-MAT scale 23 (.57, .19, .19), 5n draws, LCC, w ~ U[1, 4]; 5000 trees persistent "
+                               "+ adjoint for 1000 targets, k = 64", "n": g.n, "m": g.m, "trees": l,
+                   "walkers_per_tree": s["walkers_per_tree"], "trees_in_flight": s["trees_in_flight"],
+                   "walk_launches": s["batches"], "starts": s["starts"], "launch": "persistent"},
+        "walk_steps_per_s": round(total_steps / elapsed, 1),
+        "walk_steps_per_tree": total_steps / l,
+        "sampler_trees_per_s": round(l / (np.mean(walk_ms) * 1e-3), 3),
+        "grad_edges_per_s": round(g.m / float(np.mean(back_s)), 1), "backward_ms": round(1e3 * float(np.mean(back_s)), 3),
+        "pcg_iters": e["iters"], "adjoint_iters": r["iters"],
+        "rwc_rel_stderr_mean": float(rel_se.mean()),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": s["walk_kernel"],
+                     "avg_launch_ms": round(wms, 3), "algorithmic_bytes_per_launch": bytes_launch,
+                     "traffic_unit": "HBM bytes per launch"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
-    if args.config == "grad100k":
-        return grad_main(args)
-    if args.config == "batch256":
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return batch_main(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler shards by "
               "sample range with one all-reduce of the visit totals, which this build does not run.",
               file=sys.stderr)
         sys.exit(2)
+    if args.config == "grad100k":
+        return grad_main(args)
+    if args.config == "rmat23":
+        return rmat_main(args)
+    if args.config == "batch256":
+        return batch_main(args)
     import torch
     import paper_2510_20604_amd as P
     from paper_2510_20604_amd import _lib

@@ -115,7 +115,9 @@ typedef struct rwc_sample_params {
     int64_t num_samples;         /* trees per graph (l in Algorithm 3)                    */
     int32_t root;                /* -1: each graph's pivot; otherwise the root (1 graph)   */
     uint32_t flags;              /* RWC_SAMPLE_*                                          */
-    int32_t trees_in_flight;     /* trees resident at once per graph; 0 = automatic       */
+    int32_t trees_in_flight;     /* trees resident at once per graph; 0 = automatic: all
+                                    trees, scaled down to fit 8 B x n per tree of every
+                                    graph into half of the device's memory                */
     int32_t walkers_per_tree;    /* 0 = automatic; 1 = one walker per tree                */
     uint64_t max_steps_per_tree; /* guard; 0 = 2^20 + 4096 n                              */
     uint32_t graph_index_base;   /* Philox graph word of graphs[0]; graph g uses base + g */

@@ -766,7 +766,18 @@ struct Plan {
     bool team = false;                // some graph uses more than one walker per tree
 };
 
-constexpr int64_t kDefaultStateBudget = 96ll << 30;  // bytes of slot state chosen automatically
+// Bytes of tree state the automatic plan may use: half of the device's memory (144 GB of the
+// 288 GB of an MI355X), so that every tree of BA(10^6) x 10^4 (80 GB) or of R-MAT scale 23 x
+// 5000 (133 GB) is in flight at once.  Total, not free, memory keeps the plan identical between
+// the workspace query and the call that uses the workspace.
+int64_t default_state_budget() {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || total_b == 0) {
+        (void)hipGetLastError();
+        return 96ll << 30;
+    }
+    return static_cast<int64_t>(total_b / 2);
+}
 constexpr int64_t kTargetWalkers = 1 << 17;          // one walker per tree from this many trees on
 
 // Walkers per tree when the caller leaves it open.  Full-wave teams, narrowed only for tiny
@@ -813,9 +824,10 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
         plan->team = plan->team || W > 1;
         state_words += T * plan->stride[g];
     }
-    if (p->trees_in_flight <= 0 && state_words * 8 > kDefaultStateBudget) {
+    const int64_t budget = (p->trees_in_flight <= 0) ? default_state_budget() : 0;
+    if (p->trees_in_flight <= 0 && state_words * 8 > budget) {
         // shrink every graph's slots by the same factor to fit the automatic budget
-        const double f = static_cast<double>(kDefaultStateBudget) / (8.0 * static_cast<double>(state_words));
+        const double f = static_cast<double>(budget) / (8.0 * static_cast<double>(state_words));
         for (int32_t g = 0; g < G; ++g) {
             int64_t T = static_cast<int64_t>(plan->T[g] * f) / plan->S[g] * plan->S[g];
             plan->T[g] = static_cast<int32_t>(T < plan->S[g] ? plan->S[g] : T);

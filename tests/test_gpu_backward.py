@@ -93,3 +93,49 @@ def test_ba100k_sampled_edges_match_sparse_oracle(k):
     want = GR.grad_at_edges_sparse(g.n, g.src, g.dst, g.w, t, gv, edges, cols)
     _close(got[edges], want, 1e-6)
     assert abs(np.dot(g.w, got)) <= 1e-7 * np.abs(g.w * got).sum()
+
+
+def test_ba2000_gradient_against_central_differences_on_50_edges():
+    """BA(2000, 4), w ~ U[0.5, 2], loss = sum of RWC over 100 targets: the GPU adjoint (exact
+    probe mode) against central differences of the exact FP64 loss on 50 random edges, step
+    h = 1e-4 w_e.  The perturbed losses are exact: w_e -> w_e + h changes L by h b b^T, so
+    (L + J/n)^{-1} changes by the Sherman-Morrison rank-one term (checked against a full dense
+    re-evaluation on two edges); the degrees of e's endpoints and vol change by h and 2h.  The
+    quotient's truncation error is O(h^2), its rounding error ~1e-16 * loss / h."""
+    from oracle import exact as E
+    g = _graph(2000, 4, 91)
+    t, gv = _targets(g.n, 100, 92)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    got = P.backward(Gd, t, gv, k=0, tol=1e-12)["grad_w"].cpu().numpy()
+
+    w0 = g.w.astype(np.float64)
+    n = g.n
+    A = E.adjacency(n, g.src, g.dst, w0)
+    d0 = A.sum(axis=1)
+    Minv = np.linalg.inv(E.laplacian(A) + 1.0 / n)       # (L + J/n)^{-1}
+
+    def loss_perturbed(e, h):
+        a, b = int(g.src[e]), int(g.dst[e])
+        u = Minv[:, a] - Minv[:, b]                        # M^{-1} b_e
+        c = h / (1.0 + h * (u[a] - u[b]))
+        d = d0.copy()
+        d[a] += h
+        d[b] += h
+        vol = d.sum()
+        diag_t = np.diag(Minv)[t] - c * u[t] ** 2 - 1.0 / n
+        Ld = Minv @ d - c * u * (u @ d) - vol / n           # L'^+ d with L'^+ = M'^{-1} - J/n
+        return float(np.dot(gv, vol * diag_t - 2.0 * Ld[t] + (d @ Ld) / vol))
+
+    def loss_dense(w):
+        return float(np.dot(gv, E.rwc_laplacian_pinv(n, g.src, g.dst, w)[t]))
+
+    edges = np.random.default_rng(93).choice(g.m, size=50, replace=False)
+    for e in edges[:2]:
+        w1 = w0.copy()
+        w1[e] += 1e-4 * w0[e]
+        assert abs(loss_perturbed(e, 1e-4 * w0[e]) - loss_dense(w1)) <= 1e-11 * abs(loss_dense(w1))
+    fd = []
+    for e in edges:
+        h = 1e-4 * w0[e]
+        fd.append((loss_perturbed(e, h) - loss_perturbed(e, -h)) / (2.0 * h))
+    _close(got[edges], np.array(fd), 1e-6)
