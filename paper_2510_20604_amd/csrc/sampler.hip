@@ -388,9 +388,14 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         } else if (mode == tWait || mode == tRetrace || mode == tRelease) {
             node = c;
         }
-        const bool reads = (mode != tDone) && (mode != tIdle);
+        // a waiting walker re-reads its target every other iteration (cycle checks, every
+        // fourth iteration, always see fresh words)
+        const bool reads = (mode != tDone) && (mode != tIdle) && (mode != tWait || (iters & 1u) == 0);
         const uint64_t w = reads ? st_load(&st[node]) : 0ull;
-        if (mode == tWalk || mode == tStart || mode == tWait) keep_record(node);   // may become the head
+        // the next node of a walk may become the head: fetch its record with the state word.
+        // Starts and waited-on nodes fetch theirs only when they are claimed (below): most
+        // start checks find the node in the tree and most polls find it still owned.
+        if (mode == tWalk) keep_record(node);
         const bool w_tree = (w & kInTree) != 0;
         const bool w_owned = (w & kOwned) != 0;
         const bool w_mine = w_owned && st_owner(w) == tl;
@@ -436,6 +441,8 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 mode = tIdle;
             else if (!w_owned)
                 claim = true;
+        } else if (mode == tWait && !reads) {
+            // nothing read this iteration
         } else if (mode == tWait) {
             if (w_tree) {
                 act = kActAttach;
@@ -568,6 +575,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         // keep the chase store ahead of the claim, so that both are in flight together
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (claim) {
+            keep_record(node);
             const uint64_t want = st_make_owned(st_next(w), st_cnt(w), tl);
             if (st_cas(&st[node], w, want)) {
                 if (mode == tStart) nbuf = 0;   // a start claim begins a new path at j
