@@ -273,7 +273,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler shards by "
-              "sample range with one all-reduce of the visit totals, which this build does not run.",
+              "sample range with one all-reduce of the visit totals, which is not implemented here.",
               file=sys.stderr)
         sys.exit(2)
     if args.config == "grad100k":

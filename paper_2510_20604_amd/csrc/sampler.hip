@@ -7,10 +7,12 @@
 // reduction pass folds the per-tree departure counts into the per-node totals, writes the
 // requested parent dumps and resets the slots for the next batch.
 //
-// One lane grows one tree.  The lane runs Algorithm 3's three loops -- pick the next start
-// node that is not yet in the tree, walk until the tree is hit, retrace the loop-erased path
-// -- as one flat state machine, so every iteration of the wave does one step of some lane's
-// work instead of parking lanes that finished a phase early.
+// Two kernels.  wilson_walk: one lane grows one tree, running Algorithm 3's three loops --
+// pick the next start node that is not yet in the tree, walk until the tree is hit, retrace
+// the loop-erased path -- as one flat state machine, so every iteration of the wave does one
+// step of some lane's work instead of parking lanes that finished a phase early.
+// wilson_team: W lanes of one wave grow one tree together (below); used for large graphs,
+// whose per-tree state limits how many trees can be in flight.
 //
 // RandomNeighbor(u) at the k-th departure from u in sample i of graph word g is
 // Philox4x32-10((k, u, i, g), seed).  A node's successive choices are therefore fixed in
@@ -241,14 +243,17 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
 // counts as Algorithm 3's serial order.  A team runs W such walks at once:
 //  * a walker owns the nodes of its current (loop-erased) path: state word OWNED + its team
 //    lane id; its head's arrow is read at each step (departure count incremented);
-//  * arrow into the tree       -> the path attaches (retrace from its start marking INTREE);
+//  * arrow into the tree       -> the path attaches (its nodes are marked INTREE: the newest
+//                                 ones from the LDS ring at once, older ones by a chase from
+//                                 the path's start);
 //  * arrow into its own path   -> a cycle of its own arrows: the segment after the hit node is
 //                                 released (FREE, counts kept) and the hit node is the head;
 //  * arrow into a free node    -> claim it (compare-and-swap; the loser waits on the winner);
 //  * arrow into another walker's path -> wait.  Waiting walkers whose targets form a cycle of
 //    walkers hold a genuine arrow cycle: it is popped by every member releasing the segment
 //    after its junction (the node its cycle predecessor points at), which becomes its head.
-// Start nodes are handed out in ascending order; a start owned by another walker is waited
+// Start nodes are handed out shared (a team takes consecutive positions of the start order)
+// or spread (each walker its own contiguous range); a start owned by another walker is waited
 // on until it is in the tree (skip) or free (claim).  Every iteration reads before it writes
 // and ends with a work-group fence, so all lanes see one consistent snapshot per iteration.
 // ---------------------------------------------------------------------------------------

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped, not failed, where no GPU is visible (they still run with -m gpu
-    # on a GPU machine).
+    # on a machine with one).
     try:
         import torch
         have_gpu = torch.cuda.is_available()
