@@ -64,9 +64,11 @@ typedef struct rwc_csr {
     uint64_t* cdf;         /* [nnz] inclusive prefix sums within each row of the integer
                               weights W_e = w_e * 2^24 (NULL for unweighted graphs)         */
     double* strength;      /* [n] weighted degree d_u                                       */
-    uint32_t* rec;         /* [16 n] 64-byte node records: degree, row offset, then the first
-                              14 neighbour ids (unweighted) or the first 4 ids in words 2..5
-                              and their CDF values in words 8..15 (weighted)               */
+    uint32_t* rec;         /* [16 n] 64-byte node records: word 0 the degree, word 1 the row
+                              offset; unweighted rows: the first 14 neighbour ids in words
+                              2..15; weighted rows: the first 4 ids in words 2..5, the row's
+                              total (last CDF value) in words 6..7 and the first 4 CDF values
+                              in words 8..15; unused words are zero                         */
     int32_t* bfs_order;    /* [n] nodes in breadth-first order from the pivot: the order in
                               which walker teams take start nodes                          */
     int32_t bfs_depth;     /* largest hop distance from the pivot (its eccentricity)       */

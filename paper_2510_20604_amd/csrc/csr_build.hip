@@ -308,31 +308,42 @@ __global__ void row_pass(int32_t n, const int32_t* __restrict__ row_ptr, const f
     }
 }
 
-// 64-byte node records: one aligned load gives a walker the degree, the row offset and, for
-// low-degree rows, the neighbours themselves (and their CDF values when weighted).
+// 64-byte node records (layout in device.hpp): one aligned load gives a walker the degree, the
+// row offset and the row's first neighbours (with their CDF values and the row's total when
+// weighted).
 __global__ void build_records(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                               const uint64_t* __restrict__ cdf, uint32_t* __restrict__ rec) {
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int32_t beg = row_ptr[u], deg = row_ptr[u + 1] - beg;
-        uint32_t r[16];
+        uint32_t r[kRecWords];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) r[i] = 0;
+        for (int i = 0; i < kRecWords; ++i) r[i] = 0;
         r[0] = static_cast<uint32_t>(deg);
         r[1] = static_cast<uint32_t>(beg);
         if (cdf) {
-            for (int i = 0; i < kRecInlineWeighted && i < deg; ++i) {
-                r[2 + i] = static_cast<uint32_t>(col[beg + i]);
-                const uint64_t c = cdf[beg + i];
-                r[8 + 2 * i] = static_cast<uint32_t>(c);
-                r[9 + 2 * i] = static_cast<uint32_t>(c >> 32);
+#pragma unroll
+            for (int i = 0; i < kRecInlineWeighted; ++i) {
+                if (i < deg) {
+                    r[2 + i] = static_cast<uint32_t>(col[beg + i]);
+                    const uint64_t c = cdf[beg + i];
+                    r[8 + 2 * i] = static_cast<uint32_t>(c);
+                    r[9 + 2 * i] = static_cast<uint32_t>(c >> 32);
+                }
+            }
+            if (deg > 0) {
+                const uint64_t total = cdf[beg + deg - 1];
+                r[6] = static_cast<uint32_t>(total);
+                r[7] = static_cast<uint32_t>(total >> 32);
             }
         } else {
-            for (int i = 0; i < kRecInline && i < deg; ++i) r[2 + i] = static_cast<uint32_t>(col[beg + i]);
-        }
-        uint4* out = reinterpret_cast<uint4*>(rec + 16 * u);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = make_uint4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+            for (int i = 0; i < kRecInline; ++i)
+                if (i < deg) r[2 + i] = static_cast<uint32_t>(col[beg + i]);
+        }
+        uint4* out = reinterpret_cast<uint4*>(rec + static_cast<int64_t>(kRecWords) * u);
+#pragma unroll
+        for (int q = 0; q < kRecWords / 4; ++q) out[q] = make_uint4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
     }
 }
 
@@ -465,7 +476,7 @@ BuildLayout carve_build(void* ws, int32_t n, int64_t m, bool weighted) {
     L.edge_id = c.take<int32_t>(nnz);
     L.cdf = weighted ? c.take<uint64_t>(nnz) : nullptr;
     L.strength = c.take<double>(n);
-    L.rec = c.take<uint32_t>(static_cast<size_t>(16) * n);
+    L.rec = c.take<uint32_t>(static_cast<size_t>(kRecWords) * n);
     L.bfs_order = c.take<int32_t>(n);
     L.sfix = c.take<uint64_t>(n);
     L.scalars = c.take<BuildScalars>(1);

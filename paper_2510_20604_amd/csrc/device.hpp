@@ -58,29 +58,20 @@ __host__ __device__ __forceinline__ uint64_t philox_x64(uint32_t c0, uint32_t c1
 // floor(a * b / 2^64)
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
-// RandomNeighbor: the position within the row of the chosen neighbour.
-//   unweighted: floor(x * deg / 2^64)
-//   weighted:   r = floor(x * S / 2^64), S = cdf[end-1]; the first k with r < cdf[beg+k]
+// RandomNeighbor, unweighted: the position within the row of the chosen neighbour,
+// floor(x * deg / 2^64).  (Weighted rows: the first position k with floor(x * S / 2^64) <
+// cdf[beg + k], S = cdf[end - 1]; the search lives with the node records in the sampler.)
 __device__ __forceinline__ int32_t select_unweighted(uint64_t x, int32_t deg) {
     return static_cast<int32_t>(mulhi64(x, static_cast<uint64_t>(deg)));
 }
 
-template <class CdfPtr>
-__device__ __forceinline__ int32_t select_weighted(uint64_t x, CdfPtr cdf, int32_t beg, int32_t deg) {
-    const uint64_t total = cdf[beg + deg - 1];
-    const uint64_t r = mulhi64(x, total);
-    int32_t lo = 0, hi = deg - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (r < cdf[beg + mid])
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
-// Node records (rwc_csr::rec): 16 x uint32 per node.
+// Node records (rwc_csr::rec): 16 x uint32 per node, 64-byte aligned.  Word 0 is the degree
+// and word 1 the row offset.  Unweighted rows store their first 14 neighbours in words 2..15
+// (position p in word 2 + p).  Weighted rows store the ids of their first 4 entries in words
+// 2..5, the row's total (its last CDF value) in words 6..7 and the CDF values of the first 4
+// entries in words 8..15.  Whatever degree the row has, these positions need no read of the
+// row itself.
+constexpr int kRecWords = 16;
 constexpr int kRecInline = 14;          // neighbours stored inline for unweighted rows
 constexpr int kRecInlineWeighted = 4;   // (id, cdf) pairs stored inline for weighted rows
 

@@ -68,17 +68,49 @@ __device__ __forceinline__ uint32_t rec_word(const uint4& a, const uint4& b, con
     return s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
 }
 
-// RandomNeighbor from a weighted record with deg <= kRecInlineWeighted inline (id, cdf) pairs:
-// the position k of the chosen pair (its id is record word 2 + k).  c and d are record
-// words 8..15, the four CDF values.
-__device__ __forceinline__ uint32_t rec_weighted_slot(const uint4& c, const uint4& d, uint64_t x, uint32_t deg) {
-    const uint64_t c0 = c.x | (static_cast<uint64_t>(c.y) << 32);
-    const uint64_t c1 = c.z | (static_cast<uint64_t>(c.w) << 32);
-    const uint64_t c2 = d.x | (static_cast<uint64_t>(d.y) << 32);
-    const uint64_t c3 = d.z | (static_cast<uint64_t>(d.w) << 32);
-    const uint64_t total = deg == 1 ? c0 : (deg == 2 ? c1 : (deg == 3 ? c2 : c3));
-    const uint64_t r = mulhi64(x, total);
-    return (r < c0) ? 0u : ((r < c1) ? 1u : ((r < c2) ? 2u : 3u));
+// RandomNeighbor (Algorithm 3): the neighbour id chosen at a node by the 64 random bits x,
+// read from the node's record wherever it holds the answer.  rec(i) returns word i of the
+// record, already local (registers or LDS).  Unweighted: position floor(x deg / 2^64), inline
+// below kRecInline.  Weighted: the first position k with floor(x S / 2^64) < cdf[k], S the
+// row's total; the record's four CDF values settle it without a read of the row whenever r
+// falls below the fourth, else a binary search over the rest of the row's CDF does.
+template <class Rec>
+__device__ __forceinline__ uint32_t choose_neighbor(uint64_t x, Rec rec, const RWC_GLOBAL int32_t* col,
+                                                    const RWC_GLOBAL uint64_t* cdf) {
+    const uint32_t deg = rec(0);
+    const int32_t beg = static_cast<int32_t>(rec(1));
+    uint32_t pos;
+    if (cdf == nullptr) {
+        pos = static_cast<uint32_t>(select_unweighted(x, static_cast<int32_t>(deg)));
+        if (pos < static_cast<uint32_t>(kRecInline)) return rec(2u + pos);
+    } else {
+        const uint64_t total = rec(6) | (static_cast<uint64_t>(rec(7)) << 32);
+        const uint64_t r = mulhi64(x, total);
+        uint64_t c[kRecInlineWeighted];
+#pragma unroll
+        for (int i = 0; i < kRecInlineWeighted; ++i)
+            c[i] = rec(8u + 2u * i) | (static_cast<uint64_t>(rec(9u + 2u * i)) << 32);
+        if (deg <= static_cast<uint32_t>(kRecInlineWeighted) || r < c[kRecInlineWeighted - 1]) {
+            // the CDF is non-decreasing and exceeds r at position lim, so the first position
+            // above r is the number of positions below lim whose value is <= r
+            const uint32_t lim = (deg < static_cast<uint32_t>(kRecInlineWeighted) ? deg : kRecInlineWeighted) - 1u;
+            pos = 0;
+#pragma unroll
+            for (int i = 0; i < kRecInlineWeighted - 1; ++i)
+                pos += (static_cast<uint32_t>(i) < lim && c[i] <= r) ? 1u : 0u;
+            return rec(2u + pos);
+        }
+        int32_t lo = kRecInlineWeighted, hi = static_cast<int32_t>(deg) - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (r < cdf[beg + mid])
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        pos = static_cast<uint32_t>(lo);
+    }
+    return static_cast<uint32_t>(col[beg + static_cast<int32_t>(pos)]);
 }
 
 // Grows the tree of slot `slot` for absolute sample `sample` (one lane).
@@ -123,30 +155,19 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
         } else if (phase == kWalk) {
             const uint32_t k = st_cnt(wx);
             if (rh_node != x) {
-                const auto q = rec + 4 * static_cast<int64_t>(x);
+                const auto q = rec + (kRecWords / 4) * static_cast<int64_t>(x);
                 ra = load_u4(q + 0);
                 rb = load_u4(q + 1);
                 rc = load_u4(q + 2);
                 rd = load_u4(q + 3);
                 rh_node = x;
             }
-            const uint32_t deg = ra.x;
-            const int32_t beg = static_cast<int32_t>(ra.y);
             const uint64_t r = philox_x64(k, x, sw, gw, k0, k1);
-            uint32_t y;
-            if (cdf == nullptr) {
-                const int32_t pick = select_unweighted(r, static_cast<int32_t>(deg));
-                y = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_word(ra, rb, rc, rd, 2u + pick)
-                                                                : static_cast<uint32_t>(col[beg + pick]);
-            } else if (deg <= static_cast<uint32_t>(kRecInlineWeighted)) {
-                y = rec_word(ra, rb, rc, rd, 2u + rec_weighted_slot(rc, rd, r, deg));
-            } else {
-                y = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
-            }
+            const uint32_t y = choose_neighbor(r, [&](uint32_t i) { return rec_word(ra, rb, rc, rd, i); }, col, cdf);
             st[x] = st_make(y, k + 1);
             const uint64_t wy = st[y];
             {
-                const auto q = rec + 4 * static_cast<int64_t>(y);   // y is the next position
+                const auto q = rec + (kRecWords / 4) * static_cast<int64_t>(y);   // y is the next position
                 ra = load_u4(q + 0);
                 rb = load_u4(q + 1);
                 rc = load_u4(q + 2);
@@ -296,7 +317,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     // it wait for the copy with wait_vm().
     uint32_t rh_node = kNoNode;
     auto keep_record = [&](uint32_t v) {
-        const auto q = rec + 4 * static_cast<int64_t>(v);
+        const auto q = rec + (kRecWords / 4) * static_cast<int64_t>(v);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             __builtin_amdgcn_global_load_lds((const RWC_GLOBAL void*)(q + i),
@@ -375,19 +396,8 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             if (rh_node != h) keep_record(h);
             wait_vm();
             k = hk;
-            const uint2 db = *reinterpret_cast<const uint2*>(&lds_rec[0][lane]);
-            const uint32_t deg = db.x;
-            const int32_t beg = static_cast<int32_t>(db.y);
             const uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
-            if (cdf == nullptr) {
-                const int32_t pick = select_unweighted(r, static_cast<int32_t>(deg));
-                node = (deg <= static_cast<uint32_t>(kRecInline)) ? rec_at(2u + static_cast<uint32_t>(pick))
-                                                                   : static_cast<uint32_t>(col[beg + pick]);
-            } else if (deg <= static_cast<uint32_t>(kRecInlineWeighted)) {
-                node = rec_at(2u + rec_weighted_slot(lds_rec[2][lane], lds_rec[3][lane], r, deg));
-            } else {
-                node = static_cast<uint32_t>(col[beg + select_weighted(r, cdf, beg, static_cast<int32_t>(deg))]);
-            }
+            node = choose_neighbor(r, rec_at, col, cdf);
         } else if (mode == tStart) {
             node = j;
         } else if (mode == tWait || mode == tRetrace || mode == tRelease) {

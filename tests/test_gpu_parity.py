@@ -22,6 +22,8 @@ def _case(name):
     if name == "er1000_w":
         g = G.erdos_renyi_lcc(1000, 8, 1001)
         return g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 3))
+    if name == "ba3000":
+        return G.barabasi_albert(3000, 3, 5)
     if name == "ba3000_w":
         g = G.barabasi_albert(3000, 3, 5)
         return g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 6))
@@ -37,7 +39,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["er1000", "er1000_w", "ba3000_w", "grid_w", "star", "path", "k2"]
+CASES = ["er1000", "er1000_w", "ba3000", "ba3000_w", "grid_w", "star", "path", "k2"]
 
 
 def _u64(t):
@@ -57,18 +59,26 @@ def test_csr_matches_oracle(name):
     if g.w is not None:
         np.testing.assert_array_equal(_u64(Gd.cdf()), o.cdf)
         np.testing.assert_array_equal(Gd.weight().cpu().numpy().astype(np.float64), o.weight)
-    # 64-byte node records: degree, row offset, inline neighbours (and CDF values)
+    # 64-byte node records: degree, row offset, inline neighbours (and CDF values with the
+    # row's total); unused words are zero
     rec = Gd.rec().cpu().numpy().reshape(g.n, 16).view(np.uint32)
     deg = np.diff(o.row_ptr)
     np.testing.assert_array_equal(rec[:, 0], deg)
     np.testing.assert_array_equal(rec[:, 1], o.row_ptr[:-1])
     inline = 4 if g.w is not None else 14
+    lo32 = np.uint64(0xFFFFFFFF)
     for u in range(0, g.n, max(1, g.n // 200)):
         b, k = o.row_ptr[u], min(deg[u], inline)
-        np.testing.assert_array_equal(rec[u, 2:2 + k], o.col[b:b + k])
+        want = np.zeros(16, dtype=np.uint32)
+        want[0], want[1] = deg[u], b
+        want[2:2 + k] = o.col[b:b + k]
         if g.w is not None:
-            c = rec[u, 8:8 + 2 * k].astype(np.uint64)
-            np.testing.assert_array_equal(c[0::2] | (c[1::2] << np.uint64(32)), o.cdf[b:b + k])
+            c = o.cdf[b:b + k].astype(np.uint64)
+            want[8:8 + 2 * k:2] = (c & lo32).astype(np.uint32)
+            want[9:9 + 2 * k:2] = (c >> np.uint64(32)).astype(np.uint32)
+            total = np.uint64(o.cdf[o.row_ptr[u + 1] - 1])
+            want[6], want[7] = np.uint32(total & lo32), np.uint32(total >> np.uint64(32))
+        np.testing.assert_array_equal(rec[u], want, err_msg=f"record of node {u}")
     # breadth-first start order: a permutation starting at the pivot, distances non-decreasing
     order = Gd.bfs_order().cpu().numpy()
     np.testing.assert_array_equal(np.sort(order), np.arange(g.n))
@@ -126,8 +136,8 @@ def oracle_runs():
     return get
 
 
-@pytest.mark.parametrize("name,l", [("er1000", 2000), ("er1000_w", 300), ("ba3000_w", 200), ("grid_w", 100),
-                                    ("star", 50), ("path", 70), ("k2", 10)])
+@pytest.mark.parametrize("name,l", [("er1000", 2000), ("er1000_w", 300), ("ba3000", 200), ("ba3000_w", 200),
+                                    ("grid_w", 100), ("star", 50), ("path", 70), ("k2", 10)])
 def test_forest_bit_exact(name, l, oracle_runs):
     g, o, ref = oracle_runs(name, l, 2001)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
@@ -153,7 +163,7 @@ def test_launch_shape_does_not_change_the_forest(tif, persistent, capture, oracl
 
 
 @pytest.mark.parametrize("walkers", [2, 4, 8, 16, 32, 64])
-@pytest.mark.parametrize("name,l", [("er1000", 150), ("er1000_w", 100), ("ba3000_w", 70), ("grid_w", 40),
+@pytest.mark.parametrize("name,l", [("er1000", 150), ("er1000_w", 100), ("ba3000", 70), ("ba3000_w", 70), ("grid_w", 40),
                                     ("star", 20), ("path", 30), ("k2", 8)])
 def test_walker_teams_are_bit_exact(walkers, name, l, oracle_runs):
     """Several walkers per tree pop the same cycles as the serial order of Algorithm 3."""
