@@ -1,8 +1,8 @@
 """Full-size checks in the launch configuration bench.py times.
 
 BA(n = 1e6, m = 5), 10^4 trees: the automatic plan (64-walker teams, one batch) must
-reproduce the oracle's trees one by one for sampled sample indices (checksum and parent
-array), plus properties that hold at any size.  R-MAT scale 23 (largest component, weighted),
+reproduce the oracle's trees: parent arrays of sampled trees, the checksum of every tree and
+the visit totals, plus properties that hold at any size.  R-MAT scale 23 (largest component, weighted),
 5000 trees in a persistent launch: the same, and the adjoint's Euler identity for 1000 targets.
 """
 import numpy as np
@@ -33,7 +33,11 @@ def _check_sampled_trees(g, s, l, seed, picks, dump):
     assert int(counts.sum()) == int(P.as_uint64(s["total_steps"])[0])
 
 
-def test_ba1m_bench_configuration_sampled_trees():
+def test_ba1m_bench_configuration_matches_oracle_on_every_tree():
+    """All 10^4 trees of the bench's launch against the oracle run over the host cores: every
+    tree checksum, the visit totals and their squares, bit for bit (the oracle needs about
+    90 s on 16 threads)."""
+    import os
     g = G.barabasi_albert(1_000_000, 5, 1002)
     l, seed = 10_000, 2002
     Gd = P.Graph(g.n, g.src, g.dst)
@@ -41,6 +45,12 @@ def test_ba1m_bench_configuration_sampled_trees():
     s = P.sample_forests(Gd, l, seed, dump=dump)
     assert s["walkers_per_tree"] == 64 and s["trees_in_flight"] == l     # the bench's team plan
     _check_sampled_trees(g, s, l, seed, [0, 1, 2047, 2048, 5001, 9_999], dump)
+    o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+    ref = W.fastwalk_sample(o, o.pivot, seed, 0, 0, l, threads=max(1, min(16, os.cpu_count() or 1)))
+    np.testing.assert_array_equal(P.as_uint64(s["tree_hash"][0]), ref["hash"])
+    np.testing.assert_array_equal(P.as_uint64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(P.as_uint64(s["counts_sq"]), ref["visits_sq"])
+    assert int(P.as_uint64(s["total_steps"])[0]) == int(ref["steps"].sum())
 
 
 def test_rmat_scale23_sampled_trees_and_adjoint():
