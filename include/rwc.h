@@ -104,12 +104,14 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
                                         With neither this nor SPREAD, each graph gets spread
                                         starts if its bfs_depth exceeds 32 (long walks, e.g.
                                         meshes), shared starts otherwise                    */
-#define RWC_SAMPLE_PATH_RING     64u /* team kernel keeps each walker's newest path nodes in
-                                        LDS so loop erasure and attachment of them are single
-                                        atomic flips (same forest)                          */
+#define RWC_SAMPLE_PATH_RING     64u /* team kernel keeps each walker's newest path nodes and
+                                        their departure counts in LDS, so loop erasure and
+                                        attachment of them are single stores with no read
+                                        (same forest)                                       */
 #define RWC_SAMPLE_NO_PATH_RING 128u /* team kernel without that ring.  With neither, the
-                                        ring is used iff some graph of the call has spread
-                                        starts                                              */
+                                        ring is used when some graph has spread starts, when
+                                        no graph is weighted, or when the call's waves fill
+                                        less than two thirds of the device (same forest)    */
 
 typedef struct rwc_sample_params {
     uint64_t seed;               /* Philox key (seed mod 2^32, seed >> 32)                 */

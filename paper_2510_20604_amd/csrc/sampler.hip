@@ -266,7 +266,9 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
 //    lane id; its head's arrow is read at each step (departure count incremented);
 //  * arrow into the tree       -> the path attaches (its nodes are marked INTREE: the newest
 //                                 ones from the LDS ring at once, older ones by a chase from
-//                                 the path's start);
+//                                 the path's start).  The ring holds each buffered node with
+//                                 its departure count, so its final word is written without
+//                                 reading the old one;
 //  * arrow into its own path   -> a cycle of its own arrows: the segment after the hit node is
 //                                 released (FREE, counts kept) and the hit node is the head;
 //  * arrow into a free node    -> claim it (compare-and-swap; the loser waits on the winner);
@@ -278,7 +280,7 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
 // on until it is in the tree (skip) or free (claim).  Every iteration reads before it writes
 // and ends with a work-group fence, so all lanes see one consistent snapshot per iteration.
 // ---------------------------------------------------------------------------------------
-constexpr uint32_t kPathBuf = 16;   // newest path nodes kept per walker (power of two)
+constexpr uint32_t kPathBuf = 8;    // newest path nodes kept per walker (power of two)
 
 enum TeamMode : int { tIdle = 0, tStart = 1, tWalk = 2, tWait = 3, tRetrace = 4, tRelease = 5, tDone = 6 };
 
@@ -295,7 +297,7 @@ __device__ __forceinline__ bool st_cas(RWC_GLOBAL uint64_t* p, uint64_t expected
 
 template <bool kRing>
 __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
-                          uint32_t* lds_pred, uint32_t (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
+                          uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
                           bool want_hash, uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
     constexpr uint32_t kNone = 64;
     constexpr uint32_t kNoNode = 0xFFFFFFFFu;
@@ -344,11 +346,12 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     // ring of the newest nodes of this walker's path in LDS: entry 0 is the head and the
     // entries form a contiguous suffix of the path ending at it (nbuf >= 1 while walking)
     uint32_t nbuf = 0, bhead = 0;
-    auto buf = [&](uint32_t d) -> uint32_t { return lds_path[(bhead - d) & (kPathBuf - 1)][lane]; };
+    // entry = (node, its departure count after its latest departure from it)
+    auto buf = [&](uint32_t d) -> uint32_t { return lds_path[(bhead - d) & (kPathBuf - 1)][lane].x; };
     auto push = [&](uint32_t v) {
         if constexpr (kRing) {
             bhead = (bhead + 1) & (kPathBuf - 1);
-            lds_path[bhead][lane] = v;
+            lds_path[bhead][lane] = make_uint2(v, 0u);
             nbuf = nbuf < kPathBuf ? nbuf + 1 : kPathBuf;
         }
     };
@@ -420,7 +423,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         // soon as it is known (no lane reads state words again before the iteration's fence,
         // and issuing it early lets it drain while the rest of the iteration runs; measured
         // faster than issuing it with the other writes), or one chase store; then either a
-        // batch of atomic flips of ring entries or one compare-and-swap claim of `node`.
+        // batch of final-word stores of ring entries or one compare-and-swap claim of `node`.
         bool departed = false;
         uint32_t st_node = kNoNode;
         uint64_t st_word = 0;
@@ -431,6 +434,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         if (mode == tWalk) {
             // departure from the head along arrow k
             st_store(&st[h], st_make_owned(node, k + 1, tl));
+            if constexpr (kRing) lds_path[bhead][lane].y = k + 1;   // h is the newest entry
             departed = true;
             ++steps;
             if (k + 1 >= kCntMax) {
@@ -517,13 +521,14 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) img |= __shfl_xor(img, off, kWave);
             const bool on_cycle = waiting && ((img >> lane) & 1ull);
-            // each cycle member has exactly one predecessor on its cycle
-            if (on_cycle) lds_pred[wf] = static_cast<uint32_t>(lane);
-            __syncthreads();
-            const uint32_t pred = on_cycle ? lds_pred[lane] : static_cast<uint32_t>(lane);
+            // each cycle member has exactly one predecessor on its cycle: a forward permute
+            // (ds_permute: lane i's value lands in lane addr_i / 4, no LDS allocated) hands
+            // every member the lane id of its predecessor; other lanes send to themselves
+            const uint32_t dst = on_cycle ? wf : static_cast<uint32_t>(lane);
+            const uint32_t got = static_cast<uint32_t>(__builtin_amdgcn_ds_permute(static_cast<int>(dst << 2), lane));
+            const uint32_t pred = on_cycle ? got : static_cast<uint32_t>(lane);
             const uint32_t py = __shfl(c, static_cast<int>(pred), kWave);
             const uint64_t pw = __shfl(w, static_cast<int>(pred), kWave);
-            __syncthreads();
             if (on_cycle) {
                 // the cycle enters my path at py: the arrows from py on are popped
                 if (py == h) {
@@ -541,18 +546,18 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         }
 
         // ---- the two path actions
-        uint32_t xor_cnt = 0, xor_head = 0;   // atomically flip the xor_cnt newest ring entries
-        uint64_t xor_mask = 0;
+        uint32_t ring_cnt = 0, ring_head = 0;   // final words for the ring_cnt newest ring entries:
+        bool ring_attach = false;               // INTREE (attach) or FREE (release)
         if (act == kActAttach) {
-            // the path attaches at tree node act_v: the buffered suffix flips to INTREE now,
+            // the path attaches at tree node act_v: the buffered suffix becomes INTREE now,
             // an older prefix is chased from the start afterwards
             mode = tRetrace;
             c = j;
             cstop = act_v;   // without a ring: the chase runs up to the head
             if (kRing && nbuf > 0) {
-                xor_cnt = nbuf;
-                xor_head = bhead;
-                xor_mask = kOwned | kInTree | (static_cast<uint64_t>(tl) << 56);
+                ring_cnt = nbuf;
+                ring_head = bhead;
+                ring_attach = true;
                 if (want_hash)
                     for (uint32_t d = 0; d < nbuf; ++d)
                         hsum += splitmix64((static_cast<uint64_t>(buf(d)) << 32) | (d == 0 ? act_v : buf(d - 1)));
@@ -565,9 +570,8 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             const uint32_t d = find(act_v);
             mode = tWalk;
             if (d > 0) {
-                xor_cnt = d;
-                xor_head = bhead;
-                xor_mask = kOwned | (static_cast<uint64_t>(tl) << 56);
+                ring_cnt = d;
+                ring_head = bhead;
                 bhead = (bhead - d) & (kPathBuf - 1);
                 nbuf -= d;
                 h = act_v;
@@ -582,12 +586,17 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             }
         }
 
-        // ---- writes (a lane that flips ring entries does not claim in the same iteration)
+        // ---- writes (a lane that writes ring entries does not claim in the same iteration).
+        // Ring entries carry their departure counts, so their final words are plain stores
+        // (only the owner writes an owned node's word): no read of the old word, no fetch of
+        // its line.
         if (st_node != kNoNode) st_store(&st[st_node], st_word);
         if constexpr (kRing) {
-            for (uint32_t d = 0; d < xor_cnt; ++d) {
-                const uint32_t v = lds_path[(xor_head - d) & (kPathBuf - 1)][lane];
-                __hip_atomic_fetch_xor(&st[v], xor_mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            uint32_t next = act_v;   // the newest entry's arrow points at the tree node hit
+            for (uint32_t d = 0; d < ring_cnt; ++d) {
+                const uint2 e = lds_path[(ring_head - d) & (kPathBuf - 1)][lane];
+                st_store(&st[e.x], ring_attach ? (kInTree | st_make(next, e.y)) : st_make(0u, e.y));
+                next = e.x;
             }
         }
         // keep the chase store ahead of the claim, so that both are in flight together
@@ -615,8 +624,8 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
 
 template <bool kRing>
 __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t batch,
-                                              int64_t sample_begin, int64_t l, uint64_t seed, uint32_t* lds_pred,
-                                              uint32_t (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
+                                              int64_t sample_begin, int64_t l, uint64_t seed,
+                                              uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
                                               uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
                                               uint32_t* __restrict__ status) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -627,7 +636,7 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
     const bool active = slot < G.T && rel < l;
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    grow_team<kRing>(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_pred,
+    grow_team<kRing>(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed,
                      lds_path, lds_rec, tree_hash != nullptr, steps, h, err);
     for (int off = W / 2; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off, kWave);
@@ -648,12 +657,11 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
                                                      int32_t nitems, uint32_t* queue, int32_t batch,
                                                      int64_t sample_begin, int64_t l, uint64_t seed,
                                                      uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
-    __shared__ uint32_t lds_pred[kWave];
-    __shared__ uint32_t lds_path[kRing ? kPathBuf : 1][kWave];
+    __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
     __shared__ uint4 lds_rec[4][kWave];
     if (queue == nullptr) {
         if (static_cast<int32_t>(blockIdx.x) < nitems)
-            run_team_item<kRing>(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_pred, lds_path,
+            run_team_item<kRing>(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_path,
                                  lds_rec, tree_hash, total_steps, status);
         return;
     }
@@ -662,7 +670,7 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
         if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
         idx = __shfl(idx, 0, kWave);
         if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_team_item<kRing>(graphs, items[idx], batch, sample_begin, l, seed, lds_pred, lds_path, lds_rec,
+        run_team_item<kRing>(graphs, items[idx], batch, sample_begin, l, seed, lds_path, lds_rec,
                              tree_hash, total_steps, status);
     }
 }
@@ -1012,7 +1020,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     const int64_t l = p->num_samples;
 
     std::vector<GraphArgs> hg(G);
-    bool any_spread = false;
+    bool any_spread = false, any_weighted = false;
     for (int32_t g = 0; g < G; ++g) {
         const uint64_t n = static_cast<uint64_t>(graphs[g].n);
         // default step guard: far above the expected walk length of any graph we accept,
@@ -1035,11 +1043,20 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         hg[g].T = plan.T[g];
         hg[g].W = plan.W[g];
         hg[g].spread = spread_starts(graphs[g], p->flags) ? 1 : 0;
-        any_spread = any_spread || (plan.W[g] > 1 && hg[g].spread);
+        if (plan.W[g] > 1) {
+            any_spread = any_spread || hg[g].spread;
+            any_weighted = any_weighted || graphs[g].cdf != nullptr;
+        }
     }
+    // The ring saves the read of every buffered path node's word on attach and on loop
+    // erasure, and shortens the iterations that do them.  Measured: needed on meshes (spread
+    // starts); faster on unweighted graphs (BA(10^6) 5-8 %, BA(3*10^6) 10 %) and whenever the
+    // call leaves much of the device idle (R-MAT, 2000 trees: 23 %); slower on weighted
+    // graphs that fill the device (weighted R-MAT scale 21-23: 16-27 %).
+    const bool fills = plan.team && 3 * max_items(G, plan) >= 2 * static_cast<int64_t>(team_resident_waves(true));
     const bool ring = (p->flags & RWC_SAMPLE_PATH_RING) ? true
                       : (p->flags & RWC_SAMPLE_NO_PATH_RING) ? false
-                                                              : any_spread;
+                                                              : (any_spread || !any_weighted || !fills);
     // Work items with the longest trees first: a tree's time grows with n / W.
     std::vector<int32_t> order(G);
     std::iota(order.begin(), order.end(), 0);
