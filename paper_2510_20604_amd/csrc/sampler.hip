@@ -341,17 +341,29 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     uint32_t h = 0;       // head of the current path
     uint32_t hk = 0;      // departures from the head so far (its next arrow's index)
     uint32_t c = 0;       // node waited on (tWait) or chase cursor (tRetrace, tRelease)
-    uint32_t cstop = 0;   // retrace: stop once the next node is cstop; release: stop after cstop
+    uint32_t cstop = 0;   // retrace (and release with the ring): stop once the next node is
+                          // cstop; release without the ring: stop after cstop
     uint32_t jn = 0, jk = 0;   // release: the node that becomes the head afterwards, its count
     // ring of the newest nodes of this walker's path in LDS: entry 0 is the head and the
-    // entries form a contiguous suffix of the path ending at it (nbuf >= 1 while walking)
+    // entries form a contiguous suffix of the path ending at it (nbuf >= 1 while walking).
+    // An entry is (node, its departure count so far).  The departures of ring nodes live only
+    // here: their state words keep the claim's (OWNED, owner, stale next and count), which
+    // is all other walkers look at, and get their real word when they leave the ring (the
+    // oldest entry, when a push finds the ring full) or their final word on attach or loop
+    // erasure.  Chases therefore only ever walk nodes older than the ring.
     uint32_t nbuf = 0, bhead = 0;
-    // entry = (node, its departure count after its latest departure from it)
     auto buf = [&](uint32_t d) -> uint32_t { return lds_path[(bhead - d) & (kPathBuf - 1)][lane].x; };
-    auto push = [&](uint32_t v) {
+    auto buf_cnt = [&](uint32_t d) -> uint32_t { return lds_path[(bhead - d) & (kPathBuf - 1)][lane].y; };
+    auto push = [&](uint32_t v, uint32_t cnt) {
         if constexpr (kRing) {
+            if (nbuf == kPathBuf) {
+                // the oldest entry leaves: its arrow points at the next-older entry's node
+                const uint2 e = lds_path[(bhead + 1) & (kPathBuf - 1)][lane];
+                const uint32_t next = lds_path[(bhead + 2) & (kPathBuf - 1)][lane].x;
+                st_store(&st[e.x], st_make_owned(next, e.y, tl));
+            }
             bhead = (bhead + 1) & (kPathBuf - 1);
-            lds_path[bhead][lane] = make_uint2(v, 0u);
+            lds_path[bhead][lane] = make_uint2(v, cnt);
             nbuf = nbuf < kPathBuf ? nbuf + 1 : kPathBuf;
         }
     };
@@ -432,9 +444,12 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         int act = kActNone;
         uint32_t act_v = 0, act_k = 0, act_next = 0;   // attach: tree node hit; pop: kept node
         if (mode == tWalk) {
-            // departure from the head along arrow k
-            st_store(&st[h], st_make_owned(node, k + 1, tl));
-            if constexpr (kRing) lds_path[bhead][lane].y = k + 1;   // h is the newest entry
+            // departure from the head along arrow k (with the ring: recorded in the head's
+            // entry only)
+            if constexpr (kRing)
+                lds_path[bhead][lane].y = k + 1;
+            else
+                st_store(&st[h], st_make_owned(node, k + 1, tl));
             departed = true;
             ++steps;
             if (k + 1 >= kCntMax) {
@@ -494,11 +509,11 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 // chase release of a popped segment: FREE, departure count kept
                 st_node = c;
                 st_word = st_make(0u, st_cnt(w));
-                if (c == cstop) {
+                if (kRing ? st_next(w) == cstop : c == cstop) {
                     mode = tWalk;
                     h = jn;
                     hk = jk;
-                    push(jn);
+                    push(jn, jk);
                 } else {
                     c = st_next(w);
                 }
@@ -535,7 +550,10 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                     // only my head's arrow is popped; if I departed in this iteration the
                     // snapshot the predecessor read predates my departure
                     mode = tWalk;
-                    hk = departed ? k + 1 : st_cnt(pw);
+                    if constexpr (kRing)
+                        hk = buf_cnt(0);
+                    else
+                        hk = departed ? k + 1 : st_cnt(pw);
                 } else {
                     act = kActPop;
                     act_v = py;
@@ -548,6 +566,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         // ---- the two path actions
         uint32_t ring_cnt = 0, ring_head = 0;   // final words for the ring_cnt newest ring entries:
         bool ring_attach = false;               // INTREE (attach) or FREE (release)
+        bool repush = false;                    // after the ring's release: jn becomes the head
         if (act == kActAttach) {
             // the path attaches at tree node act_v: the buffered suffix becomes INTREE now,
             // an older prefix is chased from the start afterwards
@@ -566,7 +585,8 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
             }
         } else if (act == kActPop) {
             // keep act_v (on the path, older than the head) as the head and release what is
-            // newer: from the ring if act_v is buffered, else by a chase from its successor
+            // newer: from the ring if act_v is buffered, else the whole ring now and the older
+            // part by a chase from act_v's successor
             const uint32_t d = find(act_v);
             mode = tWalk;
             if (d > 0) {
@@ -575,7 +595,23 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 bhead = (bhead - d) & (kPathBuf - 1);
                 nbuf -= d;
                 h = act_v;
-                hk = act_k;
+                if constexpr (kRing)
+                    hk = buf_cnt(0);   // the ring holds act_v's current count
+                else
+                    hk = act_k;
+            } else if constexpr (kRing) {
+                ring_cnt = nbuf;
+                ring_head = bhead;
+                jn = act_v;
+                jk = act_k;
+                cstop = buf(nbuf - 1);
+                if (act_next == cstop) {
+                    repush = true;   // nothing older to release
+                } else {
+                    mode = tRelease;
+                    c = act_next;
+                }
+                nbuf = 0;
             } else {
                 mode = tRelease;
                 c = act_next;
@@ -598,6 +634,12 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 st_store(&st[e.x], ring_attach ? (kInTree | st_make(next, e.y)) : st_make(0u, e.y));
                 next = e.x;
             }
+            if (repush) {
+                mode = tWalk;
+                h = jn;
+                hk = jk;
+                push(jn, jk);
+            }
         }
         // keep the chase store ahead of the claim, so that both are in flight together
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -609,7 +651,7 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
                 h = node;
                 hk = st_cnt(w);
                 mode = tWalk;
-                push(node);
+                push(node, hk);
             } else if (mode == tWalk) {
                 mode = tWait;     // lost the race: the winner owns the node now
                 c = node;
