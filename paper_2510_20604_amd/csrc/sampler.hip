@@ -956,9 +956,9 @@ struct Timer {
         for (auto& e : ev) RWC_HIP(hipEventCreate(&e));
         return RWC_OK;
     }
-    ~Timer() {
+    ~Timer() {   // teardown: failures here have nobody to report to
         for (auto& e : ev)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -992,17 +992,17 @@ struct CaptureStream {
         RWC_HIP(hipStreamWaitEvent(caller, ev, 0));
         return RWC_OK;
     }
-    ~CaptureStream() {
+    ~CaptureStream() {   // teardown: failures here have nobody to report to
         if (capturing) {
             hipGraph_t g = nullptr;
-            hipStreamEndCapture(stream, &g);
-            if (g) hipGraphDestroy(g);
+            (void)hipStreamEndCapture(stream, &g);
+            if (g) (void)hipGraphDestroy(g);
         }
-        if (stream) hipStreamSynchronize(stream);
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
-        if (ev) hipEventDestroy(ev);
-        if (stream) hipStreamDestroy(stream);
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev) (void)hipEventDestroy(ev);
+        if (stream) (void)hipStreamDestroy(stream);
     }
 };
 
