@@ -58,7 +58,7 @@ class SolveParams(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("walkers_per_tree", c_i32), ("trees_in_flight", c_i32), ("steps_per_s", c_dbl),
-                ("candidates", c_i32), ("cached", c_i32)]
+                ("candidates", c_i32), ("cached", c_i32), ("flags", c_u32), ("reserved", c_i32)]
 
 
 class BackwardParams(ctypes.Structure):

@@ -181,8 +181,10 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
 
 def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
              budget_bytes: int = 64 << 30) -> dict:
-    """Times one batch of each candidate (walkers per tree, trees in flight) and returns the
-    fastest (rwc_autotune_sampler); cached per graph class for the process."""
+    """Times one batch of each candidate (walkers per tree, trees in flight, path ring) and
+    returns the fastest (rwc_autotune_sampler); cached per graph class for the process.
+    `path_ring` is None for one walker per tree, else whether the winner used the ring (pass
+    it to sample_forests)."""
     L = _lib.lib()
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=-1)
     size = ctypes.c_size_t()
@@ -192,8 +194,14 @@ def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
     r = TuneResult()
     check(L.rwc_autotune_sampler(ctypes.byref(graph.csr), ctypes.byref(p), int(budget_bytes), ctypes.byref(r),
                                  _ptr(ws), ws.numel(), _stream()), "rwc_autotune_sampler")
+    ring = None
+    if r.flags & _lib.RWC_SAMPLE_PATH_RING:
+        ring = True
+    elif r.flags & _lib.RWC_SAMPLE_NO_PATH_RING:
+        ring = False
     return {"walkers_per_tree": r.walkers_per_tree, "trees_in_flight": r.trees_in_flight,
-            "steps_per_s": r.steps_per_s, "candidates": r.candidates, "cached": bool(r.cached)}
+            "steps_per_s": r.steps_per_s, "candidates": r.candidates, "cached": bool(r.cached),
+            "path_ring": ring}
 
 
 def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor | None = None,

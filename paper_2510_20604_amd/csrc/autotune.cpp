@@ -1,5 +1,6 @@
-// rwc_autotune_sampler: picks walkers per tree and trees in flight for a graph by timing short
-// probes of the real sampler, and caches the winner per graph class for the process.
+// rwc_autotune_sampler: picks walkers per tree, trees in flight and (for walker teams) the LDS
+// path ring for a graph by timing short probes of the real sampler, and caches the winner per
+// graph class for the process.
 //
 // The sampler's outputs are a fixed function of (graph, seed, sample index), so the choice
 // only changes speed.  Throughput depends on the number of concurrent walkers, on the state
@@ -19,6 +20,7 @@ namespace {
 struct Candidate {
     int32_t W;
     int64_t T;
+    uint32_t flags;   // RWC_SAMPLE_PATH_RING or RWC_SAMPLE_NO_PATH_RING for teams, else 0
 };
 
 using ClassKey = std::tuple<int, int, int, int>;  // log2 n, mean degree, weighted, log2 l
@@ -36,8 +38,8 @@ ClassKey class_of(const rwc_csr* g, int64_t l) {
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // One walker per tree with every tree in flight, and teams of 8 to 64 walkers with one or two
-// device-fulls of resident waves or every tree in flight (the last avoids batch tails), all
-// capped by the state budget.
+// device-fulls of resident waves or every tree in flight (the last avoids batch tails), each
+// with and without the path ring, all capped by the state budget.
 std::vector<Candidate> candidates(const rwc_csr* g, int64_t l, int64_t budget_bytes) {
     std::vector<Candidate> out;
     const int64_t stride = round_up(g->n, 8);
@@ -50,7 +52,12 @@ std::vector<Candidate> candidates(const rwc_csr* g, int64_t l, int64_t budget_by
         if (T < S) return;
         for (const Candidate& c : out)
             if (c.W == W && c.T == T) return;
-        out.push_back({W, T});
+        if (W == 1) {
+            out.push_back({W, T, 0u});
+        } else {
+            out.push_back({W, T, RWC_SAMPLE_PATH_RING});
+            out.push_back({W, T, RWC_SAMPLE_NO_PATH_RING});
+        }
     };
     add(1, l);
     const int64_t resident = team_resident_waves(g->bfs_depth > 32);
@@ -90,7 +97,7 @@ int max_sample_bytes(const rwc_csr* g, const rwc_sample_params* p, const std::ve
         q.walkers_per_tree = c.W;
         q.trees_in_flight = static_cast<int32_t>(c.T);
         q.num_samples = c.T;
-        q.flags = 0;
+        q.flags = c.flags;
         size_t b = 0;
         RWC_CHECK(rwc_sample_forests_workspace(g, 1, &q, &b));
         best = b > best ? b : best;
@@ -145,7 +152,7 @@ extern "C" int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p
         q.walkers_per_tree = c.W;
         q.trees_in_flight = static_cast<int32_t>(c.T);
         q.num_samples = c.T;        // one full batch of the real sample range
-        q.flags = 0;
+        q.flags = c.flags;
         float ms[2] = {0.f, 0.f};
         rwc_sample_outputs o{};
         o.counts = L.counts;
@@ -160,6 +167,7 @@ extern "C" int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p
             best.steps_per_s = rate;
             best.walkers_per_tree = c.W;
             best.trees_in_flight = static_cast<int32_t>(c.T);
+            best.flags = c.flags;
         }
     }
     best.cached = 0;

@@ -312,8 +312,9 @@ def test_autotuner_choice_does_not_change_the_forest(oracle_runs):
     t = P.autotune(Gd, 200, 2001)
     assert t["candidates"] >= 2 and not t["cached"]
     assert t["walkers_per_tree"] in (1, 8, 16, 32, 64) and t["trees_in_flight"] >= 1
+    assert (t["path_ring"] is None) == (t["walkers_per_tree"] == 1)
     s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=t["walkers_per_tree"],
-                         trees_in_flight=t["trees_in_flight"])
+                         trees_in_flight=t["trees_in_flight"], path_ring=t["path_ring"])
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
     again = P.autotune(Gd, 200, 2001)
