@@ -109,9 +109,10 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
                                         attachment of them are single stores with no read
                                         (same forest)                                       */
 #define RWC_SAMPLE_NO_PATH_RING 128u /* team kernel without that ring.  With neither, the
-                                        ring is used when some graph has spread starts, when
-                                        no graph is weighted, or when the call's waves fill
-                                        less than two thirds of the device (same forest)    */
+                                        ring is used unless the call's waves fill two thirds
+                                        of the device or more, some graph is weighted with
+                                        more than 16 entries per node, and no graph has
+                                        spread starts (same forest)                         */
 
 typedef struct rwc_sample_params {
     uint64_t seed;               /* Philox key (seed mod 2^32, seed >> 32)                 */

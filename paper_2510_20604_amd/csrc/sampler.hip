@@ -281,6 +281,9 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
 // and ends with a work-group fence, so all lanes see one consistent snapshot per iteration.
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kPathBuf = 8;    // newest path nodes kept per walker (power of two)
+// Weighted graphs whose mean degree (entries per node) exceeds this run without the path ring
+// when they fill the device (see the plan).
+constexpr int64_t kRingMaxMeanDegree = 16;
 // Waiting walkers re-read their target, and the team looks for wait cycles, every kPollEvery-th
 // iteration (a power of two): polls are reads that rarely change anything, and fewer of them
 // leave the memory system to the walking lanes (256 mixed graphs: 7 % faster than every
@@ -1069,7 +1072,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     const int64_t l = p->num_samples;
 
     std::vector<GraphArgs> hg(G);
-    bool any_spread = false, any_weighted = false;
+    bool any_spread = false, any_dense_weighted = false;
     for (int32_t g = 0; g < G; ++g) {
         const uint64_t n = static_cast<uint64_t>(graphs[g].n);
         // default step guard: far above the expected walk length of any graph we accept,
@@ -1095,18 +1098,20 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         hg[g].spread = spread_starts(graphs[g], p->flags) ? 1 : 0;
         if (plan.W[g] > 1) {
             any_spread = any_spread || hg[g].spread;
-            any_weighted = any_weighted || graphs[g].cdf != nullptr;
+            any_dense_weighted =
+                any_dense_weighted || (graphs[g].cdf != nullptr && graphs[g].nnz > kRingMaxMeanDegree * graphs[g].n);
         }
     }
     // The ring saves the read of every buffered path node's word on attach and on loop
     // erasure, and shortens the iterations that do them.  Measured: needed on meshes (spread
-    // starts); faster on unweighted graphs (BA(10^6) 5-8 %, BA(3*10^6) 10 %) and whenever the
-    // call leaves much of the device idle (R-MAT, 2000 trees: 23 %); slower on weighted
-    // graphs that fill the device (weighted R-MAT scale 21-23: 16-27 %).
+    // starts); faster on unweighted graphs (BA(10^6) 5-8 %, BA(3*10^6) 10 %), on weighted BA
+    // (BA(10^6), 4000 trees: 15 %) and whenever the call leaves much of the device idle
+    // (R-MAT, 2000 trees: 23 %); slower on weighted graphs of high mean degree that fill the
+    // device (weighted R-MAT scale 21-23, mean degree 22-25: 16-27 %).
     const bool fills = plan.team && 3 * max_items(G, plan) >= 2 * static_cast<int64_t>(team_resident_waves(true));
     const bool ring = (p->flags & RWC_SAMPLE_PATH_RING) ? true
                       : (p->flags & RWC_SAMPLE_NO_PATH_RING) ? false
-                                                              : (any_spread || !any_weighted || !fills);
+                                                              : (any_spread || !any_dense_weighted || !fills);
     // Work items with the longest trees first: a tree's time grows with n / W.
     std::vector<int32_t> order(G);
     std::iota(order.begin(), order.end(), 0);
