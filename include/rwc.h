@@ -98,6 +98,11 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
 #define RWC_SAMPLE_GRAPH_CAPTURE 4u  /* record the launches in a hipGraph and replay it     */
 #define RWC_SAMPLE_BFS_STARTS    8u  /* walker teams take start nodes in breadth-first order
                                         from the root instead of ascending ids (same forest) */
+#define RWC_SAMPLE_ID_STARTS   256u  /* walker teams take start nodes by ascending id.  With
+                                        neither this nor BFS, graphs with spread starts take
+                                        them breadth-first when the call has several graphs
+                                        and queues at least twice the waves the device
+                                        holds, ascending otherwise (same forest)            */
 #define RWC_SAMPLE_SPREAD_STARTS 16u /* each walker of a team takes start nodes from its own
                                         contiguous range of the start order (same forest)   */
 #define RWC_SAMPLE_SHARED_STARTS 32u /* a team's walkers take consecutive start positions.
@@ -146,10 +151,11 @@ typedef struct rwc_sample_outputs {
     float* timing_ms;            /* HOST [2] or NULL: device time of the walk kernels and of
                                     the reduction kernels, summed over batches (hipEvents on
                                     `stream`; not available with RWC_SAMPLE_GRAPH_CAPTURE) */
-    int32_t* plan;               /* HOST [5] or NULL, as used for graph 0: walkers per tree,
+    int32_t* plan;               /* HOST [6] or NULL, as used for graph 0: walkers per tree,
                                     trees in flight, number of batches, walk kernel (0 one
                                     walker per tree, 1 walker teams, 2 walker teams with the
-                                    LDS path ring), team starts (0 shared, 1 spread)      */
+                                    LDS path ring), team starts (0 shared, 1 spread), start
+                                    order (0 ascending ids, 1 breadth-first)              */
 } rwc_sample_outputs;
 
 /* Workspace for rwc_sample_forests with these graphs and parameters. */

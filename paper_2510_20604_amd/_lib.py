@@ -23,6 +23,7 @@ RWC_SAMPLE_SPREAD_STARTS = 16
 RWC_SAMPLE_SHARED_STARTS = 32
 RWC_SAMPLE_PATH_RING = 64
 RWC_SAMPLE_NO_PATH_RING = 128
+RWC_SAMPLE_ID_STARTS = 256
 
 STATUS = {
     0: "RWC_OK", -1: "RWC_ERR_INVALID_ARG", -2: "RWC_ERR_NODE_RANGE", -3: "RWC_ERR_SELF_LOOP",

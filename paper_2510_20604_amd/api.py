@@ -106,15 +106,16 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
                    want_hash: bool = True, dump: Sequence[int] = (), max_steps_per_tree: int = 0,
                    graph_index_base: int = 0, accumulate: dict | None = None,
                    workspace: torch.Tensor | None = None, timing: bool = False,
-                   bfs_starts: bool = False, starts: str = "auto", path_ring: bool | None = None) -> dict:
+                   bfs_starts: bool | None = None, starts: str = "auto", path_ring: bool | None = None) -> dict:
     """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
 
     Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
     total_steps [G], tree_hash [G, num_samples], parents [len(dump), n] and the workspace
     used (pass it back as `workspace` to reuse it).  With timing=True also walk_ms and
     reduce_ms: device time of the walk and reduction kernels (hipEvents on the stream).
-    `starts` ("auto", "shared", "spread") and `path_ring` (None = automatic) pick how walker
-    teams schedule their walks; the forest does not depend on them."""
+    `starts` ("auto", "shared", "spread"), `bfs_starts` (None = automatic, True =
+    breadth-first from the root, False = ascending ids) and `path_ring` (None = automatic) pick
+    how walker teams schedule their walks; the forest does not depend on them."""
     L = _lib.lib()
     gl = [graphs] if isinstance(graphs, Graph) else list(graphs)
     G = len(gl)
@@ -127,8 +128,8 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
         flags |= _lib.RWC_SAMPLE_GRAPH_CAPTURE
     if accumulate is not None:
         flags |= _lib.RWC_SAMPLE_ACCUMULATE
-    if bfs_starts:
-        flags |= _lib.RWC_SAMPLE_BFS_STARTS
+    if bfs_starts is not None:
+        flags |= _lib.RWC_SAMPLE_BFS_STARTS if bfs_starts else _lib.RWC_SAMPLE_ID_STARTS
     if starts == "spread":
         flags |= _lib.RWC_SAMPLE_SPREAD_STARTS
     elif starts == "shared":
@@ -166,7 +167,7 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     tms = (ctypes.c_float * 2)()
     if timing:
         out.timing_ms = ctypes.cast(tms, ctypes.c_void_p)
-    plan = (ctypes.c_int32 * 5)()
+    plan = (ctypes.c_int32 * 6)()
     out.plan = ctypes.cast(plan, ctypes.c_void_p)
     check(L.rwc_sample_forests(arr, G, ctypes.byref(p), ctypes.byref(out), _ptr(workspace), workspace.numel(),
                                _stream()), "rwc_sample_forests")
@@ -174,6 +175,7 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     res["walkers_per_tree"], res["trees_in_flight"], res["batches"] = int(plan[0]), int(plan[1]), int(plan[2])
     res["walk_kernel"] = ("wilson_walk", "wilson_team<false>", "wilson_team<true>")[int(plan[3])]
     res["starts"] = "spread" if plan[4] else "shared"
+    res["start_order"] = "breadth-first" if plan[5] else "ascending"
     if timing:
         res["walk_ms"], res["reduce_ms"] = float(tms[0]), float(tms[1])
     return res

@@ -1030,6 +1030,8 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
         return fail(RWC_ERR_INVALID_ARG, "spread and shared starts are exclusive");
     if ((p->flags & RWC_SAMPLE_PATH_RING) && (p->flags & RWC_SAMPLE_NO_PATH_RING))
         return fail(RWC_ERR_INVALID_ARG, "path ring and no path ring are exclusive");
+    if ((p->flags & RWC_SAMPLE_BFS_STARTS) && (p->flags & RWC_SAMPLE_ID_STARTS))
+        return fail(RWC_ERR_INVALID_ARG, "breadth-first and ascending starts are exclusive");
     return RWC_OK;
 }
 
@@ -1086,7 +1088,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         hg[g].col = graphs[g].col;
         hg[g].cdf = graphs[g].weighted ? graphs[g].cdf : nullptr;
         hg[g].rec = reinterpret_cast<const uint4*>(graphs[g].rec);
-        hg[g].order = (p->flags & RWC_SAMPLE_BFS_STARTS) ? graphs[g].bfs_order : nullptr;
+        hg[g].order = nullptr;   // set below, once every graph's start mode is known
         hg[g].state = L.state[g];
         hg[g].stride = plan.stride[g];
         hg[g].guard = steps;
@@ -1108,7 +1110,20 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     // (BA(10^6), 4000 trees: 15 %) and whenever the call leaves much of the device idle
     // (R-MAT, 2000 trees: 23 %); slower on weighted graphs of high mean degree that fill the
     // device (weighted R-MAT scale 21-23, mean degree 22-25: 16-27 %).
-    const bool fills = plan.team && 3 * max_items(G, plan) >= 2 * static_cast<int64_t>(team_resident_waves(true));
+    const int64_t resident = team_resident_waves(true);
+    const bool fills = plan.team && 3 * max_items(G, plan) >= 2 * resident;
+    // Start order, measured: breadth-first starts make batches of many meshes (spread starts)
+    // a third faster (256 mixed graphs: 4.5 -> 3.0 s, their 128 grids alone 4.0 -> 3.1 s) but
+    // every single graph slower, meshes included (a 25 k-node grid with 50 000 trees: 10 %, a
+    // 97 k-node grid with 2000-20 000 trees: 5-15 %), and small-world graphs (shared starts)
+    // by much more.  So they are taken for the meshes of calls with several graphs and a queue
+    // of at least twice the resident waves.
+    const bool queued = plan.team && G > 1 && max_items(G, plan) >= 2 * resident;
+    for (int32_t g = 0; g < G; ++g) {
+        const bool bfs = (p->flags & RWC_SAMPLE_BFS_STARTS) ||
+                         (!(p->flags & RWC_SAMPLE_ID_STARTS) && queued && plan.W[g] > 1 && hg[g].spread);
+        hg[g].order = bfs ? graphs[g].bfs_order : nullptr;
+    }
     const bool ring = (p->flags & RWC_SAMPLE_PATH_RING) ? true
                       : (p->flags & RWC_SAMPLE_NO_PATH_RING) ? false
                                                               : (any_spread || !any_dense_weighted || !fills);
@@ -1213,6 +1228,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         out->plan[2] = plan.batches;
         out->plan[3] = !plan.team ? 0 : (ring ? 2 : 1);
         out->plan[4] = hg[0].spread;
+        out->plan[5] = hg[0].order != nullptr ? 1 : 0;
     }
     return device_error_to_status(status);
 }

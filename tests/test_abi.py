@@ -89,7 +89,8 @@ def test_exclusive_schedule_flags_are_rejected():
     g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8, rec=8, bfs_order=8)
     size = ctypes.c_size_t()
     for bad in (_lib.RWC_SAMPLE_SPREAD_STARTS | _lib.RWC_SAMPLE_SHARED_STARTS,
-                _lib.RWC_SAMPLE_PATH_RING | _lib.RWC_SAMPLE_NO_PATH_RING):
+                _lib.RWC_SAMPLE_PATH_RING | _lib.RWC_SAMPLE_NO_PATH_RING,
+                _lib.RWC_SAMPLE_BFS_STARTS | _lib.RWC_SAMPLE_ID_STARTS):
         p = _lib.SampleParams(seed=1, num_samples=10, root=-1, flags=bad)
         assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(size)) == -1
     p = _lib.SampleParams(seed=1, num_samples=10, root=-1, flags=_lib.RWC_SAMPLE_SPREAD_STARTS | _lib.RWC_SAMPLE_PATH_RING)
