@@ -128,7 +128,9 @@ typedef struct rwc_sample_params {
     int32_t trees_in_flight;     /* trees resident at once per graph; 0 = automatic: all
                                     trees, scaled down to fit 8 B x n per tree of every
                                     graph into half of the device's memory                */
-    int32_t walkers_per_tree;    /* 0 = automatic; 1 = one walker per tree                */
+    int32_t walkers_per_tree;    /* 0 = automatic (teams of 64, fewer for graphs under
+                                    1024 nodes); 1 = one walker per tree; else a power of
+                                    two up to 64                                          */
     uint64_t max_steps_per_tree; /* guard; 0 = 2^20 + 4096 n                              */
     uint32_t graph_index_base;   /* Philox graph word of graphs[0]; graph g uses base + g */
     uint32_t reserved;

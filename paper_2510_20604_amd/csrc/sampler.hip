@@ -864,15 +864,15 @@ int64_t default_state_budget() {
     }
     return static_cast<int64_t>(total_b / 2);
 }
-constexpr int64_t kTargetWalkers = 1 << 17;          // one walker per tree from this many trees on
 
 // Walkers per tree when the caller leaves it open.  Full-wave teams, narrowed only for tiny
 // graphs (at least 16 nodes per walker): on BA(10^6), 10^4 trees, 64 walkers beat 32, and on
 // the 256-graph batch (BA and meshes, 10^3..10^5 nodes) 64 walkers for every graph beat widths
-// growing with n by 3-5%.  A single graph whose trees are too many (>= 2^17) or too small
-// (n * l <= 2^22 node-trees) for teams to matter gets one walker per tree.
-int auto_walkers(int64_t n, int32_t G, int64_t l) {
-    if (G == 1 && (l >= kTargetWalkers || n * l <= (int64_t(1) << 22))) return 1;
+// growing with n by 3-5%.  Teams also beat one walker per tree on small problems, where one
+// lane per tree leaves the device nearly empty and every step waits on its own memory
+// latency: ER(1000) with 500 trees 9x, BA(3000) with 1000 trees 59x, a 2500-node grid 16x,
+// and still with 200 000 trees of ER(1000) (1.6x at 32 walkers).
+int auto_walkers(int64_t n) {
     int W = 64;
     while (W > 2 && W * 16 > n) W >>= 1;
     return W;
@@ -896,7 +896,7 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
     int64_t state_words = 0;
     for (int32_t g = 0; g < G; ++g) {
         const int64_t n = graphs[g].n;
-        const int W = (p->walkers_per_tree > 0) ? p->walkers_per_tree : auto_walkers(n, G, l);
+        const int W = (p->walkers_per_tree > 0) ? p->walkers_per_tree : auto_walkers(n);
         const int S = kWave / W;
         int64_t T = p->trees_in_flight;
         if (T <= 0) {

@@ -162,7 +162,7 @@ def test_launch_shape_does_not_change_the_forest(tif, persistent, capture, oracl
     np.testing.assert_array_equal(s["parents"].cpu().numpy(), ref["parents"][[0, 299]])
 
 
-@pytest.mark.parametrize("walkers", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("walkers", [1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("name,l", [("er1000", 150), ("er1000_w", 100), ("ba3000", 70), ("ba3000_w", 70), ("grid_w", 40),
                                     ("star", 20), ("path", 30), ("k2", 8)])
 def test_walker_teams_are_bit_exact(walkers, name, l, oracle_runs):
@@ -267,7 +267,7 @@ def test_step_guard_reports_an_error():
     g = _case("grid_w")
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     with pytest.raises(P.RWCError) as ei:
-        P.sample_forests(Gd, 8, 1, max_steps_per_tree=100)
+        P.sample_forests(Gd, 8, 1, max_steps_per_tree=100, walkers_per_tree=1)
     assert ei.value.status == -9
 
 
