@@ -68,6 +68,21 @@ __global__ void rhs_scatter(int32_t count, const Entry* __restrict__ e, int32_t 
 }
 
 // ------------------------------------------------------------ batched PCG ------------
+// The FP32 search directions P are stored in blocks of 64 columns: block b holds columns
+// 64b .. 64b + w_b - 1 (w_b = min(64, R - 64b)) of every row, row-major with row stride w_b,
+// and starts at float 64 b n.  A row of a full block is 256 aligned bytes, two L2 lines, so the
+// SpMM's random gather of a neighbour's row touches two lines of HBM instead of three for an
+// R-wide row; the narrow last block (2 columns for 64 probes: 8 B per row) is small enough to
+// stay in the Infinity Cache.
+__device__ __forceinline__ int64_t p_block_base(int32_t b, int64_t n) { return static_cast<int64_t>(b) * kWave * n; }
+__device__ __forceinline__ int32_t p_block_width(int32_t b, int32_t R) {
+    return (R - b * kWave) < kWave ? (R - b * kWave) : kWave;
+}
+__device__ __forceinline__ int64_t p_index(int64_t u, int32_t c, int32_t R, int64_t n) {
+    const int32_t b = c / kWave;
+    return p_block_base(b, n) + u * p_block_width(b, R) + (c - b * kWave);
+}
+
 // One wave per row (grid-stride), lanes over columns.
 __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restrict__ d, double* __restrict__ Y,
                           double* __restrict__ X, float* __restrict__ P32, double* __restrict__ part) {
@@ -84,7 +99,7 @@ __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restr
             const double z = (u == v) ? 0.0 : r / d[u];
             Y[i] = r;   // Y becomes the residual
             X[i] = 0.0;
-            P32[i] = static_cast<float>(z);
+            P32[p_index(u, c, R, n)] = static_cast<float>(z);
             zr += z * r;
             rr += r * r;
         }
@@ -110,7 +125,7 @@ constexpr int kLongRow = 4 * kWave;
 template <int B>
 __device__ __forceinline__ void gather_batch(int32_t k, int32_t step, const int32_t* __restrict__ col,
                                              const float* __restrict__ weight, const float* __restrict__ P32,
-                                             int32_t R, int32_t cbase, double* sum) {
+                                             int32_t R, int64_t n, int32_t cbase, double* sum) {
     int64_t w[B];
     float t[B];
 #pragma unroll
@@ -122,9 +137,13 @@ __device__ __forceinline__ void gather_batch(int32_t k, int32_t step, const int3
     for (int j = 0; j < kColPass; ++j) {
         const int32_t c = cbase + j * kWave;
         if (c < R) {
+            // column c lies in block c / 64 (the same block for the whole wave)
+            const int32_t blk = c / kWave;
+            const int64_t stride = p_block_width(blk, R);
+            const float* __restrict__ Pb = P32 + p_block_base(blk, n) + (c - blk * kWave);
             float a[B];
 #pragma unroll
-            for (int i = 0; i < B; ++i) a[i] = P32[w[i] * R + c];
+            for (int i = 0; i < B; ++i) a[i] = Pb[w[i] * stride];
 #pragma unroll
             for (int i = 0; i < B; ++i) sum[j] += static_cast<double>(t[i]) * static_cast<double>(a[i]);
         }
@@ -135,18 +154,18 @@ __device__ __forceinline__ void gather_batch(int32_t k, int32_t step, const int3
 // memory latency, so a wave keeps 16 rows of P in flight (R-MAT scale 23: 31 % faster than 4).
 __device__ __forceinline__ void gather_rows(int32_t beg, int32_t end, int32_t step, const int32_t* __restrict__ col,
                                             const float* __restrict__ weight, const float* __restrict__ P32,
-                                            int32_t R, int32_t cbase, double* sum) {
+                                            int32_t R, int64_t n, int32_t cbase, double* sum) {
     int32_t k = beg;
-    for (; k + 15 * step < end; k += 16 * step) gather_batch<16>(k, step, col, weight, P32, R, cbase, sum);
+    for (; k + 15 * step < end; k += 16 * step) gather_batch<16>(k, step, col, weight, P32, R, n, cbase, sum);
     if (k + 7 * step < end) {
-        gather_batch<8>(k, step, col, weight, P32, R, cbase, sum);
+        gather_batch<8>(k, step, col, weight, P32, R, n, cbase, sum);
         k += 8 * step;
     }
     if (k + 3 * step < end) {
-        gather_batch<4>(k, step, col, weight, P32, R, cbase, sum);
+        gather_batch<4>(k, step, col, weight, P32, R, n, cbase, sum);
         k += 4 * step;
     }
-    for (; k < end; k += step) gather_batch<1>(k, step, col, weight, P32, R, cbase, sum);
+    for (; k < end; k += step) gather_batch<1>(k, step, col, weight, P32, R, n, cbase, sum);
 }
 
 __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __restrict__ row_ptr,
@@ -170,7 +189,7 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __rest
                 const int32_t c = c0 + lane + j * kWave;
                 if (c >= R) continue;
                 const int64_t i = u * R + c;
-                const double pu = static_cast<double>(P32[i]);
+                const double pu = static_cast<double>(P32[p_index(u, c, R, n)]);
                 const double y = (u == v) ? 0.0 : d[u] * pu - sum[j];
                 AP[i] = y;
                 rp[j] += Rr[i] * pu;
@@ -183,7 +202,7 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __rest
             double sum[kColPass];
 #pragma unroll
             for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
-            gather_rows(beg, end, 1, col, weight, P32, R, c0 + lane, sum);
+            gather_rows(beg, end, 1, col, weight, P32, R, n, c0 + lane, sum);
             finish(u, sum);
         }
         for (int64_t base = b; base < n; base += kBlock * nb) {
@@ -202,7 +221,7 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __rest
                     double sum[kColPass];
 #pragma unroll
                     for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
-                    gather_rows(beg + wib, end, kWavesPerBlock, col, weight, P32, R, c0 + lane, sum);
+                    gather_rows(beg + wib, end, kWavesPerBlock, col, weight, P32, R, n, c0 + lane, sum);
 #pragma unroll
                     for (int j = 0; j < kColPass; ++j) lds[wib][lane + j * kWave] = sum[j];
                     __syncthreads();
@@ -255,7 +274,7 @@ __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* _
         for (int64_t u = wave; u < n; u += nw) {
             if (c >= R || u == v) continue;
             const int64_t i = u * R + c;
-            const double p = static_cast<double>(P32[i]);
+            const double p = static_cast<double>(P32[p_index(u, c, R, n)]);
             X[i] = X[i] + alpha * p;
             const double r_old = Rr[i];
             const double r = r_old - alpha * AP[i];
@@ -282,7 +301,8 @@ __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars
         if (u == v) continue;
         const int32_t c = static_cast<int32_t>(i - u * R);
         const double z = Rr[i] / d[u];
-        P32[i] = static_cast<float>(z + sc[c].beta * static_cast<double>(P32[i]));
+        const int64_t pi = p_index(u, c, R, n);
+        P32[pi] = static_cast<float>(z + sc[c].beta * static_cast<double>(P32[pi]));
     }
 }
 
