@@ -261,35 +261,34 @@ int64_t spmm_resident_waves() {
     return w < kMaxWaves ? w : kMaxWaves;
 }
 
+// X += alpha P, r -= alpha AP, and the partial dots z.r, z.r_old, r.r.  One thread per (row,
+// column) element, rows strided, so every load and store is a contiguous stream; the thread
+// count is a multiple of R, so thread t keeps column t mod R and its partials fill slot t
+// (virtual wave t / R of the column-partial layout).
 __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
                             const double* __restrict__ d, double* __restrict__ X, double* __restrict__ Rr,
                             const float* __restrict__ P32, const double* __restrict__ AP, double* __restrict__ part) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-    for (int32_t c0 = 0; c0 < R; c0 += kWave) {
-        const int32_t c = c0 + lane;
-        double zr = 0.0, zro = 0.0, rr = 0.0;
-        const double alpha = (c < R) ? sc[c].alpha : 0.0;
-        for (int64_t u = wave; u < n; u += nw) {
-            if (c >= R || u == v) continue;
-            const int64_t i = u * R + c;
-            const double p = static_cast<double>(P32[p_index(u, c, R, n)]);
-            X[i] = X[i] + alpha * p;
-            const double r_old = Rr[i];
-            const double r = r_old - alpha * AP[i];
-            Rr[i] = r;
-            const double z = r / d[u];
-            zr += z * r;
-            zro += z * r_old;
-            rr += r * r;
-        }
-        if (c < R) {
-            part[(wave * R + c) * 3] = zr;
-            part[(wave * R + c) * 3 + 1] = zro;
-            part[(wave * R + c) * 3 + 2] = rr;
-        }
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t rows_step = static_cast<int64_t>(gridDim.x) * blockDim.x / R;
+    const int32_t c = static_cast<int32_t>(t % R);
+    const double alpha = sc[c].alpha;
+    double zr = 0.0, zro = 0.0, rr = 0.0;
+    for (int64_t u = t / R; u < n; u += rows_step) {
+        if (u == v) continue;
+        const int64_t i = u * R + c;
+        const double p = static_cast<double>(P32[p_index(u, c, R, n)]);
+        X[i] = X[i] + alpha * p;
+        const double r_old = Rr[i];
+        const double r = r_old - alpha * AP[i];
+        Rr[i] = r;
+        const double z = r / d[u];
+        zr += z * r;
+        zro += z * r_old;
+        rr += r * r;
     }
+    part[t * 3] = zr;
+    part[t * 3 + 1] = zro;
+    part[t * 3 + 2] = rr;
 }
 
 __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
@@ -609,6 +608,11 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
     const int32_t nw = static_cast<int32_t>(nwaves);
     const int32_t rows_per_block = static_cast<int32_t>((static_cast<int64_t>(n) + wave_blocks - 1) / wave_blocks);
     const unsigned col_blocks = blocks_for(R, 64);
+    // the update runs R * m blocks: m * kBlock rows in flight per column, m * kBlock partial
+    // slots per column (at most kMaxWaves)
+    const int64_t upd_m = blocks_for(n, kBlock) < kMaxWaves / kBlock ? blocks_for(n, kBlock) : kMaxWaves / kBlock;
+    const unsigned upd_blocks = static_cast<unsigned>(upd_m * R);
+    const int32_t upd_nw = static_cast<int32_t>(upd_m * kBlock);
     const double tol2 = tol * tol;
     hipLaunchKernelGGL(bpcg_init, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
                        L.part);
@@ -623,9 +627,9 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
             hipLaunchKernelGGL(bpcg_spmm, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->row_ptr, g->col,
                                g->weight, g->strength, L.P32, L.Y, L.AP, L.part);
             hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 1, tol2);
-            hipLaunchKernelGGL(bpcg_update, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
+            hipLaunchKernelGGL(bpcg_update, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
                                L.Y, L.P32, L.AP, L.part);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 2, tol2);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, L.sc, 2, tol2);
             hipLaunchKernelGGL(bpcg_direction, dim3(flat), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y, L.P32);
         }
         RWC_HIP(hipGetLastError());
