@@ -182,8 +182,10 @@ typedef struct rwc_tune_result {
     double steps_per_s;          /* walk steps per second of the winning probe               */
     int32_t candidates;          /* probes run (0 when served from the cache)                */
     int32_t cached;              /* 1 if the result came from the per-process cache          */
-    uint32_t flags;              /* sampler flags of the winner: RWC_SAMPLE_PATH_RING or
-                                    RWC_SAMPLE_NO_PATH_RING for walker teams, else 0         */
+    uint32_t flags;              /* schedule flags of the winner: for walker teams one of
+                                    each pair PATH_RING / NO_PATH_RING, SHARED_STARTS /
+                                    SPREAD_STARTS, ID_STARTS / BFS_STARTS, or 0 when the
+                                    automatic schedule won; 0 for one walker per tree       */
     int32_t reserved;
 } rwc_tune_result;
 
@@ -192,12 +194,13 @@ typedef struct rwc_tune_result {
 int rwc_autotune_workspace(const rwc_csr* g, const rwc_sample_params* p, int64_t budget_bytes,
                            size_t* bytes);
 
-/* Chooses walkers_per_tree, trees_in_flight and the path ring for sampling `g` with parameters
- * `p` by timing one batch of each candidate (1, 8, 16, 32 or 64 walkers per tree; about 2^16,
- * 2^17 or 2^18 concurrent walkers or all trees at once; teams with and without the ring; slot
- * state within budget_bytes) on the real sample range, and caches the winner per graph class
- * (log2 n, mean degree, weighted, log2 l) for the process.  The forest does not depend on the
- * choice, only the speed.  Synchronises `stream`. */
+/* Chooses walkers_per_tree, trees_in_flight and the team schedule for sampling `g` with
+ * parameters `p` by timing one batch of each candidate on the real sample range: first 1, 8,
+ * 16, 32 or 64 walkers per tree with one or two device-fulls of resident waves or all trees in
+ * flight (slot state within budget_bytes) under the automatic schedule, then, for a winning
+ * team, all eight combinations of path ring, start sharing and start order.  Caches the winner
+ * per graph class (log2 n, mean degree, weighted, log2 l) for the process.  The forest does not
+ * depend on the choice, only the speed.  Synchronises `stream`. */
 int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p, int64_t budget_bytes,
                          rwc_tune_result* out, void* ws, size_t ws_bytes, void* stream);
 

@@ -183,10 +183,10 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
 
 def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
              budget_bytes: int = 64 << 30) -> dict:
-    """Times one batch of each candidate (walkers per tree, trees in flight, path ring) and
-    returns the fastest (rwc_autotune_sampler); cached per graph class for the process.
-    `path_ring` is None for one walker per tree, else whether the winner used the ring (pass
-    it to sample_forests)."""
+    """Times one batch of each candidate (walkers per tree and trees in flight, then the team
+    schedule) and returns the fastest (rwc_autotune_sampler); cached per graph class for the
+    process.  `path_ring`, `starts` and `bfs_starts` are the winner's schedule in the form
+    sample_forests takes (None / "auto" when the automatic schedule won)."""
     L = _lib.lib()
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=-1)
     size = ctypes.c_size_t()
@@ -196,14 +196,13 @@ def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
     r = TuneResult()
     check(L.rwc_autotune_sampler(ctypes.byref(graph.csr), ctypes.byref(p), int(budget_bytes), ctypes.byref(r),
                                  _ptr(ws), ws.numel(), _stream()), "rwc_autotune_sampler")
-    ring = None
-    if r.flags & _lib.RWC_SAMPLE_PATH_RING:
-        ring = True
-    elif r.flags & _lib.RWC_SAMPLE_NO_PATH_RING:
-        ring = False
+    def pick(on, off, yes, no, neither):
+        return yes if r.flags & on else (no if r.flags & off else neither)
     return {"walkers_per_tree": r.walkers_per_tree, "trees_in_flight": r.trees_in_flight,
             "steps_per_s": r.steps_per_s, "candidates": r.candidates, "cached": bool(r.cached),
-            "path_ring": ring}
+            "path_ring": pick(_lib.RWC_SAMPLE_PATH_RING, _lib.RWC_SAMPLE_NO_PATH_RING, True, False, None),
+            "starts": pick(_lib.RWC_SAMPLE_SPREAD_STARTS, _lib.RWC_SAMPLE_SHARED_STARTS, "spread", "shared", "auto"),
+            "bfs_starts": pick(_lib.RWC_SAMPLE_BFS_STARTS, _lib.RWC_SAMPLE_ID_STARTS, True, False, None)}
 
 
 def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor | None = None,

@@ -1,6 +1,7 @@
-// rwc_autotune_sampler: picks walkers per tree, trees in flight and (for walker teams) the LDS
-// path ring for a graph by timing short probes of the real sampler, and caches the winner per
-// graph class for the process.
+// rwc_autotune_sampler: picks walkers per tree, trees in flight and (for walker teams) the
+// schedule -- LDS path ring, shared or spread starts, ascending or breadth-first start order --
+// for a graph by timing short probes of the real sampler, and caches the winner per graph class
+// for the process.
 //
 // The sampler's outputs are a fixed function of (graph, seed, sample index), so the choice
 // only changes speed.  Throughput depends on the number of concurrent walkers, on the state
@@ -20,7 +21,7 @@ namespace {
 struct Candidate {
     int32_t W;
     int64_t T;
-    uint32_t flags;   // RWC_SAMPLE_PATH_RING or RWC_SAMPLE_NO_PATH_RING for teams, else 0
+    uint32_t flags;   // schedule flags (0 = the automatic schedule)
 };
 
 using ClassKey = std::tuple<int, int, int, int>;  // log2 n, mean degree, weighted, log2 l
@@ -37,9 +38,9 @@ ClassKey class_of(const rwc_csr* g, int64_t l) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// One walker per tree with every tree in flight, and teams of 8 to 64 walkers with one or two
-// device-fulls of resident waves or every tree in flight (the last avoids batch tails), each
-// with and without the path ring, all capped by the state budget.
+// Stage 1: one walker per tree with every tree in flight, and teams of 8 to 64 walkers with one
+// or two device-fulls of resident waves or every tree in flight (the last avoids batch tails),
+// all capped by the state budget, under the automatic schedule.
 std::vector<Candidate> candidates(const rwc_csr* g, int64_t l, int64_t budget_bytes) {
     std::vector<Candidate> out;
     const int64_t stride = round_up(g->n, 8);
@@ -52,12 +53,7 @@ std::vector<Candidate> candidates(const rwc_csr* g, int64_t l, int64_t budget_by
         if (T < S) return;
         for (const Candidate& c : out)
             if (c.W == W && c.T == T) return;
-        if (W == 1) {
-            out.push_back({W, T, 0u});
-        } else {
-            out.push_back({W, T, RWC_SAMPLE_PATH_RING});
-            out.push_back({W, T, RWC_SAMPLE_NO_PATH_RING});
-        }
+        out.push_back({W, T, 0u});
     };
     add(1, l);
     const int64_t resident = team_resident_waves(g->bfs_depth > 32);
@@ -67,6 +63,17 @@ std::vector<Candidate> candidates(const rwc_csr* g, int64_t l, int64_t budget_by
         add(W, 2 * resident * S);
         add(W, l);
     }
+    return out;
+}
+
+// Stage 2, for a winning team: every combination of path ring, start sharing and start order.
+std::vector<Candidate> schedules(const Candidate& best) {
+    std::vector<Candidate> out;
+    if (best.W == 1) return out;
+    for (uint32_t ring : {RWC_SAMPLE_PATH_RING, RWC_SAMPLE_NO_PATH_RING})
+        for (uint32_t share : {RWC_SAMPLE_SHARED_STARTS, RWC_SAMPLE_SPREAD_STARTS})
+            for (uint32_t order : {RWC_SAMPLE_ID_STARTS, RWC_SAMPLE_BFS_STARTS})
+                out.push_back({best.W, best.T, ring | share | order});
     return out;
 }
 
@@ -147,7 +154,8 @@ extern "C" int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p
     TuneLayout L = carve_tune(ws, g, sb);
     rwc_tune_result best{};
     best.steps_per_s = -1.0;
-    for (const Candidate& c : cand) {
+    Candidate best_c = cand.front();
+    auto probe = [&](const Candidate& c) -> int {
         rwc_sample_params q = *p;
         q.walkers_per_tree = c.W;
         q.trees_in_flight = static_cast<int32_t>(c.T);
@@ -168,8 +176,12 @@ extern "C" int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p
             best.walkers_per_tree = c.W;
             best.trees_in_flight = static_cast<int32_t>(c.T);
             best.flags = c.flags;
+            best_c = c;
         }
-    }
+        return RWC_OK;
+    };
+    for (const Candidate& c : cand) RWC_CHECK(probe(c));
+    for (const Candidate& c : schedules(best_c)) RWC_CHECK(probe(c));
     best.cached = 0;
     {
         std::lock_guard<std::mutex> lock(g_mu);

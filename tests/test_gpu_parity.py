@@ -312,9 +312,11 @@ def test_autotuner_choice_does_not_change_the_forest(oracle_runs):
     t = P.autotune(Gd, 200, 2001)
     assert t["candidates"] >= 2 and not t["cached"]
     assert t["walkers_per_tree"] in (1, 8, 16, 32, 64) and t["trees_in_flight"] >= 1
-    assert (t["path_ring"] is None) == (t["walkers_per_tree"] == 1)
+    if t["walkers_per_tree"] == 1:
+        assert t["path_ring"] is None and t["starts"] == "auto" and t["bfs_starts"] is None
     s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=t["walkers_per_tree"],
-                         trees_in_flight=t["trees_in_flight"], path_ring=t["path_ring"])
+                         trees_in_flight=t["trees_in_flight"], path_ring=t["path_ring"], starts=t["starts"],
+                         bfs_starts=t["bfs_starts"])
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
     again = P.autotune(Gd, 200, 2001)
