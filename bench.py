@@ -31,24 +31,30 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_team_ba1m_traffic.json")
 SAMPLER_SOURCES = ("paper_2510_20604_amd/csrc/sampler.hip", "paper_2510_20604_amd/csrc/device.hpp")
 
 
-def sampler_sha256() -> str:
+def sampler_code_sha256() -> str:
+    """SHA-256 of the walk kernel's sources with comments removed and whitespace collapsed: the
+    committed counters stay valid exactly while the code they were taken on is unchanged."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in SAMPLER_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
 def measured_counters(kernel: str, trees: int, trees_in_flight: int):
     """The committed counter summary of the walk launch (HBM bytes, L2 misses), or None when it
-    is missing or was taken on other sources, another kernel or another plan."""
+    is missing or was taken on other code, another kernel or another plan."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if (t.get("sources_sha256") != sampler_sha256() or t.get("kernel") != kernel or t.get("trees") != trees
+    if (t.get("code_sha256") != sampler_code_sha256() or t.get("kernel") != kernel or t.get("trees") != trees
             or t.get("trees_in_flight") != trees_in_flight):
         return None
     return t

@@ -440,11 +440,12 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
         const bool w_owned = (w & kOwned) != 0;
         const bool w_mine = w_owned && st_owner(w) == tl;
 
-        // ---- decide.  Writes of this iteration: the departure word of the head, issued as
-        // soon as it is known (no lane reads state words again before the iteration's fence,
-        // and issuing it early lets it drain while the rest of the iteration runs; measured
-        // faster than issuing it with the other writes), or one chase store; then either a
-        // batch of final-word stores of ring entries or one compare-and-swap claim of `node`.
+        // ---- decide.  Writes of this iteration: without the ring, the departure word of the
+        // head, issued as soon as it is known (no lane reads state words again before the
+        // iteration's fence, and issuing it early lets it drain while the rest of the iteration
+        // runs; measured faster than issuing it with the other writes), or one chase store;
+        // then either a batch of final-word stores of ring entries or one compare-and-swap
+        // claim of `node` (whose push may store the word of the entry leaving the ring).
         bool departed = false;
         uint32_t st_node = kNoNode;
         uint64_t st_word = 0;
