@@ -2,8 +2,10 @@
 
 BA(n = 1e6, m = 5), 10^4 trees: the automatic plan (64-walker teams, one batch) must
 reproduce the oracle's trees: parent arrays of sampled trees, the checksum of every tree and
-the visit totals, plus properties that hold at any size.  R-MAT scale 23 (largest component, weighted),
-5000 trees in a persistent launch: the same, and the adjoint's Euler identity for 1000 targets.
+the visit totals, plus properties that hold at any size.  The 256-graph batch in its
+persistent, hipGraph-captured launch: sampled trees of BA graphs and grids against the oracle.
+R-MAT scale 23 (largest component, weighted), 5000 trees in a persistent launch: the same, and
+the adjoint's Euler identity for 1000 targets.
 """
 import numpy as np
 import pytest
@@ -51,6 +53,34 @@ def test_ba1m_bench_configuration_matches_oracle_on_every_tree():
     np.testing.assert_array_equal(P.as_uint64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(P.as_uint64(s["counts_sq"]), ref["visits_sq"])
     assert int(P.as_uint64(s["total_steps"])[0]) == int(ref["steps"].sum())
+
+
+def test_batch256_bench_configuration_sampled_trees():
+    """The 256-graph batch exactly as bench.py launches it (persistent, hipGraph-captured,
+    automatic plan: breadth-first starts for the meshes): sampled trees of BA graphs and grids,
+    the largest grid among them, match the oracle's serial trees, and every graph's visit totals
+    obey the per-tree invariants."""
+    gl = G.batch_mix(256, 1e3, 1e5, seed=1003)
+    l, seed = 1000, 2003
+    dev = [P.Graph(g.n, g.src, g.dst, g.w) for g in gl]
+    s = P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=False)
+    hashes = P.as_uint64(s["tree_hash"])
+    counts = P.as_uint64(s["counts"])
+    steps = P.as_uint64(s["total_steps"])
+    largest_grid = max(range(128, 256), key=lambda i: gl[i].n)
+    picks = [(0, 0), (64, 999), (127, 500), (130, 0), (200, 999), (largest_grid, 0), (largest_grid, 999)]
+    for gi, tree in picks:
+        g = gl[gi]
+        o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+        ref = W.fastwalk_sample(o, o.pivot, seed, gi, tree, 1)
+        assert int(hashes[gi, tree]) == int(ref["hash"][0]), f"graph {gi} tree {tree}"
+    off = 0
+    for gi, g in enumerate(gl):
+        c = counts[off:off + g.n]
+        off += g.n
+        o_piv = int(dev[gi].pivot)
+        assert c[o_piv] == 0 and (np.delete(c, o_piv) >= l).all(), f"graph {gi}"
+        assert int(c.sum()) == int(steps[gi])
 
 
 def test_rmat_scale23_sampled_trees_and_adjoint():
