@@ -27,3 +27,17 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _release_device_memory(request):
+    """The full-size GPU tests hold tens to over a hundred GB of tree state each; hand the
+    cached blocks back after every GPU test so that they do not add up within one process."""
+    yield
+    if "gpu" in request.keywords:
+        import gc
+
+        import torch
+        gc.collect()
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.empty_cache()
