@@ -83,6 +83,16 @@ __device__ __forceinline__ int64_t p_index(int64_t u, int32_t c, int32_t R, int6
     return p_block_base(b, n) + u * p_block_width(b, R) + (c - b * kWave);
 }
 
+// Per-wave partial dot products of the PCG kernels: value k of column c from wave (or partial
+// slot) w of nw lives at (k R + c) nw + w, so the reduction of one column reads contiguous
+// memory.
+__device__ __forceinline__ int64_t part_index(int k, int32_t c, int64_t w, int32_t R, int64_t nw) {
+    return (static_cast<int64_t>(k) * R + c) * nw + w;
+}
+
+// partials each thread of bpcg_scalars loads at once
+constexpr int kScalarBatch = 8;
+
 // One wave per row (grid-stride), lanes over columns.
 __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restrict__ d, double* __restrict__ Y,
                           double* __restrict__ X, float* __restrict__ P32, double* __restrict__ part) {
@@ -104,8 +114,8 @@ __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restr
             rr += r * r;
         }
         if (c < R) {
-            part[(wave * R + c) * 2] = zr;
-            part[(wave * R + c) * 2 + 1] = rr;
+            part[part_index(0, c, wave, R, nw)] = zr;
+            part[part_index(1, c, wave, R, nw)] = rr;
         }
     }
 }
@@ -178,6 +188,7 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __rest
     const int wib = threadIdx.x / kWave;
     const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib;
     const int64_t b = blockIdx.x, nb = gridDim.x;
+    const int64_t nw = nb * kWavesPerBlock;
     for (int32_t c0 = 0; c0 < R; c0 += kColPass * kWave) {
         double rp[kColPass], pap[kColPass];
 #pragma unroll
@@ -243,8 +254,8 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __rest
         for (int j = 0; j < kColPass; ++j) {
             const int32_t c = c0 + lane + j * kWave;
             if (c < R) {
-                part[(wave * R + c) * 2] = rp[j];
-                part[(wave * R + c) * 2 + 1] = pap[j];
+                part[part_index(0, c, wave, R, nw)] = rp[j];
+                part[part_index(1, c, wave, R, nw)] = pap[j];
             }
         }
     }
@@ -286,9 +297,10 @@ __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* _
         zro += z * r_old;
         rr += r * r;
     }
-    part[t * 3] = zr;
-    part[t * 3 + 1] = zro;
-    part[t * 3 + 2] = rr;
+    const int64_t slot = t / R;
+    part[part_index(0, c, slot, R, rows_step)] = zr;
+    part[part_index(1, c, slot, R, rows_step)] = zro;
+    part[part_index(2, c, slot, R, rows_step)] = rr;
 }
 
 __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
@@ -312,13 +324,32 @@ __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict
                              double tol2) {
     __shared__ double la[kBlock], lb[kBlock], le[kBlock];
     const int32_t c = blockIdx.x;
-    const int stride = (mode == 2) ? 3 : 2;
+    const double* qa = part + part_index(0, c, 0, R, nwaves);
+    const double* qb = part + part_index(1, c, 0, R, nwaves);
+    const double* qe = part + part_index(2, c, 0, R, nwaves);
     double a = 0.0, b = 0.0, e = 0.0;
-    for (int32_t w = threadIdx.x; w < nwaves; w += kBlock) {
-        const double* q = part + (static_cast<int64_t>(w) * R + c) * stride;
-        a += q[0];
-        b += q[1];
-        if (stride == 3) e += q[2];
+    // kScalarBatch loads in flight per thread (one at a time leaves this kernel waiting on
+    // memory latency once per partial); the sums keep the order of a plain strided loop
+    int32_t w = threadIdx.x;
+    for (; w + (kScalarBatch - 1) * kBlock < nwaves; w += kScalarBatch * kBlock) {
+        double va[kScalarBatch], vb[kScalarBatch], ve[kScalarBatch];
+#pragma unroll
+        for (int j = 0; j < kScalarBatch; ++j) {
+            va[j] = qa[w + j * kBlock];
+            vb[j] = qb[w + j * kBlock];
+            ve[j] = (mode == 2) ? qe[w + j * kBlock] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kScalarBatch; ++j) {
+            a += va[j];
+            b += vb[j];
+            if (mode == 2) e += ve[j];
+        }
+    }
+    for (; w < nwaves; w += kBlock) {
+        a += qa[w];
+        b += qb[w];
+        if (mode == 2) e += qe[w];
     }
     la[threadIdx.x] = a;
     lb[threadIdx.x] = b;
@@ -357,9 +388,22 @@ __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict
     sc[c] = s;
 }
 
+// Sum of v over the kBlock threads of a block in a fixed tree order; every thread gets it.
+__device__ double block_sum(double v, double* lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double total = lds[0];
+    __syncthreads();
+    return total;
+}
+
 // Column sums (for centring) in two fixed-order stages: block b sums its contiguous range of
-// rows per column (threads over columns, so the reads are coalesced), then one thread per
-// column adds the block partials in block order.
+// rows per column (threads over columns, so the reads are coalesced) into part[c nparts + b],
+// then one block per column adds its nparts partials.
 __global__ void column_partials(int32_t n, int32_t R, int32_t rows_per_block, const double* __restrict__ M,
                                 double* __restrict__ part) {
     const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
@@ -367,17 +411,19 @@ __global__ void column_partials(int32_t n, int32_t R, int32_t rows_per_block, co
     for (int32_t c = threadIdx.x; c < R; c += blockDim.x) {
         double s = 0.0;
         for (int64_t u = lo; u < hi; ++u) s += M[u * R + c];
-        part[static_cast<int64_t>(blockIdx.x) * R + c] = s;
+        part[static_cast<int64_t>(c) * gridDim.x + blockIdx.x] = s;
     }
 }
 
-__global__ void column_finish(int32_t R, int32_t nparts, const double* __restrict__ part, double* __restrict__ out,
+__global__ void column_finish(int32_t nparts, const double* __restrict__ part, double* __restrict__ out,
                               double scale) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= R) return;
+    __shared__ double lds[kBlock];
+    const int32_t c = blockIdx.x;
+    const double* q = part + static_cast<int64_t>(c) * nparts;
     double s = 0.0;
-    for (int32_t b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * R + c];
-    out[c] = s * scale;
+    for (int32_t b = threadIdx.x; b < nparts; b += kBlock) s += q[b];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[c] = s * scale;
 }
 
 __global__ void center_columns(int32_t n, int32_t R, const double* __restrict__ mean, double* __restrict__ M) {
@@ -401,13 +447,8 @@ __global__ void dld_partials(int32_t n, int32_t R, int32_t rows_per_block, const
     const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
     double q = 0.0;
     for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) q += d[u] * Z[u * R + 1];
-    lds[threadIdx.x] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < kBlock; ++i) s += lds[i];
-        part[blockIdx.x] = s;
-    }
+    q = block_sum(q, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = q;
 }
 
 // trGL from the probe entries and dLd from the block partials (one block, fixed order).
@@ -418,14 +459,12 @@ __global__ void edge_scalars(int32_t R, int32_t count, const Entry* __restrict__
     double t = 0.0;
     for (int32_t i = threadIdx.x; i < count; i += blockDim.x)
         if (e[i].col >= 2) t += coef[e[i].col] * e[i].val * Z[static_cast<int64_t>(e[i].node) * R + e[i].col];
-    lds[threadIdx.x] = t;
-    __syncthreads();
+    t = block_sum(t, lds);
+    double q = 0.0;
+    for (int32_t b = threadIdx.x; b < nparts; b += kBlock) q += part[b];
+    q = block_sum(q, lds);
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < kBlock; ++i) s += lds[i];
-        out->trgl = s;
-        double q = 0.0;
-        for (int32_t b = 0; b < nparts; ++b) q += part[b];
+        out->trgl = t;
         out->dld = q;
     }
 }
@@ -607,7 +646,6 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
     nwaves = static_cast<int64_t>(wave_blocks) * kWavesPerBlock;
     const int32_t nw = static_cast<int32_t>(nwaves);
     const int32_t rows_per_block = static_cast<int32_t>((static_cast<int64_t>(n) + wave_blocks - 1) / wave_blocks);
-    const unsigned col_blocks = blocks_for(R, 64);
     // the update runs R * m blocks: m * kBlock rows in flight per column, m * kBlock partial
     // slots per column (at most kMaxWaves)
     const int64_t upd_m = blocks_for(n, kBlock) < kMaxWaves / kBlock ? blocks_for(n, kBlock) : kMaxWaves / kBlock;
@@ -649,7 +687,7 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
     // L^+ y = z - mean(z)
     // (the partial arrays reuse the PCG partials: kMaxWaves * R * 3 doubles >= wave_blocks * R)
     hipLaunchKernelGGL(column_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.X, L.part);
-    hipLaunchKernelGGL(column_finish, dim3(col_blocks), dim3(64), 0, s, R, static_cast<int32_t>(wave_blocks), L.part,
+    hipLaunchKernelGGL(column_finish, dim3(R), dim3(kBlock), 0, s, static_cast<int32_t>(wave_blocks), L.part,
                        L.colmean, 1.0 / n);
     hipLaunchKernelGGL(center_columns, dim3(flat), dim3(kBlock), 0, s, n, R, L.colmean, L.X);
     hipLaunchKernelGGL(dld_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.X, g->strength,
