@@ -137,7 +137,7 @@ template <int B>
 __device__ __forceinline__ void gather_batch(int32_t k, int32_t step, const int32_t* __restrict__ col,
                                              const float* __restrict__ weight, const float* __restrict__ P32,
                                              int32_t R, int64_t n, int32_t cbase, double* sum) {
-    int64_t w[B];
+    int32_t w[B];
     float t[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
@@ -154,7 +154,7 @@ __device__ __forceinline__ void gather_batch(int32_t k, int32_t step, const int3
             const float* __restrict__ Pb = P32 + p_block_base(blk, n) + (c - blk * kWave);
             float a[B];
 #pragma unroll
-            for (int i = 0; i < B; ++i) a[i] = Pb[w[i] * stride];
+            for (int i = 0; i < B; ++i) a[i] = Pb[static_cast<int64_t>(w[i]) * stride];
 #pragma unroll
             for (int i = 0; i < B; ++i) sum[j] += static_cast<double>(t[i]) * static_cast<double>(a[i]);
         }
@@ -194,28 +194,68 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __rest
         double rp[kColPass], pap[kColPass];
 #pragma unroll
         for (int j = 0; j < kColPass; ++j) rp[j] = pap[j] = 0.0;
+        // what one lane needs of row u itself to finish it: its P entries, residuals and d[u]
+        struct RowIn {
+            float pu[kColPass];
+            double rr[kColPass];
+            double du;
+        };
+        auto load_row = [&](int64_t u, RowIn& in) {
+            in.du = d[u];
+#pragma unroll
+            for (int j = 0; j < kColPass; ++j) {
+                const int32_t c = c0 + lane + j * kWave;
+                in.pu[j] = (c < R) ? P32[p_index(u, c, R, n)] : 0.0f;
+                in.rr[j] = (c < R) ? Rr[u * R + c] : 0.0;
+            }
+        };
         // finishes row u from its neighbour sums (one lane, its columns)
-        auto finish = [&](int64_t u, const double* sum) {
+        auto finish_row = [&](int64_t u, const double* sum, const RowIn& in) {
 #pragma unroll
             for (int j = 0; j < kColPass; ++j) {
                 const int32_t c = c0 + lane + j * kWave;
                 if (c >= R) continue;
-                const int64_t i = u * R + c;
-                const double pu = static_cast<double>(P32[p_index(u, c, R, n)]);
-                const double y = (u == v) ? 0.0 : d[u] * pu - sum[j];
-                AP[i] = y;
-                rp[j] += Rr[i] * pu;
+                const double pu = static_cast<double>(in.pu[j]);
+                const double y = (u == v) ? 0.0 : in.du * pu - sum[j];
+                AP[u * R + c] = y;
+                rp[j] += in.rr[j] * pu;
                 pap[j] += pu * y;
             }
         };
-        for (int64_t u = b + wib * nb; u < n; u += kWavesPerBlock * nb) {
-            const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
-            if (end - beg > kLongRow) continue;
-            double sum[kColPass];
+        auto finish = [&](int64_t u, const double* sum) {
+            RowIn in;
+            load_row(u, in);
+            finish_row(u, sum, in);
+        };
+        // A row's loads form a chain (row bounds, then entries, then gathers); the next row's
+        // bounds and this row's own inputs are loaded before this row's gathers, so their
+        // latency overlaps the chain instead of adding to it.
+        const int64_t ustep = static_cast<int64_t>(kWavesPerBlock) * nb;
+        int64_t u = b + wib * nb;
+        int32_t beg = 0, end = 0;
+        if (u < n) {
+            beg = row_ptr[u];
+            end = row_ptr[u + 1];
+        }
+        while (u < n) {
+            const int64_t un = u + ustep;
+            int32_t nbeg = 0, nend = 0;
+            if (un < n) {
+                nbeg = row_ptr[un];
+                nend = row_ptr[un + 1];
+            }
+            if (end - beg <= kLongRow) {
+                RowIn in;
+                load_row(u, in);
+                double sum[kColPass];
 #pragma unroll
-            for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
-            gather_rows(beg, end, 1, col, weight, P32, R, n, c0 + lane, sum);
-            finish(u, sum);
+                for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
+                gather_rows(beg, end, 1, col, weight, P32, R, n, c0 + lane, sum);
+                finish_row(u, sum, in);
+            }
+            u = un;
+            beg = nbeg;
+            end = nend;
         }
         for (int64_t base = b; base < n; base += kBlock * nb) {
             const int64_t u = base + threadIdx.x * nb;
