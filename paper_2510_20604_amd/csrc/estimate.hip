@@ -84,18 +84,54 @@ __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_p
     constexpr int kGroups = kBlock / kRowLanes;
     const int64_t b = blockIdx.x, nb = gridDim.x;
     double acc = 0.0;
-    for (int64_t u = b + group * nb; u < n; u += kGroups * nb) {
-        const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
-        if (end - beg > kLongRow) continue;
-        double s = 0.0;
-        for (int32_t k = beg + sub; k < end; k += kRowLanes) s += static_cast<double>(weight[k]) * p[col[k]];
-#pragma unroll
-        for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-        if (sub == 0) {
-            const double y = (u == v) ? 0.0 : d[u] * p[u] - s;
-            ap[u] = y;
-            acc += p[u] * y;
+    // A row's loads form a chain (bounds, entries, gathers).  The next row's bounds and this
+    // row's d and p are loaded before this row's entries, and a lane loads four entries, then
+    // their four gathers, before it adds them (in entry order), so fewer latencies follow one
+    // another.
+    const int64_t ustep = static_cast<int64_t>(kGroups) * nb;
+    int64_t u = b + group * nb;
+    int32_t beg = 0, end = 0;
+    if (u < n) {
+        beg = row_ptr[u];
+        end = row_ptr[u + 1];
+    }
+    while (u < n) {
+        const int64_t un = u + ustep;
+        int32_t nbeg = 0, nend = 0;
+        if (un < n) {
+            nbeg = row_ptr[un];
+            nend = row_ptr[un + 1];
         }
+        if (end - beg <= kLongRow) {
+            const double du = d[u], pu = p[u];
+            double s = 0.0;
+            int32_t k = beg + sub;
+            for (; k + 3 * kRowLanes < end; k += 4 * kRowLanes) {
+                int32_t c[4];
+                float w[4];
+                double x[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    c[i] = col[k + i * kRowLanes];
+                    w[i] = weight[k + i * kRowLanes];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[i] = p[c[i]];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s += static_cast<double>(w[i]) * x[i];
+            }
+            for (; k < end; k += kRowLanes) s += static_cast<double>(weight[k]) * p[col[k]];
+#pragma unroll
+            for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+            if (sub == 0) {
+                const double y = (u == v) ? 0.0 : du * pu - s;
+                ap[u] = y;
+                acc += pu * y;
+            }
+        }
+        u = un;
+        beg = nbeg;
+        end = nend;
     }
     for (int64_t base = b; base < n; base += kBlock * nb) {
         const int64_t u = base + threadIdx.x * nb;
