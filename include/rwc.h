@@ -244,7 +244,12 @@ typedef struct rwc_backward_params {
 } rwc_backward_params;
 
 /* Workspace for rwc_backward with this target list (its size depends on the number of
- * solve columns, hence on the targets and the signs of their g values). */
+ * solve columns, hence on the targets and the signs of their g values).  Both calls return
+ * RWC_ERR_INVALID_ARG for k < 0 or a target outside [0, n), and RWC_ERR_TOO_LARGE, before
+ * building anything, for more than 2^24 solve columns (2 + the
+ * number of targets when exact, else 2 + k per sign class present) or more than 2^31 - 1
+ * right-hand-side entries (num_targets plus, per target, one per probe column of its sign
+ * class, or one when exact). */
 int rwc_backward_workspace(const rwc_csr* g, int32_t num_targets, const int32_t* targets,
                            const double* gvals, const rwc_backward_params* bp, size_t* bytes);
 

@@ -580,19 +580,39 @@ struct Probes {
     double G = 0.0;
 };
 
+// Bounds of one adjoint call: solve columns (grid sizes and column indices stay in 32 bits)
+// and right-hand-side entries (counted in int32 on the device).
+constexpr int64_t kMaxSolveColumns = int64_t{1} << 24;
+constexpr int64_t kMaxProbeEntries = 0x7FFFFFFF;
+
 int plan_probes(const rwc_csr* g, int32_t T, const int32_t* targets, const double* gvals,
                 const rwc_backward_params* bp, Probes* pr) {
     const int32_t n = g->n;
     const int32_t k = bp ? bp->k : 0;
+    if (k < 0) return fail(RWC_ERR_INVALID_ARG, "k must be >= 0");
+    if (n < 2) return fail(RWC_ERR_INVALID_ARG, "the graph has %d nodes", n);
     bool pos = false, neg = false;
+    int64_t npos = 0, nneg = 0;
     for (int32_t t = 0; t < T; ++t) {
         if (targets[t] < 0 || targets[t] >= n) return fail(RWC_ERR_INVALID_ARG, "target %d out of range", targets[t]);
         if (!std::isfinite(gvals[t])) return fail(RWC_ERR_INVALID_ARG, "g value of target %d is not finite", t);
         pos |= gvals[t] > 0.0;
         neg |= gvals[t] < 0.0;
+        npos += gvals[t] > 0.0;
+        nneg += gvals[t] < 0.0;
         pr->G += gvals[t];
     }
-    const int32_t P = (k == 0) ? T : k * ((pos ? 1 : 0) + (neg ? 1 : 0));
+    // sizes checked before anything is built: columns 2 + P, entries T (g column) plus one
+    // per target and probe column of its sign class (one per target when exact)
+    const int64_t P64 = (k == 0) ? T : static_cast<int64_t>(k) * ((pos ? 1 : 0) + (neg ? 1 : 0));
+    const int64_t nent64 = T + ((k == 0) ? T : static_cast<int64_t>(k) * (npos + nneg));
+    if (2 + P64 > kMaxSolveColumns)
+        return fail(RWC_ERR_TOO_LARGE, "%lld solve columns (limit %lld)", static_cast<long long>(2 + P64),
+                    static_cast<long long>(kMaxSolveColumns));
+    if (nent64 > kMaxProbeEntries)
+        return fail(RWC_ERR_TOO_LARGE, "%lld right-hand-side entries (limit %lld)", static_cast<long long>(nent64),
+                    static_cast<long long>(kMaxProbeEntries));
+    const int32_t P = static_cast<int32_t>(P64);
     pr->R = 2 + P;
     pr->coef.assign(pr->R, 0.0);
     pr->colmean.assign(pr->R, 0.0);
@@ -658,7 +678,6 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
     clear_error();
     if (!g || !grad_w || num_targets < 1 || !targets || !gvals)
         return fail(RWC_ERR_INVALID_ARG, "g, targets, gvals and grad_w are required");
-    if (bp && bp->k < 0) return fail(RWC_ERR_INVALID_ARG, "k must be >= 0");
     Probes pr;
     RWC_CHECK(plan_probes(g, num_targets, targets, gvals, bp, &pr));
     const int32_t n = g->n, R = pr.R, v = g->pivot;

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -109,3 +110,30 @@ def test_library_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_backward_sizes_are_checked_before_planning():
+    """The adjoint's workspace query sizes the solve from the target list on the host: a probe
+    count or target list past the column and entry limits is refused with RWC_ERR_TOO_LARGE,
+    without building the right-hand sides."""
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, vol=8000.0, row_ptr=8, col=8, rec=8,
+                    bfs_order=8)
+    t = np.array([3, 7, 11], dtype=np.int32)
+    gv = np.array([1.0, -2.0, 0.5], dtype=np.float64)
+    size = ctypes.c_size_t()
+
+    def query(k):
+        bp = _lib.BackwardParams(k=k, seed=1)
+        return lib.rwc_backward_workspace(ctypes.byref(g), t.size, t.ctypes.data, gv.ctypes.data, ctypes.byref(bp),
+                                          ctypes.byref(size))
+
+    assert query(64) == 0
+    cols64 = 2 + 2 * 64                       # both sign classes present
+    assert size.value >= 1000 * cols64 * (8 * 3 + 4)
+    assert query(0) == 0                      # exact: one column per target
+    assert query(1 << 23) == -7               # 2 + 2^24 columns
+    assert query(-1) == -1
+    # entry limit: 2^30 probes per class with 3 targets -> about 3 * 2^30 entries
+    assert query(1 << 30) == -7
