@@ -137,3 +137,19 @@ def test_backward_sizes_are_checked_before_planning():
     assert query(-1) == -1
     # entry limit: 2^30 probes per class with 3 targets -> about 3 * 2^30 entries
     assert query(1 << 30) == -7
+
+
+def test_backward_refuses_bad_sizes_before_device_work():
+    """rwc_backward plans its columns on the host before any device call, so a negative or
+    oversized k comes back as an error without touching the (dummy) device pointers."""
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, vol=8000.0, row_ptr=8, col=8, rec=8,
+                    bfs_order=8)
+    t = np.array([3, 7], dtype=np.int32)
+    gv = np.array([1.0, -2.0], dtype=np.float64)
+    it = ctypes.c_int32()
+    for k, code in ((-1, -1), (1 << 23, -7), (1 << 30, -7)):
+        bp = _lib.BackwardParams(k=k, seed=1)
+        assert lib.rwc_backward(ctypes.byref(g), t.size, t.ctypes.data, gv.ctypes.data, ctypes.byref(bp), 8,
+                                ctypes.byref(it), 8, 1 << 20, None) == code
