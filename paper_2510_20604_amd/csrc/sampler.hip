@@ -1020,7 +1020,7 @@ struct CaptureStream {
 int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
     if (!graphs || !p || G < 1) return fail(RWC_ERR_INVALID_ARG, "graphs/params missing or num_graphs < 1");
     if (p->num_samples < 1) return fail(RWC_ERR_INVALID_ARG, "num_samples must be positive");
-    if (p->sample_begin < 0 || p->sample_begin + p->num_samples > (1ll << 32))
+    if (p->sample_begin < 0 || p->num_samples > (1ll << 32) || p->sample_begin > (1ll << 32) - p->num_samples)
         return fail(RWC_ERR_INVALID_ARG, "sample indices must lie in [0, 2^32)");
     if (p->root >= 0 && G != 1) return fail(RWC_ERR_INVALID_ARG, "an explicit root needs a single graph");
     if (p->root >= graphs[0].n) return fail(RWC_ERR_INVALID_ARG, "root out of range");

@@ -67,6 +67,11 @@ def test_sample_workspace_scales_with_trees_in_flight():
     p.walkers_per_tree = 0
     p.num_samples = 0
     assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(b)) == -1
+    # the sample range must lie in [0, 2^32); the check does not overflow for huge values
+    for begin, count in (((1 << 32) - 10, 10), ((1 << 32) - 10, 11), (1 << 62, 1 << 62), (1, (1 << 63) - 1)):
+        p.sample_begin, p.num_samples, p.trees_in_flight = begin, count, 8
+        want = 0 if begin + count <= (1 << 32) else -1
+        assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(b)) == want
 
 
 def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
