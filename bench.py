@@ -1,13 +1,16 @@
 """FastWalk throughput on one MI355X.
 
-Default workload: Barabasi-Albert graph, n = 1,000,000, 5 edges per new node (power-law
-degrees, unit weights), 10,000 rooted spanning trees sampled by Wilson's algorithm, RWC
-assembled in FP64.  One timed step is the whole hot path on device-resident inputs: CSR build
-(rwc_build_csr), sampling (rwc_sample_forests) and the pivot solve plus assembly
-(rwc_estimate).
+Default workload: the largest single-GPU configuration -- R-MAT scale 23 ((a, b, c) = (.57,
+.19, .19), 5 edge draws per node, largest connected component: 3.34 M nodes, 41.3 M edges),
+weights U[1, 4], 5000 rooted spanning trees sampled by Wilson's algorithm in one persistent
+launch, RWC assembled in FP64, plus the adjoint of the RWC sum over 1000 targets (JL sketch,
+k = 64).  One timed step is the whole hot path on device-resident inputs: CSR build
+(rwc_build_csr), sampling (rwc_sample_forests), the pivot solve plus assembly (rwc_estimate)
+and the adjoint (rwc_backward).
 
 Prints one JSON line.  `value` is rooted trees per second for the whole step; walk steps/s,
-the dominant kernel's roofline and the CPU oracle's rate on the host cores ride along.
+grad edges/s, the dominant kernel's roofline, the CPU oracle's rate on the host cores (all of
+them and one), and the BA(10^6) and BA(10^5) adjoint configurations ride along.
 """
 from __future__ import annotations
 
@@ -24,11 +27,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rooted trees/s + walk steps/s at fixed RWC rel. error; plain vs batched; grad edges/s"
 HBM_PEAK_GBS = 8000.0
-# HBM byte counters of the walk kernel on the default workload, taken with rocprofv3 (FETCH_SIZE
-# and WRITE_SIZE runs, scaled by the same counters on a plain copy kernel); valid only for the
-# sampler sources they were taken on, which the file records by SHA-256.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_team_ba1m_traffic.json")
-SAMPLER_SOURCES = ("paper_2510_20604_amd/csrc/sampler.hip", "paper_2510_20604_amd/csrc/device.hpp")
+# HBM byte counters of the walk kernel, per workload, taken with rocprofv3 (FETCH_SIZE and
+# WRITE_SIZE runs, scaled by the same counters on a plain copy kernel); valid only for the walk
+# kernel sources they were taken on, which each file records by SHA-256.
+TRAFFIC_FILES = {"rmat23": os.path.join(ROOT, "profiles", "wilson_team_rmat23_traffic.json"),
+                 "ba1m": os.path.join(ROOT, "profiles", "wilson_team_ba1m_traffic.json")}
+SAMPLER_SOURCES = ("paper_2510_20604_amd/csrc/walk.hpp", "paper_2510_20604_amd/csrc/select.hpp",
+                   "paper_2510_20604_amd/csrc/device.hpp")
 
 
 def sampler_code_sha256() -> str:
@@ -46,11 +51,11 @@ def sampler_code_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_counters(kernel: str, trees: int, trees_in_flight: int):
+def measured_counters(config: str, kernel: str, trees: int, trees_in_flight: int):
     """The committed counter summary of the walk launch (HBM bytes, L2 misses), or None when it
     is missing or was taken on other code, another kernel or another plan."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[config]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -65,7 +70,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="ba1m", choices=["ba1m", "er1000", "batch256", "grad100k", "rmat23"])
+    ap.add_argument("--config", default="rmat23", choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="rmat23: skip the BA(1e6) and BA(1e5)-adjoint side measurements")
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
     ap.add_argument("--walkers", type=int, default=0, help="walkers per tree (0 = automatic)")
     ap.add_argument("--tif", type=int, default=0, help="trees in flight (0 = automatic)")
@@ -101,22 +108,54 @@ def walk_accesses(total_steps: int, trees: int, n: int) -> float:
     return 4.0 * total_steps + trees * (2.0 * (n - 1) + n)
 
 
-def cpu_baseline(g, l, seed, seconds):
+def host_info() -> dict:
+    """Host cores visible to this process and the CPU model (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(g, l, seed, seconds, single_seconds=None):
+    """The oracle's serial Wilson sampler (C) on this host: on all cores available to the
+    process (the sample range split across threads), and on one core (the paper's
+    single-thread setting), each over a bounded prefix of the workload's trees."""
     from oracle import wilson
     o = wilson.OracleCSR(g.n, g.src, g.dst, g.w)
-    threads = max(1, min(16, os.cpu_count() or 1))
+    host = host_info()
+    # the host cores this process may use: all it sees, capped by the thread budget the
+    # environment sets for it (the GPU host shares its cores between GPUs)
+    threads = max(1, min(host["nproc"], int(os.environ.get("OMP_NUM_THREADS", host["nproc"]))))
     t0 = time.perf_counter()
     one = wilson.fastwalk_sample(o, o.pivot, seed, 0, 0, 1)
     t1 = time.perf_counter() - t0
+    print(f"cpu baseline: one tree in {t1:.2f} s", file=sys.stderr, flush=True)
     per_thread = max(1, int(seconds / max(t1, 1e-6)))
     nsamp = min(l, per_thread * threads)
     t0 = time.perf_counter()
     r = wilson.fastwalk_sample(o, o.pivot, seed, 0, 0, nsamp, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": nsamp / dt, "unit": "trees/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {nsamp} of the {l} trees (samples 0..{nsamp - 1}), serial Wilson "
-                      f"per thread, {threads} threads",
-            "walk_steps_per_s": float(r["steps"].sum()) / dt}, r
+    print(f"cpu baseline: {nsamp} trees on {threads} threads in {dt:.1f} s", file=sys.stderr, flush=True)
+    out = {"value": nsamp / dt, "unit": "trees/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {nsamp} of the {l} trees (samples 0..{nsamp - 1}), serial Wilson per thread, "
+                     f"{threads} threads",
+           "walk_steps_per_s": float(r["steps"].sum()) / dt, "host": host}
+    if single_seconds:
+        n1 = max(1, min(l, int(single_seconds / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        r1 = wilson.fastwalk_sample(o, o.pivot, seed, 0, 0, n1, threads=1)
+        d1 = time.perf_counter() - t0
+        print(f"cpu baseline: {n1} trees on 1 thread in {d1:.1f} s", file=sys.stderr, flush=True)
+        out["single_thread"] = {"value": n1 / d1, "unit": "trees/s", "cores": 1,
+                                "sample": f"first {n1} trees (samples 0..{n1 - 1}), one thread",
+                                "walk_steps_per_s": float(r1["steps"].sum()) / d1}
+    return out, r
 
 
 def batch_main(args):
@@ -133,8 +172,15 @@ def batch_main(args):
     dev = [P.Graph(g.n, g.src, g.dst, g.w, "cuda:0") for g in gl]
     torch.cuda.synchronize()
 
+    keep = {}
+
     def batched():
-        return P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=False)
+        # the same workspace and outputs each step: after the first call captures the launches
+        # into a hipGraph, the later calls replay it
+        r = P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=False,
+                             workspace=keep.get("workspace"), out=keep.get("out"))
+        keep["workspace"], keep["out"] = r["workspace"], r
+        return r
 
     def plain():
         out = []
@@ -173,6 +219,7 @@ def batch_main(args):
         "walk_steps_per_s": round(steps / tb, 1),
         "plain_trees_per_s": round(len(gl) * l / tp, 3), "plain_ms": round(1e3 * tp, 3),
         "batched_over_plain": round(tp / tb, 3), "bit_identical": bool(same),
+        "graph_replayed": sb["graph_replayed"],
     }
     print(json.dumps(line), flush=True)
 
@@ -188,12 +235,13 @@ def grad_main(args):
     t = np.random.default_rng(6).choice(g.n, size=100, replace=False).astype(np.int32)
     gv = np.ones(100)
     G = P.Graph(g.n, g.src, g.dst, g.w, "cuda:0")
+    gd = P.dense_g(g.n, t, gv, "cuda:0")
     for _ in range(args.warmup):
-        P.backward(G, t, gv, k=64, seed=2004, tol=1e-8)
+        P.backward(G, gd, k=64, seed=2004, tol=1e-8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = P.backward(G, t, gv, k=64, seed=2004, tol=1e-8)
+        r = P.backward(G, gd, k=64, seed=2004, tol=1e-8)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
     line = {"metric": METRIC, "value": round(g.m / el, 1), "unit": "grad edges/s", "n_gpus": 1, "steps": args.steps,
@@ -204,8 +252,93 @@ def grad_main(args):
     print(json.dumps(line), flush=True)
 
 
+def probe_gather(ws, dev):
+    """Measured random-access roofline: 524 288 dependent random 8-byte gather chains of 64
+    loads each over the sampler's own workspace (its footprint), timed with HIP events."""
+    import ctypes
+    import torch
+    from paper_2510_20604_amd import _lib
+    words = ws.numel() // 8
+    lanes, chain = 256 * 2048, 64
+    sink = torch.empty(lanes, dtype=torch.int64, device=dev)
+    ms = ctypes.c_float()
+    lib = _lib.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for seed_probe in (1, 2):   # the first call warms up
+        _lib.check(lib.rwc_probe_random_gather(ctypes.c_void_p(ws.data_ptr()), words, lanes, chain, seed_probe,
+                                               ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms), stream),
+                   "rwc_probe_random_gather")
+    return lanes * chain / (ms.value * 1e-3), f"dependent random 8-byte gathers, {lanes} chains x {chain}, " \
+                                              f"footprint {ws.numel() / 2**30:.1f} GiB"
+
+
+def roofline_line(config, kernel, total_steps, l, n, weighted, walk_ms_launch, trees_in_flight, launches):
+    bytes_launch = walk_bytes(total_steps, l, n, weighted) / launches
+    achieved = bytes_launch / (walk_ms_launch * 1e-3) / 1e9
+    counters = measured_counters(config, kernel, l, trees_in_flight)
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": counters["traffic_bytes_per_launch"] if counters else None,
+            "kernel": kernel, "avg_launch_ms": round(walk_ms_launch, 3),
+            "algorithmic_bytes_per_launch": bytes_launch, "traffic_unit": "HBM bytes per launch"}
+    return roof, counters
+
+
+def ba1m_side(args):
+    """BA(1e6, 5), unit weights, 1e4 trees: CSR build + sampling + estimate per step."""
+    import torch
+    import paper_2510_20604_amd as P
+    g, l, seed, desc = workload("ba1m")
+    dev = torch.device("cuda:0")
+    src, dst = torch.as_tensor(g.src).to(dev), torch.as_tensor(g.dst).to(dev)
+    ws = {"sample": None}
+
+    def step():
+        G = P.Graph(g.n, src, dst, None, dev)
+        s = P.sample_forests(G, l, seed, want_sq=False, want_hash=False, workspace=ws["sample"], sync=False)
+        ws["sample"] = s["workspace"]
+        P.estimate(G, s["counts"], l, want_hit=False)
+        P.workspace_status(s["workspace"])
+        return s
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 3
+    for _ in range(k):
+        s = step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / k
+    steps = int(P.as_uint64(s["total_steps"])[0])
+    del ws["sample"], s
+    return {"workload": desc, "trees_per_s": round(l / el, 3), "ms_per_step": round(1e3 * el, 3),
+            "walk_steps_per_s": round(steps / el, 1), "steps": k}
+
+
+def grad_side(args):
+    """BA(1e5, 4), w ~ U[0.5, 2], 100 targets, k = 64: grad edges per second."""
+    import torch
+    import paper_2510_20604_amd as P
+    import rwcgen
+    g = rwcgen.barabasi_albert(100_000, 4, 1004)
+    g = g.with_weights(rwcgen.uniform_weights(g.m, 0.5, 2.0, 1005))
+    t = np.random.default_rng(6).choice(g.n, size=100, replace=False).astype(np.int32)
+    G = P.Graph(g.n, g.src, g.dst, g.w, "cuda:0")
+    gd = P.dense_g(g.n, t, np.ones(100), "cuda:0")
+    P.backward(G, gd, k=64, seed=2004, tol=1e-8)
+    torch.cuda.synchronize()
+    k = 5
+    t0 = time.perf_counter()
+    for _ in range(k):
+        r = P.backward(G, gd, k=64, seed=2004, tol=1e-8)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / k
+    return {"workload": "BA(n=1e5, m=4), w ~ U[0.5, 2], 100 targets, JL sketch k = 64", "m": g.m,
+            "grad_edges_per_s": round(g.m / el, 1), "ms": round(1e3 * el, 3), "pcg_iters": r["iters"]}
+
+
 def rmat_main(args):
-    """Scale: R-MAT scale 23 (a, b, c) = (.57, .19, .19), 5 edge draws per node, largest
+    """The default: R-MAT scale 23 (a, b, c) = (.57, .19, .19), 5 edge draws per node, largest
     component, w ~ U[1, 4]; one step = CSR build + 5000 trees in a persistent launch + pivot
     solve and assembly + the adjoint of the RWC sum over 1000 targets (k = 64)."""
     import torch
@@ -217,21 +350,21 @@ def rmat_main(args):
     print(f"generated R-MAT LCC n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     l, seed = args.trees or 5000, 2005
     targets = np.random.default_rng(7).choice(g.n, size=1000, replace=False).astype(np.int32)
-    gv = np.ones(1000)
     dev = torch.device("cuda:0")
     src, dst = torch.as_tensor(g.src).to(dev), torch.as_tensor(g.dst).to(dev)
     w = torch.as_tensor(g.w).to(dev)
+    gvec = P.dense_g(g.n, targets, np.ones(1000), dev)
     ws = {"sample": None}
 
     def step():
         G = P.Graph(g.n, src, dst, w, dev)
         s = P.sample_forests(G, l, seed, persistent=True, want_sq=True, want_hash=False, workspace=ws["sample"],
-                             timing=True)
+                             timing=True, walkers_per_tree=args.walkers, trees_in_flight=args.tif)
         ws["sample"] = s["workspace"]
         e = P.estimate(G, s["counts"], l, counts_sq=s["counts_sq"], want_stderr=True)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        r = P.backward(G, targets, gv, k=64, seed=2006, tol=1e-8)
+        r = P.backward(G, gvec, k=64, seed=2006, tol=1e-8)
         torch.cuda.synchronize()
         return G, s, e, r, time.perf_counter() - tb
 
@@ -241,18 +374,21 @@ def rmat_main(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     walk_ms, back_s = [], []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         G, s, e, r, tb = step()
         walk_ms.append(s["walk_ms"])
         back_s.append(tb)
-        print("timed step done", file=sys.stderr, flush=True)
+        if i % 5 == 4 or i == args.steps - 1:
+            print(f"timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = (time.perf_counter() - t0) / args.steps
     total_steps = int(P.as_uint64(s["total_steps"])[0])
     wms = float(np.mean(walk_ms)) / s["batches"]
-    bytes_launch = walk_bytes(total_steps, l, g.n, True) / s["batches"]
-    achieved = bytes_launch / (wms * 1e-3) / 1e9
+    roof, counters = roofline_line("rmat23", s["walk_kernel"], total_steps, l, g.n, True, wms, s["trees_in_flight"],
+                                   s["batches"])
     rel_se = (e["stderr"] / e["rwc"]).double()
+    mask = torch.ones(g.n, dtype=torch.bool, device=dev)
+    mask[G.pivot] = False
     line = {
         "metric": METRIC, "value": round(l / elapsed, 3), "unit": "trees/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed, 3), "higher_is_better": True, "scaling": "weak",
@@ -264,14 +400,33 @@ def rmat_main(args):
         "walk_steps_per_s": round(total_steps / elapsed, 1),
         "walk_steps_per_tree": total_steps / l,
         "sampler_trees_per_s": round(l / (np.mean(walk_ms) * 1e-3), 3),
-        "grad_edges_per_s": round(g.m / float(np.mean(back_s)), 1), "backward_ms": round(1e3 * float(np.mean(back_s)), 3),
+        "grad_edges_per_s": round(g.m / float(np.mean(back_s)), 1),
+        "backward_ms": round(1e3 * float(np.mean(back_s)), 3),
         "pcg_iters": e["iters"], "adjoint_iters": r["iters"],
-        "rwc_rel_stderr_mean": float(rel_se.mean()),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": s["walk_kernel"],
-                     "avg_launch_ms": round(wms, 3), "algorithmic_bytes_per_launch": bytes_launch,
-                     "traffic_unit": "HBM bytes per launch"},
+        "rwc_rel_stderr_mean": float(rel_se[mask].mean()),
+        "roofline": roof,
     }
+    if not args.no_probe:
+        peak_acc, desc = probe_gather(ws["sample"], dev)
+        gr = {"probe": desc, "peak_accesses_per_s": peak_acc,
+              "walk_algorithmic_accesses_per_s": walk_accesses(total_steps, l, g.n) / s["batches"] / (wms * 1e-3)}
+        if counters:
+            miss = counters["tcc_miss_per_dispatch"] / (wms * 1e-3)
+            gr.update({"walk_l2_misses_per_s": miss, "frac": round(miss / peak_acc, 4)})
+        else:
+            gr["frac"] = None
+        line["gather_roofline"] = gr
+    del ws["sample"], s, e, r, G
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        line["ba1m"] = ba1m_side(args)
+        print("BA(1e6) side measurement done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        line["grad100k"] = grad_side(args)
+        print("BA(1e5) adjoint side measurement done", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        cb, _ = cpu_baseline(g, l, seed, args.cpu_seconds, single_seconds=args.cpu_seconds * 0.67)
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 
@@ -327,33 +482,12 @@ def main():
 
     # roofline of the dominant kernel (the walk)
     wms = float(np.mean(walk_ms)) / launches
-    bytes_launch = walk_bytes(total_steps, l, g.n, False) / launches
-    achieved = bytes_launch / (wms * 1e-3) / 1e9
-    counters = measured_counters(s["walk_kernel"], l, trees_in_flight)
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": counters["traffic_bytes_per_launch"] if counters else None,
-            "kernel": s["walk_kernel"], "avg_launch_ms": round(wms, 3),
-            "algorithmic_bytes_per_launch": bytes_launch, "traffic_unit": "HBM bytes per launch"}
-
+    roof, counters = roofline_line(args.config, s["walk_kernel"], total_steps, l, g.n, False, wms, trees_in_flight,
+                                   launches)
     extra = {}
     if not args.no_probe:
-        # measured random-gather roofline over the sampler's own state footprint
-        import ctypes
-        wsp = ws["sample"]
-        words = wsp.numel() // 8
-        lanes, chain = 256 * 2048, 64
-        sink = torch.empty(lanes, dtype=torch.int64, device=dev)
-        ms = ctypes.c_float()
-        lib = _lib.lib()
-        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-        for seed_probe in (1, 2):   # the first call warms up
-            _lib.check(lib.rwc_probe_random_gather(ctypes.c_void_p(wsp.data_ptr()), words, lanes, chain,
-                                                   seed_probe, ctypes.c_void_p(sink.data_ptr()),
-                                                   ctypes.byref(ms), stream), "rwc_probe_random_gather")
-        peak_acc = lanes * chain / (ms.value * 1e-3)
-        gr = {"probe": f"dependent random 8-byte gathers, {lanes} chains x {chain}, "
-                       f"footprint {wsp.numel() / 2**30:.1f} GiB", "peak_accesses_per_s": peak_acc,
+        peak_acc, desc_probe = probe_gather(ws["sample"], dev)
+        gr = {"probe": desc_probe, "peak_accesses_per_s": peak_acc,
               "walk_algorithmic_accesses_per_s": walk_accesses(total_steps, l, g.n) / launches / (wms * 1e-3)}
         if counters:
             # every L2 miss of the walk is one random line access to the fabric, the quantity the
@@ -405,7 +539,7 @@ def main():
     }
     line.update(extra)
     if not args.no_cpu_baseline:
-        cb, _ = cpu_baseline(g, l, seed, args.cpu_seconds)
+        cb, _ = cpu_baseline(g, l, seed, args.cpu_seconds, single_seconds=args.cpu_seconds * 0.67)
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 

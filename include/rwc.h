@@ -33,10 +33,11 @@ extern "C" {
 typedef enum rwc_status {
     RWC_OK = 0,
     RWC_ERR_INVALID_ARG = -1,      /* null pointer, negative size, bad flag combination      */
-    RWC_ERR_NODE_RANGE = -2,       /* an edge endpoint outside [0, n)                        */
+    RWC_ERR_NODE_RANGE = -2,       /* an edge endpoint or root id outside [0, n)             */
     RWC_ERR_SELF_LOOP = -3,        /* an edge (u, u)                                         */
     RWC_ERR_DUP_EDGE = -4,         /* the same undirected edge listed twice                  */
-    RWC_ERR_WEIGHT_RANGE = -5,     /* a weight outside [0.5, 65536) or not finite            */
+    RWC_ERR_WEIGHT_RANGE = -5,     /* a weight outside [0.5, 65536) or not finite, a weighted
+                                      degree of 2^29 or more, or total weight of 2^40 or more */
     RWC_ERR_DISCONNECTED = -6,     /* more than one connected component (or an isolated node)*/
     RWC_ERR_TOO_LARGE = -7,        /* n >= 2^31 - 1, 2m >= 2^31, or an index space overflow  */
     RWC_ERR_WORKSPACE = -8,        /* workspace null, misaligned or smaller than required    */
@@ -95,7 +96,13 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
                                         overwriting them                                    */
 #define RWC_SAMPLE_PERSISTENT    2u  /* batched: one persistent launch whose waves pop (graph,
                                         tree block) work items from a device queue          */
-#define RWC_SAMPLE_GRAPH_CAPTURE 4u  /* record the launches in a hipGraph and replay it     */
+#define RWC_SAMPLE_GRAPH_CAPTURE 4u  /* run the call's launches as a hipGraph: captured and
+                                        instantiated on the first call with a given set of
+                                        graphs, parameters, workspace and outputs, and replayed
+                                        (after a fresh upload of the call's argument tables) by
+                                        later calls with the same set.  The library keeps at
+                                        most 8 such graphs (least recently used dropped);
+                                        rwc_release_cached_graphs frees them                 */
 #define RWC_SAMPLE_BFS_STARTS    8u  /* walker teams take start nodes in breadth-first order
                                         from the root instead of ascending ids (same forest) */
 #define RWC_SAMPLE_ID_STARTS   256u  /* walker teams take start nodes by ascending id.  With
@@ -134,6 +141,14 @@ typedef struct rwc_sample_params {
     uint64_t max_steps_per_tree; /* guard; 0 = 2^20 + 4096 n                              */
     uint32_t graph_index_base;   /* Philox graph word of graphs[0]; graph g uses base + g */
     uint32_t reserved;
+    const int32_t* roots;        /* DEVICE int32 [num_roots]: a root set S instead of one root
+                                    (single graph, root = -1): every tree is a spanning forest
+                                    rooted at S, i.e. Algorithm 3 with InTree = S at the start
+                                    of each sample.  Ids must be distinct and in [0, n); a
+                                    violation is reported by rwc_workspace_status (the
+                                    outputs are then meaningless).  NULL when num_roots = 0  */
+    int32_t num_roots;           /* 0: one root (`root`); else 1 .. n - 1                    */
+    int32_t reserved2;
 } rwc_sample_params;
 
 typedef struct rwc_sample_outputs {
@@ -153,11 +168,13 @@ typedef struct rwc_sample_outputs {
     float* timing_ms;            /* HOST [2] or NULL: device time of the walk kernels and of
                                     the reduction kernels, summed over batches (hipEvents on
                                     `stream`; not available with RWC_SAMPLE_GRAPH_CAPTURE) */
-    int32_t* plan;               /* HOST [6] or NULL, as used for graph 0: walkers per tree,
+    int32_t* plan;               /* HOST [8] or NULL, as used for graph 0: walkers per tree,
                                     trees in flight, number of batches, walk kernel (0 one
                                     walker per tree, 1 walker teams, 2 walker teams with the
                                     LDS path ring), team starts (0 shared, 1 spread), start
-                                    order (0 ascending ids, 1 breadth-first)              */
+                                    order (0 ascending ids, 1 breadth-first), hipGraph
+                                    (-1 none, 0 captured by this call, 1 a cached graph
+                                    replayed), 0                                          */
 } rwc_sample_outputs;
 
 /* Workspace for rwc_sample_forests with these graphs and parameters. */
@@ -171,10 +188,65 @@ int rwc_sample_forests_workspace(const rwc_csr* graphs, int32_t num_graphs,
  * function of (graph, seed, sample index) whatever the launch shape, the number of trees in
  * flight, the walkers per tree, or plain versus batched launches.
  *   graphs   HOST array [num_graphs] of graphs from rwc_build_csr
- * Synchronises `stream` before returning and reports device-side errors
- * (RWC_ERR_STEP_LIMIT, RWC_ERR_COUNT_OVERFLOW). */
+ * Stream-ordered: the call enqueues its work on `stream` and returns without waiting for it
+ * (the small host arrays it reads, graphs, params, outputs and dump_samples, may be reused as
+ * soon as it returns).  Device-side errors (RWC_ERR_STEP_LIMIT, RWC_ERR_COUNT_OVERFLOW, a bad
+ * root set) are left in the workspace and returned by rwc_workspace_status.  Exception: with
+ * out->timing_ms the call waits for its work (the timings need it) and returns the device
+ * status itself.
+ * On a stream that is being captured into a caller's hipGraph, the workspace must have been
+ * prepared by rwc_sample_prepare with the same graphs, parameters (other than seed and
+ * sample_begin) and workspace; the call then only launches kernels. */
 int rwc_sample_forests(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p,
                        const rwc_sample_outputs* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Writes the device-side argument tables that rwc_sample_forests reads (graph arguments, node
+ * offsets, work items) into the workspace, for calls made while `stream` is being captured
+ * into a hipGraph (a capture cannot hold the host-to-device copies).  The same arguments as
+ * rwc_sample_forests; seed and sample_begin may differ in the captured calls.  Synchronises
+ * `stream`.  The workspace must not be changed between this call and the replays. */
+int rwc_sample_prepare(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Frees the hipGraphs kept for RWC_SAMPLE_GRAPH_CAPTURE (waiting for their last launches). */
+void rwc_release_cached_graphs(void);
+
+/* Synchronises `stream` and returns the device-side outcome of the last stream-ordered call
+ * that used the workspace `ws` (a sampling, estimate or adjoint workspace): RWC_OK or the
+ * rwc_status its kernels reported.  RWC_ERR_INVALID_ARG if the workspace was never used. */
+int rwc_workspace_status(const void* ws, void* stream);
+
+/* Synchronises `stream` and stores the solver iterations run by the last estimate call on
+ * the workspace `ws` in *iters. */
+int rwc_workspace_iterations(const void* ws, int32_t* iters, void* stream);
+
+/* ---- Trap walks: the estimator that FastWalk improves on (Lemma 5.1) -------------------- */
+typedef struct rwc_trap_params {
+    uint64_t seed;                /* Philox key (seed mod 2^32, seed >> 32)                  */
+    int64_t walk_begin;           /* index of the first walk from each start node            */
+    int64_t num_walks;            /* walks per start node (l)                                */
+    int32_t trap;                 /* -1: the pivot                                           */
+    uint32_t graph_index;         /* the walks use the Philox graph word graph_index ^ 2^31  */
+    uint64_t max_steps_per_walk;  /* guard; 0 = 2^20 + 4096 n                                */
+} rwc_trap_params;
+
+int rwc_sample_trap_walks_workspace(const rwc_csr* g, const rwc_trap_params* p, size_t* bytes);
+
+/* Lemma 5.1: (calL_v^{-1})_uu is the expected number of visits to u of a random walk from u
+ * that stops at the trap v.  From every node u != v, num_walks independent walks (indices
+ * walk_begin .. walk_begin + num_walks - 1) run until they reach v, each counting its visits
+ * to u (the start included); walk i from u takes its s-th step by RandomNeighbor (the rule of
+ * rwc_sample_forests) with Philox4x32-10 on the counter (s, u, i, graph_index ^ 2^31).
+ *   counts_dev       uint64 [n] per start node, the sum of its walks' visit counts (0 at v):
+ *                    rwc_estimate(counts, l = num_walks) assembles RWC from them exactly as
+ *                    from the Wilson forests' visit totals
+ *   counts_sq_dev    uint64 [n] sum of the squared counts, or NULL
+ *   total_steps_dev  uint64 [1] RandomNeighbor calls, or NULL
+ * Stream-ordered; a walk longer than max_steps_per_walk is reported by rwc_workspace_status
+ * (RWC_ERR_STEP_LIMIT). */
+int rwc_sample_trap_walks(const rwc_csr* g, const rwc_trap_params* p, uint64_t* counts_dev,
+                          uint64_t* counts_sq_dev, uint64_t* total_steps_dev, void* ws, size_t ws_bytes,
+                          void* stream);
 
 typedef struct rwc_tune_result {
     int32_t walkers_per_tree;    /* the winning walkers per tree                            */
@@ -209,8 +281,17 @@ void rwc_autotune_clear_cache(void);
 
 typedef struct rwc_solve_params {
     double tol;        /* relative residual of the pivot solve; 0 = 1e-12                 */
-    int32_t max_iter;  /* 0 = 20000                                                       */
-    int32_t check_every; /* iterations between host convergence checks; 0 = 16            */
+    int32_t max_iter;  /* 0 = 20000 (host-checked mode); stream-ordered mode: 1..4096,
+                          required                                                        */
+    int32_t check_every; /* iterations between host convergence checks; 0 = 16.  A negative
+                          value selects stream-ordered mode: max_iter iterations are
+                          enqueued at once and the solve stops on the device when the
+                          residual meets tol (the same iterations a host-checked solve
+                          runs, so the results are identical); the call then returns
+                          without waiting, *iters is set to -1, and convergence is
+                          reported by rwc_workspace_status (RWC_ERR_NOT_CONVERGED), the
+                          count by rwc_workspace_iterations.  This mode can be captured
+                          into a hipGraph.                                                 */
 } rwc_solve_params;
 
 int rwc_estimate_workspace(const rwc_csr* g, size_t* bytes);
@@ -226,49 +307,70 @@ int rwc_estimate_workspace(const rwc_csr* g, size_t* bytes);
  *   hit_dev        double [n] output hitting times to the pivot, or NULL
  *   stderr_dev     double [n] output standard error of rwc from the sample variance, or NULL
  *   iters          HOST int32 output: CG iterations used, or NULL
- * Synchronises `stream`. */
+ * Host-checked mode synchronises `stream` (every check_every iterations and at the end) and
+ * returns RWC_ERR_NOT_CONVERGED itself; stream-ordered mode (sp->check_every < 0) does not. */
 int rwc_estimate(const rwc_csr* g, const uint64_t* counts_dev, const uint64_t* counts_sq_dev,
                  int64_t l, const rwc_solve_params* sp, double* rwc_dev, double* hit_dev,
                  double* stderr_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
+int rwc_estimate_group_workspace(const rwc_csr* g, size_t* bytes);
+
+/* Random walk centrality of a group of nodes (the generalisation named in the paper's
+ * Conclusion): the group RWC H_S = sum_u pi_u H_{u,S} of a root set S (hitting time to the
+ * set), and for every node u the estimate of H_{S + u} from spanning forests rooted at S
+ * (rwc_sample_forests with p->roots = S).  With h the hitting times to S (the system grounded
+ * at S, solved as in rwc_estimate) and t~_u = counts_u / l, which estimates d_u (L_S^-1)_uu as
+ * Lemma 5.2 does for one root, removing u from the grounded system is a rank-one update:
+ *   H_{S + u} = H_S - d_u h_u^2 / (vol t~_u)   (u not in S),   H_{S + u} = H_S (u in S).
+ *   roots_dev      int32 [num_roots] the set S (distinct ids in [0, n), 1 <= num_roots < n)
+ *   counts_dev     uint64 [n] visit totals of l forests rooted at S
+ *   group_rwc_dev  double [1] output H_S
+ *   marginal_dev   double [n] output H_{S + u}
+ *   hit_dev        double [n] output hitting times to S, or NULL
+ * Modes and synchronisation as rwc_estimate; a bad root set is RWC_ERR_INVALID_ARG or
+ * RWC_ERR_NODE_RANGE (host-checked mode), or reported by rwc_workspace_status. */
+int rwc_estimate_group(const rwc_csr* g, const int32_t* roots_dev, int32_t num_roots,
+                       const uint64_t* counts_dev, int64_t l, const rwc_solve_params* sp,
+                       double* group_rwc_dev, double* marginal_dev, double* hit_dev, int32_t* iters,
+                       void* ws, size_t ws_bytes, void* stream);
+
 typedef struct rwc_backward_params {
     int32_t k;           /* Rademacher probes per sign class of g; 0 = exact (one column per
-                            target)                                                       */
+                            nonzero of g)                                                 */
     int32_t max_iter;    /* 0 = 20000                                                      */
     uint64_t seed;       /* probe key: the sign of probe i at node u is bit 0 of word 0 of
                             Philox4x32-10 on the counter (i, u, 0, 2^32 - 1); probes of the
                             negative class are numbered k .. 2k-1                          */
     double tol;          /* relative residual of every solve column; 0 = 1e-10            */
     int32_t check_every; /* iterations between host convergence checks; 0 = 16            */
-    int32_t reserved;
+    int32_t max_support; /* exact mode (k = 0): the most nonzeros g may have (the workspace
+                            holds 2 + max_support solve columns); ignored when k > 0       */
 } rwc_backward_params;
 
-/* Workspace for rwc_backward with this target list (its size depends on the number of
- * solve columns, hence on the targets and the signs of their g values).  Both calls return
- * RWC_ERR_INVALID_ARG for k < 0 or a target outside [0, n), and RWC_ERR_TOO_LARGE, before
- * building anything, for more than 2^24 solve columns (2 + the
- * number of targets when exact, else 2 + k per sign class present) or more than 2^31 - 1
- * right-hand-side entries (num_targets plus, per target, one per probe column of its sign
- * class, or one when exact). */
-int rwc_backward_workspace(const rwc_csr* g, int32_t num_targets, const int32_t* targets,
-                           const double* gvals, const rwc_backward_params* bp, size_t* bytes);
+/* Workspace for rwc_backward: sized for 2 + 2k solve columns (k > 0: both sign classes of g)
+ * or 2 + bp->max_support (exact mode).  RWC_ERR_INVALID_ARG for k < 0 or an exact-mode
+ * max_support outside [1, n]; RWC_ERR_TOO_LARGE for more than 2^24 solve columns. */
+int rwc_backward_workspace(const rwc_csr* g, const rwc_backward_params* bp, size_t* bytes);
 
 /* Gradient of l(w) = sum_j g_j RWC_j (exact RWC, Eq. (2)) with respect to every edge weight.
  * The paper does not differentiate RWC; this is the adjoint of its quantity, with the
  * derivative of L^+ through the incidence form L = B^T B of Section 2.2:
  *   dl/dw_e = 2 trGL - vol Q_e + 2 D_A D_B - 2 S_A + G ((2 S_B - D_B^2)/vol - 2 d^T B/vol^2)
  * A = L^+ g, B = L^+ d, G = sum g, trGL = sum_j g_j L^+_jj, Q_e = sum_j g_j (L^+ b_e)_j^2,
- * D_X = X_a - X_b, S_X = X_a + X_b for e = (a, b).  Q_e and trGL are exact (k = 0) or a
- * Johnson-Lindenstrauss / Hutchinson sketch with k probes per sign class of g.  All solves
- * run together as one batched Jacobi-preconditioned CG on the grounded Laplacian (FP32
- * search directions, FP64 iterate, residual and dot products).
- *   targets, gvals  HOST arrays [num_targets]: the nodes with g_j != 0 and their g_j
- *   grad_w_dev      double [m] output in input-edge order (device)
- *   iters           HOST int32 output: CG iterations used, or NULL
- * Synchronises `stream`. */
-int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t* targets, const double* gvals,
-                 const rwc_backward_params* bp, double* grad_w_dev, int32_t* iters, void* ws,
-                 size_t ws_bytes, void* stream);
+ * D_X = X_a - X_b, S_X = X_a + X_b for e = (a, b).  Q_e and trGL are exact (k = 0: one solve
+ * column per nonzero of g) or a Johnson-Lindenstrauss / Hutchinson sketch with k probes per
+ * sign class of g.  All solves run together as one batched Jacobi-preconditioned CG on the
+ * grounded Laplacian (FP32 search directions, FP64 iterate, residual and dot products).
+ *   grad_rwc_dev  double [n] the vector g (device); its support and signs are found on the
+ *                 device.  RWC_ERR_INVALID_ARG if it holds a value that is not finite or
+ *                 (exact mode) more than max_support nonzeros; if it is zero everywhere the
+ *                 gradient is zero
+ *   grad_w_dev    double [m] output in input-edge order (device)
+ *   iters         HOST int32 output: CG iterations used, or NULL
+ * Synchronises `stream` (it reads back the support counts, then checks convergence every
+ * check_every iterations). */
+int rwc_backward(const rwc_csr* g, const double* grad_rwc_dev, const rwc_backward_params* bp,
+                 double* grad_w_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
 const char* rwc_status_string(int status);
 /* Copies the calling thread's last error detail into buf (NUL-terminated); returns its

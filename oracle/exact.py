@@ -177,13 +177,15 @@ def _sparse_laplacian(n: int, src, dst, w):
     return (sp.diags(d) - A).tocsr(), d
 
 
-def lap_solve(n: int, src, dst, w, b: np.ndarray, method: str = "dense", v: int | None = None) -> np.ndarray:
+def lap_solve(n: int, src, dst, w, b: np.ndarray, method: str = "dense", v: int | None = None,
+              rtol: float = 1e-14) -> np.ndarray:
     """LapSolve of Lemma 3.3 taken exact: a solution z of L z = b for b orthogonal to 1.
 
     ``dense`` returns L^+ b from the closed form.  ``sparse_direct`` / ``sparse_cg`` ground
     one node (row and column v removed, z_v = 0) and solve the remaining SPD system with
     SciPy's sparse LU or conjugate gradients; the result differs from L^+ b by a multiple
-    of the all-ones vector, which every later step of Algorithm 1 projects away.
+    of the all-ones vector, which every later step of Algorithm 1 projects away.  ``rtol``
+    is the relative residual at which ``sparse_cg`` stops.
     """
     if method == "dense":
         return laplacian_pinv(laplacian(adjacency(n, src, dst, w))) @ b
@@ -198,7 +200,7 @@ def lap_solve(n: int, src, dst, w, b: np.ndarray, method: str = "dense", v: int 
     elif method == "sparse_cg":
         dg = Lg.diagonal()
         M = sp.diags(1.0 / dg)
-        sol, info = spla.cg(Lg, b[keep], rtol=1e-14, atol=0.0, maxiter=200000, M=M)
+        sol, info = spla.cg(Lg, b[keep], rtol=rtol, atol=0.0, maxiter=200000, M=M)
         if info != 0:
             raise RuntimeError(f"oracle CG did not converge (info={info})")
         z[keep] = sol
@@ -264,3 +266,55 @@ def kendall_tau_a(x: np.ndarray, y: np.ndarray) -> float:
     sy = np.sign(y[:, None] - y[None, :])
     s = np.sum(np.triu(sx * sy, k=1))
     return float(2.0 * s / (n * (n - 1)))
+
+
+# ---------------------------------------------------------------------------------------
+# Groups of nodes (the generalisation named in the paper's Conclusion): random walk
+# centrality of a set S, H_S = sum_i pi_i H_{i,S}, where H_{i,S} is the expected time for a
+# walk from i to first reach S.
+# ---------------------------------------------------------------------------------------
+def hitting_times_to_set(n: int, src, dst, w, S) -> np.ndarray:
+    """h_i = H_{i,S}: the first-step equations h_i = 1 + sum_k P_ik h_k for i outside S,
+    h_i = 0 on S (Section 2.3's definition with S absorbing), by a dense solve."""
+    A = adjacency(n, src, dst, w)
+    P = A / A.sum(axis=1)[:, None]
+    S = np.atleast_1d(np.asarray(S, dtype=np.int64))
+    keep = np.setdiff1d(np.arange(n), S)
+    h = np.zeros(n)
+    h[keep] = np.linalg.solve(np.eye(keep.size) - P[np.ix_(keep, keep)], np.ones(keep.size))
+    return h
+
+
+def group_rwc(n: int, src, dst, w, S) -> float:
+    """H_S = sum_i pi_i H_{i,S} with pi = d / vol."""
+    d = adjacency(n, src, dst, w).sum(axis=1)
+    return float((d / d.sum()) @ hitting_times_to_set(n, src, dst, w, S))
+
+
+def grounded_inverse_diag_set(n: int, src, dst, w, S) -> np.ndarray:
+    """d_u (L_S^{-1})_uu for u outside S (0 on S): the expected departures from u in one
+    Wilson forest rooted at S, the root-set form of Lemma 5.2."""
+    L = laplacian(adjacency(n, src, dst, w))
+    d = np.diag(L).copy()
+    S = np.atleast_1d(np.asarray(S, dtype=np.int64))
+    keep = np.setdiff1d(np.arange(n), S)
+    out = np.zeros(n)
+    out[keep] = d[keep] * np.diag(np.linalg.inv(L[np.ix_(keep, keep)]))
+    return out
+
+
+def group_marginal_estimate(n: int, src, dst, w, S, t: np.ndarray) -> np.ndarray:
+    """H_{S + u} for every u from H_S, the hitting times h to S and t_u, an estimate of
+    d_u (L_S^{-1})_uu (the forests' visit totals over l): removing u from the system grounded
+    at S is a rank-one update of its inverse, which gives
+    H_{S + u} = H_S - d_u h_u^2 / (vol t_u) for u outside S, and H_S for u in S."""
+    d = adjacency(n, src, dst, w).sum(axis=1)
+    vol = d.sum()
+    h = hitting_times_to_set(n, src, dst, w, S)
+    hs = float((d / vol) @ h)
+    S = np.atleast_1d(np.asarray(S, dtype=np.int64))
+    out = np.full(n, hs)
+    keep = np.setdiff1d(np.arange(n), S)
+    t = np.asarray(t, dtype=np.float64)
+    out[keep] = hs - d[keep] * h[keep] ** 2 / (vol * t[keep])
+    return out

@@ -155,10 +155,29 @@ def grad_from_probes(n: int, src, dst, w, g, cols) -> np.ndarray:
     return _assemble(vol, g, A, B, a, b, Q, trGL, float(d @ B))
 
 
-def grad_at_edges_sparse(n: int, src, dst, w, targets, gvals, edges, cols=None) -> np.ndarray:
+_POOL_GRAPH = None
+
+
+def _pool_init(n, src, dst, w, rtol):
+    global _POOL_GRAPH
+    _POOL_GRAPH = (n, src, dst, w, rtol)
+
+
+def _pool_pinv(y):
+    n, src, dst, w, rtol = _POOL_GRAPH
+    from .exact import lap_solve
+    yc = y - y.mean()
+    z = lap_solve(n, src, dst, w, yc, "sparse_cg", rtol=rtol)
+    return z - z.mean()
+
+
+def grad_at_edges_sparse(n: int, src, dst, w, targets, gvals, edges, cols=None, rtol: float = 1e-14,
+                         workers: int = 1) -> np.ndarray:
     """dl/dw_e for the input edges `edges` from sparse conjugate-gradient solves (SciPy), for
     graphs too large for dense matrices.  cols=None evaluates Q_e and trGL exactly (one solve
-    per sampled edge and per target); otherwise from the given probe columns."""
+    per sampled edge and per target); otherwise from the given probe columns.  Each L^+ y is
+    one grounded CG solve to relative residual `rtol`, centred; with workers > 1 the probe
+    columns' solves run in that many processes (the same solves, in any order)."""
     from .exact import _sparse_laplacian, lap_solve
     L, d = _sparse_laplacian(n, src, dst, w)
     vol = d.sum()
@@ -169,7 +188,7 @@ def grad_at_edges_sparse(n: int, src, dst, w, targets, gvals, edges, cols=None) 
 
     def pinv(y):
         yc = y - y.mean()
-        z = lap_solve(n, src, dst, w, yc, "sparse_cg")
+        z = lap_solve(n, src, dst, w, yc, "sparse_cg", rtol=rtol)
         return z - z.mean()
 
     A = pinv(g)
@@ -191,8 +210,14 @@ def grad_at_edges_sparse(n: int, src, dst, w, targets, gvals, edges, cols=None) 
     else:
         Q = np.zeros(len(edges))
         trGL = 0.0
-        for c, y in cols:
-            z = pinv(y)
+        if workers > 1:
+            import concurrent.futures as cf
+            with cf.ProcessPoolExecutor(max_workers=workers, initializer=_pool_init,
+                                        initargs=(n, src, dst, w, rtol)) as ex:
+                zs = list(ex.map(_pool_pinv, [y for _, y in cols]))
+        else:
+            zs = [pinv(y) for _, y in cols]
+        for (c, y), z in zip(cols, zs):
             dz = z[a] - z[b]
             Q += c * dz * dz
             trGL += c * float(y @ z)

@@ -33,7 +33,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.oracle_fastwalk.restype = ctypes.c_int
-        lib.oracle_fastwalk.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.c_uint64,
+        lib.oracle_fastwalk.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int64, ctypes.c_uint64,
                                         ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, P,
                                         ctypes.c_uint64, P, P, P, P, P]
         lib.oracle_philox4x32_10.restype = None
@@ -41,6 +41,9 @@ def _load():
         lib.oracle_random_neighbor.restype = ctypes.c_int64
         lib.oracle_random_neighbor.argtypes = [ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
                                                ctypes.c_uint32, ctypes.c_uint64, P, P, P]
+        lib.oracle_trapwalk.restype = ctypes.c_int
+        lib.oracle_trapwalk.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, P, P, P]
         lib.oracle_splitmix64.restype = ctypes.c_uint64
         lib.oracle_splitmix64.argtypes = [ctypes.c_uint64]
         _lib = lib
@@ -114,14 +117,18 @@ def splitmix64(z: int) -> int:
     return int(_load().oracle_splitmix64(ctypes.c_uint64(z & ((1 << 64) - 1))))
 
 
-def fastwalk_sample(g: OracleCSR, root: int, seed: int, graph: int, sample_begin: int, nsamples: int,
+def fastwalk_sample(g: OracleCSR, root, seed: int, graph: int, sample_begin: int, nsamples: int,
                     order=None, want_parents: bool = False, threads: int = 1,
                     max_steps: int = (1 << 62)) -> dict:
     """Run samples [sample_begin, sample_begin + nsamples) serially (or split over threads,
     each thread running a contiguous sample sub-range; sums are integers, so the split does
-    not change any output)."""
+    not change any output).  `root` is one node (a rooted spanning tree per sample) or a
+    sequence of distinct nodes (a spanning forest rooted at that set)."""
     lib = _load()
     n = g.n
+    roots = np.ascontiguousarray(np.atleast_1d(np.asarray(root, dtype=np.int64)))
+    if roots.size != np.unique(roots).size:
+        raise ValueError("the root set lists a node twice")
     visits = np.zeros(n, dtype=np.uint64)
     visits_sq = np.zeros(n, dtype=np.uint64)
     steps = np.zeros(nsamples, dtype=np.uint64)
@@ -133,7 +140,7 @@ def fastwalk_sample(g: OracleCSR, root: int, seed: int, graph: int, sample_begin
         v = np.zeros(n, dtype=np.uint64)
         v2 = np.zeros(n, dtype=np.uint64)
         par = parents[lo:hi] if parents is not None else None
-        rc = lib.oracle_fastwalk(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.cdf), root, seed, graph,
+        rc = lib.oracle_fastwalk(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.cdf), _ptr(roots), roots.size, seed, graph,
                                  sample_begin + lo, hi - lo, _ptr(ordr), max_steps, _ptr(v), _ptr(v2),
                                  _ptr(steps[lo:hi]), _ptr(hsh[lo:hi]), _ptr(par))
         if rc != 0:
@@ -150,3 +157,31 @@ def fastwalk_sample(g: OracleCSR, root: int, seed: int, graph: int, sample_begin
         visits += v
         visits_sq += v2
     return {"visits": visits, "visits_sq": visits_sq, "steps": steps, "hash": hsh, "parents": parents}
+
+
+def trapwalk_sample(g: OracleCSR, v: int, seed: int, graph: int, walk_begin: int, nwalks: int, threads: int = 1,
+                    max_steps: int = (1 << 62)) -> dict:
+    """Walks [walk_begin, walk_begin + nwalks) from every node u != v, each stopped at the trap v
+    and counting its visits to u (Lemma 5.1); split over threads by walk range (integer sums,
+    so the split changes nothing).  Returns visits, visits_sq [n] and the total steps."""
+    lib = _load()
+    n = g.n
+
+    def run(lo, hi):
+        a = np.zeros(n, dtype=np.uint64)
+        b = np.zeros(n, dtype=np.uint64)
+        st = np.zeros(1, dtype=np.uint64)
+        rc = lib.oracle_trapwalk(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.cdf), v, seed, graph, walk_begin + lo,
+                                 hi - lo, max_steps, _ptr(a), _ptr(b), _ptr(st))
+        if rc != 0:
+            raise RuntimeError(f"oracle_trapwalk failed with code {rc}")
+        return a, b, int(st[0])
+
+    if threads <= 1 or nwalks < 2:
+        parts = [run(0, nwalks)]
+    else:
+        bounds = np.linspace(0, nwalks, min(threads, nwalks) + 1).astype(int)
+        with cf.ThreadPoolExecutor(max_workers=len(bounds) - 1) as ex:
+            parts = list(ex.map(lambda ab: run(*ab), zip(bounds[:-1], bounds[1:])))
+    return {"visits": sum(p[0] for p in parts), "visits_sq": sum(p[1] for p in parts),
+            "steps": sum(p[2] for p in parts)}

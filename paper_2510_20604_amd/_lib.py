@@ -25,6 +25,8 @@ RWC_SAMPLE_PATH_RING = 64
 RWC_SAMPLE_NO_PATH_RING = 128
 RWC_SAMPLE_ID_STARTS = 256
 
+RWC_SOLVE_STREAM_ORDERED = -1   # rwc_solve_params.check_every value selecting stream-ordered mode
+
 STATUS = {
     0: "RWC_OK", -1: "RWC_ERR_INVALID_ARG", -2: "RWC_ERR_NODE_RANGE", -3: "RWC_ERR_SELF_LOOP",
     -4: "RWC_ERR_DUP_EDGE", -5: "RWC_ERR_WEIGHT_RANGE", -6: "RWC_ERR_DISCONNECTED",
@@ -44,13 +46,19 @@ class RwcCsr(ctypes.Structure):
 class SampleParams(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("sample_begin", c_i64), ("num_samples", c_i64), ("root", c_i32),
                 ("flags", c_u32), ("trees_in_flight", c_i32), ("walkers_per_tree", c_i32),
-                ("max_steps_per_tree", c_u64), ("graph_index_base", c_u32), ("reserved", c_u32)]
+                ("max_steps_per_tree", c_u64), ("graph_index_base", c_u32), ("reserved", c_u32),
+                ("roots", c_vp), ("num_roots", c_i32), ("reserved2", c_i32)]
 
 
 class SampleOutputs(ctypes.Structure):
     _fields_ = [("counts", c_vp), ("counts_sq", c_vp), ("total_steps", c_vp), ("tree_hash", c_vp),
                 ("parents", c_vp), ("dump_samples", c_vp), ("ndump", c_i32), ("reserved", c_i32),
                 ("timing_ms", c_vp), ("plan", c_vp)]
+
+
+class TrapParams(ctypes.Structure):
+    _fields_ = [("seed", c_u64), ("walk_begin", c_i64), ("num_walks", c_i64), ("trap", c_i32),
+                ("graph_index", c_u32), ("max_steps_per_walk", c_u64)]
 
 
 class SolveParams(ctypes.Structure):
@@ -64,7 +72,7 @@ class TuneResult(ctypes.Structure):
 
 class BackwardParams(ctypes.Structure):
     _fields_ = [("k", c_i32), ("max_iter", c_i32), ("seed", c_u64), ("tol", c_dbl), ("check_every", c_i32),
-                ("reserved", c_i32)]
+                ("max_support", c_i32)]
 
 
 # (name, restype, argtypes) for every entry point declared in include/*.h
@@ -76,12 +84,22 @@ SIGNATURES = [
                                              ctypes.POINTER(c_sz)]),
     ("rwc_sample_forests", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),
                                    ctypes.POINTER(SampleOutputs), c_vp, c_sz, c_vp]),
+    ("rwc_sample_prepare", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams), c_vp, c_sz, c_vp]),
+    ("rwc_release_cached_graphs", None, []),
+    ("rwc_workspace_status", c_i32, [c_vp, c_vp]),
+    ("rwc_workspace_iterations", c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp]),
+    ("rwc_sample_trap_walks_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(TrapParams),
+                                                ctypes.POINTER(c_sz)]),
+    ("rwc_sample_trap_walks", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(TrapParams), c_vp, c_vp, c_vp, c_vp,
+                                      c_sz, c_vp]),
     ("rwc_estimate_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
     ("rwc_estimate", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_vp, c_i64, ctypes.POINTER(SolveParams), c_vp, c_vp,
                              c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
-    ("rwc_backward_workspace", c_i32, [ctypes.POINTER(RwcCsr), c_i32, c_vp, c_vp, ctypes.POINTER(BackwardParams),
-                                       ctypes.POINTER(c_sz)]),
-    ("rwc_backward", c_i32, [ctypes.POINTER(RwcCsr), c_i32, c_vp, c_vp, ctypes.POINTER(BackwardParams), c_vp,
+    ("rwc_estimate_group_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
+    ("rwc_estimate_group", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_i32, c_vp, c_i64, ctypes.POINTER(SolveParams),
+                                   c_vp, c_vp, c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_backward_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(BackwardParams), ctypes.POINTER(c_sz)]),
+    ("rwc_backward", c_i32, [ctypes.POINTER(RwcCsr), c_vp, ctypes.POINTER(BackwardParams), c_vp,
                              ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
     ("rwc_autotune_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(SampleParams), c_i64,
                                        ctypes.POINTER(c_sz)]),

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BackwardParams, RwcCsr, SampleOutputs, SampleParams, SolveParams, TuneResult, check
+from ._lib import BackwardParams, RwcCsr, SampleOutputs, SampleParams, SolveParams, TrapParams, TuneResult, check
 
 
 def _stream() -> ctypes.c_void_p:
@@ -100,33 +100,15 @@ class Graph:
         return self._view(self.csr.rec, 16 * self.n, torch.int32)
 
 
-def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int, sample_begin: int = 0,
-                   root: int = -1, trees_in_flight: int = 0, walkers_per_tree: int = 0,
-                   persistent: bool = False, capture: bool = False, want_sq: bool = True,
-                   want_hash: bool = True, dump: Sequence[int] = (), max_steps_per_tree: int = 0,
-                   graph_index_base: int = 0, accumulate: dict | None = None,
-                   workspace: torch.Tensor | None = None, timing: bool = False,
-                   bfs_starts: bool | None = None, starts: str = "auto", path_ring: bool | None = None) -> dict:
-    """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
-
-    Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
-    total_steps [G], tree_hash [G, num_samples], parents [len(dump), n] and the workspace
-    used (pass it back as `workspace` to reuse it).  With timing=True also walk_ms and
-    reduce_ms: device time of the walk and reduction kernels (hipEvents on the stream).
-    `starts` ("auto", "shared", "spread"), `bfs_starts` (None = automatic, True =
-    breadth-first from the root, False = ascending ids) and `path_ring` (None = automatic) pick
-    how walker teams schedule their walks; the forest does not depend on them."""
-    L = _lib.lib()
-    gl = [graphs] if isinstance(graphs, Graph) else list(graphs)
-    G = len(gl)
-    dev = gl[0].device
-    arr = (RwcCsr * G)(*[g.csr for g in gl])
+def _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, walkers_per_tree, persistent,
+                  capture, accumulate, max_steps_per_tree, graph_index_base, bfs_starts, starts, path_ring, roots):
+    arr = (RwcCsr * len(gl))(*[g.csr for g in gl])
     flags = 0
     if persistent:
         flags |= _lib.RWC_SAMPLE_PERSISTENT
     if capture:
         flags |= _lib.RWC_SAMPLE_GRAPH_CAPTURE
-    if accumulate is not None:
+    if accumulate:
         flags |= _lib.RWC_SAMPLE_ACCUMULATE
     if bfs_starts is not None:
         flags |= _lib.RWC_SAMPLE_BFS_STARTS if bfs_starts else _lib.RWC_SAMPLE_ID_STARTS
@@ -141,6 +123,48 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=root, flags=flags,
                      trees_in_flight=trees_in_flight, walkers_per_tree=walkers_per_tree,
                      max_steps_per_tree=max_steps_per_tree, graph_index_base=graph_index_base)
+    if roots is not None:
+        p.roots = roots.data_ptr()
+        p.num_roots = roots.numel()
+    return arr, p
+
+
+def _roots_tensor(roots, device):
+    if roots is None:
+        return None
+    return _dev_tensor(roots, torch.int32, device)
+
+
+def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int, sample_begin: int = 0,
+                   root: int = -1, trees_in_flight: int = 0, walkers_per_tree: int = 0,
+                   persistent: bool = False, capture: bool = False, want_sq: bool = True,
+                   want_hash: bool = True, dump: Sequence[int] = (), max_steps_per_tree: int = 0,
+                   graph_index_base: int = 0, accumulate: dict | None = None,
+                   workspace: torch.Tensor | None = None, timing: bool = False,
+                   bfs_starts: bool | None = None, starts: str = "auto", path_ring: bool | None = None,
+                   roots=None, sync: bool = True, out: dict | None = None) -> dict:
+    """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
+
+    Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
+    total_steps [G], tree_hash [G, num_samples], parents [len(dump), n] and the workspace
+    used (pass it back as `workspace` to reuse it).  With timing=True also walk_ms and
+    reduce_ms: device time of the walk and reduction kernels (hipEvents on the stream).
+    `starts` ("auto", "shared", "spread"), `bfs_starts` (None = automatic, True =
+    breadth-first from the root, False = ascending ids) and `path_ring` (None = automatic) pick
+    how walker teams schedule their walks; the forest does not depend on them.  `roots` (ids,
+    single graph) samples spanning forests rooted at that set instead of trees rooted at one
+    node.  `out` (a dict returned by an earlier call) reuses its output tensors, so that a
+    repeated call with capture=True replays the library's cached hipGraph.  The call is
+    stream-ordered; with sync=True (default) it then waits and raises on a device-side error
+    (rwc_workspace_status)."""
+    L = _lib.lib()
+    gl = [graphs] if isinstance(graphs, Graph) else list(graphs)
+    G = len(gl)
+    dev = gl[0].device
+    rt = _roots_tensor(roots, dev)
+    arr, p = _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, walkers_per_tree, persistent,
+                           capture, accumulate is not None, max_steps_per_tree, graph_index_base, bfs_starts, starts,
+                           path_ring, rt)
     size = ctypes.c_size_t()
     check(L.rwc_sample_forests_workspace(arr, G, ctypes.byref(p), ctypes.byref(size)),
           "rwc_sample_forests_workspace")
@@ -149,35 +173,112 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     total = sum(g.n for g in gl)
     if accumulate is not None:
         res = accumulate
+    elif out is not None:
+        res = out
     else:
         res = {
             "counts": torch.empty(total, dtype=torch.int64, device=dev),
             "counts_sq": torch.empty(total, dtype=torch.int64, device=dev) if want_sq else None,
             "total_steps": torch.empty(G, dtype=torch.int64, device=dev),
         }
-    res["tree_hash"] = torch.empty((G, num_samples), dtype=torch.int64, device=dev) if want_hash else None
+    th = res.get("tree_hash")
+    if not want_hash:
+        res["tree_hash"] = None
+    elif th is None or tuple(th.shape) != (G, num_samples):
+        res["tree_hash"] = torch.empty((G, num_samples), dtype=torch.int64, device=dev)
     dump = list(dump)
-    res["parents"] = torch.empty((len(dump), gl[0].n), dtype=torch.int32, device=dev) if dump else None
+    pa = res.get("parents")
+    if not dump:
+        res["parents"] = None
+    elif pa is None or tuple(pa.shape) != (len(dump), gl[0].n):
+        res["parents"] = torch.empty((len(dump), gl[0].n), dtype=torch.int32, device=dev)
     dump_host = (ctypes.c_int64 * max(1, len(dump)))(*dump) if dump else None
-    out = SampleOutputs(counts=_ptr(res["counts"]), counts_sq=_ptr(res.get("counts_sq")),
-                        total_steps=_ptr(res.get("total_steps")), tree_hash=_ptr(res["tree_hash"]),
-                        parents=_ptr(res["parents"]),
-                        dump_samples=ctypes.cast(dump_host, ctypes.c_void_p) if dump else None,
-                        ndump=len(dump))
+    so = SampleOutputs(counts=_ptr(res["counts"]), counts_sq=_ptr(res.get("counts_sq")),
+                       total_steps=_ptr(res.get("total_steps")), tree_hash=_ptr(res["tree_hash"]),
+                       parents=_ptr(res["parents"]),
+                       dump_samples=ctypes.cast(dump_host, ctypes.c_void_p) if dump else None,
+                       ndump=len(dump))
     tms = (ctypes.c_float * 2)()
     if timing:
-        out.timing_ms = ctypes.cast(tms, ctypes.c_void_p)
-    plan = (ctypes.c_int32 * 6)()
-    out.plan = ctypes.cast(plan, ctypes.c_void_p)
-    check(L.rwc_sample_forests(arr, G, ctypes.byref(p), ctypes.byref(out), _ptr(workspace), workspace.numel(),
+        so.timing_ms = ctypes.cast(tms, ctypes.c_void_p)
+    plan = (ctypes.c_int32 * 8)()
+    so.plan = ctypes.cast(plan, ctypes.c_void_p)
+    check(L.rwc_sample_forests(arr, G, ctypes.byref(p), ctypes.byref(so), _ptr(workspace), workspace.numel(),
                                _stream()), "rwc_sample_forests")
+    if sync and not timing:
+        check(L.rwc_workspace_status(_ptr(workspace), _stream()), "rwc_sample_forests (device status)")
     res["workspace"] = workspace
+    res["roots"] = rt
     res["walkers_per_tree"], res["trees_in_flight"], res["batches"] = int(plan[0]), int(plan[1]), int(plan[2])
     res["walk_kernel"] = ("wilson_walk", "wilson_team<false>", "wilson_team<true>")[int(plan[3])]
     res["starts"] = "spread" if plan[4] else "shared"
     res["start_order"] = "breadth-first" if plan[5] else "ascending"
+    res["graph_replayed"] = int(plan[6])
     if timing:
         res["walk_ms"], res["reduce_ms"] = float(tms[0]), float(tms[1])
+    return res
+
+
+def prepare_sampling(graphs: Graph | Sequence[Graph], num_samples: int, workspace: torch.Tensor | None = None,
+                     roots=None, **kw) -> dict:
+    """rwc_sample_prepare: writes the argument tables of a sampling call into its workspace so
+    that sample_forests(..., workspace=...) with the same graphs and parameters (seed and
+    sample_begin may differ) can run on a stream that is being captured into a hipGraph.
+    Returns {"workspace": ..., "roots": ...}; pass both back."""
+    L = _lib.lib()
+    gl = [graphs] if isinstance(graphs, Graph) else list(graphs)
+    dev = gl[0].device
+    rt = _roots_tensor(roots, dev)
+    arr, p = _sample_setup(gl, num_samples, kw.get("seed", 0), kw.get("sample_begin", 0), kw.get("root", -1),
+                           kw.get("trees_in_flight", 0), kw.get("walkers_per_tree", 0), kw.get("persistent", False),
+                           False, kw.get("accumulate", False), kw.get("max_steps_per_tree", 0),
+                           kw.get("graph_index_base", 0), kw.get("bfs_starts"), kw.get("starts", "auto"),
+                           kw.get("path_ring"), rt)
+    size = ctypes.c_size_t()
+    check(L.rwc_sample_forests_workspace(arr, len(gl), ctypes.byref(p), ctypes.byref(size)),
+          "rwc_sample_forests_workspace")
+    if workspace is None or workspace.numel() < size.value:
+        workspace = _workspace(size.value, dev)
+    check(L.rwc_sample_prepare(arr, len(gl), ctypes.byref(p), _ptr(workspace), workspace.numel(), _stream()),
+          "rwc_sample_prepare")
+    return {"workspace": workspace, "roots": rt}
+
+
+def workspace_status(workspace: torch.Tensor) -> None:
+    """Waits for the stream and raises if the last stream-ordered call on `workspace` reported
+    a device-side error."""
+    check(_lib.lib().rwc_workspace_status(_ptr(workspace), _stream()), "rwc_workspace_status")
+
+
+def release_cached_graphs() -> None:
+    _lib.lib().rwc_release_cached_graphs()
+
+
+def sample_trap_walks(graph: Graph, num_walks: int, seed: int, walk_begin: int = 0, trap: int = -1,
+                      graph_index: int = 0, max_steps_per_walk: int = 0, want_sq: bool = True,
+                      sync: bool = True) -> dict:
+    """Trap walks (rwc_sample_trap_walks): num_walks walks from every node u != trap (default the
+    pivot), each stopped at the trap and counting its visits to u.  Returns counts [n],
+    counts_sq [n] and total_steps [1] (int64 tensors holding uint64 values): counts / l
+    estimates the same diagonal as the Wilson forests, so estimate(graph, counts, num_walks)
+    gives RWC."""
+    L = _lib.lib()
+    dev = graph.device
+    p = TrapParams(seed=seed, walk_begin=walk_begin, num_walks=num_walks, trap=trap, graph_index=graph_index,
+                   max_steps_per_walk=max_steps_per_walk)
+    size = ctypes.c_size_t()
+    check(L.rwc_sample_trap_walks_workspace(ctypes.byref(graph.csr), ctypes.byref(p), ctypes.byref(size)),
+          "rwc_sample_trap_walks_workspace")
+    ws = _workspace(size.value, dev)
+    res = {"counts": torch.empty(graph.n, dtype=torch.int64, device=dev),
+           "counts_sq": torch.empty(graph.n, dtype=torch.int64, device=dev) if want_sq else None,
+           "total_steps": torch.empty(1, dtype=torch.int64, device=dev)}
+    check(L.rwc_sample_trap_walks(ctypes.byref(graph.csr), ctypes.byref(p), _ptr(res["counts"]),
+                                  _ptr(res["counts_sq"]), _ptr(res["total_steps"]), _ptr(ws), ws.numel(), _stream()),
+          "rwc_sample_trap_walks")
+    if sync:
+        check(L.rwc_workspace_status(_ptr(ws), _stream()), "rwc_sample_trap_walks (device status)")
+    res["workspace"] = ws
     return res
 
 
@@ -206,47 +307,82 @@ def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
 
 
 def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor | None = None,
-             tol: float = 1e-12, max_iter: int = 0, want_hit: bool = True, want_stderr: bool = False) -> dict:
+             tol: float = 1e-12, max_iter: int = 0, want_hit: bool = True, want_stderr: bool = False,
+             stream_ordered: bool = False, workspace: torch.Tensor | None = None, out: dict | None = None) -> dict:
     """RWC from visit totals (rwc_estimate): returns rwc, hit (hitting times to the pivot),
-    stderr and the CG iteration count."""
+    stderr and the CG iteration count.  stream_ordered=True enqueues max_iter iterations that
+    stop on the device (no host synchronisation; capturable): iters is then -1 and the outcome
+    is read with workspace_status(res["workspace"])."""
     L = _lib.lib()
     dev = graph.device
     size = ctypes.c_size_t()
     check(L.rwc_estimate_workspace(ctypes.byref(graph.csr), ctypes.byref(size)), "rwc_estimate_workspace")
-    ws = _workspace(size.value, dev)
-    rwc = torch.empty(graph.n, dtype=torch.float64, device=dev)
-    hit = torch.empty(graph.n, dtype=torch.float64, device=dev) if want_hit else None
-    se = torch.empty(graph.n, dtype=torch.float64, device=dev) if want_stderr else None
-    sp = SolveParams(tol=tol, max_iter=max_iter, check_every=0)
+    ws = workspace if workspace is not None and workspace.numel() >= size.value else _workspace(size.value, dev)
+    if out is None:
+        out = {"rwc": torch.empty(graph.n, dtype=torch.float64, device=dev),
+               "hit": torch.empty(graph.n, dtype=torch.float64, device=dev) if want_hit else None,
+               "stderr": torch.empty(graph.n, dtype=torch.float64, device=dev) if want_stderr else None}
+    sp = SolveParams(tol=tol, max_iter=max_iter, check_every=_lib.RWC_SOLVE_STREAM_ORDERED if stream_ordered else 0)
     iters = ctypes.c_int32()
     check(L.rwc_estimate(ctypes.byref(graph.csr), _ptr(counts), _ptr(counts_sq), int(l), ctypes.byref(sp),
-                         _ptr(rwc), _ptr(hit), _ptr(se), ctypes.byref(iters), _ptr(ws), ws.numel(), _stream()),
+                         _ptr(out["rwc"]), _ptr(out.get("hit")), _ptr(out.get("stderr")), ctypes.byref(iters),
+                         _ptr(ws), ws.numel(), _stream()),
           "rwc_estimate")
-    return {"rwc": rwc, "hit": hit, "stderr": se, "iters": iters.value}
+    return {**out, "iters": iters.value, "workspace": ws}
 
 
-def backward(graph: Graph, targets, gvals, k: int = 0, seed: int = 0, tol: float = 1e-10,
-             max_iter: int = 0) -> dict:
+def estimate_group(graph: Graph, roots, counts: torch.Tensor, l: int, tol: float = 1e-12, max_iter: int = 0,
+                   want_hit: bool = True, stream_ordered: bool = False) -> dict:
+    """Group RWC of the root set S and the estimate of H_{S + u} for every u from forests rooted
+    at S (rwc_estimate_group).  Returns group_rwc (a 1-element tensor), marginal [n], hit [n]
+    (hitting times to S) and the iteration count."""
+    L = _lib.lib()
+    dev = graph.device
+    rt = _roots_tensor(roots, dev)
+    size = ctypes.c_size_t()
+    check(L.rwc_estimate_group_workspace(ctypes.byref(graph.csr), ctypes.byref(size)), "rwc_estimate_group_workspace")
+    ws = _workspace(size.value, dev)
+    grp = torch.empty(1, dtype=torch.float64, device=dev)
+    marg = torch.empty(graph.n, dtype=torch.float64, device=dev)
+    hit = torch.empty(graph.n, dtype=torch.float64, device=dev) if want_hit else None
+    sp = SolveParams(tol=tol, max_iter=max_iter, check_every=_lib.RWC_SOLVE_STREAM_ORDERED if stream_ordered else 0)
+    iters = ctypes.c_int32()
+    check(L.rwc_estimate_group(ctypes.byref(graph.csr), _ptr(rt), rt.numel(), _ptr(counts), int(l),
+                               ctypes.byref(sp), _ptr(grp), _ptr(marg), _ptr(hit), ctypes.byref(iters), _ptr(ws),
+                               ws.numel(), _stream()), "rwc_estimate_group")
+    return {"group_rwc": grp, "marginal": marg, "hit": hit, "iters": iters.value, "workspace": ws}
+
+
+def dense_g(n: int, targets, gvals, device) -> torch.Tensor:
+    """The vector g (float64 [n] on the device) with g[targets] = gvals, zero elsewhere."""
+    g = torch.zeros(n, dtype=torch.float64)
+    g[torch.as_tensor(np.asarray(targets, dtype=np.int64))] = torch.as_tensor(np.asarray(gvals, dtype=np.float64))
+    return g.to(device)
+
+
+def backward(graph: Graph, g: torch.Tensor, k: int = 0, seed: int = 0, tol: float = 1e-10,
+             max_iter: int = 0, max_support: int | None = None) -> dict:
     """Gradient of sum_j g_j RWC_j with respect to the edge weights (rwc_backward).
 
-    targets / gvals: the nodes with nonzero g and their values (host arrays).  k = 0 solves
-    one column per target (exact); k > 0 uses k Rademacher probes per sign class of g.
+    g: float64 [n] device tensor (the upstream gradient).  k = 0 solves one column per nonzero
+    of g (exact; the workspace is sized for max_support nonzeros, by default the count of g's
+    nonzeros, read once); k > 0 uses k Rademacher probes per sign class of g.
     Returns grad_w (float64 [m] on the device, input-edge order) and the CG iterations."""
     L = _lib.lib()
-    t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
-    gv = np.ascontiguousarray(np.asarray(gvals, dtype=np.float64))
-    if t.shape != gv.shape or t.ndim != 1 or t.size == 0:
-        raise ValueError("targets and gvals must be matching non-empty 1-D arrays")
-    bp = BackwardParams(k=k, max_iter=max_iter, seed=seed, tol=tol, check_every=0)
-    tp = t.ctypes.data_as(ctypes.c_void_p)
-    gp = gv.ctypes.data_as(ctypes.c_void_p)
+    gt = _dev_tensor(g, torch.float64, graph.device)
+    if gt.numel() != graph.n:
+        raise ValueError(f"g must have n = {graph.n} entries, not {gt.numel()}")
+    if k == 0 and max_support is None:
+        max_support = int(torch.count_nonzero(gt))
+    bp = BackwardParams(k=k, max_iter=max_iter, seed=seed, tol=tol, check_every=0,
+                        max_support=max_support if k == 0 else 0)
     size = ctypes.c_size_t()
-    check(L.rwc_backward_workspace(ctypes.byref(graph.csr), t.size, tp, gp, ctypes.byref(bp), ctypes.byref(size)),
+    check(L.rwc_backward_workspace(ctypes.byref(graph.csr), ctypes.byref(bp), ctypes.byref(size)),
           "rwc_backward_workspace")
     ws = _workspace(size.value, graph.device)
     grad = torch.empty(graph.m, dtype=torch.float64, device=graph.device)
     iters = ctypes.c_int32()
-    check(L.rwc_backward(ctypes.byref(graph.csr), t.size, tp, gp, ctypes.byref(bp), _ptr(grad), ctypes.byref(iters),
+    check(L.rwc_backward(ctypes.byref(graph.csr), _ptr(gt), ctypes.byref(bp), _ptr(grad), ctypes.byref(iters),
                          _ptr(ws), ws.numel(), _stream()), "rwc_backward")
     return {"grad_w": grad, "iters": iters.value}
 
@@ -271,12 +407,14 @@ class RWCFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_rwc):
-        gr = grad_rwc.detach().to(torch.float64)
-        nz = torch.nonzero(gr).flatten()
-        if nz.numel() == 0:
+        gr = grad_rwc.detach().to(torch.float64).contiguous()
+        # the upstream gradient goes to the library as it is (a device vector); only the exact
+        # mode needs its number of nonzeros to size the workspace
+        nnz = int(torch.count_nonzero(gr)) if ctx.k == 0 else None
+        if nnz == 0:
             gw = torch.zeros(ctx.graph.m, dtype=ctx.wdtype, device=gr.device)
         else:
-            res = backward(ctx.graph, nz.cpu().numpy(), gr[nz].cpu().numpy(), k=ctx.k, seed=ctx.probe_seed)
+            res = backward(ctx.graph, gr, k=ctx.k, seed=ctx.probe_seed, max_support=nnz)
             gw = res["grad_w"].to(ctx.wdtype)
         return gw, None, None, None, None, None, None, None
 

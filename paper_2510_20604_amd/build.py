@@ -16,8 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librwc.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["common.cpp", "csr_build.hip", "sampler.hip", "estimate.hip", "backward.hip", "probe.hip",
-           "autotune.cpp"]
+SOURCES = ["common.cpp", "csr_build.hip", "sampler.hip", "trapwalk.hip", "estimate.hip", "backward.hip",
+           "probe.hip", "autotune.cpp"]
 # Translation units whose floating-point results are compared against FP64 references:
 # no fused multiply-add contraction.
 NO_CONTRACT = {"estimate.hip", "backward.hip"}

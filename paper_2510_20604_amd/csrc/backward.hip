@@ -36,6 +36,14 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxWaves = 8192;   // bound of the per-wave partial arrays
 constexpr int kUpdateSlots = 2048;   // partial slots per column of bpcg_update (<= kMaxWaves)
 
+__global__ void header_start(WsHeader* header) { header_begin(header); }
+
+__global__ void fill_zero(double* __restrict__ x, int64_t count) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        x[i] = 0.0;
+}
+
 struct ColScalars {
     double alpha, beta, zr, rr, rr0, zr_new, zro, rp, pap;
     int32_t done;
@@ -43,29 +51,122 @@ struct ColScalars {
 };
 
 // ----------------------------------------------------------------- RHS ---------------
-// Column 0: g (sparse, added below), column 1: d; all columns then get -mean.
-__global__ void rhs_dense(int32_t n, int32_t R, const double* __restrict__ d, const double* __restrict__ colmean,
-                          double* __restrict__ Y) {
+// The right-hand sides are built on the device from the dense g: column 0 is g, column 1 is d,
+// columns 2.. are the probe columns y_i, then every column is centred.
+//   Exact mode (k = 0): the nonzeros of g in ascending node order get columns 2, 3, ...;
+//   y = sqrt|g_u| e_u with coefficient sign(g_u).
+//   Sketch mode: k columns per sign class of g present (positive class first); probe i of
+//   class s (0 positive, 1 negative) is numbered s k + i, y_u = +-sqrt|g_u| on the nodes of
+//   its class with the sign from bit 0 of Philox word 0 on (s k + i, u, 0, 2^32 - 1) under
+//   the probe key, coefficient +-1/k.
+struct ProbeSpec {
+    int32_t k;          // 0: exact
+    int32_t pos;        // 1 if the positive class is present (it then takes the first k columns)
+    uint32_t s0, s1;    // probe key
+};
+
+// Class of g_u's sign, and the first probe column of that class.
+__device__ __forceinline__ int32_t class_first_column(const ProbeSpec& ps, double gu) {
+    return 2 + ((gu > 0.0 || !ps.pos) ? 0 : ps.k);
+}
+
+__device__ __forceinline__ double probe_entry(const ProbeSpec& ps, double gu, uint32_t u, int32_t i) {
+    const uint32_t cls = gu > 0.0 ? 0u : 1u;
+    const uint64_t x = philox_x64(cls * static_cast<uint32_t>(ps.k) + static_cast<uint32_t>(i), u, 0u, 0xFFFFFFFFu,
+                                  ps.s0, ps.s1);
+    const double a = sqrt(fabs(gu));
+    return (x & 1ull) ? -a : a;
+}
+
+// Per block over its contiguous row range: number of positive, negative, nonzero and
+// non-finite entries of g and their sum (thread sums, then a fixed tree).
+struct GPart {
+    double sum;
+    int32_t npos, nneg, nnz, nbad;
+};
+
+__device__ double block_sum(double v, double* lds);
+
+__global__ void g_partials(int32_t n, int32_t rows_per_block, const double* __restrict__ g, GPart* __restrict__ out) {
+    __shared__ double lds[kBlock];
+    __shared__ int32_t cnt[4];
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+    const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
+    double sum = 0.0;
+    int32_t np = 0, nn = 0, nb = 0;
+    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
+        const double gu = g[u];
+        if (!isfinite(gu)) {
+            ++nb;
+            continue;
+        }
+        np += gu > 0.0;
+        nn += gu < 0.0;
+        sum += gu;
+    }
+    sum = block_sum(sum, lds);
+    atomicAdd(&cnt[0], np);
+    atomicAdd(&cnt[1], nn);
+    atomicAdd(&cnt[2], nb);
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = GPart{sum, cnt[0], cnt[1], cnt[0] + cnt[1], cnt[2]};
+}
+
+// Exact mode: the rank of every nonzero of g among all nonzeros in node order (block b starts
+// at base[b]; within the block a scan over chunks of kBlock rows), and its coefficient.
+__global__ void rank_nonzeros(int32_t n, int32_t rows_per_block, const double* __restrict__ g,
+                              const int32_t* __restrict__ base, int32_t* __restrict__ rank, double* __restrict__ coef) {
+    __shared__ int32_t scan[kBlock];
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+    const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
+    int32_t carry = base[blockIdx.x];
+    for (int64_t u0 = lo; u0 < hi; u0 += kBlock) {
+        const int64_t u = u0 + threadIdx.x;
+        const double gu = u < hi ? g[u] : 0.0;
+        const int32_t f = gu != 0.0 ? 1 : 0;
+        scan[threadIdx.x] = f;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {   // inclusive Hillis-Steele scan
+            const int32_t add = static_cast<int>(threadIdx.x) >= off ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (u < hi) {
+            const int32_t r = f ? carry + scan[threadIdx.x] - 1 : -1;
+            rank[u] = r;
+            if (f) coef[2 + r] = gu > 0.0 ? 1.0 : -1.0;
+        }
+        carry += scan[kBlock - 1];
+        __syncthreads();
+    }
+}
+
+__global__ void rhs_fill(int32_t n, int32_t R, ProbeSpec ps, const double* __restrict__ g,
+                         const double* __restrict__ d, const int32_t* __restrict__ rank, double* __restrict__ Y) {
     const int64_t total = static_cast<int64_t>(n) * R;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t u = i / R;
         const int32_t c = static_cast<int32_t>(i - u * R);
-        double v = -colmean[c];
-        if (c == 1) v += d[u];
+        const double gu = g[u];
+        double v = 0.0;
+        if (c == 0) {
+            v = gu;
+        } else if (c == 1) {
+            v = d[u];
+        } else if (gu != 0.0) {
+            if (ps.k == 0) {
+                if (rank[u] == c - 2) v = sqrt(fabs(gu));
+            } else {
+                const int32_t first = class_first_column(ps, gu);
+                if (c >= first && c < first + ps.k) v = probe_entry(ps, gu, static_cast<uint32_t>(u), c - first);
+            }
+        }
         Y[i] = v;
     }
-}
-
-struct Entry {
-    int32_t node;
-    int32_t col;
-    double val;
-};
-
-__global__ void rhs_scatter(int32_t count, const Entry* __restrict__ e, int32_t R, double* __restrict__ Y) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) Y[static_cast<int64_t>(e[i].node) * R + e[i].col] += e[i].val;
 }
 
 // ------------------------------------------------------------ batched PCG ------------
@@ -479,31 +580,49 @@ struct EdgeScalars {
     double dld;
 };
 
-// trGL^ = sum_i c_i y_i^T L^+ y_i over the probe entries; dLd = d^T B.
-// d^T B over row ranges (column 1 of Z), one partial per block.
-__global__ void dld_partials(int32_t n, int32_t R, int32_t rows_per_block, const double* __restrict__ Z,
-                             const double* __restrict__ d, double* __restrict__ part) {
+// Over row ranges, one pair of partials per block: dLd = d^T B (column 1 of Z) and
+// trGL^ = sum_i c_i y_i^T L^+ y_i, with the probe entries y recomputed from g (the solve has
+// overwritten the right-hand sides).
+__global__ void scalar_partials(int32_t n, int32_t R, int32_t rows_per_block, ProbeSpec ps,
+                                const double* __restrict__ g, const int32_t* __restrict__ rank,
+                                const double* __restrict__ coef, const double* __restrict__ Z,
+                                const double* __restrict__ d, double* __restrict__ part) {
     __shared__ double lds[kBlock];
     const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
     const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
-    double q = 0.0;
-    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) q += d[u] * Z[u * R + 1];
+    double q = 0.0, t = 0.0;
+    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
+        const double* zu = Z + u * R;
+        q += d[u] * zu[1];
+        const double gu = g[u];
+        if (gu == 0.0) continue;
+        if (ps.k == 0) {
+            const int32_t c = 2 + rank[u];
+            t += coef[c] * (sqrt(fabs(gu)) * zu[c]);
+        } else {
+            const int32_t first = class_first_column(ps, gu);
+            for (int32_t i = 0; i < ps.k; ++i)
+                t += coef[first + i] * (probe_entry(ps, gu, static_cast<uint32_t>(u), i) * zu[first + i]);
+        }
+    }
     q = block_sum(q, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = q;
+    t = block_sum(t, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = q;
+        part[2 * blockIdx.x + 1] = t;
+    }
 }
 
-// trGL from the probe entries and dLd from the block partials (one block, fixed order).
-__global__ void edge_scalars(int32_t R, int32_t count, const Entry* __restrict__ e, const double* __restrict__ coef,
-                             const double* __restrict__ Z, int32_t nparts, const double* __restrict__ part,
-                             EdgeScalars* out) {
+// dLd and trGL from the block partials (one block, fixed order).
+__global__ void edge_scalars(int32_t nparts, const double* __restrict__ part, EdgeScalars* out) {
     __shared__ double lds[kBlock];
-    double t = 0.0;
-    for (int32_t i = threadIdx.x; i < count; i += blockDim.x)
-        if (e[i].col >= 2) t += coef[e[i].col] * e[i].val * Z[static_cast<int64_t>(e[i].node) * R + e[i].col];
-    t = block_sum(t, lds);
-    double q = 0.0;
-    for (int32_t b = threadIdx.x; b < nparts; b += kBlock) q += part[b];
+    double q = 0.0, t = 0.0;
+    for (int32_t b = threadIdx.x; b < nparts; b += kBlock) {
+        q += part[2 * b];
+        t += part[2 * b + 1];
+    }
     q = block_sum(q, lds);
+    t = block_sum(t, lds);
     if (threadIdx.x == 0) {
         out->trgl = t;
         out->dld = q;
@@ -545,18 +664,24 @@ __global__ void edge_gradient(int32_t n, int64_t nnz, int32_t R, const int32_t* 
 }
 
 struct BwdLayout {
+    WsHeader* header;
     double *Y, *X, *AP, *part, *colmean, *coef;
     float* P32;
     ColScalars* sc;
     EdgeScalars* es;
-    Entry* entries;
+    GPart* gpart;
+    int32_t* gbase;
+    int32_t* rank;
     size_t total;
 };
 
-BwdLayout carve_bwd(void* ws, int32_t n, int32_t R, int32_t nentries) {
+constexpr int32_t kRowBlocks = 2048;   // blocks of the row-range passes over g
+
+BwdLayout carve_bwd(void* ws, int32_t n, int32_t R) {
     Carver c(ws);
     BwdLayout L{};
     const size_t nr = static_cast<size_t>(n) * R;
+    L.header = c.take<WsHeader>(kHeaderBytes / sizeof(WsHeader));
     L.Y = c.take<double>(nr);
     L.X = c.take<double>(nr);
     L.AP = c.take<double>(nr);
@@ -566,93 +691,32 @@ BwdLayout carve_bwd(void* ws, int32_t n, int32_t R, int32_t nentries) {
     L.coef = c.take<double>(R);
     L.sc = c.take<ColScalars>(R);
     L.es = c.take<EdgeScalars>(1);
-    L.entries = c.take<Entry>(nentries > 0 ? nentries : 1);
+    L.gpart = c.take<GPart>(kRowBlocks);
+    L.gbase = c.take<int32_t>(kRowBlocks);
+    L.rank = c.take<int32_t>(n);
     L.total = c.used();
     return L;
 }
 
-// Probe layout decided on the host from the target list: number of columns and entries.
-struct Probes {
-    int32_t R = 2;
-    std::vector<Entry> entries;      // sparse part of the RHS (g column and probe columns)
-    std::vector<double> colmean;     // mean of each RHS column before centring
-    std::vector<double> coef;        // c_i (0 for the g and d columns)
-    double G = 0.0;
-};
-
-// Bounds of one adjoint call: solve columns (grid sizes and column indices stay in 32 bits)
-// and right-hand-side entries (counted in int32 on the device).
+// Bound of one adjoint call's solve columns (grid sizes and column indices stay in 32 bits).
 constexpr int64_t kMaxSolveColumns = int64_t{1} << 24;
-constexpr int64_t kMaxProbeEntries = 0x7FFFFFFF;
 
-int plan_probes(const rwc_csr* g, int32_t T, const int32_t* targets, const double* gvals,
-                const rwc_backward_params* bp, Probes* pr) {
-    const int32_t n = g->n;
-    const int32_t k = bp ? bp->k : 0;
-    if (k < 0) return fail(RWC_ERR_INVALID_ARG, "k must be >= 0");
-    if (n < 2) return fail(RWC_ERR_INVALID_ARG, "the graph has %d nodes", n);
-    bool pos = false, neg = false;
-    int64_t npos = 0, nneg = 0;
-    for (int32_t t = 0; t < T; ++t) {
-        if (targets[t] < 0 || targets[t] >= n) return fail(RWC_ERR_INVALID_ARG, "target %d out of range", targets[t]);
-        if (!std::isfinite(gvals[t])) return fail(RWC_ERR_INVALID_ARG, "g value of target %d is not finite", t);
-        pos |= gvals[t] > 0.0;
-        neg |= gvals[t] < 0.0;
-        npos += gvals[t] > 0.0;
-        nneg += gvals[t] < 0.0;
-        pr->G += gvals[t];
-    }
-    // sizes checked before anything is built: columns 2 + P, entries T (g column) plus one
-    // per target and probe column of its sign class (one per target when exact)
-    const int64_t P64 = (k == 0) ? T : static_cast<int64_t>(k) * ((pos ? 1 : 0) + (neg ? 1 : 0));
-    const int64_t nent64 = T + ((k == 0) ? T : static_cast<int64_t>(k) * (npos + nneg));
-    if (2 + P64 > kMaxSolveColumns)
-        return fail(RWC_ERR_TOO_LARGE, "%lld solve columns (limit %lld)", static_cast<long long>(2 + P64),
+// Columns the workspace is sized for: sketch mode 2 + 2k (both sign classes); exact mode
+// 2 + max_support.
+int64_t workspace_columns(const rwc_backward_params* bp) {
+    const int64_t k = bp->k;
+    return 2 + (k > 0 ? 2 * k : static_cast<int64_t>(bp->max_support));
+}
+
+int check_params(const rwc_csr* g, const rwc_backward_params* bp) {
+    if (!g || !bp) return fail(RWC_ERR_INVALID_ARG, "g and bp are required");
+    if (g->n < 2) return fail(RWC_ERR_INVALID_ARG, "the graph has %d nodes", g->n);
+    if (bp->k < 0) return fail(RWC_ERR_INVALID_ARG, "k must be >= 0");
+    if (bp->k == 0 && (bp->max_support < 1 || bp->max_support > g->n))
+        return fail(RWC_ERR_INVALID_ARG, "exact mode needs max_support in [1, n]");
+    if (workspace_columns(bp) > kMaxSolveColumns)
+        return fail(RWC_ERR_TOO_LARGE, "%lld solve columns (limit %lld)", static_cast<long long>(workspace_columns(bp)),
                     static_cast<long long>(kMaxSolveColumns));
-    if (nent64 > kMaxProbeEntries)
-        return fail(RWC_ERR_TOO_LARGE, "%lld right-hand-side entries (limit %lld)", static_cast<long long>(nent64),
-                    static_cast<long long>(kMaxProbeEntries));
-    const int32_t P = static_cast<int32_t>(P64);
-    pr->R = 2 + P;
-    pr->coef.assign(pr->R, 0.0);
-    pr->colmean.assign(pr->R, 0.0);
-    pr->colmean[1] = g->vol / n;
-    for (int32_t t = 0; t < T; ++t) {
-        pr->entries.push_back(Entry{targets[t], 0, gvals[t]});
-        pr->colmean[0] += gvals[t] / n;
-    }
-    const uint32_t s0 = bp ? static_cast<uint32_t>(bp->seed) : 0u;
-    const uint32_t s1 = bp ? static_cast<uint32_t>(bp->seed >> 32) : 0u;
-    if (k == 0) {
-        for (int32_t t = 0; t < T; ++t) {
-            const int32_t c = 2 + t;
-            const double a = std::fabs(gvals[t]);
-            pr->coef[c] = (gvals[t] > 0) ? 1.0 : (gvals[t] < 0 ? -1.0 : 0.0);
-            pr->entries.push_back(Entry{targets[t], c, std::sqrt(a)});
-            pr->colmean[c] = std::sqrt(a) / n;
-        }
-    } else {
-        int32_t c = 2;
-        for (int cls = 0; cls < 2; ++cls) {
-            const bool use = (cls == 0) ? pos : neg;
-            if (!use) continue;
-            for (int32_t i = 0; i < k; ++i, ++c) {
-                const uint32_t probe = static_cast<uint32_t>(cls * k + i);
-                pr->coef[c] = (cls == 0 ? 1.0 : -1.0) / k;
-                for (int32_t t = 0; t < T; ++t) {
-                    const double gv = gvals[t];
-                    if ((cls == 0 && gv <= 0) || (cls == 1 && gv >= 0)) continue;
-                    // Rademacher sign of probe i at node targets[t]: bit 0 of Philox word 0 on
-                    // the counter (probe, node, 0, 2^32 - 1) under the probe key
-                    const uint64_t x = philox_x64(probe, static_cast<uint32_t>(targets[t]), 0u, 0xFFFFFFFFu, s0, s1);
-                    const double sgn = (x & 1ull) ? -1.0 : 1.0;
-                    const double val = sgn * std::sqrt(std::fabs(gv));
-                    pr->entries.push_back(Entry{targets[t], c, val});
-                    pr->colmean[c] += val / n;
-                }
-            }
-        }
-    }
     return RWC_OK;
 }
 
@@ -661,41 +725,84 @@ int plan_probes(const rwc_csr* g, int32_t T, const int32_t* targets, const doubl
 
 using namespace rwc;
 
-extern "C" int rwc_backward_workspace(const rwc_csr* g, int32_t num_targets, const int32_t* targets,
-                                      const double* gvals, const rwc_backward_params* bp, size_t* bytes) {
+extern "C" int rwc_backward_workspace(const rwc_csr* g, const rwc_backward_params* bp, size_t* bytes) {
     clear_error();
-    if (!g || !bytes || num_targets < 1 || !targets || !gvals)
-        return fail(RWC_ERR_INVALID_ARG, "g, targets, gvals and bytes are required");
-    Probes pr;
-    RWC_CHECK(plan_probes(g, num_targets, targets, gvals, bp, &pr));
-    *bytes = carve_bwd(nullptr, g->n, pr.R, static_cast<int32_t>(pr.entries.size())).total;
+    if (!bytes) return fail(RWC_ERR_INVALID_ARG, "bytes is required");
+    RWC_CHECK(check_params(g, bp));
+    *bytes = carve_bwd(nullptr, g->n, static_cast<int32_t>(workspace_columns(bp))).total;
     return RWC_OK;
 }
 
-extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t* targets, const double* gvals,
-                            const rwc_backward_params* bp, double* grad_w, int32_t* iters, void* ws, size_t ws_bytes,
-                            void* stream) {
+extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_backward_params* bp, double* grad_w,
+                            int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
-    if (!g || !grad_w || num_targets < 1 || !targets || !gvals)
-        return fail(RWC_ERR_INVALID_ARG, "g, targets, gvals and grad_w are required");
-    Probes pr;
-    RWC_CHECK(plan_probes(g, num_targets, targets, gvals, bp, &pr));
-    const int32_t n = g->n, R = pr.R, v = g->pivot;
-    const int32_t nent = static_cast<int32_t>(pr.entries.size());
-    RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, R, nent).total));
-    BwdLayout L = carve_bwd(ws, n, R, nent);
+    if (!grad_rwc || !grad_w) return fail(RWC_ERR_INVALID_ARG, "grad_rwc and grad_w are required");
+    RWC_CHECK(check_params(g, bp));
+    const int32_t n = g->n, v = g->pivot, k = bp->k;
+    const int32_t Rmax = static_cast<int32_t>(workspace_columns(bp));
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, Rmax).total));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const double tol = (bp && bp->tol > 0) ? bp->tol : 1e-10;
-    const int max_iter = (bp && bp->max_iter > 0) ? bp->max_iter : 20000;
-    const int check = (bp && bp->check_every > 0) ? bp->check_every : 16;
+    const double tol = bp->tol > 0 ? bp->tol : 1e-10;
+    const int max_iter = bp->max_iter > 0 ? bp->max_iter : 20000;
+    const int check = bp->check_every > 0 ? bp->check_every : 16;
 
-    RWC_HIP(hipMemcpyAsync(L.entries, pr.entries.data(), sizeof(Entry) * nent, hipMemcpyHostToDevice, s));
-    RWC_HIP(hipMemcpyAsync(L.colmean, pr.colmean.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
-    RWC_HIP(hipMemcpyAsync(L.coef, pr.coef.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    // 1. The support of g: counts per sign and the sum, per row block, read back once.  The
+    // number of solve columns depends on them.
+    BwdLayout L = carve_bwd(ws, n, Rmax);
+    const int32_t rblocks = static_cast<int32_t>(blocks_for(n, 1) < kRowBlocks ? blocks_for(n, 1) : kRowBlocks);
+    const int32_t rpb = static_cast<int32_t>((static_cast<int64_t>(n) + rblocks - 1) / rblocks);
+    hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
+    hipLaunchKernelGGL(g_partials, dim3(rblocks), dim3(kBlock), 0, s, n, rpb, grad_rwc, L.gpart);
+    RWC_HIP(hipGetLastError());
+    std::vector<GPart> gp(rblocks);
+    RWC_HIP(hipMemcpyAsync(gp.data(), L.gpart, sizeof(GPart) * rblocks, hipMemcpyDeviceToHost, s));
+    RWC_HIP(hipStreamSynchronize(s));
+    double G = 0.0;
+    int64_t npos = 0, nneg = 0, nbad = 0;
+    std::vector<int32_t> base(rblocks);
+    int64_t nz = 0;
+    for (int32_t b = 0; b < rblocks; ++b) {   // fixed order
+        G += gp[b].sum;
+        npos += gp[b].npos;
+        nneg += gp[b].nneg;
+        nbad += gp[b].nbad;
+        base[b] = static_cast<int32_t>(nz);
+        nz += gp[b].nnz;
+    }
+    if (nbad) return fail(RWC_ERR_INVALID_ARG, "grad_rwc holds %lld values that are not finite", (long long)nbad);
+    if (nz == 0) {   // the loss is identically zero: so is its gradient
+        hipLaunchKernelGGL(fill_zero, dim3(blocks_for(g->m, kBlock) < 8192 ? blocks_for(g->m, kBlock) : 8192),
+                           dim3(kBlock), 0, s, grad_w, g->m);
+        RWC_HIP(hipGetLastError());
+        RWC_HIP(hipStreamSynchronize(s));
+        if (iters) *iters = 0;
+        return RWC_OK;
+    }
+    if (k == 0 && nz > bp->max_support)
+        return fail(RWC_ERR_INVALID_ARG, "grad_rwc has %lld nonzeros, more than max_support = %d", (long long)nz,
+                    bp->max_support);
+    const int32_t R = static_cast<int32_t>(2 + (k == 0 ? nz : static_cast<int64_t>(k) * ((npos > 0) + (nneg > 0))));
+    // the layout of this call (R columns) fits inside the workspace sized for Rmax
+    L = carve_bwd(ws, n, R);
+    ProbeSpec ps{k, npos > 0 ? 1 : 0, static_cast<uint32_t>(bp->seed), static_cast<uint32_t>(bp->seed >> 32)};
+    std::vector<double> coef(R, 0.0);
+    if (k > 0) {
+        int32_t c = 2;
+        for (int cls = 0; cls < 2; ++cls) {
+            if ((cls == 0 ? npos : nneg) == 0) continue;
+            for (int32_t i = 0; i < k; ++i) coef[c++] = (cls == 0 ? 1.0 : -1.0) / k;
+        }
+    }
+    RWC_HIP(hipMemcpyAsync(L.coef, coef.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    RWC_HIP(hipMemcpyAsync(L.gbase, base.data(), sizeof(int32_t) * rblocks, hipMemcpyHostToDevice, s));
+    // the host vectors above are read by the copies before the synchronisations below
+
+    // 2. Right-hand sides, centred
+    if (k == 0)
+        hipLaunchKernelGGL(rank_nonzeros, dim3(rblocks), dim3(kBlock), 0, s, n, rpb, grad_rwc, L.gbase, L.rank, L.coef);
     const int64_t nr = static_cast<int64_t>(n) * R;
     const unsigned flat = blocks_for(nr, kBlock) < 8192 ? blocks_for(nr, kBlock) : 8192;
-    hipLaunchKernelGGL(rhs_dense, dim3(flat), dim3(kBlock), 0, s, n, R, g->strength, L.colmean, L.Y);
-    hipLaunchKernelGGL(rhs_scatter, dim3(blocks_for(nent, kBlock)), dim3(kBlock), 0, s, nent, L.entries, R, L.Y);
+    hipLaunchKernelGGL(rhs_fill, dim3(flat), dim3(kBlock), 0, s, n, R, ps, grad_rwc, g->strength, L.rank, L.Y);
 
     // one wave per row up to what the device holds at once: the SpMM is bound by the latency
     // of its row gathers, so every resident wave slot should hold one (4096 -> 6144 waves:
@@ -706,10 +813,16 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
     nwaves = static_cast<int64_t>(wave_blocks) * kWavesPerBlock;
     const int32_t nw = static_cast<int32_t>(nwaves);
     const int32_t rows_per_block = static_cast<int32_t>((static_cast<int64_t>(n) + wave_blocks - 1) / wave_blocks);
-    // the update runs R * m blocks: m * kBlock rows in flight per column, m * kBlock partial
-    // slots per column, m at most kUpdateSlots / kBlock (2048 slots per column, R = 66: a
-    // gradient 5 % faster than with 8192 on BA(1e5, 4) and 1.4 % on R-MAT scale 23, from fewer
-    // scattered partial writes and reads; 1024 slots are slower on both)
+    // (the partial arrays hold kMaxWaves * R * 3 doubles >= wave_blocks * R)
+    hipLaunchKernelGGL(column_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.Y, L.part);
+    hipLaunchKernelGGL(column_finish, dim3(R), dim3(kBlock), 0, s, static_cast<int32_t>(wave_blocks), L.part,
+                       L.colmean, 1.0 / n);
+    hipLaunchKernelGGL(center_columns, dim3(flat), dim3(kBlock), 0, s, n, R, L.colmean, L.Y);
+
+    // 3. Batched PCG.  The update runs R * m blocks: m * kBlock rows in flight per column,
+    // m * kBlock partial slots per column, m at most kUpdateSlots / kBlock (2048 slots per
+    // column, R = 66: a gradient 5 % faster than with 8192 on BA(1e5, 4) and 1.4 % on R-MAT
+    // scale 23, from fewer scattered partial writes and reads; 1024 slots are slower on both)
     const int64_t upd_m = blocks_for(n, kBlock) < kUpdateSlots / kBlock ? blocks_for(n, kBlock) : kUpdateSlots / kBlock;
     const unsigned upd_blocks = static_cast<unsigned>(upd_m * R);
     const int32_t upd_nw = static_cast<int32_t>(upd_m * kBlock);
@@ -746,19 +859,17 @@ extern "C" int rwc_backward(const rwc_csr* g, int32_t num_targets, const int32_t
             if (host[c].rr0 > 0) worst = std::fmax(worst, std::sqrt(host[c].rr / host[c].rr0));
         return fail(RWC_ERR_NOT_CONVERGED, "adjoint solves: worst relative residual %.3e after %d iterations", worst, it);
     }
-    // L^+ y = z - mean(z)
-    // (the partial arrays reuse the PCG partials: kMaxWaves * R * 3 doubles >= wave_blocks * R)
+    // 4. L^+ y = z - mean(z), the two scalars, and the per-edge gradient
     hipLaunchKernelGGL(column_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.X, L.part);
     hipLaunchKernelGGL(column_finish, dim3(R), dim3(kBlock), 0, s, static_cast<int32_t>(wave_blocks), L.part,
                        L.colmean, 1.0 / n);
     hipLaunchKernelGGL(center_columns, dim3(flat), dim3(kBlock), 0, s, n, R, L.colmean, L.X);
-    hipLaunchKernelGGL(dld_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.X, g->strength,
-                       L.part);
-    hipLaunchKernelGGL(edge_scalars, dim3(1), dim3(kBlock), 0, s, R, nent, L.entries, L.coef, L.X,
-                       static_cast<int32_t>(wave_blocks), L.part, L.es);
+    hipLaunchKernelGGL(scalar_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, ps, grad_rwc,
+                       L.rank, L.coef, L.X, g->strength, L.part);
+    hipLaunchKernelGGL(edge_scalars, dim3(1), dim3(kBlock), 0, s, static_cast<int32_t>(wave_blocks), L.part, L.es);
     const unsigned edge_blocks = blocks_for(g->nnz, kBlock) < 16384 ? blocks_for(g->nnz, kBlock) : 16384;
     hipLaunchKernelGGL(edge_gradient, dim3(edge_blocks), dim3(kBlock), 0, s, n, g->nnz, R, g->row_ptr, g->col,
-                       g->edge_id, L.X, L.coef, L.es, pr.G, g->vol, grad_w);
+                       g->edge_id, L.X, L.coef, L.es, G, g->vol, grad_w);
     RWC_HIP(hipGetLastError());
     RWC_HIP(hipStreamSynchronize(s));
     return RWC_OK;

@@ -31,13 +31,19 @@ void clear_error() {
 
 int device_error_to_status(uint32_t bits) {
     if (bits == 0) return RWC_OK;
-    if (bits & kErrNodeRange) return fail(RWC_ERR_NODE_RANGE, "an edge endpoint is outside [0, n)");
+    if (bits & kErrNodeRange) return fail(RWC_ERR_NODE_RANGE, "a node id (edge endpoint or root) is outside [0, n)");
     if (bits & kErrSelfLoop) return fail(RWC_ERR_SELF_LOOP, "the edge list contains a self-loop");
     if (bits & kErrDupEdge) return fail(RWC_ERR_DUP_EDGE, "the edge list repeats an undirected edge");
     if (bits & kErrWeight)
         return fail(RWC_ERR_WEIGHT_RANGE, "an edge weight is not a float32 value in [0.5, 65536)");
     if (bits & kErrStrength)
         return fail(RWC_ERR_WEIGHT_RANGE, "a weighted degree reaches 2^53 (fixed-point overflow)");
+    if (bits & kErrVolume)
+        return fail(RWC_ERR_WEIGHT_RANGE, "the total weight times 2^24 reaches 2^64 (fixed-point overflow)");
+    if (bits & kErrDupRoot) return fail(RWC_ERR_INVALID_ARG, "the root set lists a node twice");
+    if (bits & kErrNonFinite) return fail(RWC_ERR_INVALID_ARG, "an input value is not finite");
+    if (bits & kErrNotConverged)
+        return fail(RWC_ERR_NOT_CONVERGED, "the solve missed its tolerance within max_iter iterations");
     if (bits & kErrStepLimit)
         return fail(RWC_ERR_STEP_LIMIT, "a tree exceeded max_steps_per_tree walk steps");
     if (bits & kErrCountOverflow)
@@ -95,4 +101,29 @@ extern "C" int rwc_last_error(char* buf, size_t len) {
         buf[k] = '\0';
     }
     return static_cast<int>(s.size());
+}
+
+extern "C" int rwc_workspace_status(const void* ws, void* stream) {
+    using namespace rwc;
+    clear_error();
+    if (!ws) return fail(RWC_ERR_INVALID_ARG, "workspace is null");
+    WsHeader h{};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RWC_HIP(hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s));
+    RWC_HIP(hipStreamSynchronize(s));
+    if (h.tag != kHeaderTag) return fail(RWC_ERR_INVALID_ARG, "the workspace holds no call's status");
+    return device_error_to_status(h.status);
+}
+
+extern "C" int rwc_workspace_iterations(const void* ws, int32_t* iters, void* stream) {
+    using namespace rwc;
+    clear_error();
+    if (!ws || !iters) return fail(RWC_ERR_INVALID_ARG, "workspace and iters are required");
+    WsHeader h{};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RWC_HIP(hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s));
+    RWC_HIP(hipStreamSynchronize(s));
+    if (h.tag != kHeaderTag) return fail(RWC_ERR_INVALID_ARG, "the workspace holds no call's status");
+    *iters = h.iters;
+    return RWC_OK;
 }

@@ -78,9 +78,32 @@ enum DeviceError : uint32_t {
     kErrStrength = 1u << 6,
     kErrRetrace = 1u << 7,
     kErrProtocol = 1u << 8,
+    kErrVolume = 1u << 9,
+    kErrNotConverged = 1u << 10,
+    kErrDupRoot = 1u << 11,
+    kErrNonFinite = 1u << 12,
 };
 
 int device_error_to_status(uint32_t bits);
+
+// The first kHeaderBytes of every sampling, estimate and adjoint workspace.  The first kernel
+// of each call sets `tag` and clears `status`; later kernels of the call OR error bits
+// (DeviceError) into `status`, so the outcome of a call that returned before its device work
+// finished can be read afterwards (rwc_workspace_status).
+struct WsHeader {
+    uint32_t status;
+    uint32_t tag;
+    int32_t iters;      // solve iterations run (estimate)
+    uint32_t reserved;
+};
+constexpr size_t kHeaderBytes = 256;
+constexpr uint32_t kHeaderTag = 0x52574331u;
+
+__device__ __forceinline__ void header_begin(WsHeader* h) {
+    h->status = 0;
+    h->tag = kHeaderTag;
+    h->iters = 0;
+}
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();

@@ -283,9 +283,12 @@ __global__ void row_pass(int32_t n, const int32_t* __restrict__ row_ptr, const f
                 const int32_t i = b0 + lane;
                 // weight is a float32 in [0.5, 65536): w * 2^24 is an exact integer below 2^40
                 const uint64_t W = (i < end) ? static_cast<uint64_t>(static_cast<double>(weight[i]) * 16777216.0) : 0ull;
-                const uint64_t x = wave_incl_scan_u64(W, lane);
+                const uint64_t x = wave_incl_scan_u64(W, lane);   // < 64 * 2^40, no wrap
                 if (i < end) cdf[i] = carry + x;
-                carry += __shfl(x, kWave - 1, kWave);
+                // saturate at 2^63: a row above 2^53 is rejected below, and a long row of
+                // large weights must not wrap back under that bound first
+                const uint64_t chunk = __shfl(x, kWave - 1, kWave);
+                carry = (carry >= (1ull << 63) - chunk) ? (1ull << 63) : carry + chunk;
             }
             S = carry;
         } else {
@@ -295,13 +298,20 @@ __global__ void row_pass(int32_t n, const int32_t* __restrict__ row_ptr, const f
             if (S >= (1ull << 53)) bits |= kErrStrength;
             strength[u] = static_cast<double>(S) * (1.0 / 16777216.0);
             sfix[u] = S;
+            // vol must stay an exact uint64: every row is below 2^63 here, so a wrap of the
+            // running sum is seen as a result smaller than the row added
+            if (vol + S < vol) bits |= kErrVolume;
             vol += S;
             maxs = S > maxs ? S : maxs;
             maxdeg = (end - beg) > maxdeg ? (end - beg) : maxdeg;
         }
     }
     if (lane == 0) {
-        if (vol) atomicAdd(reinterpret_cast<unsigned long long*>(&sc->vol_fixed), static_cast<unsigned long long>(vol));
+        if (vol) {
+            const uint64_t before = atomicAdd(reinterpret_cast<unsigned long long*>(&sc->vol_fixed),
+                                              static_cast<unsigned long long>(vol));
+            if (before + vol < before) bits |= kErrVolume;   // the total wrapped past 2^64
+        }
         if (maxs) atomicMax(reinterpret_cast<unsigned long long*>(&sc->max_s), static_cast<unsigned long long>(maxs));
         if (maxdeg) atomicMax(&sc->max_deg, maxdeg);
         if (bits) atomicOr(&sc->status, bits);

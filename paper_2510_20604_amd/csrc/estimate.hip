@@ -27,8 +27,15 @@ struct Scalars {
     double beta;
     double rr;      // r^T r
     double rr0;     // ||b||^2
-    double rwc_v;   // RWC of the pivot
+    double rwc_v;   // RWC of the pivot (of the root set for the group estimate)
+    int32_t done;   // the residual met the tolerance: later iteration kernels return at once
+    int32_t iters;  // iterations completed
 };
+
+// Grounded nodes: the pivot v, or the root set of the group estimate (bitmap of n bits).
+__device__ __forceinline__ bool grounded(const uint32_t* __restrict__ gmask, int32_t v, int64_t u) {
+    return gmask ? ((gmask[u >> 5] >> (u & 31)) & 1u) != 0 : u == v;
+}
 
 __device__ __forceinline__ double block_sum(double v, double* lds) {
     v = wave_sum(v);
@@ -42,15 +49,16 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return s;  // valid in thread 0
 }
 
-__global__ void pcg_init(int32_t n, int32_t v, const double* __restrict__ d, double* __restrict__ x,
-                         double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
+__global__ void pcg_init(int32_t n, int32_t v, const uint32_t* __restrict__ gmask, const double* __restrict__ d,
+                         double* __restrict__ x, double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
                          double* __restrict__ part) {
     __shared__ double lds[kBlock / kWave];
     double rz = 0.0, rr = 0.0;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const double ru = (u == v) ? 0.0 : d[u];
-        const double zu = (u == v) ? 0.0 : ru / d[u];
+        const bool gu = grounded(gmask, v, u);
+        const double ru = gu ? 0.0 : d[u];
+        const double zu = gu ? 0.0 : ru / d[u];
         x[u] = 0.0;
         r[u] = ru;
         z[u] = zu;
@@ -74,11 +82,13 @@ __global__ void pcg_init(int32_t n, int32_t v, const double* __restrict__ d, dou
 constexpr int kRowLanes = 8;
 constexpr int kLongRow = 16 * kRowLanes;
 
-__global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+__global__ void spmv_dot(int32_t n, int32_t v, const uint32_t* __restrict__ gmask, const Scalars* __restrict__ sc,
+                         const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                          const float* __restrict__ weight, const double* __restrict__ d, const double* __restrict__ p,
                          double* __restrict__ ap, double* __restrict__ part) {
     __shared__ double lds[kBlock / kWave];
     __shared__ uint64_t long_mask[kBlock / kWave];
+    if (sc->done) return;
     const int sub = threadIdx.x & (kRowLanes - 1);
     const int group = threadIdx.x / kRowLanes;
     constexpr int kGroups = kBlock / kRowLanes;
@@ -124,7 +134,7 @@ __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_p
 #pragma unroll
             for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
             if (sub == 0) {
-                const double y = (u == v) ? 0.0 : du * pu - s;
+                const double y = grounded(gmask, v, u) ? 0.0 : du * pu - s;
                 ap[u] = y;
                 acc += pu * y;
             }
@@ -151,7 +161,7 @@ __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_p
                     s += static_cast<double>(weight[k]) * p[col[k]];
                 s = block_sum(s, lds);
                 if (threadIdx.x == 0) {
-                    const double y = (r == v) ? 0.0 : d[r] * p[r] - s;
+                    const double y = grounded(gmask, v, r) ? 0.0 : d[r] * p[r] - s;
                     ap[r] = y;
                     acc += p[r] * y;
                 }
@@ -163,15 +173,17 @@ __global__ void spmv_dot(int32_t n, int32_t v, const int32_t* __restrict__ row_p
     if (threadIdx.x == 0) part[2 * blockIdx.x] = acc;
 }
 
-__global__ void update_xr(int32_t n, int32_t v, const Scalars* __restrict__ sc, const double* __restrict__ d,
-                          double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-                          const double* __restrict__ p, const double* __restrict__ ap, double* __restrict__ part) {
+__global__ void update_xr(int32_t n, int32_t v, const uint32_t* __restrict__ gmask, const Scalars* __restrict__ sc,
+                          const double* __restrict__ d, double* __restrict__ x, double* __restrict__ r,
+                          double* __restrict__ z, const double* __restrict__ p, const double* __restrict__ ap,
+                          double* __restrict__ part) {
     __shared__ double lds[kBlock / kWave];
+    if (sc->done) return;
     const double alpha = sc->alpha;
     double rz = 0.0, rr = 0.0;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        if (u == v) continue;
+        if (grounded(gmask, v, u)) continue;
         x[u] = x[u] + alpha * p[u];
         const double ru = r[u] - alpha * ap[u];
         const double zu = ru / d[u];
@@ -188,19 +200,24 @@ __global__ void update_xr(int32_t n, int32_t v, const Scalars* __restrict__ sc, 
     }
 }
 
-__global__ void update_p(int32_t n, int32_t v, const Scalars* __restrict__ sc, const double* __restrict__ z,
-                         double* __restrict__ p) {
+__global__ void update_p(int32_t n, int32_t v, const uint32_t* __restrict__ gmask, const Scalars* __restrict__ sc,
+                         const double* __restrict__ z, double* __restrict__ p) {
+    if (sc->done) return;
     const double beta = sc->beta;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        if (u != v) p[u] = z[u] + beta * p[u];
+        if (!grounded(gmask, v, u)) p[u] = z[u] + beta * p[u];
 }
 
 // Sums the per-block partials in a fixed order and advances the CG scalars.
 //   mode 0: after pcg_init (rz, rr0)    mode 1: after spmv_dot (alpha)
 //   mode 2: after update_xr (beta, rr)  mode 3: after pivot_partials (rwc_v)
-__global__ void scalars_step(const double* __restrict__ part, int nparts, Scalars* sc, int mode, double vol) {
+//   The iteration kernels return at once after the step that met the tolerance (`done`), so
+//   a fixed number of launched iterations stops exactly where a host-checked loop would.
+__global__ void scalars_step(const double* __restrict__ part, int nparts, Scalars* sc, int mode, double vol,
+                             double tol2) {
     __shared__ double lds[kBlock / kWave];
+    if ((mode == 1 || mode == 2) && sc->done) return;
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
         a += part[2 * i];
@@ -214,12 +231,16 @@ __global__ void scalars_step(const double* __restrict__ part, int nparts, Scalar
         sc->rr0 = b;
         sc->rr = b;
         sc->beta = 0.0;
+        sc->done = (b == 0.0) ? 1 : 0;
+        sc->iters = 0;
     } else if (mode == 1) {
         sc->alpha = (a != 0.0) ? sc->rz / a : 0.0;
     } else if (mode == 2) {
         sc->beta = (sc->rz != 0.0) ? a / sc->rz : 0.0;
         sc->rz = a;
         sc->rr = b;
+        sc->iters += 1;
+        sc->done = (b <= tol2 * sc->rr0) ? 1 : 0;
     } else {
         sc->rwc_v = a / vol;
     }
@@ -242,7 +263,7 @@ __global__ void pivot_partials(int32_t n, const double* __restrict__ d, const do
 __global__ void assemble(int32_t n, int32_t v, double vol, double l, const uint64_t* __restrict__ counts,
                          const uint64_t* __restrict__ counts_sq, const double* __restrict__ d,
                          const double* __restrict__ h, const Scalars* __restrict__ sc, double* __restrict__ rwc,
-                         double* __restrict__ se) {
+                         double* __restrict__ se, double* __restrict__ hit) {
     const double rv = sc->rwc_v;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -254,6 +275,7 @@ __global__ void assemble(int32_t n, int32_t v, double vol, double l, const uint6
             const double b = 2.0 * h[u];
             rwc[u] = (a - b) + rv;
         }
+        if (hit) hit[u] = h[u];
         if (se) {
             double s = 0.0;
             if (u != v && l > 1.0) {
@@ -268,15 +290,73 @@ __global__ void assemble(int32_t n, int32_t v, double vol, double l, const uint6
     }
 }
 
+// Group RWC of a root set S (hitting time to the set, H_S = sum_u pi_u h_u with h solving the
+// system grounded at S) and, for every node u, the estimate of H_{S + u} from the S-rooted
+// forests: removing u from the grounded system is a rank-one update, so with M = L_S,
+//   h' = h - (h_u / (M^-1)_uu) M^-1 e_u   and   H_{S + u} = H_S - h_u^2 / (vol (M^-1)_uu),
+// and the forests' visit totals estimate d_u (M^-1)_uu by t~_u = C_u / l (as in Lemma 5.2 for
+// one root), so H_{S + u} ~ H_S - d_u h_u^2 / (vol t~_u).  Nodes of S keep H_S.
+__global__ void assemble_group(int32_t n, const uint32_t* __restrict__ gmask, double vol, double l,
+                               const uint64_t* __restrict__ counts, const double* __restrict__ d,
+                               const double* __restrict__ h, const Scalars* __restrict__ sc,
+                               double* __restrict__ marginal, double* __restrict__ hit, double* __restrict__ group) {
+    const double hs = sc->rwc_v;
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (u == 0) *group = hs;
+        if (hit) hit[u] = h[u];
+        if (grounded(gmask, -1, u)) {
+            marginal[u] = hs;
+        } else {
+            const double t = static_cast<double>(counts[u]) / l;
+            const double q = (d[u] * (h[u] * h[u])) / (vol * t);
+            marginal[u] = hs - q;
+        }
+    }
+}
+
+// Root set of the group estimate as a bitmap; ids out of range or repeated are reported.
+__global__ void clear_words(uint32_t* __restrict__ w, int64_t count) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        w[i] = 0u;
+}
+
+__global__ void mark_roots(const int32_t* __restrict__ roots, int32_t nroots, int32_t n, uint32_t* __restrict__ gmask,
+                           WsHeader* header) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nroots) return;
+    const int32_t r = roots[i];
+    if (r < 0 || r >= n) {
+        atomicOr(&header->status, static_cast<uint32_t>(kErrNodeRange));
+        return;
+    }
+    const uint32_t bit = 1u << (r & 31);
+    if (atomicOr(&gmask[r >> 5], bit) & bit) atomicOr(&header->status, static_cast<uint32_t>(kErrDupRoot));
+}
+
+__global__ void header_start(WsHeader* header) { header_begin(header); }
+
+// After the launched iterations: the iteration count, and an error bit if the residual never
+// met the tolerance.
+__global__ void solve_finish(const Scalars* __restrict__ sc, WsHeader* header) {
+    header->iters = sc->iters;
+    if (!sc->done) atomicOr(&header->status, static_cast<uint32_t>(kErrNotConverged));
+}
+
 struct EstLayout {
+    WsHeader* header;
     double *x, *r, *z, *p, *ap, *part;
     Scalars* sc;
+    uint32_t* gmask;
+    int64_t mask_words;
     size_t total;
 };
 
-EstLayout carve_est(void* ws, int32_t n) {
+EstLayout carve_est(void* ws, int32_t n, bool group) {
     Carver c(ws);
     EstLayout L{};
+    L.header = c.take<WsHeader>(kHeaderBytes / sizeof(WsHeader));
     L.x = c.take<double>(n);
     L.r = c.take<double>(n);
     L.z = c.take<double>(n);
@@ -284,8 +364,80 @@ EstLayout carve_est(void* ws, int32_t n) {
     L.ap = c.take<double>(n);
     L.part = c.take<double>(2 * kMaxBlocks);
     L.sc = c.take<Scalars>(1);
+    L.mask_words = group ? (static_cast<int64_t>(n) + 31) / 32 : 0;
+    L.gmask = group ? c.take<uint32_t>(L.mask_words) : nullptr;
     L.total = c.used();
     return L;
+}
+
+// Iterations launched per call in stream-ordered mode (check_every < 0): the whole solve is
+// enqueued at once, so it is bounded to keep a captured graph small.
+constexpr int kMaxAsyncIter = 4096;
+
+int check_solve_params(const rwc_solve_params* sp) {
+    if (sp && sp->check_every < 0 && (sp->max_iter < 1 || sp->max_iter > kMaxAsyncIter))
+        return fail(RWC_ERR_INVALID_ARG, "stream-ordered solves need max_iter in [1, %d]", kMaxAsyncIter);
+    if (sp && (sp->max_iter < 0 || !(sp->tol >= 0.0)))
+        return fail(RWC_ERR_INVALID_ARG, "max_iter and tol must not be negative");
+    return RWC_OK;
+}
+
+// Jacobi-PCG on the system grounded at v (or at the set in L.gmask): x solves L_G x = d_{-G}.
+// Host-checked mode reads the scalars every `check` iterations; stream-ordered mode
+// (check < 0) launches max_iter iterations, which stop on the device at convergence, and
+// leaves the outcome in the workspace header.
+int pivot_solve(const rwc_csr* g, int32_t v, const EstLayout& L, const rwc_solve_params* sp, int32_t* iters,
+                hipStream_t s, bool* async_out) {
+    const int32_t n = g->n;
+    const double tol = (sp && sp->tol > 0) ? sp->tol : 1e-12;
+    const bool async = sp && sp->check_every < 0;
+    const int max_iter = (sp && sp->max_iter > 0) ? sp->max_iter : (async ? 0 : 20000);
+    const int check = (sp && sp->check_every > 0) ? sp->check_every : 16;
+    const double tol2 = tol * tol;
+    const unsigned nb = blocks_for(n, kBlock) < kMaxBlocks ? blocks_for(n, kBlock) : kMaxBlocks;
+    const int64_t spmv_threads = static_cast<int64_t>(n) * kRowLanes;
+    const unsigned nb_spmv = blocks_for(spmv_threads, kBlock) < kMaxBlocks ? blocks_for(spmv_threads, kBlock) : kMaxBlocks;
+    *async_out = async;
+
+    hipLaunchKernelGGL(pcg_init, dim3(nb), dim3(kBlock), 0, s, n, v, L.gmask, g->strength, L.x, L.r, L.z, L.p, L.part);
+    hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 0, g->vol, tol2);
+    auto iteration = [&]() {
+        hipLaunchKernelGGL(spmv_dot, dim3(nb_spmv), dim3(kBlock), 0, s, n, v, L.gmask, L.sc, g->row_ptr, g->col,
+                           g->weight, g->strength, L.p, L.ap, L.part);
+        hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb_spmv), L.sc, 1,
+                           g->vol, tol2);
+        hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kBlock), 0, s, n, v, L.gmask, L.sc, g->strength, L.x, L.r, L.z,
+                           L.p, L.ap, L.part);
+        hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 2, g->vol,
+                           tol2);
+        hipLaunchKernelGGL(update_p, dim3(nb), dim3(kBlock), 0, s, n, v, L.gmask, L.sc, L.z, L.p);
+    };
+    if (async) {
+        for (int it = 0; it < max_iter; ++it) iteration();
+        hipLaunchKernelGGL(solve_finish, dim3(1), dim3(1), 0, s, L.sc, L.header);
+        RWC_HIP(hipGetLastError());
+        if (iters) *iters = -1;
+        return RWC_OK;
+    }
+    RWC_HIP(hipGetLastError());
+    Scalars host{};
+    RWC_HIP(hipMemcpyAsync(&host, L.sc, sizeof(host), hipMemcpyDeviceToHost, s));
+    RWC_HIP(hipStreamSynchronize(s));
+    int launched = 0;
+    while (!host.done && launched < max_iter) {
+        const int chunk = (max_iter - launched) < check ? (max_iter - launched) : check;
+        for (int c = 0; c < chunk; ++c) iteration();
+        RWC_HIP(hipGetLastError());
+        launched += chunk;
+        RWC_HIP(hipMemcpyAsync(&host, L.sc, sizeof(host), hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipStreamSynchronize(s));
+    }
+    hipLaunchKernelGGL(solve_finish, dim3(1), dim3(1), 0, s, L.sc, L.header);
+    if (iters) *iters = host.iters;
+    if (!host.done)
+        return fail(RWC_ERR_NOT_CONVERGED, "pivot solve: relative residual %.3e after %d iterations",
+                    host.rr > 0 ? std::sqrt(host.rr / host.rr0) : 0.0, host.iters);
+    return RWC_OK;
 }
 
 }  // namespace
@@ -296,7 +448,7 @@ using namespace rwc;
 extern "C" int rwc_estimate_workspace(const rwc_csr* g, size_t* bytes) {
     clear_error();
     if (!g || !bytes) return fail(RWC_ERR_INVALID_ARG, "g and bytes must not be null");
-    *bytes = carve_est(nullptr, g->n).total;
+    *bytes = carve_est(nullptr, g->n, false).total;
     return RWC_OK;
 }
 
@@ -307,55 +459,70 @@ extern "C" int rwc_estimate(const rwc_csr* g, const uint64_t* counts, const uint
     if (!g || !counts || !rwc) return fail(RWC_ERR_INVALID_ARG, "g, counts and rwc must not be null");
     if (l < 1) return fail(RWC_ERR_INVALID_ARG, "l must be positive");
     if (stderr_out && !counts_sq) return fail(RWC_ERR_INVALID_ARG, "stderr needs counts_sq");
+    RWC_CHECK(check_solve_params(sp));
     const int32_t n = g->n;
-    RWC_CHECK(check_workspace(ws, ws_bytes, carve_est(nullptr, n).total));
-    EstLayout L = carve_est(ws, n);
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_est(nullptr, n, false).total));
+    EstLayout L = carve_est(ws, n, false);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const double tol = (sp && sp->tol > 0) ? sp->tol : 1e-12;
-    const int max_iter = (sp && sp->max_iter > 0) ? sp->max_iter : 20000;
-    const int check = (sp && sp->check_every > 0) ? sp->check_every : 16;
     const int v = g->pivot;
     const unsigned nb = blocks_for(n, kBlock) < kMaxBlocks ? blocks_for(n, kBlock) : kMaxBlocks;
-    const int64_t spmv_threads = static_cast<int64_t>(n) * kRowLanes;
-    const unsigned nb_spmv = blocks_for(spmv_threads, kBlock) < kMaxBlocks ? blocks_for(spmv_threads, kBlock) : kMaxBlocks;
-
-    hipLaunchKernelGGL(pcg_init, dim3(nb), dim3(kBlock), 0, s, n, v, g->strength, L.x, L.r, L.z, L.p, L.part);
-    hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 0, g->vol);
-    RWC_HIP(hipGetLastError());
-    Scalars host{};
-    RWC_HIP(hipMemcpyAsync(&host, L.sc, sizeof(host), hipMemcpyDeviceToHost, s));
-    RWC_HIP(hipStreamSynchronize(s));
-    const double bnorm2 = host.rr0;
-    int it = 0;
-    bool converged = (bnorm2 == 0.0);
-    while (!converged && it < max_iter) {
-        const int chunk = (max_iter - it) < check ? (max_iter - it) : check;
-        for (int c = 0; c < chunk; ++c) {
-            hipLaunchKernelGGL(spmv_dot, dim3(nb_spmv), dim3(kBlock), 0, s, n, v, g->row_ptr, g->col, g->weight,
-                               g->strength, L.p, L.ap, L.part);
-            hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb_spmv), L.sc, 1,
-                               g->vol);
-            hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kBlock), 0, s, n, v, L.sc, g->strength, L.x, L.r, L.z, L.p,
-                               L.ap, L.part);
-            hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 2, g->vol);
-            hipLaunchKernelGGL(update_p, dim3(nb), dim3(kBlock), 0, s, n, v, L.sc, L.z, L.p);
-        }
-        RWC_HIP(hipGetLastError());
-        it += chunk;
-        RWC_HIP(hipMemcpyAsync(&host, L.sc, sizeof(host), hipMemcpyDeviceToHost, s));
-        RWC_HIP(hipStreamSynchronize(s));
-        converged = host.rr <= tol * tol * bnorm2;
-    }
-    if (iters) *iters = it;
-    if (!converged)
-        return fail(RWC_ERR_NOT_CONVERGED, "pivot solve: relative residual %.3e after %d iterations",
-                    host.rr > 0 ? std::sqrt(host.rr / bnorm2) : 0.0, it);
+    hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
+    bool async = false;
+    RWC_CHECK(pivot_solve(g, v, L, sp, iters, s, &async));
     hipLaunchKernelGGL(pivot_partials, dim3(nb), dim3(kBlock), 0, s, n, g->strength, L.x, L.part);
-    hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol);
+    hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol, 0.0);
     hipLaunchKernelGGL(assemble, dim3(nb), dim3(kBlock), 0, s, n, v, g->vol, static_cast<double>(l), counts, counts_sq,
-                       g->strength, L.x, L.sc, rwc, stderr_out);
-    if (hit) RWC_HIP(hipMemcpyAsync(hit, L.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                       g->strength, L.x, L.sc, rwc, stderr_out, hit);
     RWC_HIP(hipGetLastError());
-    RWC_HIP(hipStreamSynchronize(s));
+    if (!async) RWC_HIP(hipStreamSynchronize(s));
+    return RWC_OK;
+}
+
+extern "C" int rwc_estimate_group_workspace(const rwc_csr* g, size_t* bytes) {
+    clear_error();
+    if (!g || !bytes) return fail(RWC_ERR_INVALID_ARG, "g and bytes must not be null");
+    *bytes = carve_est(nullptr, g->n, true).total;
+    return RWC_OK;
+}
+
+extern "C" int rwc_estimate_group(const rwc_csr* g, const int32_t* roots, int32_t num_roots, const uint64_t* counts,
+                                  int64_t l, const rwc_solve_params* sp, double* group_rwc, double* marginal,
+                                  double* hit, int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!g || !roots || !counts || !group_rwc || !marginal)
+        return fail(RWC_ERR_INVALID_ARG, "g, roots, counts, group_rwc and marginal must not be null");
+    if (l < 1) return fail(RWC_ERR_INVALID_ARG, "l must be positive");
+    const int32_t n = g->n;
+    if (num_roots < 1 || num_roots >= n) return fail(RWC_ERR_INVALID_ARG, "num_roots must be in [1, n - 1]");
+    RWC_CHECK(check_solve_params(sp));
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_est(nullptr, n, true).total));
+    EstLayout L = carve_est(ws, n, true);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned nb = blocks_for(n, kBlock) < kMaxBlocks ? blocks_for(n, kBlock) : kMaxBlocks;
+    hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
+    hipLaunchKernelGGL(clear_words, dim3(blocks_for(L.mask_words, kBlock)), dim3(kBlock), 0, s, L.gmask, L.mask_words);
+    hipLaunchKernelGGL(mark_roots, dim3(blocks_for(num_roots, kBlock)), dim3(kBlock), 0, s, roots, num_roots, n,
+                       L.gmask, L.header);
+    if (!(sp && sp->check_every < 0)) {
+        // host-checked mode: a bad root set would leave the system singular, so stop here
+        WsHeader h{};
+        RWC_HIP(hipMemcpyAsync(&h, L.header, sizeof(h), hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipStreamSynchronize(s));
+        RWC_CHECK(device_error_to_status(h.status));
+    }
+    bool async = false;
+    RWC_CHECK(pivot_solve(g, -1, L, sp, iters, s, &async));
+    hipLaunchKernelGGL(pivot_partials, dim3(nb), dim3(kBlock), 0, s, n, g->strength, L.x, L.part);
+    hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol, 0.0);
+    hipLaunchKernelGGL(assemble_group, dim3(nb), dim3(kBlock), 0, s, n, L.gmask, g->vol, static_cast<double>(l), counts,
+                       g->strength, L.x, L.sc, marginal, hit, group_rwc);
+    RWC_HIP(hipGetLastError());
+    if (!async) {
+        // the root set is validated on the device: report it with the synchronous result
+        WsHeader h{};
+        RWC_HIP(hipMemcpyAsync(&h, L.header, sizeof(h), hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipStreamSynchronize(s));
+        return device_error_to_status(h.status);
+    }
     return RWC_OK;
 }

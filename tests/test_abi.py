@@ -118,43 +118,80 @@ def test_library_shares_torchs_hip_runtime():
 
 
 def test_backward_sizes_are_checked_before_planning():
-    """The adjoint's workspace query sizes the solve from the target list on the host: a probe
-    count or target list past the column and entry limits is refused with RWC_ERR_TOO_LARGE,
-    without building the right-hand sides."""
+    """The adjoint's workspace is sized from k (2 + 2k solve columns, both sign classes) or,
+    in exact mode, from max_support; bad sizes are refused without any device work."""
     from paper_2510_20604_amd import _lib
     lib = _lib.load()
     g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, vol=8000.0, row_ptr=8, col=8, rec=8,
                     bfs_order=8)
-    t = np.array([3, 7, 11], dtype=np.int32)
-    gv = np.array([1.0, -2.0, 0.5], dtype=np.float64)
     size = ctypes.c_size_t()
 
-    def query(k):
-        bp = _lib.BackwardParams(k=k, seed=1)
-        return lib.rwc_backward_workspace(ctypes.byref(g), t.size, t.ctypes.data, gv.ctypes.data, ctypes.byref(bp),
-                                          ctypes.byref(size))
+    def query(k, support=0):
+        bp = _lib.BackwardParams(k=k, seed=1, max_support=support)
+        return lib.rwc_backward_workspace(ctypes.byref(g), ctypes.byref(bp), ctypes.byref(size))
 
     assert query(64) == 0
-    cols64 = 2 + 2 * 64                       # both sign classes present
+    cols64 = 2 + 2 * 64                       # room for both sign classes
     assert size.value >= 1000 * cols64 * (8 * 3 + 4)
-    assert query(0) == 0                      # exact: one column per target
+    assert query(0, 3) == 0                   # exact: one column per nonzero of g
+    exact3 = size.value
+    assert exact3 >= 1000 * 5 * (8 * 3 + 4) and exact3 < 1000 * cols64 * (8 * 3 + 4)
+    assert query(0, 0) == -1                  # exact mode needs max_support >= 1
+    assert query(0, 1001) == -1               # ... and at most n
     assert query(1 << 23) == -7               # 2 + 2^24 columns
     assert query(-1) == -1
-    # entry limit: 2^30 probes per class with 3 targets -> about 3 * 2^30 entries
-    assert query(1 << 30) == -7
 
 
 def test_backward_refuses_bad_sizes_before_device_work():
-    """rwc_backward plans its columns on the host before any device call, so a negative or
-    oversized k comes back as an error without touching the (dummy) device pointers."""
+    """rwc_backward checks its parameters before any device call, so a negative or oversized k
+    comes back as an error without touching the (dummy) device pointers."""
     from paper_2510_20604_amd import _lib
     lib = _lib.load()
     g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, vol=8000.0, row_ptr=8, col=8, rec=8,
                     bfs_order=8)
-    t = np.array([3, 7], dtype=np.int32)
-    gv = np.array([1.0, -2.0], dtype=np.float64)
     it = ctypes.c_int32()
-    for k, code in ((-1, -1), (1 << 23, -7), (1 << 30, -7)):
-        bp = _lib.BackwardParams(k=k, seed=1)
-        assert lib.rwc_backward(ctypes.byref(g), t.size, t.ctypes.data, gv.ctypes.data, ctypes.byref(bp), 8,
-                                ctypes.byref(it), 8, 1 << 20, None) == code
+    for k, support, code in ((-1, 0, -1), (1 << 23, 0, -7), (0, 0, -1), (0, 5000, -1)):
+        bp = _lib.BackwardParams(k=k, seed=1, max_support=support)
+        assert lib.rwc_backward(ctypes.byref(g), 8, ctypes.byref(bp), 8, ctypes.byref(it), 8, 1 << 20, None) == code
+    assert lib.rwc_backward(ctypes.byref(g), None, ctypes.byref(bp), 8, ctypes.byref(it), 8, 1 << 20, None) == -1
+
+
+def test_sampler_rejects_bad_root_sets_before_device_work():
+    """A root set needs a single graph, root = -1, a device pointer and 1 <= count < n."""
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8, rec=8, bfs_order=8)
+    size = ctypes.c_size_t()
+    ok = _lib.SampleParams(seed=1, num_samples=10, root=-1, roots=8, num_roots=3)
+    assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(ok), ctypes.byref(size)) == 0
+    for bad in (dict(roots=None, num_roots=3), dict(roots=8, num_roots=-1), dict(roots=8, num_roots=1000),
+                dict(roots=8, num_roots=3, root=5)):
+        p = _lib.SampleParams(seed=1, num_samples=10, root=bad.get("root", -1), roots=bad["roots"],
+                              num_roots=bad["num_roots"])
+        assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(size)) == -1
+    two = (_lib.RwcCsr * 2)(g, g)
+    assert lib.rwc_sample_forests_workspace(two, 2, ctypes.byref(ok), ctypes.byref(size)) == -1
+
+
+def test_estimate_rejects_bad_modes_before_device_work():
+    """Stream-ordered solves need 1 <= max_iter <= 4096; the group estimate needs a root count
+    in [1, n - 1]."""
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, vol=8000.0, row_ptr=8, col=8, rec=8,
+                    bfs_order=8, strength=8)
+    size = ctypes.c_size_t()
+    assert lib.rwc_estimate_group_workspace(ctypes.byref(g), ctypes.byref(size)) == 0
+    it = ctypes.c_int32()
+    for n_roots in (0, 1000):
+        assert lib.rwc_estimate_group(ctypes.byref(g), 8, n_roots, 8, 10, None, 8, 8, None, ctypes.byref(it), 8,
+                                      size.value, None) == -1
+    assert lib.rwc_workspace_status(None, None) == -1
+    ws = ctypes.c_size_t()
+    assert lib.rwc_estimate_workspace(ctypes.byref(g), ctypes.byref(ws)) == 0
+    for max_iter in (0, 5000):
+        sp = _lib.SolveParams(tol=1e-12, max_iter=max_iter, check_every=_lib.RWC_SOLVE_STREAM_ORDERED)
+        assert lib.rwc_estimate(ctypes.byref(g), 8, None, 10, ctypes.byref(sp), 8, None, None, ctypes.byref(it), 256,
+                                ws.value, None) == -1
+        assert lib.rwc_estimate_group(ctypes.byref(g), 8, 3, 8, 10, ctypes.byref(sp), 8, 8, None, ctypes.byref(it),
+                                      256, size.value, None) == -1

@@ -44,7 +44,7 @@ def test_exact_mode_matches_dense_gradient(signed):
     gd[t] = gv
     want = GR.grad_exact(g.n, g.src, g.dst, g.w, gd)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    res = P.backward(Gd, t, gv, k=0, tol=1e-12)
+    res = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=0, tol=1e-12)
     got = res["grad_w"].cpu().numpy()
     _close(got, want, 1e-7)
     assert abs(np.dot(g.w, got)) <= 1e-8 * np.abs(g.w * got).sum()
@@ -60,7 +60,7 @@ def test_sketch_mode_matches_oracle_probes(signed):
     cols = GR.probe_columns(g.n, t, gv, k, seed)
     want = GR.grad_from_probes(g.n, g.src, g.dst, g.w, gd, cols)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    got = P.backward(Gd, t, gv, k=k, seed=seed, tol=1e-12)["grad_w"].cpu().numpy()
+    got = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=k, seed=seed, tol=1e-12)["grad_w"].cpu().numpy()
     _close(got, want, 1e-7)
     # the sketch keeps Euler's identity for the scale-invariant RWC exactly
     assert abs(np.dot(g.w, got)) <= 1e-8 * np.abs(g.w * got).sum()
@@ -86,7 +86,7 @@ def test_ba100k_sampled_edges_match_sparse_oracle(k):
     g = _graph(100_000, 4, 1004)
     t, gv = _targets(g.n, 100, 6)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    res = P.backward(Gd, t, gv, k=k, seed=2004, tol=1e-11)
+    res = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=k, seed=2004, tol=1e-11)
     got = res["grad_w"].cpu().numpy()
     edges = np.random.default_rng(8).choice(g.m, size=20, replace=False)
     cols = None if k == 0 else GR.probe_columns(g.n, t, gv, k, 2004)
@@ -106,7 +106,7 @@ def test_ba2000_gradient_against_central_differences_on_50_edges():
     g = _graph(2000, 4, 91)
     t, gv = _targets(g.n, 100, 92)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    got = P.backward(Gd, t, gv, k=0, tol=1e-12)["grad_w"].cpu().numpy()
+    got = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=0, tol=1e-12)["grad_w"].cpu().numpy()
 
     w0 = g.w.astype(np.float64)
     n = g.n

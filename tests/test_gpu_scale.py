@@ -1,11 +1,12 @@
-"""Full-size checks in the launch configuration bench.py times.
+"""Full-size checks in the launch configurations bench.py times.
 
 BA(n = 1e6, m = 5), 10^4 trees: the automatic plan (64-walker teams, one batch) must
 reproduce the oracle's trees: parent arrays of sampled trees, the checksum of every tree and
 the visit totals, plus properties that hold at any size.  The 256-graph batch in its
-persistent, hipGraph-captured launch: sampled trees of BA graphs and grids against the oracle.
-R-MAT scale 23 (largest component, weighted), 5000 trees in a persistent launch: the same, and
-the adjoint's Euler identity for 1000 targets.
+persistent, hipGraph-captured launch: every tree and every visit total of every graph against
+the oracle and against plain per-graph launches.  R-MAT scale 23 (largest component, weighted),
+5000 trees in a persistent launch: every tree and the visit totals against the oracle, and the
+adjoint for 1000 targets against the oracle's stored sparse evaluation.
 """
 import numpy as np
 import pytest
@@ -55,48 +56,156 @@ def test_ba1m_bench_configuration_matches_oracle_on_every_tree():
     assert int(P.as_uint64(s["total_steps"])[0]) == int(ref["steps"].sum())
 
 
-def test_batch256_bench_configuration_sampled_trees():
-    """The 256-graph batch exactly as bench.py launches it (persistent, hipGraph-captured,
-    automatic plan: breadth-first starts for the meshes): sampled trees of BA graphs and grids,
-    the largest grid among them, match the oracle's serial trees, and every graph's visit totals
-    obey the per-tree invariants."""
+# ---------------------------------------------------------------------------------------
+# The 256-graph batch in the bench's launch (persistent, hipGraph-captured, automatic plan):
+# every tree checksum and every visit total of every graph against the oracle, and against
+# one plain launch per graph.  The oracle's 2.8e10 steps are split into chunks of about equal
+# work (from the GPU's step totals), one test per chunk, so no test runs long.
+# ---------------------------------------------------------------------------------------
+BATCH_CHUNKS = 6
+
+
+@pytest.fixture(scope="module")
+def batch256():
     gl = G.batch_mix(256, 1e3, 1e5, seed=1003)
     l, seed = 1000, 2003
     dev = [P.Graph(g.n, g.src, g.dst, g.w) for g in gl]
-    s = P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=False)
-    hashes = P.as_uint64(s["tree_hash"])
-    counts = P.as_uint64(s["counts"])
-    steps = P.as_uint64(s["total_steps"])
-    largest_grid = max(range(128, 256), key=lambda i: gl[i].n)
-    picks = [(0, 0), (64, 999), (127, 500), (130, 0), (200, 999), (largest_grid, 0), (largest_grid, 999)]
-    for gi, tree in picks:
-        g = gl[gi]
+    s = P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=True)
+    out = {"gl": gl, "dev": dev, "l": l, "seed": seed, "hash": P.as_uint64(s["tree_hash"]).copy(),
+           "counts": P.as_uint64(s["counts"]).copy(), "counts_sq": P.as_uint64(s["counts_sq"]).copy(),
+           "steps": P.as_uint64(s["total_steps"]).copy(), "off": np.concatenate([[0], np.cumsum([g.n for g in gl])])}
+    # contiguous chunks of graphs with about equal oracle work
+    cum = np.cumsum(out["steps"].astype(np.float64))
+    bounds = np.searchsorted(cum, cum[-1] * np.arange(1, BATCH_CHUNKS) / BATCH_CHUNKS)
+    out["chunks"] = np.split(np.arange(len(gl)), bounds)
+    del s
+    P.release_cached_graphs()
+    return out
+
+
+def test_batch256_invariants_and_plain_launches_bit_identical(batch256):
+    """Per-tree invariants of every graph, and the batched launch's outputs equal to 256 plain
+    per-graph launches (the acceptance of the batched form: the same outputs either way), bit
+    for bit."""
+    b = batch256
+    for gi, g in enumerate(b["gl"]):
+        c = b["counts"][b["off"][gi]:b["off"][gi + 1]]
+        piv = int(b["dev"][gi].pivot)
+        assert c[piv] == 0 and (np.delete(c, piv) >= b["l"]).all(), f"graph {gi}"
+        assert int(c.sum()) == int(b["steps"][gi])
+    ws = None
+    for gi, Gd in enumerate(b["dev"]):
+        r = P.sample_forests(Gd, b["l"], b["seed"], graph_index_base=gi, want_sq=True, workspace=ws)
+        ws = r["workspace"]
+        np.testing.assert_array_equal(P.as_uint64(r["tree_hash"][0]), b["hash"][gi], err_msg=f"graph {gi}")
+        np.testing.assert_array_equal(P.as_uint64(r["counts"]), b["counts"][b["off"][gi]:b["off"][gi + 1]])
+        np.testing.assert_array_equal(P.as_uint64(r["counts_sq"]), b["counts_sq"][b["off"][gi]:b["off"][gi + 1]])
+
+
+@pytest.mark.parametrize("chunk", range(BATCH_CHUNKS))
+def test_batch256_every_tree_matches_oracle(batch256, chunk):
+    import os
+    b = batch256
+    threads = max(1, min(16, os.cpu_count() or 1))
+    for gi in b["chunks"][chunk]:
+        g = b["gl"][gi]
         o = W.OracleCSR(g.n, g.src, g.dst, g.w)
-        ref = W.fastwalk_sample(o, o.pivot, seed, gi, tree, 1)
-        assert int(hashes[gi, tree]) == int(ref["hash"][0]), f"graph {gi} tree {tree}"
-    off = 0
-    for gi, g in enumerate(gl):
-        c = counts[off:off + g.n]
-        off += g.n
-        o_piv = int(dev[gi].pivot)
-        assert c[o_piv] == 0 and (np.delete(c, o_piv) >= l).all(), f"graph {gi}"
-        assert int(c.sum()) == int(steps[gi])
+        ref = W.fastwalk_sample(o, o.pivot, b["seed"], int(gi), 0, b["l"], threads=threads)
+        np.testing.assert_array_equal(b["hash"][gi], ref["hash"], err_msg=f"graph {gi}")
+        np.testing.assert_array_equal(b["counts"][b["off"][gi]:b["off"][gi + 1]], ref["visits"])
+        np.testing.assert_array_equal(b["counts_sq"][b["off"][gi]:b["off"][gi + 1]], ref["visits_sq"])
+        assert int(b["steps"][gi]) == int(ref["steps"].sum())
 
 
-def test_rmat_scale23_sampled_trees_and_adjoint():
+# ---------------------------------------------------------------------------------------
+# R-MAT scale 23 (largest component, w ~ U[1, 4]), 5000 trees in the bench's persistent
+# launch: every tree checksum, the visit totals and their squares against the oracle (in
+# three sample-range chunks whose integer sums add up), and the adjoint for 1000 targets
+# (k = 64) against the oracle's sparse evaluation stored in tests/golden.
+# ---------------------------------------------------------------------------------------
+RMAT_CHUNKS = 3
+# Adjoint tolerance, relative to the largest stored gradient magnitude.  Both sides stop each
+# solve at relative residual 1e-11 (the GPU with FP32 search directions but FP64 residuals, so
+# its stopping test is as strict as the oracle's); the error of a solution is then bounded by
+# cond(L_v) * 1e-11 relative, and the gradient takes differences of solution entries scaled by
+# vol.  Same bound as the BA(1e5) sampled-edge test of the adjoint.
+RMAT_ADJOINT_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def rmat23():
     g = G.rmat_lcc(23, 5, 0.57, 0.19, 0.19, 1005)
     g = g.with_weights(G.uniform_weights(g.m, 1.0, 4.0, 1006))
     l, seed = 5000, 2005
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     dump = [3, 4999]
-    s = P.sample_forests(Gd, l, seed, dump=dump, persistent=True, want_sq=False)
+    s = P.sample_forests(Gd, l, seed, dump=dump, persistent=True, want_sq=True)
     print(f"R-MAT LCC n={g.n} m={g.m}: {s['walkers_per_tree']} walkers x {s['trees_in_flight']} trees, "
           f"{s['batches']} batches, {s['walk_kernel']}, {s['starts']} starts")
-    _check_sampled_trees(g, s, l, seed, [0, 3, 2500, 4999], dump)
-    rng = np.random.default_rng(7)
-    t = rng.choice(g.n, size=1000, replace=False).astype(np.int32)
-    res = P.backward(Gd, t, np.ones(1000), k=64, seed=2006, tol=1e-8)
+    out = {"g": g, "Gd": Gd, "l": l, "seed": seed, "dump": dump, "parents": s["parents"].cpu().numpy(),
+           "hash": P.as_uint64(s["tree_hash"][0]).copy(), "counts": P.as_uint64(s["counts"]).copy(),
+           "counts_sq": P.as_uint64(s["counts_sq"]).copy(), "steps": int(P.as_uint64(s["total_steps"])[0]),
+           "o": W.OracleCSR(g.n, g.src, g.dst, g.w), "acc": {}}
+    del s
+    return out
+
+
+def test_rmat23_launch_and_dumped_trees(rmat23):
+    r = rmat23
+    o = r["o"]
+    assert r["counts"][o.pivot] == 0
+    mask = np.ones(r["g"].n, dtype=bool)
+    mask[o.pivot] = False
+    assert (r["counts"][mask] >= r["l"]).all()
+    assert int(r["counts"].sum()) == r["steps"]
+    for j, i in enumerate(r["dump"]):
+        ref = W.fastwalk_sample(o, o.pivot, r["seed"], 0, i, 1, want_parents=True)
+        np.testing.assert_array_equal(r["parents"][j], ref["parents"][0])
+        assert int(r["hash"][i]) == int(ref["hash"][0])
+
+
+@pytest.mark.parametrize("chunk", range(RMAT_CHUNKS))
+def test_rmat23_every_tree_matches_oracle(rmat23, chunk):
+    """Samples of this chunk: every checksum; the oracle's visit totals of all chunks add up to
+    the GPU's totals and squared totals (checked once the last chunk has run)."""
+    import os
+    r = rmat23
+    o = r["o"]
+    lo, hi = chunk * r["l"] // RMAT_CHUNKS, (chunk + 1) * r["l"] // RMAT_CHUNKS
+    ref = W.fastwalk_sample(o, o.pivot, r["seed"], 0, lo, hi - lo, threads=max(1, min(16, os.cpu_count() or 1)))
+    np.testing.assert_array_equal(r["hash"][lo:hi], ref["hash"])
+    r["acc"][chunk] = (ref["visits"], ref["visits_sq"], int(ref["steps"].sum()))
+    if len(r["acc"]) == RMAT_CHUNKS:
+        v = sum(a[0] for a in r["acc"].values())
+        v2 = sum(a[1] for a in r["acc"].values())
+        np.testing.assert_array_equal(r["counts"], v)
+        np.testing.assert_array_equal(r["counts_sq"], v2)
+        assert r["steps"] == sum(a[2] for a in r["acc"].values())
+
+
+def _rmat23_adjoint_fixture():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "rmat23_adjoint_grad.txt")
+    rows = [line.split("|") for line in open(path) if not line.startswith("#")]
+    return (np.array([int(a) for a, _, _, _ in rows]), np.array([int(b) for _, b, _, _ in rows]),
+            np.array([int(c) for _, _, c, _ in rows]), np.array([float(d) for _, _, _, d in rows]))
+
+
+def test_rmat23_adjoint_matches_oracle_fixture(rmat23):
+    """The adjoint for 1000 targets (g = 1, k = 64 probes, probe seed 2006) at the 24 edges the
+    oracle evaluated (tests/golden/make_rmat23_adjoint.py: sparse CG solves to 1e-11)."""
+    r = rmat23
+    g = r["g"]
+    edges, a, b, want = _rmat23_adjoint_fixture()
+    np.testing.assert_array_equal(g.src[edges], a)
+    np.testing.assert_array_equal(g.dst[edges], b)
+    t = np.random.default_rng(7).choice(g.n, size=1000, replace=False).astype(np.int32)
+    res = P.backward(r["Gd"], P.dense_g(g.n, t, np.ones(1000), "cuda"), k=64, seed=2006, tol=1e-11)
     grad = res["grad_w"].cpu().numpy()
+    scale = np.abs(want).max()
+    err = np.abs(grad[edges] - want)
+    print(f"R-MAT adjoint: {res['iters']} iterations, max |err| / max |grad| = {err.max() / scale:.3e}")
+    assert err.max() <= RMAT_ADJOINT_TOL * scale
     assert np.isfinite(grad).all()
     assert abs(np.dot(g.w, grad)) <= 1e-6 * np.abs(g.w * grad).sum()
 

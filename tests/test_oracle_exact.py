@@ -191,3 +191,27 @@ def test_ba20k_fixture_matches_the_hitting_time_definition():
                           M=spla.LinearOperator(Lu.shape, matvec=lambda x: x / d[keep]))
         assert info == 0
         assert abs(d[keep] @ h / d.sum() - val) <= 1e-9 * val
+
+
+def test_group_rwc_definition_and_marginal_formula():
+    """Group RWC H_S (hitting time to a set, stationary start): one node is that node's RWC;
+    the star's centre gives 1/2; adding a node u to S, the rank-one form H_S - d_u h_u^2 /
+    (vol d_u (L_S^{-1})_uu) equals H_{S + u} computed from its own definition, for every u."""
+    g = _small_graphs()[2]
+    h_def = E.rwc_by_hitting_times(g.n, g.src, g.dst, g.w)
+    for v in (0, 5):
+        assert E.group_rwc(g.n, g.src, g.dst, g.w, [v]) == pytest.approx(h_def[v], rel=1e-11)
+    star = G.star_graph(9)
+    assert E.group_rwc(star.n, star.src, star.dst, None, [0]) == pytest.approx(0.5, rel=1e-12)
+    for S in ([0], [1, 6], [2, 3, 9]):
+        t = E.grounded_inverse_diag_set(g.n, g.src, g.dst, g.w, S)
+        est = E.group_marginal_estimate(g.n, g.src, g.dst, g.w, S, t)
+        for u in range(g.n):
+            want = E.group_rwc(g.n, g.src, g.dst, g.w, sorted(set(S) | {u}))
+            assert est[u] == pytest.approx(want, rel=1e-9), (S, u)
+    # a planted slip (dropping d_u) is caught
+    t = E.grounded_inverse_diag_set(g.n, g.src, g.dst, g.w, [1, 6])
+    d = E.adjacency(g.n, g.src, g.dst, g.w).sum(1)
+    bad = E.group_marginal_estimate(g.n, g.src, g.dst, g.w, [1, 6], t * d)
+    want = np.array([E.group_rwc(g.n, g.src, g.dst, g.w, sorted({1, 6, u})) for u in range(g.n)])
+    assert np.max(np.abs(bad - want) / want) > 1e-3
