@@ -54,6 +54,8 @@ def sampler_code_sha256() -> str:
 def measured_counters(config: str, kernel: str, trees: int, trees_in_flight: int):
     """The committed counter summary of the walk launch (HBM bytes, L2 misses), or None when it
     is missing or was taken on other code, another kernel or another plan."""
+    if config not in TRAFFIC_FILES:
+        return None
     try:
         with open(TRAFFIC_FILES[config]) as f:
             t = json.load(f)
@@ -70,12 +72,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="rmat23", choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k"])
+    ap.add_argument("--config", default="rmat23",
+                    choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k", "trap"])
     ap.add_argument("--no-extras", action="store_true",
                     help="rmat23: skip the BA(1e6) and BA(1e5)-adjoint side measurements")
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
     ap.add_argument("--walkers", type=int, default=0, help="walkers per tree (0 = automatic)")
     ap.add_argument("--tif", type=int, default=0, help="trees in flight (0 = automatic)")
+    ap.add_argument("--no-lds", action="store_true", help="keep every tree's state in HBM (no LDS-resident trees)")
+    ap.add_argument("--no-tune", action="store_true", help="batch256: automatic plan instead of rwc_autotune_batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -173,19 +178,28 @@ def batch_main(args):
     torch.cuda.synchronize()
 
     keep = {}
+    tune, tune_s, kw = None, None, {"lds_state": False if args.no_lds else None}
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tune = P.autotune_batch(dev, l, seed)
+        tune_s = time.perf_counter() - t0
+        kw = {"walkers_per_graph": tune["walkers_per_graph"], "path_ring": tune["path_ring"],
+              "bfs_starts": tune["bfs_starts"], "lds_state": tune["lds_state"]}
+        print(f"autotuned in {tune_s:.1f}s: {tune}", file=sys.stderr, flush=True)
 
     def batched():
         # the same workspace and outputs each step: after the first call captures the launches
         # into a hipGraph, the later calls replay it
         r = P.sample_forests(dev, l, seed, persistent=True, capture=True, want_sq=False,
-                             workspace=keep.get("workspace"), out=keep.get("out"))
+                             workspace=keep.get("workspace"), out=keep.get("out"), **kw)
         keep["workspace"], keep["out"] = r["workspace"], r
         return r
 
     def plain():
         out = []
         for i, G in enumerate(dev):
-            out.append(P.sample_forests(G, l, seed, graph_index_base=i, want_sq=False))
+            out.append(P.sample_forests(G, l, seed, graph_index_base=i, want_sq=False,
+                                        lds_state=False if args.no_lds else None))
             if i % 32 == 31:
                 print(f"plain: {i + 1} graphs done", file=sys.stderr, flush=True)
         return out
@@ -219,7 +233,11 @@ def batch_main(args):
         "walk_steps_per_s": round(steps / tb, 1),
         "plain_trees_per_s": round(len(gl) * l / tp, 3), "plain_ms": round(1e3 * tp, 3),
         "batched_over_plain": round(tp / tb, 3), "bit_identical": bool(same),
-        "graph_replayed": sb["graph_replayed"],
+        "graph_replayed": sb["graph_replayed"], "lds_graphs": sb["lds_graphs"],
+        "tuned_plan": None if tune is None else {k: tune[k] for k in ("walkers_mesh", "walkers_other", "path_ring",
+                                                                       "bfs_starts", "lds_state", "candidates",
+                                                                       "probe_samples")},
+        "tuning_s": None if tune_s is None else round(tune_s, 3),
     }
     print(json.dumps(line), flush=True)
 
@@ -430,6 +448,79 @@ def rmat_main(args):
     print(json.dumps(line), flush=True)
 
 
+def _golden_rwc(name):
+    """Stored exact RWC values (node -> value) written by the committed oracle scripts under
+    tests/golden (plain text; nothing is computed here)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    rows = [line.split("|") for line in open(path) if not line.startswith("#")]
+    return np.array([int(a) for a, _ in rows]), np.array([float(b) for _, b in rows])
+
+
+def trap_main(args):
+    """Same-GPU ablation of Wilson's reuse of every walk step (FastWalk, Algorithm 3) against the
+    trap walks of Lemma 5.1 (independent walks from every node, counting returns), at equal
+    accuracy: both estimate diag(calL_v^{-1}) and go through the same rwc_estimate.  The trap
+    walks' count per node is chosen from a pilot run so that their mean relative error matches
+    Wilson's (the error falls as 1/sqrt(l)); reported are the device times to that accuracy."""
+    import torch
+    import paper_2510_20604_amd as P
+    import rwcgen
+    cases = [("ER(n=1000, d=8) LCC, unit weights", rwcgen.erdos_renyi_lcc(1000, 8, 1001), "er1000_exact_rwc.txt",
+              2000, 2001),
+             ("BA(n=20000, m=5), unit weights", rwcgen.barabasi_albert(20_000, 5, 1002), "ba20k_exact_rwc.txt",
+              2000, 2002)]
+    out = []
+    for desc, g, golden, l_w, seed in cases:
+        nodes, exact = _golden_rwc(golden)
+        G = P.Graph(g.n, g.src, g.dst, g.w, "cuda:0")
+
+        def mre(rwc):
+            got = rwc.cpu().numpy()[nodes]
+            return float(np.mean(np.abs(got - exact) / exact))
+
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            torch.cuda.synchronize()
+            return r, (time.perf_counter() - t0) / reps
+
+        def wilson():
+            s = P.sample_forests(G, l_w, seed, want_sq=False, want_hash=False)
+            return s, P.estimate(G, s["counts"], l_w, want_hit=False)["rwc"]
+
+        def trap(l_t):
+            def run():
+                t = P.sample_trap_walks(G, l_t, seed, want_sq=False)
+                return t, P.estimate(G, t["counts"], l_t, want_hit=False)["rwc"]
+            return run
+
+        (sw, rw), tw = timed(wilson)
+        e_w = mre(rw)
+        l0 = 200
+        (_, r0), _ = timed(trap(l0), reps=1)
+        e0 = mre(r0)
+        l_t = max(1, int(np.ceil(l0 * (e0 / e_w) ** 2)))
+        (st_, rt), tt = timed(trap(l_t))
+        e_t = mre(rt)
+        steps_w = int(P.as_uint64(sw["total_steps"])[0])
+        steps_t = int(P.as_uint64(st_["total_steps"])[0])
+        out.append({"workload": desc, "wilson": {"trees": l_w, "mre": e_w, "ms": round(1e3 * tw, 3),
+                                                 "walk_steps": steps_w},
+                    "trap_walks": {"walks_per_node": l_t, "mre": e_t, "ms": round(1e3 * tt, 3), "walk_steps": steps_t,
+                                   "pilot": {"walks_per_node": l0, "mre": e0}},
+                    "time_ratio_trap_over_wilson": round(tt / tw, 3),
+                    "step_ratio_trap_over_wilson": round(steps_t / steps_w, 3)})
+        print(f"{desc}: Wilson {1e3 * tw:.2f} ms (MRE {e_w:.4%}), trap walks {1e3 * tt:.2f} ms "
+              f"(MRE {e_t:.4%}, {l_t} walks per node)", file=sys.stderr, flush=True)
+    line = {"metric": METRIC, "value": out[0]["time_ratio_trap_over_wilson"], "unit": "x (trap / Wilson time)",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "u64/f64", "data": "synthetic",
+            "config": {"workload": "trap walks (Lemma 5.1) vs Wilson forests at equal MRE"}, "cases": out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -443,6 +534,8 @@ def main():
         return rmat_main(args)
     if args.config == "batch256":
         return batch_main(args)
+    if args.config == "trap":
+        return trap_main(args)
     import torch
     import paper_2510_20604_amd as P
     from paper_2510_20604_amd import _lib
@@ -458,7 +551,8 @@ def main():
     def step():
         G = P.Graph(g.n, src, dst, None, dev)
         s = P.sample_forests(G, l, seed, want_sq=True, want_hash=False, workspace=ws["sample"], timing=True,
-                             walkers_per_tree=args.walkers, trees_in_flight=args.tif)
+                             walkers_per_tree=args.walkers, trees_in_flight=args.tif,
+                             lds_state=False if args.no_lds else None)
         ws["sample"] = s["workspace"]
         e = P.estimate(G, s["counts"], l, counts_sq=s["counts_sq"], want_stderr=True)
         return G, s, e
@@ -529,7 +623,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m": g.m, "trees": l, "trees_in_flight": trees_in_flight,
                    "walkers_per_tree": s["walkers_per_tree"], "starts": s["starts"], "walk_launches": launches,
-                   "launch": "plain"},
+                   "launch": "plain", "walk_kernel": s["walk_kernel"]},
         "walk_steps_per_s": round(args.steps * total_steps / elapsed, 1),
         "walk_steps_per_tree": total_steps / l,
         "sampler_trees_per_s": round(l / (np.mean(walk_ms) + np.mean(reduce_ms)) * 1e3, 3),

@@ -126,6 +126,13 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
                                         more than 16 entries per node, and no graph has
                                         spread starts (same forest)                         */
 
+#define RWC_SAMPLE_NO_LDS_STATE 512u /* keep every graph's tree state in HBM.  Without it,
+                                        walker-team graphs whose trees fit (64 / W trees of n
+                                        8-byte words in 48 KB of LDS; calls of at most 2^24
+                                        samples) grow them in LDS instead:
+                                        no HBM tree slots, LDS accesses for every state read
+                                        and write (same forest)                            */
+
 typedef struct rwc_sample_params {
     uint64_t seed;               /* Philox key (seed mod 2^32, seed >> 32)                 */
     int64_t sample_begin;        /* global index of the first sample                      */
@@ -149,6 +156,9 @@ typedef struct rwc_sample_params {
                                     outputs are then meaningless).  NULL when num_roots = 0  */
     int32_t num_roots;           /* 0: one root (`root`); else 1 .. n - 1                    */
     int32_t reserved2;
+    const int32_t* walkers_per_graph; /* HOST [num_graphs] or NULL: walkers per tree of each
+                                    graph (1 or a power of two up to 64), overriding
+                                    walkers_per_tree (rwc_autotune_batch picks them)       */
 } rwc_sample_params;
 
 typedef struct rwc_sample_outputs {
@@ -174,7 +184,9 @@ typedef struct rwc_sample_outputs {
                                     LDS path ring), team starts (0 shared, 1 spread), start
                                     order (0 ascending ids, 1 breadth-first), hipGraph
                                     (-1 none, 0 captured by this call, 1 a cached graph
-                                    replayed), 0                                          */
+                                    replayed), graphs with LDS-resident trees.  The walk
+                                    kernel is 3 (4 with the path ring) when graph 0's trees
+                                    live in LDS                                           */
 } rwc_sample_outputs;
 
 /* Workspace for rwc_sample_forests with these graphs and parameters. */
@@ -275,6 +287,35 @@ int rwc_autotune_workspace(const rwc_csr* g, const rwc_sample_params* p, int64_t
  * depend on the choice, only the speed.  Synchronises `stream`. */
 int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p, int64_t budget_bytes,
                          rwc_tune_result* out, void* ws, size_t ws_bytes, void* stream);
+
+typedef struct rwc_batch_tune_result {
+    int32_t walkers_mesh;        /* walkers per tree for the graphs with spread starts (pivot
+                                    eccentricity above 32: mesh-like, long walks)            */
+    int32_t walkers_other;       /* walkers per tree for the other graphs                    */
+    uint32_t flags;              /* the winner's schedule flags: one of each pair PATH_RING /
+                                    NO_PATH_RING, ID_STARTS / BFS_STARTS, and NO_LDS_STATE or
+                                    0 (LDS-resident trees where they fit)                     */
+    int32_t candidates;          /* probes run (0 when served from the cache)                */
+    double steps_per_s;          /* walk steps per second of the winning probe               */
+    int32_t probe_samples;       /* trees per graph in each probe                            */
+    int32_t cached;              /* 1 if the result came from the per-process cache          */
+} rwc_batch_tune_result;
+
+/* Workspace for rwc_autotune_batch with these graphs and parameters. */
+int rwc_autotune_batch_workspace(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p,
+                                 size_t* bytes);
+
+/* Autotuning of a multi-graph call (the batched persistent launch): times probes of the real
+ * sampler on all graphs at once, each with min(l, max(64, l / 8)) trees per graph from the
+ * call's sample range: first the walkers per tree of the mesh-like graphs and of the others
+ * (16, 32 or 64 each, nine probes) under the automatic schedule, then, for the winning pair,
+ * the path ring on or off, ascending or breadth-first start order, and LDS-resident trees on
+ * or off (eight probes).  Use the result with p->walkers_per_graph (mesh-like graphs, pivot
+ * eccentricity above 32, take walkers_mesh) and p->flags |= flags.  Cached per (number of
+ * graphs, their total nodes and entries, probe size) for the process.  The forest does not
+ * depend on the choice, only the speed.  Synchronises `stream`. */
+int rwc_autotune_batch(const rwc_csr* graphs, int32_t num_graphs, const rwc_sample_params* p,
+                       rwc_batch_tune_result* out, void* ws, size_t ws_bytes, void* stream);
 
 /* Forgets every cached tuning result. */
 void rwc_autotune_clear_cache(void);

@@ -24,6 +24,7 @@ RWC_SAMPLE_SHARED_STARTS = 32
 RWC_SAMPLE_PATH_RING = 64
 RWC_SAMPLE_NO_PATH_RING = 128
 RWC_SAMPLE_ID_STARTS = 256
+RWC_SAMPLE_NO_LDS_STATE = 512
 
 RWC_SOLVE_STREAM_ORDERED = -1   # rwc_solve_params.check_every value selecting stream-ordered mode
 
@@ -47,7 +48,7 @@ class SampleParams(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("sample_begin", c_i64), ("num_samples", c_i64), ("root", c_i32),
                 ("flags", c_u32), ("trees_in_flight", c_i32), ("walkers_per_tree", c_i32),
                 ("max_steps_per_tree", c_u64), ("graph_index_base", c_u32), ("reserved", c_u32),
-                ("roots", c_vp), ("num_roots", c_i32), ("reserved2", c_i32)]
+                ("roots", c_vp), ("num_roots", c_i32), ("reserved2", c_i32), ("walkers_per_graph", c_vp)]
 
 
 class SampleOutputs(ctypes.Structure):
@@ -68,6 +69,11 @@ class SolveParams(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("walkers_per_tree", c_i32), ("trees_in_flight", c_i32), ("steps_per_s", c_dbl),
                 ("candidates", c_i32), ("cached", c_i32), ("flags", c_u32), ("reserved", c_i32)]
+
+
+class BatchTuneResult(ctypes.Structure):
+    _fields_ = [("walkers_mesh", c_i32), ("walkers_other", c_i32), ("flags", c_u32), ("candidates", c_i32),
+                ("steps_per_s", c_dbl), ("probe_samples", c_i32), ("cached", c_i32)]
 
 
 class BackwardParams(ctypes.Structure):
@@ -105,6 +111,10 @@ SIGNATURES = [
                                        ctypes.POINTER(c_sz)]),
     ("rwc_autotune_sampler", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(SampleParams), c_i64,
                                      ctypes.POINTER(TuneResult), c_vp, c_sz, c_vp]),
+    ("rwc_autotune_batch_workspace", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),
+                                             ctypes.POINTER(c_sz)]),
+    ("rwc_autotune_batch", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),
+                                   ctypes.POINTER(BatchTuneResult), c_vp, c_sz, c_vp]),
     ("rwc_autotune_clear_cache", None, []),
     ("rwc_status_string", ctypes.c_char_p, [c_i32]),
     ("rwc_probe_random_gather", c_i32, [c_vp, c_u64, c_i64, c_i32, c_u32, c_vp, ctypes.POINTER(ctypes.c_float), c_vp]),

@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BackwardParams, RwcCsr, SampleOutputs, SampleParams, SolveParams, TrapParams, TuneResult, check
+from ._lib import (BackwardParams, BatchTuneResult, RwcCsr, SampleOutputs, SampleParams, SolveParams, TrapParams,
+                   TuneResult, check)
 
 
 def _stream() -> ctypes.c_void_p:
@@ -101,7 +102,8 @@ class Graph:
 
 
 def _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, walkers_per_tree, persistent,
-                  capture, accumulate, max_steps_per_tree, graph_index_base, bfs_starts, starts, path_ring, roots):
+                  capture, accumulate, max_steps_per_tree, graph_index_base, bfs_starts, starts, path_ring, roots,
+                  lds_state=None, walkers_per_graph=None):
     arr = (RwcCsr * len(gl))(*[g.csr for g in gl])
     flags = 0
     if persistent:
@@ -120,12 +122,18 @@ def _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, wa
         raise ValueError(f"starts must be 'auto', 'shared' or 'spread', not {starts!r}")
     if path_ring is not None:
         flags |= _lib.RWC_SAMPLE_PATH_RING if path_ring else _lib.RWC_SAMPLE_NO_PATH_RING
+    if lds_state is False:
+        flags |= _lib.RWC_SAMPLE_NO_LDS_STATE
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=root, flags=flags,
                      trees_in_flight=trees_in_flight, walkers_per_tree=walkers_per_tree,
                      max_steps_per_tree=max_steps_per_tree, graph_index_base=graph_index_base)
     if roots is not None:
         p.roots = roots.data_ptr()
         p.num_roots = roots.numel()
+    if walkers_per_graph is not None:
+        wpg = (ctypes.c_int32 * len(gl))(*[int(x) for x in walkers_per_graph])
+        p.walkers_per_graph = ctypes.cast(wpg, ctypes.c_void_p)
+        p._keep = wpg   # the host array must live as long as the params
     return arr, p
 
 
@@ -142,7 +150,8 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
                    graph_index_base: int = 0, accumulate: dict | None = None,
                    workspace: torch.Tensor | None = None, timing: bool = False,
                    bfs_starts: bool | None = None, starts: str = "auto", path_ring: bool | None = None,
-                   roots=None, sync: bool = True, out: dict | None = None) -> dict:
+                   roots=None, sync: bool = True, out: dict | None = None, lds_state: bool | None = None,
+                   walkers_per_graph: Sequence[int] | None = None) -> dict:
     """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
 
     Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
@@ -151,7 +160,8 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     reduce_ms: device time of the walk and reduction kernels (hipEvents on the stream).
     `starts` ("auto", "shared", "spread"), `bfs_starts` (None = automatic, True =
     breadth-first from the root, False = ascending ids) and `path_ring` (None = automatic) pick
-    how walker teams schedule their walks; the forest does not depend on them.  `roots` (ids,
+    how walker teams schedule their walks, and lds_state=False keeps every tree's state in HBM
+    (by default small graphs grow their trees in LDS); the forest does not depend on them.  `roots` (ids,
     single graph) samples spanning forests rooted at that set instead of trees rooted at one
     node.  `out` (a dict returned by an earlier call) reuses its output tensors, so that a
     repeated call with capture=True replays the library's cached hipGraph.  The call is
@@ -164,7 +174,7 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     rt = _roots_tensor(roots, dev)
     arr, p = _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, walkers_per_tree, persistent,
                            capture, accumulate is not None, max_steps_per_tree, graph_index_base, bfs_starts, starts,
-                           path_ring, rt)
+                           path_ring, rt, lds_state, walkers_per_graph)
     size = ctypes.c_size_t()
     check(L.rwc_sample_forests_workspace(arr, G, ctypes.byref(p), ctypes.byref(size)),
           "rwc_sample_forests_workspace")
@@ -210,7 +220,9 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     res["workspace"] = workspace
     res["roots"] = rt
     res["walkers_per_tree"], res["trees_in_flight"], res["batches"] = int(plan[0]), int(plan[1]), int(plan[2])
-    res["walk_kernel"] = ("wilson_walk", "wilson_team<false>", "wilson_team<true>")[int(plan[3])]
+    res["walk_kernel"] = ("wilson_walk", "wilson_team<false>", "wilson_team<true>", "wilson_team_lds<false>",
+                          "wilson_team_lds<true>")[int(plan[3])]
+    res["lds_graphs"] = int(plan[7])
     res["starts"] = "spread" if plan[4] else "shared"
     res["start_order"] = "breadth-first" if plan[5] else "ascending"
     res["graph_replayed"] = int(plan[6])
@@ -233,7 +245,7 @@ def prepare_sampling(graphs: Graph | Sequence[Graph], num_samples: int, workspac
                            kw.get("trees_in_flight", 0), kw.get("walkers_per_tree", 0), kw.get("persistent", False),
                            False, kw.get("accumulate", False), kw.get("max_steps_per_tree", 0),
                            kw.get("graph_index_base", 0), kw.get("bfs_starts"), kw.get("starts", "auto"),
-                           kw.get("path_ring"), rt)
+                           kw.get("path_ring"), rt, kw.get("lds_state"), kw.get("walkers_per_graph"))
     size = ctypes.c_size_t()
     check(L.rwc_sample_forests_workspace(arr, len(gl), ctypes.byref(p), ctypes.byref(size)),
           "rwc_sample_forests_workspace")
@@ -303,7 +315,34 @@ def autotune(graph: Graph, num_samples: int, seed: int, sample_begin: int = 0,
             "steps_per_s": r.steps_per_s, "candidates": r.candidates, "cached": bool(r.cached),
             "path_ring": pick(_lib.RWC_SAMPLE_PATH_RING, _lib.RWC_SAMPLE_NO_PATH_RING, True, False, None),
             "starts": pick(_lib.RWC_SAMPLE_SPREAD_STARTS, _lib.RWC_SAMPLE_SHARED_STARTS, "spread", "shared", "auto"),
-            "bfs_starts": pick(_lib.RWC_SAMPLE_BFS_STARTS, _lib.RWC_SAMPLE_ID_STARTS, True, False, None)}
+            "bfs_starts": pick(_lib.RWC_SAMPLE_BFS_STARTS, _lib.RWC_SAMPLE_ID_STARTS, True, False, None),
+            "lds_state": False if r.flags & _lib.RWC_SAMPLE_NO_LDS_STATE else None}
+
+
+def autotune_batch(graphs: Sequence[Graph], num_samples: int, seed: int, sample_begin: int = 0) -> dict:
+    """rwc_autotune_batch: walkers per tree for the mesh-like graphs and for the others, then the
+    schedule, timed on probes of the whole batch.  Returns the choice in the form sample_forests
+    takes (walkers_per_graph, path_ring, bfs_starts, lds_state) plus the probe statistics."""
+    L = _lib.lib()
+    gl = list(graphs)
+    arr = (RwcCsr * len(gl))(*[g.csr for g in gl])
+    p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=-1,
+                     flags=_lib.RWC_SAMPLE_PERSISTENT)
+    size = ctypes.c_size_t()
+    check(L.rwc_autotune_batch_workspace(arr, len(gl), ctypes.byref(p), ctypes.byref(size)),
+          "rwc_autotune_batch_workspace")
+    ws = _workspace(size.value, gl[0].device)
+    r = BatchTuneResult()
+    check(L.rwc_autotune_batch(arr, len(gl), ctypes.byref(p), ctypes.byref(r), _ptr(ws), ws.numel(), _stream()),
+          "rwc_autotune_batch")
+    del ws
+    wpg = [r.walkers_mesh if int(g.csr.bfs_depth) > 32 else r.walkers_other for g in gl]
+    return {"walkers_mesh": r.walkers_mesh, "walkers_other": r.walkers_other, "walkers_per_graph": wpg,
+            "path_ring": bool(r.flags & _lib.RWC_SAMPLE_PATH_RING),
+            "bfs_starts": bool(r.flags & _lib.RWC_SAMPLE_BFS_STARTS),
+            "lds_state": False if r.flags & _lib.RWC_SAMPLE_NO_LDS_STATE else None,
+            "flags": int(r.flags), "candidates": r.candidates, "steps_per_s": r.steps_per_s,
+            "probe_samples": r.probe_samples, "cached": bool(r.cached)}
 
 
 def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor | None = None,

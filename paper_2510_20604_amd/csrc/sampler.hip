@@ -62,6 +62,8 @@ bool spread_starts(const rwc_csr& g, uint32_t flags) {
     return g.bfs_depth > kLongWalkDepth;
 }
 
+using LdsKernel = void (*)(const GraphArgs*, const Item*, int32_t, uint32_t*, int64_t, int64_t, uint64_t,
+                           const int64_t*, uint64_t*, uint64_t*, int32_t*, DumpArgs, uint64_t*, uint64_t*, uint32_t*);
 using WalkKernel = void (*)(const GraphArgs*, const Item*, int32_t, uint32_t*, int32_t, int64_t, int64_t, uint64_t,
                             uint64_t*, uint64_t*, uint32_t*);
 
@@ -109,7 +111,8 @@ __global__ void zero_outputs(uint64_t* counts, uint64_t* counts_sq, int64_t tota
         if (total_steps) total_steps[i] = 0;
     if (tid == 0) {
         header_begin(header);
-        *queue = 0;
+        queue[0] = 0;
+        queue[1] = 0;
     }
 }
 
@@ -181,11 +184,21 @@ __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t
 struct Plan {
     std::vector<int32_t> W, T, S;     // per graph: walkers per tree, tree slots, trees per wave
     std::vector<int64_t> stride;      // per graph: words per slot
+    std::vector<char> lds;            // per graph: its trees live in LDS (no slots in HBM)
     std::vector<int64_t> node_off;
     int64_t total_nodes = 0;
+    int64_t lds_words = 0;            // dynamic LDS of the LDS-state kernel, in 8-byte words
     int32_t batches = 1;
+    int32_t lds_graphs = 0;
     bool team = false;                // some graph uses more than one walker per tree
+    bool hbm_team = false;            // some graph with HBM state uses walker teams
 };
+
+// LDS per wave for the state words of an LDS-resident graph's trees (64 / W trees of n
+// words, n rounded up to 8): with the 8 KB of path ring and record copies, 56 KB per wave,
+// two waves per compute unit at the largest size.
+constexpr int64_t kLdsStateBytes = 48 * 1024;
+constexpr int64_t kLdsMaxSamples = int64_t{1} << 24;
 
 // Bytes of tree state the automatic plan may use: half of the device's memory (144 GB of the
 // 288 GB of an MI355X), so that every tree of BA(10^6) x 10^4 (80 GB) or of R-MAT scale 23 x
@@ -235,6 +248,7 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
     plan->T.assign(G, 1);
     plan->S.assign(G, kWave);
     plan->stride.assign(G, 0);
+    plan->lds.assign(G, 0);
     for (int32_t g = 0; g < G; ++g) {
         if (graphs[g].n < 2 || !graphs[g].row_ptr || !graphs[g].col || !graphs[g].rec || !graphs[g].bfs_order)
             return fail(RWC_ERR_INVALID_ARG, "graph %d is not a built CSR", g);
@@ -245,7 +259,8 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
     int64_t state_words = 0;
     for (int32_t g = 0; g < G; ++g) {
         const int64_t n = graphs[g].n;
-        const int W = (p->walkers_per_tree > 0) ? p->walkers_per_tree : auto_walkers(n);
+        const int W = p->walkers_per_graph ? p->walkers_per_graph[g]
+                      : (p->walkers_per_tree > 0) ? p->walkers_per_tree : auto_walkers(n);
         const int S = kWave / W;
         int64_t T = p->trees_in_flight;
         if (T <= 0) {
@@ -257,6 +272,18 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
         plan->T[g] = static_cast<int32_t>(T);
         plan->stride[g] = round_up(n, 8);
         plan->team = plan->team || W > 1;
+        // trees in LDS when a wave's trees fit (walker teams only), unless the caller forbids it
+        // (the work items of LDS graphs list every block of samples, so very long sample
+        // ranges keep their trees in HBM slots)
+        const bool fits = W > 1 && S * plan->stride[g] * 8 <= kLdsStateBytes && l <= kLdsMaxSamples;
+        if (fits && !(p->flags & RWC_SAMPLE_NO_LDS_STATE)) {
+            plan->lds[g] = 1;
+            plan->T[g] = 0;
+            plan->lds_words = std::max<int64_t>(plan->lds_words, S * plan->stride[g]);
+            ++plan->lds_graphs;
+            continue;
+        }
+        plan->hbm_team = plan->hbm_team || W > 1;
         state_words += T * plan->stride[g];
     }
     const int64_t budget = (p->trees_in_flight <= 0) ? default_state_budget() : 0;
@@ -264,12 +291,14 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
         // shrink every graph's slots by the same factor to fit the automatic budget
         const double f = static_cast<double>(budget) / (8.0 * static_cast<double>(state_words));
         for (int32_t g = 0; g < G; ++g) {
+            if (plan->lds[g]) continue;
             int64_t T = static_cast<int64_t>(plan->T[g] * f) / plan->S[g] * plan->S[g];
             plan->T[g] = static_cast<int32_t>(T < plan->S[g] ? plan->S[g] : T);
         }
     }
     int32_t batches = 1;
     for (int32_t g = 0; g < G; ++g) {
+        if (plan->lds[g]) continue;   // all of an LDS graph's trees run in the first batch
         const int64_t b = (l + plan->T[g] - 1) / plan->T[g];
         batches = b > batches ? static_cast<int32_t>(b) : batches;
     }
@@ -289,13 +318,23 @@ struct SampleLayout {
     size_t total;
 };
 
-int64_t max_items(int32_t G, const Plan& plan) {
+// Work items of one batch of HBM-state graphs (a block of S tree slots each), then of the
+// LDS-state graphs (a block of S samples each, all samples in one launch).
+int64_t max_items(int32_t G, const Plan& plan, int64_t l) {
     int64_t k = 0;
-    for (int32_t g = 0; g < G; ++g) k += (plan.T[g] + plan.S[g] - 1) / plan.S[g];
+    for (int32_t g = 0; g < G; ++g)
+        k += plan.lds[g] ? (l + plan.S[g] - 1) / plan.S[g] : (plan.T[g] + plan.S[g] - 1) / plan.S[g];
     return k;
 }
 
-SampleLayout carve_sample(void* ws, int32_t G, const Plan& plan, int32_t n0) {
+int64_t hbm_items(int32_t G, const Plan& plan) {
+    int64_t k = 0;
+    for (int32_t g = 0; g < G; ++g)
+        if (!plan.lds[g]) k += (plan.T[g] + plan.S[g] - 1) / plan.S[g];
+    return k;
+}
+
+SampleLayout carve_sample(void* ws, int32_t G, const Plan& plan, int32_t n0, int64_t l) {
     Carver c(ws);
     SampleLayout L{};
     L.header = c.take<WsHeader>(kHeaderBytes / sizeof(WsHeader));
@@ -303,8 +342,8 @@ SampleLayout carve_sample(void* ws, int32_t G, const Plan& plan, int32_t n0) {
     for (int32_t g = 0; g < G; ++g) L.state[g] = c.take<uint64_t>(static_cast<size_t>(plan.T[g]) * plan.stride[g]);
     L.graphs = c.take<GraphArgs>(G);
     L.node_off = c.take<int64_t>(G + 1);
-    L.items = c.take<Item>(max_items(G, plan));
-    L.queue = c.take<uint32_t>(1);
+    L.items = c.take<Item>(max_items(G, plan, l));
+    L.queue = c.take<uint32_t>(2);   // [0] HBM-state walk, [1] LDS-state walk
     // root bitmap of graph 0 (an explicit root set is for single-graph calls)
     L.mask_words = (static_cast<int64_t>(n0) + 31) / 32;
     L.rootmask = c.take<uint32_t>(L.mask_words);
@@ -340,6 +379,12 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
     const int W = p->walkers_per_tree;
     if (W < 0 || W > kWave || (W & (W - 1)) != 0)
         return fail(RWC_ERR_INVALID_ARG, "walkers_per_tree must be 0 (automatic) or a power of two up to 64");
+    if (p->walkers_per_graph)
+        for (int32_t g = 0; g < G; ++g) {
+            const int w = p->walkers_per_graph[g];
+            if (w < 1 || w > kWave || (w & (w - 1)) != 0)
+                return fail(RWC_ERR_INVALID_ARG, "walkers_per_graph[%d] must be a power of two up to 64", g);
+        }
     if ((p->flags & RWC_SAMPLE_SPREAD_STARTS) && (p->flags & RWC_SAMPLE_SHARED_STARTS))
         return fail(RWC_ERR_INVALID_ARG, "spread and shared starts are exclusive");
     if ((p->flags & RWC_SAMPLE_PATH_RING) && (p->flags & RWC_SAMPLE_NO_PATH_RING))
@@ -355,16 +400,19 @@ struct Setup {
     Plan plan;
     std::vector<GraphArgs> hg;
     std::vector<Item> items;
-    bool ring = false;
+    bool ring = false, lds_ring = false;
     WalkKernel walk = nullptr;
+    LdsKernel walk_lds = nullptr;
     int grid_persistent = 0;
+    int32_t nit_hbm = 0, nit_lds = 0, grid_lds = 0;
+    size_t lds_bytes = 0;
     SampleLayout L;
 };
 
 int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, void* ws, Setup* S) {
     Plan& plan = S->plan;
     RWC_CHECK(make_plan(graphs, G, p, &plan));
-    S->L = carve_sample(ws, G, plan, graphs[0].n);
+    S->L = carve_sample(ws, G, plan, graphs[0].n, p->num_samples);
     std::vector<GraphArgs>& hg = S->hg;
     hg.assign(G, GraphArgs{});
     bool any_spread = false, any_dense_weighted = false;
@@ -405,14 +453,15 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
     // (R-MAT, 2000 trees: 23 %); slower on weighted graphs of high mean degree that fill the
     // device (weighted R-MAT scale 21-23, mean degree 22-25: 16-27 %).
     const int64_t resident = team_resident_waves(true);
-    const bool fills = plan.team && 3 * max_items(G, plan) >= 2 * resident;
+    const int64_t l = p->num_samples;
+    const bool fills = plan.hbm_team && 3 * hbm_items(G, plan) >= 2 * resident;
     // Start order, measured: breadth-first starts make batches of many meshes (spread starts)
     // a third faster (256 mixed graphs: 4.5 -> 3.0 s, their 128 grids alone 4.0 -> 3.1 s) but
     // every single graph slower, meshes included (a 25 k-node grid with 50 000 trees: 10 %, a
     // 97 k-node grid with 2000-20 000 trees: 5-15 %), and small-world graphs (shared starts)
     // by much more.  So they are taken for the meshes of calls with several graphs and a queue
     // of at least twice the resident waves.
-    const bool queued = plan.team && G > 1 && max_items(G, plan) >= 2 * resident;
+    const bool queued = plan.team && G > 1 && max_items(G, plan, l) >= 2 * resident;
     for (int32_t g = 0; g < G; ++g) {
         const bool bfs = (p->flags & RWC_SAMPLE_BFS_STARTS) ||
                          (!(p->flags & RWC_SAMPLE_ID_STARTS) && queued && plan.W[g] > 1 && hg[g].spread);
@@ -421,6 +470,9 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
     S->ring = (p->flags & RWC_SAMPLE_PATH_RING) ? true
               : (p->flags & RWC_SAMPLE_NO_PATH_RING) ? false
                                                       : (any_spread || !any_dense_weighted || !fills);
+    // LDS-state trees: a buffered path node's word is an LDS access like any other, so the ring
+    // saves little there; it is used only on request
+    S->lds_ring = (p->flags & RWC_SAMPLE_PATH_RING) != 0;
     // Work items with the longest trees first: a tree's time grows with n / W.
     std::vector<int32_t> order(G);
     std::iota(order.begin(), order.end(), 0);
@@ -428,10 +480,17 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
         return static_cast<int64_t>(graphs[a].n) * plan.W[b] > static_cast<int64_t>(graphs[b].n) * plan.W[a];
     });
     S->items.clear();
-    S->items.reserve(max_items(G, plan));
+    S->items.reserve(max_items(G, plan, l));
     for (int32_t g : order)
-        for (int32_t s0 = 0; s0 < plan.T[g]; s0 += plan.S[g]) S->items.push_back(Item{g, s0});
-    S->walk = !plan.team ? static_cast<WalkKernel>(wilson_walk)
+        if (!plan.lds[g])
+            for (int32_t s0 = 0; s0 < plan.T[g]; s0 += plan.S[g]) S->items.push_back(Item{g, s0});
+    S->nit_hbm = static_cast<int32_t>(S->items.size());
+    for (int32_t g : order)
+        if (plan.lds[g])
+            for (int64_t s0 = 0; s0 < l; s0 += plan.S[g]) S->items.push_back(Item{g, static_cast<int32_t>(s0)});
+    S->nit_lds = static_cast<int32_t>(S->items.size()) - S->nit_hbm;
+    const bool hbm_team = plan.hbm_team || (plan.team && S->nit_hbm == 0);
+    S->walk = !hbm_team  ? static_cast<WalkKernel>(wilson_walk)
               : S->ring  ? static_cast<WalkKernel>(wilson_team<true>)
                          : static_cast<WalkKernel>(wilson_team<false>);
     if (p->flags & RWC_SAMPLE_PERSISTENT) {
@@ -439,6 +498,16 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
         RWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->walk, kWave, 0));
         if (per_cu < 1) per_cu = 1;
         S->grid_persistent = per_cu * device_cu_count();
+    }
+    if (S->nit_lds > 0) {
+        S->walk_lds = S->lds_ring ? static_cast<LdsKernel>(wilson_team_lds<true>)
+                                  : static_cast<LdsKernel>(wilson_team_lds<false>);
+        S->lds_bytes = static_cast<size_t>(plan.lds_words) * 8;
+        int per_cu = 0;
+        RWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->walk_lds, kWave, S->lds_bytes));
+        if (per_cu < 1) per_cu = 1;
+        const int64_t grid = static_cast<int64_t>(per_cu) * device_cu_count();
+        S->grid_lds = static_cast<int32_t>(grid < S->nit_lds ? grid : S->nit_lds);
     }
     return RWC_OK;
 }
@@ -477,7 +546,10 @@ std::vector<uint64_t> table_signature(const rwc_csr* graphs, int32_t G, const rw
     q.seed = 0;
     q.sample_begin = 0;
     q.flags &= ~(RWC_SAMPLE_ACCUMULATE | RWC_SAMPLE_GRAPH_CAPTURE);
+    q.walkers_per_graph = nullptr;   // the contents count, not where the host keeps them
     k.add_bytes(q);
+    if (p->walkers_per_graph)
+        for (int32_t g = 0; g < G; ++g) k.add(static_cast<uint64_t>(p->walkers_per_graph[g]));
     k.add(reinterpret_cast<uintptr_t>(ws));
     k.add(static_cast<uint64_t>(ws_bytes));
     return k.words;
@@ -524,7 +596,7 @@ extern "C" int rwc_sample_forests_workspace(const rwc_csr* graphs, int32_t num_g
     RWC_CHECK(validate(graphs, num_graphs, p));
     Plan plan;
     RWC_CHECK(make_plan(graphs, num_graphs, p, &plan));
-    *bytes = carve_sample(nullptr, num_graphs, plan, graphs[0].n).total;
+    *bytes = carve_sample(nullptr, num_graphs, plan, graphs[0].n, p->num_samples).total;
     return RWC_OK;
 }
 
@@ -536,7 +608,7 @@ extern "C" int rwc_sample_prepare(const rwc_csr* graphs, int32_t G, const rwc_sa
     {
         Plan plan;
         RWC_CHECK(make_plan(graphs, G, p, &plan));
-        RWC_CHECK(check_workspace(ws, ws_bytes, carve_sample(nullptr, G, plan, graphs[0].n).total));
+        RWC_CHECK(check_workspace(ws, ws_bytes, carve_sample(nullptr, G, plan, graphs[0].n, p->num_samples).total));
     }
     RWC_CHECK(make_setup(graphs, G, p, ws, &S));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -577,7 +649,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     {
         Plan plan;
         RWC_CHECK(make_plan(graphs, G, p, &plan));
-        RWC_CHECK(check_workspace(ws, ws_bytes, carve_sample(nullptr, G, plan, graphs[0].n).total));
+        RWC_CHECK(check_workspace(ws, ws_bytes, carve_sample(nullptr, G, plan, graphs[0].n, p->num_samples).total));
     }
     if (caller_capture) {
         std::lock_guard<std::mutex> lock(g_prep_mu);
@@ -592,7 +664,7 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
     const Plan& plan = S.plan;
     const SampleLayout& L = S.L;
     const int64_t l = p->num_samples;
-    const int32_t nit = static_cast<int32_t>(S.items.size());
+    const int32_t nit = S.nit_hbm;
     const bool persistent = (p->flags & RWC_SAMPLE_PERSISTENT) != 0;
     if (!caller_capture) RWC_CHECK(upload_tables(S, G, s));
 
@@ -614,17 +686,31 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
             // every graph runs its samples [b*T_g, (b+1)*T_g); graphs with fewer batches idle
             if (out->timing_ms) RWC_HIP(hipEventRecord(timer.ev[0], ls));
             uint32_t* status = &L.header->status;
-            if (persistent) {
+            if (b == 0 && S.nit_lds > 0) {
+                // every tree of the LDS-state graphs, in one persistent launch
+                DumpArgs ldumps{};
+                if (plan.lds[0])
+                    for (int d = 0; d < out->ndump; ++d) {
+                        ldumps.slot[ldumps.count] = static_cast<int32_t>(out->dump_samples[d] - p->sample_begin);
+                        ldumps.out[ldumps.count] = d;
+                        ++ldumps.count;
+                    }
+                hipLaunchKernelGGL(S.walk_lds, dim3(S.grid_lds), dim3(kWave), S.lds_bytes, ls, L.graphs,
+                                   L.items + S.nit_hbm, S.nit_lds, L.queue + 1, p->sample_begin, l, p->seed, L.node_off,
+                                   out->counts, out->counts_sq, out->parents, ldumps, out->tree_hash, out->total_steps,
+                                   status);
+            }
+            if (nit > 0 && persistent) {
                 hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, ls, L.queue);
                 const int grid = S.grid_persistent < nit ? S.grid_persistent : nit;
                 hipLaunchKernelGGL(S.walk, dim3(grid), dim3(kWave), 0, ls, L.graphs, L.items, nit, L.queue, b,
                                    p->sample_begin, l, p->seed, out->tree_hash, out->total_steps, status);
-            } else {
+            } else if (nit > 0) {
                 hipLaunchKernelGGL(S.walk, dim3(nit), dim3(kWave), 0, ls, L.graphs, L.items, nit, nullptr, b,
                                    p->sample_begin, l, p->seed, out->tree_hash, out->total_steps, status);
             }
             DumpArgs dumps{};
-            for (int d = 0; d < out->ndump; ++d) {
+            for (int d = 0; d < out->ndump && !plan.lds[0]; ++d) {
                 const int64_t rel = out->dump_samples[d] - p->sample_begin - static_cast<int64_t>(b) * plan.T[0];
                 if (rel >= 0 && rel < plan.T[0]) {
                     dumps.slot[dumps.count] = static_cast<int32_t>(rel);
@@ -709,11 +795,11 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         out->plan[0] = plan.W[0];
         out->plan[1] = plan.T[0];
         out->plan[2] = plan.batches;
-        out->plan[3] = !plan.team ? 0 : (S.ring ? 2 : 1);
+        out->plan[3] = plan.lds[0] ? (S.lds_ring ? 4 : 3) : (!plan.team ? 0 : (S.ring ? 2 : 1));
         out->plan[4] = S.hg[0].spread;
         out->plan[5] = S.hg[0].order != nullptr ? 1 : 0;
         out->plan[6] = replayed;
-        out->plan[7] = 0;
+        out->plan[7] = plan.lds_graphs;
     }
     if (out->timing_ms) {
         out->timing_ms[0] = timer.walk_ms;

@@ -237,8 +237,22 @@ __device__ __forceinline__ bool st_cas(RWC_GLOBAL uint64_t* p, uint64_t expected
                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool kRing>
-__device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, bool active, uint64_t seed,
+// The same accesses on tree state held in LDS (small graphs: all n words of a tree fit in the
+// work-group's LDS), where they are ds_read / ds_write / ds_cmpst instructions.
+__device__ __forceinline__ uint64_t st_load(const RWC_LDS uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_store(RWC_LDS uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool st_cas(RWC_LDS uint64_t* p, uint64_t expected, uint64_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// st: the tree's state words, in HBM (RWC_GLOBAL uint64_t*) or in LDS (RWC_LDS uint64_t*).
+template <bool kRing, class StatePtr>
+__device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool active, uint64_t seed,
                           uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
                           bool want_hash, uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
     constexpr uint32_t kNone = 64;
@@ -254,7 +268,6 @@ __device__ void grow_team(const GraphArgs& G, int32_t slot, uint64_t sample, boo
     const auto cdf = global_ptr(G.cdf);
     const auto rec = global_ptr(G.rec);
     const auto order = global_ptr(G.order);
-    const auto st = global_ptr(G.state + static_cast<int64_t>(slot) * G.stride);
     // record of node rh_node, loaded alongside that node's state word so that a step from a
     // fresh head needs no dependent load for low-degree rows.  It is copied straight from
     // memory into LDS (lane's column of lds_rec) without passing through registers; reads of
@@ -623,8 +636,9 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
     const bool active = slot < G.T && rel < l;
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    grow_team<kRing>(G, active ? slot : 0, static_cast<uint64_t>(sample_begin + rel), active, seed,
-                     lds_path, lds_rec, tree_hash != nullptr, steps, h, err);
+    grow_team<kRing>(G, global_ptr(G.state + static_cast<int64_t>(active ? slot : 0) * G.stride),
+                     static_cast<uint64_t>(sample_begin + rel), active, seed, lds_path, lds_rec, tree_hash != nullptr,
+                     steps, h, err);
     for (int off = W / 2; off > 0; off >>= 1) {
         steps += __shfl_xor(steps, off, kWave);
         h += __shfl_xor(h, off, kWave);
@@ -659,6 +673,97 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
         if (idx >= static_cast<uint32_t>(nitems)) break;
         run_team_item<kRing>(graphs, items[idx], batch, sample_begin, l, seed, lds_path, lds_rec,
                              tree_hash, total_steps, status);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// LDS-resident trees.  For a graph whose state words fit in the work-group's LDS (64 / W trees
+// of n words each), a wave grows its trees entirely in LDS: the team protocol above is the
+// same, but every state access is an LDS operation instead of a random HBM line, and the trees
+// need no slots in HBM.  Each work item is a block of 64 / W consecutive samples; the wave
+// clears its LDS trees, grows them, then adds every node's departure count (and its square)
+// into the call's totals with one atomic per node and writes any requested parent dump.
+// ---------------------------------------------------------------------------------------
+template <bool kRing>
+__device__ __forceinline__ void run_team_item_lds(const GraphArgs* __restrict__ graphs, const Item it,
+                                                  int64_t sample_begin, int64_t l, uint64_t seed,
+                                                  uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
+                                                  RWC_LDS uint64_t* lds_state, const int64_t* __restrict__ node_off,
+                                                  uint64_t* __restrict__ counts, uint64_t* __restrict__ counts_sq,
+                                                  int32_t* __restrict__ parents, const DumpArgs& dumps,
+                                                  uint64_t* __restrict__ tree_hash,
+                                                  uint64_t* __restrict__ total_steps, uint32_t* __restrict__ status) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const GraphArgs G = graphs[it.graph];
+    const int W = G.W;
+    const int team = lane / W;
+    const uint32_t tl = static_cast<uint32_t>(lane & (W - 1));
+    const int64_t rel = static_cast<int64_t>(it.slot0) + team;   // sample index within the call
+    const bool active = rel < l;
+    const int32_t n = G.n;
+    RWC_LDS uint64_t* st = lds_state + static_cast<int64_t>(team) * G.stride;
+    auto is_root = [&](int32_t x) {
+        return G.rootmask ? ((G.rootmask[x >> 5] >> (x & 31)) & 1u) != 0 : x == G.root;
+    };
+    for (int32_t x = static_cast<int32_t>(tl); x < n; x += W) st[x] = is_root(x) ? kInTree : 0ull;
+    __syncthreads();
+    uint64_t steps = 0, h = 0;
+    uint32_t err = 0;
+    grow_team<kRing>(G, st, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_path, lds_rec,
+                     tree_hash != nullptr, steps, h, err);
+    __syncthreads();
+    if (active) {
+        const int64_t off = node_off[it.graph];
+        int32_t dump_out = -1;
+        for (int d = 0; d < dumps.count; ++d)
+            if (dumps.slot[d] == rel) dump_out = dumps.out[d];
+        for (int32_t x = static_cast<int32_t>(tl); x < n; x += W) {
+            const uint64_t w = st[x];
+            const uint32_t c = st_cnt(w);
+            if (c) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(&counts[off + x]), static_cast<unsigned long long>(c));
+                if (counts_sq)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&counts_sq[off + x]),
+                              static_cast<unsigned long long>(square_count(c)));
+            }
+            if (dump_out >= 0)
+                parents[static_cast<int64_t>(dump_out) * n + x] = is_root(x) ? -1 : static_cast<int32_t>(st_next(w));
+        }
+    }
+    for (int off = W / 2; off > 0; off >>= 1) {
+        steps += __shfl_xor(steps, off, kWave);
+        h += __shfl_xor(h, off, kWave);
+    }
+    const bool leader = tl == 0;
+    if (active && leader && tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + rel] = h;
+    if (err) atomicOr(status, err);
+    const uint64_t wsteps = wave_sum(leader ? steps : 0ull);
+    if (lane == 0 && total_steps && wsteps)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&total_steps[it.graph]),
+                  static_cast<unsigned long long>(wsteps));
+    __syncthreads();   // the next item's clearing must not overtake this item's reads
+}
+
+// Persistent: a grid of resident waves pops items (graph, first sample) from `queue`.  The
+// dynamic LDS holds the state words of 64 / W trees of the largest graph of the call.
+template <bool kRing>
+__global__ void __launch_bounds__(kWave) wilson_team_lds(const GraphArgs* __restrict__ graphs,
+                                                         const Item* __restrict__ items, int32_t nitems, uint32_t* queue,
+                                                         int64_t sample_begin, int64_t l, uint64_t seed,
+                                                         const int64_t* __restrict__ node_off, uint64_t* counts,
+                                                         uint64_t* counts_sq, int32_t* parents, DumpArgs dumps,
+                                                         uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
+    __shared__ uint4 lds_rec[4][kWave];
+    extern __shared__ uint64_t lds_state_raw[];
+    RWC_LDS uint64_t* lds_state = (RWC_LDS uint64_t*)lds_state_raw;
+    while (true) {
+        uint32_t idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
+        idx = __shfl(idx, 0, kWave);
+        if (idx >= static_cast<uint32_t>(nitems)) break;
+        run_team_item_lds<kRing>(graphs, items[idx], sample_begin, l, seed, lds_path, lds_rec, lds_state, node_off,
+                                 counts, counts_sq, parents, dumps, tree_hash, total_steps, status);
     }
 }
 

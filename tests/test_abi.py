@@ -57,13 +57,19 @@ def test_sample_workspace_scales_with_trees_in_flight():
     from paper_2510_20604_amd import _lib
     lib = _lib.load()
     g = _lib.RwcCsr(n=1000, pivot=0, m=4000, nnz=8000, weighted=0, row_ptr=8, col=8, rec=8, bfs_order=8)
-    p = _lib.SampleParams(seed=1, sample_begin=0, num_samples=500, root=-1, trees_in_flight=64)
+    p = _lib.SampleParams(seed=1, sample_begin=0, num_samples=500, root=-1, trees_in_flight=64,
+                          flags=_lib.RWC_SAMPLE_NO_LDS_STATE)
     a = ctypes.c_size_t()
     assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(a)) == 0
     p.trees_in_flight = 128
     b = ctypes.c_size_t()
     assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(b)) == 0
     assert b.value - a.value >= 64 * 1000 * 8
+    # trees in LDS (this graph's fit) need no slots in HBM at all
+    p.flags = 0
+    c = ctypes.c_size_t()
+    assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(c)) == 0
+    assert c.value < 64 * 1000 * 8
     p.walkers_per_tree = 0
     p.num_samples = 0
     assert lib.rwc_sample_forests_workspace(ctypes.byref(g), 1, ctypes.byref(p), ctypes.byref(b)) == -1

@@ -138,11 +138,14 @@ def oracle_runs():
 
 @pytest.mark.parametrize("name,l", [("er1000", 2000), ("er1000_w", 300), ("ba3000", 200), ("ba3000_w", 200),
                                     ("grid_w", 100), ("star", 50), ("path", 70), ("k2", 10)])
-def test_forest_bit_exact(name, l, oracle_runs):
+@pytest.mark.parametrize("lds", [None, False])
+def test_forest_bit_exact(name, l, lds, oracle_runs):
+    """The automatic plan (small graphs: trees in LDS) and tree state in HBM slots."""
     g, o, ref = oracle_runs(name, l, 2001)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     dump = list(range(min(16, l)))
-    s = P.sample_forests(Gd, l, 2001, dump=dump)
+    s = P.sample_forests(Gd, l, 2001, dump=dump, lds_state=lds)
+    assert (s["lds_graphs"] == 1) == (lds is None and s["walkers_per_tree"] > 1)
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["counts_sq"]), ref["visits_sq"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
@@ -155,7 +158,8 @@ def test_forest_bit_exact(name, l, oracle_runs):
 def test_launch_shape_does_not_change_the_forest(tif, persistent, capture, oracle_runs):
     g, o, ref = oracle_runs("er1000_w", 300, 2001)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    s = P.sample_forests(Gd, 300, 2001, trees_in_flight=tif, persistent=persistent, capture=capture, dump=[0, 299])
+    s = P.sample_forests(Gd, 300, 2001, trees_in_flight=tif, persistent=persistent, capture=capture, dump=[0, 299],
+                         lds_state=False)
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["counts_sq"]), ref["visits_sq"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
@@ -165,12 +169,16 @@ def test_launch_shape_does_not_change_the_forest(tif, persistent, capture, oracl
 @pytest.mark.parametrize("walkers", [1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("name,l", [("er1000", 150), ("er1000_w", 100), ("ba3000", 70), ("ba3000_w", 70), ("grid_w", 40),
                                     ("star", 20), ("path", 30), ("k2", 8)])
-def test_walker_teams_are_bit_exact(walkers, name, l, oracle_runs):
-    """Several walkers per tree pop the same cycles as the serial order of Algorithm 3."""
+@pytest.mark.parametrize("lds", [None, False])
+def test_walker_teams_are_bit_exact(walkers, name, l, lds, oracle_runs):
+    """Several walkers per tree pop the same cycles as the serial order of Algorithm 3, with
+    the trees' state in LDS (the default for these small graphs) or in HBM."""
     g, o, ref = oracle_runs(name, l, 2001)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     dump = [0, l - 1]
-    s = P.sample_forests(Gd, l, 2001, walkers_per_tree=walkers, dump=dump)
+    s = P.sample_forests(Gd, l, 2001, walkers_per_tree=walkers, dump=dump, lds_state=lds)
+    fits = walkers > 1 and (64 // walkers) * ((g.n + 7) // 8 * 8) * 8 <= 48 * 1024   # 64 / W trees in 48 KB
+    assert s["walk_kernel"].startswith("wilson_team_lds") == (fits and lds is None)
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
     np.testing.assert_array_equal(s["parents"].cpu().numpy(), ref["parents"][dump])
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
@@ -190,6 +198,7 @@ def test_walker_teams_launch_shapes(walkers, tif, persistent, bfs, starts, ring,
     g, o, ref = oracle_runs(name, 200, 2001)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=walkers, trees_in_flight=tif, persistent=persistent,
+                         lds_state=(False if tif % 2 else None),
                          bfs_starts=bfs, starts=starts, path_ring=ring)
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
@@ -316,8 +325,36 @@ def test_autotuner_choice_does_not_change_the_forest(oracle_runs):
         assert t["path_ring"] is None and t["starts"] == "auto" and t["bfs_starts"] is None
     s = P.sample_forests(Gd, 200, 2001, walkers_per_tree=t["walkers_per_tree"],
                          trees_in_flight=t["trees_in_flight"], path_ring=t["path_ring"], starts=t["starts"],
-                         bfs_starts=t["bfs_starts"])
+                         bfs_starts=t["bfs_starts"], lds_state=t["lds_state"])
     np.testing.assert_array_equal(_u64(s["counts"]), ref["visits"])
     np.testing.assert_array_equal(_u64(s["tree_hash"][0]), ref["hash"])
     again = P.autotune(Gd, 200, 2001)
     assert again["cached"] and again["walkers_per_tree"] == t["walkers_per_tree"]
+
+
+def test_batch_autotuner_choice_does_not_change_the_forests():
+    """rwc_autotune_batch on a mixed batch (BA graphs and meshes): the tuned call (per-class
+    walkers, schedule, LDS choice) gives the automatic plan's outputs bit for bit, and both
+    match the oracle on two graphs; a second tuning call is served from the cache."""
+    graphs = G.batch_mix(8, 500, 8000, seed=47)
+    dev = [P.Graph(g.n, g.src, g.dst, g.w) for g in graphs]
+    l, seed = 96, 13
+    P._lib.lib().rwc_autotune_clear_cache()
+    t = P.autotune_batch(dev, l, seed)
+    assert t["candidates"] == 17 and not t["cached"]
+    assert t["walkers_mesh"] in (16, 32, 64) and t["walkers_other"] in (16, 32, 64)
+    assert P.autotune_batch(dev, l, seed)["cached"]
+    auto = P.sample_forests(dev, l, seed, persistent=True)
+    tuned = P.sample_forests(dev, l, seed, persistent=True, walkers_per_graph=t["walkers_per_graph"],
+                             path_ring=t["path_ring"], bfs_starts=t["bfs_starts"], lds_state=t["lds_state"])
+    for key in ("counts", "counts_sq", "tree_hash", "total_steps"):
+        assert torch.equal(auto[key], tuned[key]), key
+    off = 0
+    counts = _u64(tuned["counts"])
+    for i, g in enumerate(graphs):
+        if i in (0, len(graphs) - 1):
+            o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+            ref = W.fastwalk_sample(o, o.pivot, seed, i, 0, l, threads=8)
+            np.testing.assert_array_equal(counts[off:off + g.n], ref["visits"])
+            np.testing.assert_array_equal(_u64(tuned["tree_hash"][i]), ref["hash"])
+        off += g.n

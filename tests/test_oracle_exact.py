@@ -215,3 +215,23 @@ def test_group_rwc_definition_and_marginal_formula():
     bad = E.group_marginal_estimate(g.n, g.src, g.dst, g.w, [1, 6], t * d)
     want = np.array([E.group_rwc(g.n, g.src, g.dst, g.w, sorted({1, 6, u})) for u in range(g.n)])
     assert np.max(np.abs(bad - want) / want) > 1e-3
+
+
+def test_er1000_fixture_matches_the_definition():
+    """The stored exact RWC of the ER(1000, 8) component (pseudo-inverse route) against the
+    hitting-time definition at 40 nodes, each from its own grounded solve."""
+    import scipy.sparse.linalg as spla
+    rows = []
+    with open(os.path.join(GOLDEN, "er1000_exact_rwc.txt")) as f:
+        for line in f:
+            if not line.startswith("#"):
+                u, val = line.split("|")
+                rows.append((int(u), float(val)))
+    g = G.erdos_renyi_lcc(1000, 8, 1001)
+    assert len(rows) == g.n
+    L, d = E._sparse_laplacian(g.n, g.src, g.dst, g.w)
+    for u, val in [rows[i] for i in np.linspace(0, g.n - 1, 40).astype(int)]:
+        keep = np.ones(g.n, dtype=bool)
+        keep[u] = False
+        h = spla.spsolve(L[keep][:, keep].tocsc(), d[keep])
+        assert abs(d[keep] @ h / d.sum() - val) <= 1e-9 * val
