@@ -354,6 +354,19 @@ int rwc_estimate(const rwc_csr* g, const uint64_t* counts_dev, const uint64_t* c
                  int64_t l, const rwc_solve_params* sp, double* rwc_dev, double* hit_dev,
                  double* stderr_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
+/* rwc_estimate without a workspace, for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it).  The same
+ * arguments, kernels and results as rwc_estimate in host-checked mode, over a fixed 128 MiB
+ * device array inside the library (one per GPU the library runs on, held until the process
+ * ends), which fits graphs of up to about 3.35 million nodes.  Calls no allocating routine.
+ * RWC_ERR_TOO_LARGE if the graph needs more than the array holds; RWC_ERR_INVALID_ARG for the
+ * stream-ordered mode (sp->check_every < 0).  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other threads, other streams) race and must be serialised by
+ * the caller.  Synchronises `stream`. */
+int rwc_estimate_static(const rwc_csr* g, const uint64_t* counts_dev, const uint64_t* counts_sq_dev,
+                        int64_t l, const rwc_solve_params* sp, double* rwc_dev, double* hit_dev,
+                        double* stderr_dev, int32_t* iters, void* stream);
+
 int rwc_estimate_group_workspace(const rwc_csr* g, size_t* bytes);
 
 /* Random walk centrality of a group of nodes (the generalisation named in the paper's

@@ -101,6 +101,8 @@ SIGNATURES = [
     ("rwc_estimate_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
     ("rwc_estimate", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_vp, c_i64, ctypes.POINTER(SolveParams), c_vp, c_vp,
                              c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_estimate_static", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_vp, c_i64, ctypes.POINTER(SolveParams), c_vp,
+                                    c_vp, c_vp, ctypes.POINTER(c_i32), c_vp]),
     ("rwc_estimate_group_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
     ("rwc_estimate_group", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_i32, c_vp, c_i64, ctypes.POINTER(SolveParams),
                                    c_vp, c_vp, c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),

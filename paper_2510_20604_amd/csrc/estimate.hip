@@ -11,6 +11,7 @@
 // results are bitwise reproducible run to run.  This file is compiled without FMA
 // contraction.
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "device.hpp"
@@ -525,4 +526,50 @@ extern "C" int rwc_estimate_group(const rwc_csr* g, const int32_t* roots, int32_
         return device_error_to_status(h.status);
     }
     return RWC_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// rwc_estimate_static: rwc_estimate over a fixed device array instead of a caller workspace,
+// for callers that cannot allocate.  `scratch` is a host-side stand-in for the array in host
+// code; its device address (one per GPU) comes from hipGetSymbolAddress on the first call on
+// each device and is the only handle passed to kernels.
+// ---------------------------------------------------------------------------------------
+namespace rwc {
+namespace {
+constexpr size_t kStaticScratchBytes = size_t{128} << 20;   // 128 MiB: graphs up to ~3.35 M nodes
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+int static_scratch(void** out) {
+    static std::mutex mu;
+    static void* ptrs[64] = {};
+    int dev = 0;
+    RWC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(RWC_ERR_HIP, "device %d out of the supported range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        RWC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(RWC_ERR_HIP, "hipGetSymbolAddress returned a null address");
+        ptrs[dev] = p;
+    }
+    *out = ptrs[dev];
+    return RWC_OK;
+}
+}  // namespace
+}  // namespace rwc
+
+extern "C" int rwc_estimate_static(const rwc_csr* g, const uint64_t* counts, const uint64_t* counts_sq, int64_t l,
+                                   const rwc_solve_params* sp, double* rwc_out, double* hit, double* stderr_out,
+                                   int32_t* iters, void* stream) {
+    clear_error();
+    if (!g) return fail(RWC_ERR_INVALID_ARG, "g must not be null");
+    if (sp && sp->check_every < 0)
+        return fail(RWC_ERR_INVALID_ARG, "rwc_estimate_static runs the host-checked solve only");
+    const size_t need = carve_est(nullptr, g->n, false).total;
+    if (need > kStaticScratchBytes)
+        return fail(RWC_ERR_TOO_LARGE, "rwc_estimate_static: n = %d needs %zu bytes of scratch, the fixed array has %zu",
+                    g->n, need, kStaticScratchBytes);
+    void* ws = nullptr;
+    RWC_CHECK(static_scratch(&ws));
+    return rwc_estimate(g, counts, counts_sq, l, sp, rwc_out, hit, stderr_out, iters, ws, kStaticScratchBytes, stream);
 }
