@@ -290,6 +290,23 @@ def probe_gather(ws, dev):
                                               f"footprint {ws.numel() / 2**30:.1f} GiB"
 
 
+def copy_probe(dev):
+    """One 1 GiB streaming copy (rwc_probe_copy): the reference whose HBM byte counters scale
+    the walk kernel's."""
+    import ctypes
+    import torch
+    from paper_2510_20604_amd import _lib
+    words = (1 << 30) // 8
+    a = torch.zeros(words, dtype=torch.int64, device=dev)
+    b = torch.empty(words, dtype=torch.int64, device=dev)
+    ms = ctypes.c_float()
+    _lib.check(_lib.lib().rwc_probe_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), words,
+                                         ctypes.byref(ms), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "rwc_probe_copy")
+    return {"bytes_read": words * 8, "bytes_written": words * 8, "ms": ms.value,
+            "GB_per_s": 2 * words * 8 / (ms.value * 1e-3) / 1e9}
+
+
 def roofline_line(config, kernel, total_steps, l, n, weighted, walk_ms_launch, trees_in_flight, launches):
     bytes_launch = walk_bytes(total_steps, l, n, weighted) / launches
     achieved = bytes_launch / (walk_ms_launch * 1e-3) / 1e9
@@ -436,6 +453,8 @@ def rmat_main(args):
         line["gather_roofline"] = gr
     del ws["sample"], s, e, r, G
     torch.cuda.empty_cache()
+    if args.copy_probe:
+        line["copy_probe"] = copy_probe(dev)
     if not args.no_extras:
         line["ba1m"] = ba1m_side(args)
         print("BA(1e6) side measurement done", file=sys.stderr, flush=True)
@@ -593,17 +612,7 @@ def main():
         extra["gather_roofline"] = gr
 
     if args.copy_probe:
-        import ctypes
-        words = (1 << 30) // 8
-        a = torch.zeros(words, dtype=torch.int64, device=dev)
-        b = torch.empty(words, dtype=torch.int64, device=dev)
-        ms = ctypes.c_float()
-        _lib.check(_lib.lib().rwc_probe_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), words,
-                                             ctypes.byref(ms), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
-                   "rwc_probe_copy")
-        extra["copy_probe"] = {"bytes_read": words * 8, "bytes_written": words * 8, "ms": ms.value,
-                               "GB_per_s": 2 * words * 8 / (ms.value * 1e-3) / 1e9}
-        del a, b
+        extra["copy_probe"] = copy_probe(dev)
 
     rel_se = (e["stderr"] / e["rwc"]).double()
     mask = torch.ones(g.n, dtype=torch.bool, device=dev)

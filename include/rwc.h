@@ -127,9 +127,9 @@ int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* d
                                         spread starts (same forest)                         */
 
 #define RWC_SAMPLE_NO_LDS_STATE 512u /* keep every graph's tree state in HBM.  Without it,
-                                        walker-team graphs whose trees fit (64 / W trees of n
-                                        8-byte words in 48 KB of LDS; calls of at most 2^24
-                                        samples) grow them in LDS instead:
+                                        a call whose graphs all use walker teams and all fit
+                                        (64 / W trees of n 8-byte words in 48 KB of LDS; at
+                                        most 2^24 samples) grows its trees in LDS instead:
                                         no HBM tree slots, LDS accesses for every state read
                                         and write (same forest)                            */
 

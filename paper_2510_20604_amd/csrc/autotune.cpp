@@ -82,7 +82,8 @@ std::vector<Candidate> schedules(const Candidate& best, bool lds_fits) {
     return out;
 }
 
-// Whether a team of W walkers per tree keeps its trees in LDS on this graph (the sampler's rule).
+// Whether a team of W walkers per tree keeps its trees in LDS on this graph (the sampler's rule
+// for a single-graph call).
 bool lds_fits(const rwc_csr* g, int W, int64_t l) {
     return W > 1 && (64 / W) * round_up(g->n, 8) * 8 <= 48 * 1024 && l <= (int64_t{1} << 24);
 }

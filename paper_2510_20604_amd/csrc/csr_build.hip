@@ -375,21 +375,24 @@ __global__ void pick_pivot(int32_t n, const uint64_t* __restrict__ sfix, BuildSc
 // expands order[lo, hi) and appends newly reached nodes.  The order within a level follows
 // the atomics and is not reproducible; nothing that depends on it is observable except speed
 // (any start order yields the same forest).
-__global__ void bfs_init(int32_t n, int32_t pivot, int32_t* __restrict__ dist, int32_t* __restrict__ order,
-                         uint32_t* __restrict__ tail) {
-    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
-         u += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        dist[u] = (u == pivot) ? 0 : -1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        order[0] = pivot;
-        *tail = 1;
-    }
-}
+
+// The frontier bounds live on the device, so that levels can be launched back to back without a
+// host round trip each: the current level expands order[lo, hi); bfs_advance then moves to the
+// nodes appended meanwhile and stops the search (done) once a level adds nothing.
+struct BfsState {
+    uint32_t tail;    // nodes in the queue so far
+    uint32_t lo, hi;  // the current level's frontier
+    int32_t level;    // its distance from the pivot
+    int32_t done;     // no frontier left: further launches return at once
+    int32_t depth;    // largest distance reached
+};
 
 // One wave per frontier node, lanes over its neighbours (hub rows do not serialise a lane).
-__global__ void bfs_level(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t lo,
-                          int32_t hi, int32_t level, int32_t* __restrict__ dist, int32_t* __restrict__ order,
-                          uint32_t* __restrict__ tail) {
+__global__ void bfs_level(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                          int32_t* __restrict__ dist, int32_t* __restrict__ order, BfsState* st) {
+    if (st->done) return;
+    const uint32_t lo = st->lo, hi = st->hi;
+    const int32_t level = st->level;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
     const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
@@ -398,8 +401,32 @@ __global__ void bfs_level(const int32_t* __restrict__ row_ptr, const int32_t* __
         const int32_t end = row_ptr[u + 1];
         for (int32_t k = row_ptr[u] + lane; k < end; k += kWave) {
             const int32_t w = col[k];
-            if (dist[w] == -1 && atomicCAS(&dist[w], -1, level + 1) == -1) order[atomicAdd(tail, 1u)] = w;
+            if (dist[w] == -1 && atomicCAS(&dist[w], -1, level + 1) == -1) order[atomicAdd(&st->tail, 1u)] = w;
         }
+    }
+}
+
+__global__ void bfs_advance(BfsState* st) {
+    if (st->done) return;
+    const uint32_t t = st->tail;
+    if (t == st->hi) {
+        st->done = 1;
+        return;
+    }
+    st->lo = st->hi;
+    st->hi = t;
+    st->level += 1;
+    st->depth = st->level;
+}
+
+__global__ void bfs_init(int32_t n, int32_t pivot, int32_t* __restrict__ dist, int32_t* __restrict__ order,
+                         BfsState* st) {
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dist[u] = (u == pivot) ? 0 : -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        order[0] = pivot;
+        *st = BfsState{1u, 0u, 1u, 0, 0, 0};
     }
 }
 
@@ -472,7 +499,7 @@ struct BuildLayout {
     uint32_t* hist;
     uint32_t* sums;
     int32_t* parent;
-    uint32_t* tail;
+    BfsState* bfs;
     size_t total;
 };
 
@@ -500,7 +527,7 @@ BuildLayout carve_build(void* ws, int32_t n, int64_t m, bool weighted) {
     const int64_t scan_len = (256 * nb > n + 1) ? 256 * nb : n + 1;
     L.sums = c.take<uint32_t>(blocks_for(scan_len, kTile) + 1);
     L.parent = c.take<int32_t>(n);
-    L.tail = c.take<uint32_t>(1);
+    L.bfs = c.take<BfsState>(1);
     L.total = c.used();
     return L;
 }
@@ -612,25 +639,28 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     if (host.nroots != 1)
         return fail(RWC_ERR_DISCONNECTED, "the graph has %d connected components", host.nroots);
 
-    // breadth-first start order from the pivot (the union-find scratch holds the distances)
+    // breadth-first start order from the pivot (the union-find scratch holds the distances):
+    // levels are launched kBfsChunk at a time and the host looks once per chunk (a deep mesh's
+    // hundreds of levels cost a few round trips, not one each); levels past the last return
+    // at once
     hipLaunchKernelGGL(bfs_init, dim3(blocks_for(n, kBlock) < gs ? blocks_for(n, kBlock) : gs), dim3(kBlock), 0, s, n,
-                       host.pivot, L.parent, L.bfs_order, L.tail);
+                       host.pivot, L.parent, L.bfs_order, L.bfs);
     RWC_HIP(hipGetLastError());
-    uint32_t lo = 0, hi = 1;
-    int32_t depth = 0;
-    for (int32_t level = 0; hi < static_cast<uint32_t>(n); ++level) {
-        const unsigned wb = blocks_for(static_cast<int64_t>(hi - lo) * kWave, kBlock);
-        hipLaunchKernelGGL(bfs_level, dim3(wb < gs ? wb : gs), dim3(kBlock), 0, s, L.row_ptr, L.col, static_cast<int32_t>(lo), static_cast<int32_t>(hi),
-                           level, L.parent, L.bfs_order, L.tail);
+    constexpr int kBfsChunk = 32;
+    BfsState bs{};
+    for (int32_t launched = 0; !bs.done; launched += kBfsChunk) {
+        if (launched > n) return fail(RWC_ERR_HIP, "breadth-first search did not finish in %d levels", n);
+        for (int c = 0; c < kBfsChunk; ++c) {
+            hipLaunchKernelGGL(bfs_level, dim3(gs), dim3(kBlock), 0, s, L.row_ptr, L.col, L.parent, L.bfs_order, L.bfs);
+            hipLaunchKernelGGL(bfs_advance, dim3(1), dim3(1), 0, s, L.bfs);
+        }
         RWC_HIP(hipGetLastError());
-        uint32_t t = 0;
-        RWC_HIP(hipMemcpyAsync(&t, L.tail, sizeof(t), hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipMemcpyAsync(&bs, L.bfs, sizeof(bs), hipMemcpyDeviceToHost, s));
         RWC_HIP(hipStreamSynchronize(s));
-        if (t == hi) return fail(RWC_ERR_DISCONNECTED, "breadth-first search stopped at %u of %d nodes", t, n);
-        lo = hi;
-        hi = t;
-        depth = level + 1;
     }
+    if (bs.tail != static_cast<uint32_t>(n))
+        return fail(RWC_ERR_DISCONNECTED, "breadth-first search stopped at %u of %d nodes", bs.tail, n);
+    const int32_t depth = bs.depth;
 
     rwc_csr g{};
     g.n = n;

@@ -257,6 +257,17 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
     plan->total_nodes = plan->node_off[G];
     const int64_t l = p->num_samples;
     int64_t state_words = 0;
+    // LDS-resident trees run in a launch of their own before the HBM-state walk.  Measured: a
+    // single small graph gains (ER(1000), 2000 trees: walk 2.64 -> 1.84 ms), but in a batch that
+    // also holds larger graphs the two launches cannot overlap and the LDS launch's tail idles
+    // the device (256 mixed graphs: the batch autotuner picks HBM state), so a call uses LDS
+    // state only when every graph's trees fit.
+    bool all_fit = !(p->flags & RWC_SAMPLE_NO_LDS_STATE) && l <= kLdsMaxSamples;
+    for (int32_t g = 0; g < G && all_fit; ++g) {
+        const int Wg = p->walkers_per_graph ? p->walkers_per_graph[g]
+                       : (p->walkers_per_tree > 0) ? p->walkers_per_tree : auto_walkers(graphs[g].n);
+        all_fit = Wg > 1 && (kWave / Wg) * round_up(graphs[g].n, 8) * 8 <= kLdsStateBytes;
+    }
     for (int32_t g = 0; g < G; ++g) {
         const int64_t n = graphs[g].n;
         const int W = p->walkers_per_graph ? p->walkers_per_graph[g]
@@ -272,11 +283,10 @@ int make_plan(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, Plan
         plan->T[g] = static_cast<int32_t>(T);
         plan->stride[g] = round_up(n, 8);
         plan->team = plan->team || W > 1;
-        // trees in LDS when a wave's trees fit (walker teams only), unless the caller forbids it
-        // (the work items of LDS graphs list every block of samples, so very long sample
-        // ranges keep their trees in HBM slots)
-        const bool fits = W > 1 && S * plan->stride[g] * 8 <= kLdsStateBytes && l <= kLdsMaxSamples;
-        if (fits && !(p->flags & RWC_SAMPLE_NO_LDS_STATE)) {
+        // trees in LDS when every graph's wave of trees fits (walker teams only), unless the
+        // caller forbids it (the work items of LDS graphs list every block of samples, so very
+        // long sample ranges keep their trees in HBM slots)
+        if (all_fit) {
             plan->lds[g] = 1;
             plan->T[g] = 0;
             plan->lds_words = std::max<int64_t>(plan->lds_words, S * plan->stride[g]);

@@ -124,12 +124,15 @@ def test_batch256_every_tree_matches_oracle(batch256, chunk):
 # (k = 64) against the oracle's sparse evaluation stored in tests/golden.
 # ---------------------------------------------------------------------------------------
 RMAT_CHUNKS = 3
-# Adjoint tolerance, relative to the largest stored gradient magnitude.  Both sides stop each
-# solve at relative residual 1e-11 (the GPU with FP32 search directions but FP64 residuals, so
-# its stopping test is as strict as the oracle's); the error of a solution is then bounded by
-# cond(L_v) * 1e-11 relative, and the gradient takes differences of solution entries scaled by
-# vol.  Same bound as the BA(1e5) sampled-edge test of the adjoint.
-RMAT_ADJOINT_TOL = 1e-6
+# Adjoint tolerances.  Both sides stop each solve at relative residual 1e-11 (the GPU with FP32
+# search directions but FP64 residuals, so its stopping test is as strict as the oracle's).
+# The gradient here is dominated by its common term 2 trGL^ (about 437.8 at every edge); the
+# edge-specific part varies by about 1.6 over the stored edges.  The solution error is at most
+# cond(L_v) * 1e-11 relative; measured, the two sides agree to 7e-15 of max |grad| and to 2e-12
+# of the edge-specific spread, so the bounds below keep three orders of magnitude of margin on
+# both: the full value to 1e-11 of max |grad|, the edge-specific part to 1e-9 of its spread.
+RMAT_ADJOINT_TOL = 1e-11
+RMAT_ADJOINT_CENTRED_TOL = 1e-9
 
 
 @pytest.fixture(scope="module")
@@ -193,7 +196,8 @@ def _rmat23_adjoint_fixture():
 
 def test_rmat23_adjoint_matches_oracle_fixture(rmat23):
     """The adjoint for 1000 targets (g = 1, k = 64 probes, probe seed 2006) at the 24 edges the
-    oracle evaluated (tests/golden/make_rmat23_adjoint.py: sparse CG solves to 1e-11)."""
+    oracle evaluated (tests/golden/make_rmat23_adjoint.py: sparse CG solves to 1e-11), in full
+    and with the common term taken out."""
     r = rmat23
     g = r["g"]
     edges, a, b, want = _rmat23_adjoint_fixture()
@@ -210,6 +214,7 @@ def test_rmat23_adjoint_matches_oracle_fixture(rmat23):
           f"({err.max() / scale:.3e} of max |grad|), centred max |err| = {cen.max():.3e} "
           f"(spread {np.ptp(want):.3e})")
     assert err.max() <= RMAT_ADJOINT_TOL * scale
+    assert cen.max() <= RMAT_ADJOINT_CENTRED_TOL * np.ptp(want)
     assert np.isfinite(grad).all()
     assert abs(np.dot(g.w, grad)) <= 1e-6 * np.abs(g.w * grad).sum()
 
