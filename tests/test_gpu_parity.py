@@ -358,3 +358,26 @@ def test_batch_autotuner_choice_does_not_change_the_forests():
             np.testing.assert_array_equal(counts[off:off + g.n], ref["visits"])
             np.testing.assert_array_equal(_u64(tuned["tree_hash"][i]), ref["hash"])
         off += g.n
+
+
+@pytest.mark.parametrize("shape", ["star", "bipartite"])
+def test_csr_rejects_fixed_point_overflow(shape):
+    """Weights near the top of the accepted range on long rows: a star whose centre row passes
+    2^64 in fixed point (the row carry saturates instead of wrapping), and a complete bipartite
+    graph K(2048, 4100) whose rows all stay below 2^53 but whose total passes 2^64 (the volume
+    check).  Both are refused with RWC_ERR_WEIGHT_RANGE."""
+    if shape == "star":
+        leaves = (1 << 24) + (1 << 18)
+        src = np.zeros(leaves, dtype=np.int32)
+        dst = np.arange(1, leaves + 1, dtype=np.int32)
+        n = leaves + 1
+    else:
+        a, b = 2048, 4100
+        src = np.repeat(np.arange(a, dtype=np.int32), b)
+        dst = (a + np.tile(np.arange(b, dtype=np.int32), a)).astype(np.int32)
+        n = a + b
+    w = np.full(src.shape[0], 65535.99609375, dtype=np.float32)    # the largest float32 below 65536
+    assert float(w[0]) < 65536.0
+    with pytest.raises(P.RWCError) as ei:
+        P.Graph(n, src, dst, w)
+    assert ei.value.status == -5
