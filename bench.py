@@ -26,6 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "rooted trees/s + walk steps/s at fixed RWC rel. error; plain vs batched; grad edges/s"
+# The paper's own measurements, for context only: it publishes accuracy and wall-clock plots but
+# no trees/s or walk steps/s, on other graphs and hardware.
+PAPER_CONTEXT = {"hardware": "Intel Xeon Gold 6240 @ 2.60 GHz, one thread, Julia, 256 GB",
+                 "throughput": None,
+                 "note": "no trees/s or walk steps/s published; on a graph of over 10 M nodes FastWalk reaches "
+                         "0.5 % MRE in somewhat more than the ~4000 s its incomplete-Cholesky method needs for "
+                         "3 % (Introduction)"}
 HBM_PEAK_GBS = 8000.0
 # HBM byte counters of the walk kernel, per workload, taken with rocprofv3 (FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters on a plain copy kernel); valid only for the walk
@@ -73,7 +80,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="rmat23",
-                    choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k", "trap"])
+                    choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k", "trap", "group"])
     ap.add_argument("--no-extras", action="store_true",
                     help="rmat23: skip the BA(1e6) and BA(1e5)-adjoint side measurements")
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
@@ -464,6 +471,7 @@ def rmat_main(args):
     if not args.no_cpu_baseline:
         cb, _ = cpu_baseline(g, l, seed, args.cpu_seconds, single_seconds=args.cpu_seconds * 0.67)
         line["cpu_baseline"] = cb
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
 
@@ -540,6 +548,51 @@ def trap_main(args):
     print(json.dumps(line), flush=True)
 
 
+def group_main(args):
+    """Group RWC (root sets): BA(1e6, 5), unit weights, S = the 16 nodes of largest degree; one
+    step = CSR build + 10^4 spanning forests rooted at S + the group estimate (H_S and H_{S+u}
+    for every u)."""
+    import torch
+    import paper_2510_20604_amd as P
+    g, _, seed, _ = workload("ba1m")
+    l = args.trees or 10_000
+    dev = torch.device("cuda:0")
+    src, dst = torch.as_tensor(g.src).to(dev), torch.as_tensor(g.dst).to(dev)
+    deg = np.bincount(np.concatenate([g.src, g.dst]), minlength=g.n)
+    roots = np.sort(np.argsort(-deg, kind="stable")[:16]).astype(np.int32)
+    ws = {}
+
+    def step():
+        G = P.Graph(g.n, src, dst, None, dev)
+        s = P.sample_forests(G, l, seed, roots=roots, want_sq=False, want_hash=False, workspace=ws.get("s"),
+                             timing=True)
+        ws["s"] = s["workspace"]
+        e = P.estimate_group(G, roots, s["counts"], l)
+        return s, e
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walk_ms = []
+    for _ in range(args.steps):
+        s, e = step()
+        walk_ms.append(s["walk_ms"])
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    steps = int(P.as_uint64(s["total_steps"])[0])
+    line = {"metric": METRIC, "value": round(l / el, 3), "unit": "forests/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(1e3 * el, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64/f64", "data": "synthetic",
+            "config": {"workload": "BA(n=1e6, m=5) unit weights, 1e4 forests rooted at the 16 nodes of largest "
+                                   "degree, group estimate", "n": g.n, "m": g.m, "roots": len(roots),
+                       "walkers_per_tree": s["walkers_per_tree"], "walk_kernel": s["walk_kernel"]},
+            "walk_steps_per_s": round(steps / el, 1), "walk_steps_per_forest": steps / l,
+            "sampler_forests_per_s": round(l / (np.mean(walk_ms) * 1e-3), 3),
+            "group_rwc": float(e["group_rwc"][0]), "best_addition": int(torch.argmin(e["marginal"]))}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -555,6 +608,8 @@ def main():
         return batch_main(args)
     if args.config == "trap":
         return trap_main(args)
+    if args.config == "group":
+        return group_main(args)
     import torch
     import paper_2510_20604_amd as P
     from paper_2510_20604_amd import _lib
