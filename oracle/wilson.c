@@ -67,13 +67,79 @@ static uint64_t splitmix64(uint64_t z) {
 
 uint64_t oracle_splitmix64(uint64_t z) { return splitmix64(z); }
 
-static int64_t random_neighbor(int64_t u, uint32_t k, uint64_t sample, uint32_t graph, uint64_t seed,
-                               const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf) {
+/*
+ * Stratified stack entries (Latin hypercube sampling over the samples, McKay, Beckman and
+ * Conover 1979).  With L = strata >= 2 and samples 0 .. L-1, the word of stack entry (u, k) in
+ * sample i lies in stratum sigma(i) of [0, 2^64), where sigma is a permutation of 0 .. L-1
+ * drawn for that entry alone:
+ *   x     = the word above, from Philox on (k, u, i, g)
+ *   a     = Philox4x32-10 on (k, u, 2^32 - 1, g): four round keys of a Feistel network P on
+ *           [0, 4^h), h = max(1, ceil(ceil(log2 L) / 2)), round t: (l, r) -> (r, l xor
+ *           (fmix32(r xor a_t) mod 2^h)), output l * 2^h + r
+ *   pi(i) = P(i), P applied again while the result is >= L (cycle walking, a permutation)
+ *   s     = floor(b * L / 2^64), b = words 0, 1 of Philox4x32-10 on (k, u, 2^32 - 2, g)
+ *   sigma = (pi(i) + s) mod L
+ *   word  = sigma * M + floor(x * M / 2^64),  M = floor(2^64 / L)
+ * For one sample the entries stay independent and (up to the 2^-64 grid) uniform, because
+ * the shift s alone makes sigma(i) uniform; so every tree is still a Wilson tree.  Across the
+ * L samples each entry visits every stratum once, which removes the additive part of the
+ * variance of the mean count.  fmix32 is the 32-bit finaliser of MurmurHash3 (Appleby).
+ */
+static uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+static uint64_t feistel4(uint64_t x, int half, const uint32_t key[4]) {
+    const uint64_t mask = ((uint64_t)1 << half) - 1;
+    uint64_t left = x >> half, right = x & mask;
+    for (int t = 0; t < 4; ++t) {
+        const uint64_t f = (uint64_t)fmix32((uint32_t)right ^ key[t]) & mask;
+        const uint64_t nl = right;
+        right = left ^ f;
+        left = nl;
+    }
+    return (left << half) | right;
+}
+
+/* The 64-bit word of the k-th departure from u in sample `sample` of graph `graph`. */
+static uint64_t stack_word(uint32_t k, int64_t u, uint64_t sample, uint32_t graph, uint64_t seed, uint64_t strata) {
     uint32_t ctr[4] = {k, (uint32_t)u, (uint32_t)sample, graph};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t o[4];
     oracle_philox4x32_10(ctr, key, o);
     const uint64_t x = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+    if (strata < 2) return x;
+    uint32_t a[4], b[4];
+    ctr[2] = 0xFFFFFFFFu;
+    oracle_philox4x32_10(ctr, key, a);
+    ctr[2] = 0xFFFFFFFEu;
+    oracle_philox4x32_10(ctr, key, b);
+    int bits = 0;
+    while (((uint64_t)1 << bits) < strata) ++bits;
+    const int half = bits < 2 ? 1 : (bits + 1) / 2;
+    uint64_t y = sample;
+    do {
+        y = feistel4(y, half, a);
+    } while (y >= strata);
+    const uint64_t bw = (uint64_t)b[0] | ((uint64_t)b[1] << 32);
+    const uint64_t shift = (uint64_t)(((u128)bw * (u128)strata) >> 64);
+    const uint64_t stratum = (y + shift) % strata;
+    const uint64_t width = (uint64_t)((((u128)1) << 64) / (u128)strata);
+    return stratum * width + (uint64_t)(((u128)x * (u128)width) >> 64);
+}
+
+uint64_t oracle_stack_word(uint32_t k, int64_t u, uint64_t sample, uint32_t graph, uint64_t seed, uint64_t strata) {
+    return stack_word(k, u, sample, graph, seed, strata);
+}
+
+static int64_t random_neighbor(int64_t u, uint32_t k, uint64_t sample, uint32_t graph, uint64_t seed,
+                               uint64_t strata, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf) {
+    const uint64_t x = stack_word(k, u, sample, graph, seed, strata);
     const int64_t beg = row_ptr[u], end = row_ptr[u + 1];
     const uint64_t deg = (uint64_t)(end - beg);
     int64_t pick;
@@ -91,7 +157,13 @@ static int64_t random_neighbor(int64_t u, uint32_t k, uint64_t sample, uint32_t 
 /* RandomNeighbor on its own, exported so that tests can check the selection law. */
 int64_t oracle_random_neighbor(int64_t u, uint32_t k, uint64_t sample, uint32_t graph, uint64_t seed,
                                const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf) {
-    return random_neighbor(u, k, sample, graph, seed, row_ptr, col, cdf);
+    return random_neighbor(u, k, sample, graph, seed, 0, row_ptr, col, cdf);
+}
+
+int64_t oracle_random_neighbor_stratified(int64_t u, uint32_t k, uint64_t sample, uint32_t graph, uint64_t seed,
+                                          uint64_t strata, const int64_t* row_ptr, const int32_t* col,
+                                          const uint64_t* cdf) {
+    return random_neighbor(u, k, sample, graph, seed, strata, row_ptr, col, cdf);
 }
 
 /*
@@ -107,14 +179,14 @@ int64_t oracle_random_neighbor(int64_t u, uint32_t k, uint64_t sample, uint32_t 
  * Returns the number of RandomNeighbor calls, or UINT64_MAX when max_steps is exceeded.
  */
 static uint64_t grow_forest(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf,
-                            uint64_t seed, uint32_t graph, uint64_t sample, const int32_t* order, uint64_t max_steps,
-                            unsigned char* in_tree, int64_t* next, uint32_t* dep) {
+                            uint64_t seed, uint32_t graph, uint64_t sample, uint64_t strata, const int32_t* order,
+                            uint64_t max_steps, unsigned char* in_tree, int64_t* next, uint32_t* dep) {
     uint64_t calls = 0;
     for (int64_t jj = 0; jj < n; ++jj) {
         const int64_t j = order ? (int64_t)order[jj] : jj;
         /* the walk: one departure per step, the arrow of the latest departure kept */
         for (int64_t u = j; !in_tree[u]; u = next[u]) {
-            next[u] = random_neighbor(u, dep[u], sample, graph, seed, row_ptr, col, cdf);
+            next[u] = random_neighbor(u, dep[u], sample, graph, seed, strata, row_ptr, col, cdf);
             dep[u] += 1;
             if (++calls > max_steps) return UINT64_MAX;
         }
@@ -137,11 +209,12 @@ static uint64_t grow_forest(int64_t n, const int64_t* row_ptr, const int32_t* co
  * Returns 0, or -1 bad argument, -2 out of memory, -4 a sample needed more than max_steps
  * RandomNeighbor calls.
  */
-int oracle_fastwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf,
+static int fastwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf,
                     const int64_t* roots, int64_t nroots, uint64_t seed, uint32_t graph, int64_t sample_begin,
-                    int64_t nsamples, const int32_t* order, uint64_t max_steps, uint64_t* visits, uint64_t* visits_sq,
-                    uint64_t* steps, uint64_t* hash, int32_t* parents) {
+                    int64_t nsamples, uint64_t strata, const int32_t* order, uint64_t max_steps, uint64_t* visits,
+                    uint64_t* visits_sq, uint64_t* steps, uint64_t* hash, int32_t* parents) {
     if (n < 1 || nroots < 1 || nroots >= n + 1 || nsamples < 0 || sample_begin < 0) return -1;
+    if (strata >= 2 && (strata > ((uint64_t)1 << 31) || (uint64_t)(sample_begin + nsamples) > strata)) return -1;
     for (int64_t r = 0; r < nroots; ++r)
         if (roots[r] < 0 || roots[r] >= n) return -1;
     unsigned char* is_root = (unsigned char*)calloc((size_t)n, 1);
@@ -161,8 +234,8 @@ int oracle_fastwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const
             next[u] = -1;
             dep[u] = 0;
         }
-        const uint64_t calls = grow_forest(n, row_ptr, col, cdf, seed, graph, sample, order, max_steps, in_tree,
-                                           next, dep);
+        const uint64_t calls = grow_forest(n, row_ptr, col, cdf, seed, graph, sample, strata, order, max_steps,
+                                           in_tree, next, dep);
         if (calls == UINT64_MAX) {
             rc = -4;
             break;
@@ -179,6 +252,25 @@ int oracle_fastwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const
     }
     free(is_root); free(in_tree); free(next); free(dep);
     return rc;
+}
+
+int oracle_fastwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf,
+                    const int64_t* roots, int64_t nroots, uint64_t seed, uint32_t graph, int64_t sample_begin,
+                    int64_t nsamples, const int32_t* order, uint64_t max_steps, uint64_t* visits, uint64_t* visits_sq,
+                    uint64_t* steps, uint64_t* hash, int32_t* parents) {
+    return fastwalk(n, row_ptr, col, cdf, roots, nroots, seed, graph, sample_begin, nsamples, 0, order, max_steps,
+                    visits, visits_sq, steps, hash, parents);
+}
+
+/* The same with stratified stack entries over samples 0 .. strata - 1 (strata <= 2^31, the
+ * run's samples inside that range; strata < 2 is the plain sampler). */
+int oracle_fastwalk_stratified(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf,
+                               const int64_t* roots, int64_t nroots, uint64_t seed, uint32_t graph,
+                               int64_t sample_begin, int64_t nsamples, uint64_t strata, const int32_t* order,
+                               uint64_t max_steps, uint64_t* visits, uint64_t* visits_sq, uint64_t* steps,
+                               uint64_t* hash, int32_t* parents) {
+    return fastwalk(n, row_ptr, col, cdf, roots, nroots, seed, graph, sample_begin, nsamples, strata, order,
+                    max_steps, visits, visits_sq, steps, hash, parents);
 }
 
 /*

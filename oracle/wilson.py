@@ -36,6 +36,16 @@ def _load():
         lib.oracle_fastwalk.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int64, ctypes.c_uint64,
                                         ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, P,
                                         ctypes.c_uint64, P, P, P, P, P]
+        lib.oracle_fastwalk_stratified.restype = ctypes.c_int
+        lib.oracle_fastwalk_stratified.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int64, ctypes.c_uint64,
+                                                   ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                                   P, ctypes.c_uint64, P, P, P, P, P]
+        lib.oracle_stack_word.restype = ctypes.c_uint64
+        lib.oracle_stack_word.argtypes = [ctypes.c_uint32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_random_neighbor_stratified.restype = ctypes.c_int64
+        lib.oracle_random_neighbor_stratified.argtypes = [ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
+                                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P, P]
         lib.oracle_philox4x32_10.restype = None
         lib.oracle_philox4x32_10.argtypes = [P, P, P]
         lib.oracle_random_neighbor.restype = ctypes.c_int64
@@ -107,10 +117,20 @@ def philox4x32_10(ctr, key) -> tuple[int, int, int, int]:
     return tuple(int(x) for x in o)
 
 
-def random_neighbor(g: OracleCSR, u: int, k: int, sample: int, graph: int, seed: int) -> int:
-    """The neighbour chosen at the k-th departure from u in sample `sample`."""
+def random_neighbor(g: OracleCSR, u: int, k: int, sample: int, graph: int, seed: int, strata: int = 0) -> int:
+    """The neighbour chosen at the k-th departure from u in sample `sample` (stack entries
+    stratified over samples [0, strata) when strata >= 2)."""
+    if strata >= 2:
+        return int(_load().oracle_random_neighbor_stratified(u, k, sample, graph, seed, strata, _ptr(g.row_ptr),
+                                                             _ptr(g.col), _ptr(g.cdf)))
     return int(_load().oracle_random_neighbor(u, k, sample, graph, seed, _ptr(g.row_ptr), _ptr(g.col),
                                               _ptr(g.cdf)))
+
+
+def stack_word(k: int, u: int, sample: int, graph: int, seed: int, strata: int = 0) -> int:
+    """The 64-bit word of stack entry (u, k) in sample `sample`: the Philox word, or with
+    strata >= 2 its Latin-hypercube placement (stratum sigma(sample) of L = strata)."""
+    return int(_load().oracle_stack_word(k, u, sample, graph, seed & ((1 << 64) - 1), strata))
 
 
 def splitmix64(z: int) -> int:
@@ -119,11 +139,12 @@ def splitmix64(z: int) -> int:
 
 def fastwalk_sample(g: OracleCSR, root, seed: int, graph: int, sample_begin: int, nsamples: int,
                     order=None, want_parents: bool = False, threads: int = 1,
-                    max_steps: int = (1 << 62)) -> dict:
+                    max_steps: int = (1 << 62), strata: int = 0) -> dict:
     """Run samples [sample_begin, sample_begin + nsamples) serially (or split over threads,
     each thread running a contiguous sample sub-range; sums are integers, so the split does
     not change any output).  `root` is one node (a rooted spanning tree per sample) or a
-    sequence of distinct nodes (a spanning forest rooted at that set)."""
+    sequence of distinct nodes (a spanning forest rooted at that set).  strata >= 2 stratifies
+    every stack entry over samples [0, strata) (Latin hypercube), which must hold the run."""
     lib = _load()
     n = g.n
     roots = np.ascontiguousarray(np.atleast_1d(np.asarray(root, dtype=np.int64)))
@@ -140,9 +161,9 @@ def fastwalk_sample(g: OracleCSR, root, seed: int, graph: int, sample_begin: int
         v = np.zeros(n, dtype=np.uint64)
         v2 = np.zeros(n, dtype=np.uint64)
         par = parents[lo:hi] if parents is not None else None
-        rc = lib.oracle_fastwalk(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.cdf), _ptr(roots), roots.size, seed, graph,
-                                 sample_begin + lo, hi - lo, _ptr(ordr), max_steps, _ptr(v), _ptr(v2),
-                                 _ptr(steps[lo:hi]), _ptr(hsh[lo:hi]), _ptr(par))
+        rc = lib.oracle_fastwalk_stratified(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.cdf), _ptr(roots), roots.size,
+                                            seed, graph, sample_begin + lo, hi - lo, strata, _ptr(ordr), max_steps,
+                                            _ptr(v), _ptr(v2), _ptr(steps[lo:hi]), _ptr(hsh[lo:hi]), _ptr(par))
         if rc != 0:
             raise RuntimeError(f"oracle_fastwalk failed with code {rc}")
         return v, v2

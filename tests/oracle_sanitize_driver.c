@@ -1,7 +1,7 @@
 /* Runs the serial oracle (oracle/wilson.c) on small graphs so that a build with the address and
  * undefined-behaviour sanitizers can check its memory accesses and arithmetic: rooted trees and
- * root-set forests on a weighted and an unweighted graph, every output requested, and the trap
- * walks.  Exits 0 when every call returns 0. */
+ * root-set forests on a weighted and an unweighted graph, every output requested, stratified
+ * stack entries, and the trap walks.  Exits 0 when every call returns 0. */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -10,6 +10,11 @@ int oracle_fastwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const
                     const int64_t* roots, int64_t nroots, uint64_t seed, uint32_t graph, int64_t sample_begin,
                     int64_t nsamples, const int32_t* order, uint64_t max_steps, uint64_t* visits, uint64_t* visits_sq,
                     uint64_t* steps, uint64_t* hash, int32_t* parents);
+int oracle_fastwalk_stratified(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf,
+                               const int64_t* roots, int64_t nroots, uint64_t seed, uint32_t graph,
+                               int64_t sample_begin, int64_t nsamples, uint64_t strata, const int32_t* order,
+                               uint64_t max_steps, uint64_t* visits, uint64_t* visits_sq, uint64_t* steps,
+                               uint64_t* hash, int32_t* parents);
 int oracle_trapwalk(int64_t n, const int64_t* row_ptr, const int32_t* col, const uint64_t* cdf, int64_t v,
                     uint64_t seed, uint32_t graph, int64_t walk_begin, int64_t nwalks, uint64_t max_steps,
                     uint64_t* visits, uint64_t* visits_sq, uint64_t* steps);
@@ -46,6 +51,10 @@ int main(void) {
                           parents);
     rc |= oracle_fastwalk(N, row_ptr, col, cdf, set, 3, 6, 1, 3, 8, order, 1ull << 40, visits, visits_sq, steps, hash,
                           parents);
+    rc |= oracle_fastwalk_stratified(N, row_ptr, col, cdf, one, 1, 9, 0, 5, 8, 13, NULL, 1ull << 40, visits,
+                                     visits_sq, steps, hash, parents);
+    rc |= oracle_fastwalk_stratified(N, row_ptr, col, NULL, set, 3, 10, 0, 0, 8, 1u << 31, order, 1ull << 40,
+                                     visits, visits_sq, steps, hash, parents);
     uint64_t total = 0;
     rc |= oracle_trapwalk(N, row_ptr, col, cdf, 14, 7, 2, 0, 5, 1ull << 40, visits, visits_sq, &total);
     rc |= oracle_trapwalk(N, row_ptr, col, NULL, 0, 8, 2, 4, 3, 1ull << 40, visits, NULL, &total);

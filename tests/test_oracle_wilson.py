@@ -250,7 +250,7 @@ def test_estimate_accuracy_er1000():
 
 
 # ------------------------------------------------------------ cycle popping -----------
-def _cycle_popping(csr, roots, seed, graph, sample):
+def _cycle_popping(csr, roots, seed, graph, sample, strata=0):
     """Wilson's cycle-popping construction, written independently of the walk: node u's k-th
     arrow is the neighbour RandomNeighbor chooses at its k-th departure; while the current top
     arrows of the non-root nodes contain a cycle, pop it (every node on it moves to its next
@@ -262,7 +262,7 @@ def _cycle_popping(csr, roots, seed, graph, sample):
     cur = np.full(n, -1, dtype=np.int64)
     for u in range(n):
         if not is_root[u]:
-            cur[u] = W.random_neighbor(csr, u, 0, sample, graph, seed)
+            cur[u] = W.random_neighbor(csr, u, 0, sample, graph, seed, strata)
     while True:
         state = np.zeros(n, dtype=np.int8)      # 0 unseen, 1 on the current chain, 2 done
         cycles = []
@@ -284,24 +284,25 @@ def _cycle_popping(csr, roots, seed, graph, sample):
         for cyc in cycles:                              # disjoint: pop them all
             for u in cyc:
                 top[u] += 1
-                cur[u] = W.random_neighbor(csr, u, int(top[u]), sample, graph, seed)
+                cur[u] = W.random_neighbor(csr, u, int(top[u]), sample, graph, seed, strata)
     dep = np.where(is_root, 0, top + 1).astype(np.uint64)
     par = np.where(is_root, -1, cur).astype(np.int32)
     return dep, par
 
 
-@pytest.mark.parametrize("roots", [None, (0, 7), (3, 11, 19, 25)])
-def test_walks_equal_cycle_popping(roots):
+@pytest.mark.parametrize("roots,strata", [(None, 0), ((0, 7), 0), ((3, 11, 19, 25), 0), (None, 24), ((0, 7), 24)])
+def test_walks_equal_cycle_popping(roots, strata):
     """The oracle's loop-erased walks pop exactly the cycles of the stack picture: same forest,
-    same departure count at every node, for one root and for root sets."""
+    same departure count at every node, for one root and for root sets, with independent or
+    stratified stack entries."""
     g = G.erdos_renyi_lcc(30, 4, 12)
     g = g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 13))
     csr = W.OracleCSR(g.n, g.src, g.dst, g.w)
     S = [csr.pivot] if roots is None else list(roots)
-    r = W.fastwalk_sample(csr, S if roots else csr.pivot, 404, 2, 10, 12, want_parents=True)
+    r = W.fastwalk_sample(csr, S if roots else csr.pivot, 404, 2, 10, 12, want_parents=True, strata=strata)
     tot = np.zeros(g.n, dtype=np.uint64)
     for s in range(12):
-        dep, par = _cycle_popping(csr, S, 404, 2, 10 + s)
+        dep, par = _cycle_popping(csr, S, 404, 2, 10 + s, strata)
         np.testing.assert_array_equal(r["parents"][s], par)
         assert int(r["steps"][s]) == int(dep.sum())
         tot += dep
