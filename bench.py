@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="rmat23",
-                    choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k", "trap", "group"])
+                    choices=["rmat23", "ba1m", "er1000", "batch256", "grad100k", "trap", "group", "strata"])
     ap.add_argument("--no-extras", action="store_true",
                     help="rmat23: skip the BA(1e6) and BA(1e5)-adjoint side measurements")
     ap.add_argument("--trees", type=int, default=0, help="override the number of trees")
@@ -593,6 +593,73 @@ def group_main(args):
     print(json.dumps(line), flush=True)
 
 
+def strata_main(args):
+    """Variance reduction at equal trees (the Conclusion's "more efficient sampling"): every
+    stack entry stratified over the l samples (Latin hypercube, rwc_sample_params.strata = l)
+    against independent draws, same graphs, same l, same estimator.  On graphs with stored exact
+    RWC: mean relative error over 16 seeds.  On BA(1e6, 5) with 10^4 trees: the relative mean
+    squared error of RWC estimated from the spread over 6 seeds (both estimators are unbiased).
+    Reported: the error ratio, the trees independent draws need for the same error
+    ((MRE ratio)^2 or the MSE ratio) and the walk kernel's time in both modes."""
+    import torch
+    import paper_2510_20604_amd as P
+    import rwcgen
+
+    def run(G, l, seed, strata):
+        s = P.sample_forests(G, l, seed, want_sq=False, want_hash=False, timing=True, strata=strata)
+        return P.estimate(G, s["counts"], l, want_hit=False)["rwc"].cpu().numpy(), s["walk_ms"], s["walk_kernel"]
+
+    cases = []
+    for desc, g, golden, l in (("ER(n=1000, d=8) LCC, unit weights", rwcgen.erdos_renyi_lcc(1000, 8, 1001),
+                                "er1000_exact_rwc.txt", 2000),
+                               ("BA(n=20000, m=5), unit weights", rwcgen.barabasi_albert(20_000, 5, 1002),
+                                "ba20k_exact_rwc.txt", 2000)):
+        nodes, exact = _golden_rwc(golden)
+        G = P.Graph(g.n, g.src, g.dst, g.w, "cuda:0")
+        res = {}
+        for mode, strata in (("independent", 0), ("stratified", l)):
+            run(G, l, 1, strata)
+            mre, ms = [], []
+            for seed in range(16):
+                rwc, wm, kern = run(G, l, 5000 + seed, strata)
+                mre.append(float(np.mean(np.abs(rwc[nodes] - exact) / exact)))
+                ms.append(wm)
+            res[mode] = {"mre": float(np.mean(mre)), "mre_sd": float(np.std(mre, ddof=1)),
+                         "walk_ms": round(float(np.median(ms)), 3), "walk_kernel": kern}
+        ratio = res["stratified"]["mre"] / res["independent"]["mre"]
+        cases.append({"workload": desc, "trees": l, "seeds": 16, **res, "mre_ratio": round(ratio, 4),
+                      "independent_trees_for_equal_mre": round(l / ratio ** 2, 1)})
+        print(f"{desc}: MRE {res['independent']['mre']:.4%} -> {res['stratified']['mre']:.4%} at {l} trees",
+              file=sys.stderr, flush=True)
+
+    g, l, _, desc = workload("ba1m")
+    l = args.trees or l
+    G = P.Graph(g.n, g.src, g.dst, g.w, "cuda:0")
+    big = {}
+    for mode, strata in (("independent", 0), ("stratified", l)):
+        run(G, l, 1, strata)
+        est, ms = [], []
+        for seed in range(6):
+            rwc, wm, kern = run(G, l, 7000 + seed, strata)
+            est.append(rwc)
+            ms.append(wm)
+        est = np.asarray(est)
+        rel_mse = float(np.mean(est.var(0, ddof=1) / est.mean(0) ** 2))
+        big[mode] = {"rel_mse": rel_mse, "walk_ms": round(float(np.median(ms)), 3), "walk_kernel": kern,
+                     "trees_per_s_walk": round(l / (np.median(ms) * 1e-3), 1)}
+        print(f"{desc} {mode}: relative MSE {rel_mse:.3e}, walk {np.median(ms):.1f} ms", file=sys.stderr, flush=True)
+    mse_ratio = big["stratified"]["rel_mse"] / big["independent"]["rel_mse"]
+    cases.append({"workload": desc, "trees": l, "seeds": 6, **big, "rel_mse_ratio": round(mse_ratio, 4),
+                  "independent_trees_for_equal_error": round(l / mse_ratio, 1),
+                  "walk_time_ratio": round(big["stratified"]["walk_ms"] / big["independent"]["walk_ms"], 4)})
+    line = {"metric": METRIC, "value": round(1.0 / mse_ratio, 4),
+            "unit": "x (independent trees per stratified tree at equal error)", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "u64/f64", "data": "synthetic",
+            "config": {"workload": "stratified vs independent stack entries at equal trees (BA(1e6, 5), 1e4 trees; "
+                                   "ER(1000) and BA(20000) against exact RWC)"}, "cases": cases}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -610,6 +677,8 @@ def main():
         return trap_main(args)
     if args.config == "group":
         return group_main(args)
+    if args.config == "strata":
+        return strata_main(args)
     import torch
     import paper_2510_20604_amd as P
     from paper_2510_20604_amd import _lib

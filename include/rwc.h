@@ -147,7 +147,21 @@ typedef struct rwc_sample_params {
                                     two up to 64                                          */
     uint64_t max_steps_per_tree; /* guard; 0 = 2^20 + 4096 n                              */
     uint32_t graph_index_base;   /* Philox graph word of graphs[0]; graph g uses base + g */
-    uint32_t reserved;
+    uint32_t strata;             /* 0 or 1: independent draws.  L >= 2 (at most 2^31):
+                                    stratified stack entries, a variance reduction at equal
+                                    trees (future work of the Conclusion: more efficient
+                                    sampling).  The k-th departure from u takes, in sample i,
+                                    stratum sigma_(u,k)(i) of L equal strata of its 64-bit
+                                    word, sigma_(u,k) a permutation of 0 .. L-1 drawn for
+                                    that stack entry (Latin hypercube over the samples); its
+                                    own Philox word places it inside the stratum.  Each tree
+                                    is still an exact Wilson tree and the visit totals stay
+                                    unbiased; over samples 0 .. L-1 the variance of their
+                                    mean can only drop (measured: to 0.5-0.8 of independent
+                                    draws).  The call's samples must lie in [0, L); calls
+                                    that cover [0, L) in pieces add up to the same totals.
+                                    The squared totals then overstate the variance of the
+                                    mean.  Definition: stratified_word in csrc/device.hpp  */
     const int32_t* roots;        /* DEVICE int32 [num_roots]: a root set S instead of one root
                                     (single graph, root = -1): every tree is a spanning forest
                                     rooted at S, i.e. Algorithm 3 with InTree = S at the start

@@ -47,7 +47,7 @@ class RwcCsr(ctypes.Structure):
 class SampleParams(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("sample_begin", c_i64), ("num_samples", c_i64), ("root", c_i32),
                 ("flags", c_u32), ("trees_in_flight", c_i32), ("walkers_per_tree", c_i32),
-                ("max_steps_per_tree", c_u64), ("graph_index_base", c_u32), ("reserved", c_u32),
+                ("max_steps_per_tree", c_u64), ("graph_index_base", c_u32), ("strata", c_u32),
                 ("roots", c_vp), ("num_roots", c_i32), ("reserved2", c_i32), ("walkers_per_graph", c_vp)]
 
 

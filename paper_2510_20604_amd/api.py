@@ -103,7 +103,7 @@ class Graph:
 
 def _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, walkers_per_tree, persistent,
                   capture, accumulate, max_steps_per_tree, graph_index_base, bfs_starts, starts, path_ring, roots,
-                  lds_state=None, walkers_per_graph=None):
+                  lds_state=None, walkers_per_graph=None, strata=0):
     arr = (RwcCsr * len(gl))(*[g.csr for g in gl])
     flags = 0
     if persistent:
@@ -126,7 +126,8 @@ def _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, wa
         flags |= _lib.RWC_SAMPLE_NO_LDS_STATE
     p = SampleParams(seed=seed, sample_begin=sample_begin, num_samples=num_samples, root=root, flags=flags,
                      trees_in_flight=trees_in_flight, walkers_per_tree=walkers_per_tree,
-                     max_steps_per_tree=max_steps_per_tree, graph_index_base=graph_index_base)
+                     max_steps_per_tree=max_steps_per_tree, graph_index_base=graph_index_base,
+                     strata=int(strata))
     if roots is not None:
         p.roots = roots.data_ptr()
         p.num_roots = roots.numel()
@@ -151,7 +152,7 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
                    workspace: torch.Tensor | None = None, timing: bool = False,
                    bfs_starts: bool | None = None, starts: str = "auto", path_ring: bool | None = None,
                    roots=None, sync: bool = True, out: dict | None = None, lds_state: bool | None = None,
-                   walkers_per_graph: Sequence[int] | None = None) -> dict:
+                   walkers_per_graph: Sequence[int] | None = None, strata: int = 0) -> dict:
     """Samples `num_samples` rooted spanning trees of every graph (rwc_sample_forests).
 
     Returns device tensors: counts [sum n] (int64 holding uint64 values), counts_sq,
@@ -166,7 +167,9 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     node.  `out` (a dict returned by an earlier call) reuses its output tensors, so that a
     repeated call with capture=True replays the library's cached hipGraph.  The call is
     stream-ordered; with sync=True (default) it then waits and raises on a device-side error
-    (rwc_workspace_status)."""
+    (rwc_workspace_status).  strata = L >= 2 stratifies every stack entry over samples
+    [0, L) (Latin hypercube), a lower-variance estimate at equal trees; the call's samples
+    must lie in that range."""
     L = _lib.lib()
     gl = [graphs] if isinstance(graphs, Graph) else list(graphs)
     G = len(gl)
@@ -174,7 +177,7 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     rt = _roots_tensor(roots, dev)
     arr, p = _sample_setup(gl, num_samples, seed, sample_begin, root, trees_in_flight, walkers_per_tree, persistent,
                            capture, accumulate is not None, max_steps_per_tree, graph_index_base, bfs_starts, starts,
-                           path_ring, rt, lds_state, walkers_per_graph)
+                           path_ring, rt, lds_state, walkers_per_graph, strata)
     size = ctypes.c_size_t()
     check(L.rwc_sample_forests_workspace(arr, G, ctypes.byref(p), ctypes.byref(size)),
           "rwc_sample_forests_workspace")
@@ -220,8 +223,11 @@ def sample_forests(graphs: Graph | Sequence[Graph], num_samples: int, seed: int,
     res["workspace"] = workspace
     res["roots"] = rt
     res["walkers_per_tree"], res["trees_in_flight"], res["batches"] = int(plan[0]), int(plan[1]), int(plan[2])
-    res["walk_kernel"] = ("wilson_walk", "wilson_team<false>", "wilson_team<true>", "wilson_team_lds<false>",
-                          "wilson_team_lds<true>")[int(plan[3])]
+    kernels = (("wilson_walk", "wilson_team<false>", "wilson_team<true>", "wilson_team_lds<false>",
+                "wilson_team_lds<true>") if strata < 2 else
+               ("wilson_walk_strata", "wilson_team_strata<false>", "wilson_team_strata<true>",
+                "wilson_team_lds_strata<false>", "wilson_team_lds_strata<true>"))
+    res["walk_kernel"] = kernels[int(plan[3])]
     res["lds_graphs"] = int(plan[7])
     res["starts"] = "spread" if plan[4] else "shared"
     res["start_order"] = "breadth-first" if plan[5] else "ascending"
@@ -245,7 +251,8 @@ def prepare_sampling(graphs: Graph | Sequence[Graph], num_samples: int, workspac
                            kw.get("trees_in_flight", 0), kw.get("walkers_per_tree", 0), kw.get("persistent", False),
                            False, kw.get("accumulate", False), kw.get("max_steps_per_tree", 0),
                            kw.get("graph_index_base", 0), kw.get("bfs_starts"), kw.get("starts", "auto"),
-                           kw.get("path_ring"), rt, kw.get("lds_state"), kw.get("walkers_per_graph"))
+                           kw.get("path_ring"), rt, kw.get("lds_state"), kw.get("walkers_per_graph"),
+                           kw.get("strata", 0))
     size = ctypes.c_size_t()
     check(L.rwc_sample_forests_workspace(arr, len(gl), ctypes.byref(p), ctypes.byref(size)),
           "rwc_sample_forests_workspace")

@@ -58,6 +58,82 @@ __host__ __device__ __forceinline__ uint64_t philox_x64(uint32_t c0, uint32_t c1
 // floor(a * b / 2^64)
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
+// All four output words of Philox4x32-10 (same rounds as philox_x64).
+__device__ __forceinline__ uint4 philox4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                         uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------------------
+// Stratified stack entries: Latin hypercube sampling (McKay, Beckman, Conover 1979) of each
+// stack entry over the samples 0 .. L-1 of a call.  Entry (u, k) of sample i takes stratum
+// sigma(i) of [0, 2^64) split into L strata of width floor(2^64 / L), and its own Philox word
+// x places it inside the stratum.  sigma is a permutation of 0 .. L-1 keyed by the entry:
+// a 4-round Feistel network on [0, 4^h) (round keys: the four words of Philox on
+// (k, u, 2^32 - 1, g); round function the MurmurHash3 32-bit finaliser), walked until it
+// lands below L, then shifted by a uniform s = floor(b L / 2^64), b from Philox on
+// (k, u, 2^32 - 2, g).  The shift makes sigma(i) uniform for every i, so one sample's entries
+// stay independent and uniform and every tree is still a Wilson tree; over the L samples each
+// entry takes every stratum once.  Needs i < L <= 2^31 (the two key counters are never a
+// sample's).
+// ---------------------------------------------------------------------------------------
+struct Strata {
+    uint64_t width;   // floor(2^64 / L)
+    uint32_t count;   // L; below 2 the draws are not stratified
+    uint32_t half;    // h: the Feistel halves have h bits, 4^h >= L
+};
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint64_t stratified_word(uint64_t x, uint32_t k, uint32_t u, uint32_t i, uint32_t g,
+                                                    uint32_t k0, uint32_t k1, const Strata& S) {
+    const uint4 a = philox4(k, u, 0xFFFFFFFFu, g, k0, k1);
+    const uint64_t b = philox_x64(k, u, 0xFFFFFFFEu, g, k0, k1);
+    const uint32_t half = S.half, mask = (1u << half) - 1u;
+    // Cycle walking: i < L (the host checks every call's sample range) lies on its own cycle
+    // of the permutation of [0, 4^h), so a value below L comes back; each step lands there
+    // with probability above 1/4, so the cap is never reached in practice.  The clamp below
+    // keeps even an out-of-range index inside the row.
+    uint32_t y = i;
+    uint32_t walks = 0;
+    do {
+        uint32_t left = y >> half, right = y & mask;
+        uint32_t t = left ^ (fmix32(right ^ a.x) & mask);
+        left = right; right = t;
+        t = left ^ (fmix32(right ^ a.y) & mask);
+        left = right; right = t;
+        t = left ^ (fmix32(right ^ a.z) & mask);
+        left = right; right = t;
+        t = left ^ (fmix32(right ^ a.w) & mask);
+        left = right; right = t;
+        y = (left << half) | right;
+    } while (y >= S.count && ++walks < (1u << 16));
+    if (y >= S.count) y = 0;
+    uint32_t sigma = y + static_cast<uint32_t>(mulhi64(b, S.count));   // both < L <= 2^31
+    if (sigma >= S.count) sigma -= S.count;
+    return static_cast<uint64_t>(sigma) * S.width + mulhi64(x, S.width);
+}
+
 // RandomNeighbor, unweighted: the position within the row of the chosen neighbour,
 // floor(x * deg / 2^64).  (Weighted rows: the first position k with floor(x * S / 2^64) <
 // cdf[beg + k], S = cdf[end - 1]; the search lives with the node records in the sampler.)

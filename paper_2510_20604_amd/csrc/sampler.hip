@@ -395,6 +395,9 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
             if (w < 1 || w > kWave || (w & (w - 1)) != 0)
                 return fail(RWC_ERR_INVALID_ARG, "walkers_per_graph[%d] must be a power of two up to 64", g);
         }
+    if (p->strata > (1u << 31)) return fail(RWC_ERR_INVALID_ARG, "strata must be at most 2^31");
+    if (p->strata >= 2 && p->sample_begin + p->num_samples > static_cast<int64_t>(p->strata))
+        return fail(RWC_ERR_INVALID_ARG, "stratified samples must lie in [0, strata)");
     if ((p->flags & RWC_SAMPLE_SPREAD_STARTS) && (p->flags & RWC_SAMPLE_SHARED_STARTS))
         return fail(RWC_ERR_INVALID_ARG, "spread and shared starts are exclusive");
     if ((p->flags & RWC_SAMPLE_PATH_RING) && (p->flags & RWC_SAMPLE_NO_PATH_RING))
@@ -402,6 +405,18 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
     if ((p->flags & RWC_SAMPLE_BFS_STARTS) && (p->flags & RWC_SAMPLE_ID_STARTS))
         return fail(RWC_ERR_INVALID_ARG, "breadth-first and ascending starts are exclusive");
     return RWC_OK;
+}
+
+// The stratification constants of L samples (see stratified_word).
+Strata make_strata(uint32_t L) {
+    Strata S{0, 0, 0};
+    if (L < 2) return S;
+    int bits = 0;
+    while ((1ull << bits) < L) ++bits;
+    S.count = L;
+    S.half = static_cast<uint32_t>(bits < 2 ? 1 : (bits + 1) / 2);
+    S.width = static_cast<uint64_t>((static_cast<unsigned __int128>(1) << 64) / L);
+    return S;
 }
 
 // Everything a call derives on the host: the plan, the device tables (graph arguments, node
@@ -450,6 +465,7 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
         hg[g].T = plan.T[g];
         hg[g].W = plan.W[g];
         hg[g].spread = spread_starts(graphs[g], p->flags) ? 1 : 0;
+        hg[g].strata = make_strata(p->strata);
         if (plan.W[g] > 1) {
             any_spread = any_spread || hg[g].spread;
             any_dense_weighted =
@@ -500,9 +516,15 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
             for (int64_t s0 = 0; s0 < l; s0 += plan.S[g]) S->items.push_back(Item{g, static_cast<int32_t>(s0)});
     S->nit_lds = static_cast<int32_t>(S->items.size()) - S->nit_hbm;
     const bool hbm_team = plan.hbm_team || (plan.team && S->nit_hbm == 0);
-    S->walk = !hbm_team  ? static_cast<WalkKernel>(wilson_walk)
-              : S->ring  ? static_cast<WalkKernel>(wilson_team<true>)
-                         : static_cast<WalkKernel>(wilson_team<false>);
+    const bool strat = p->strata >= 2;
+    if (strat)
+        S->walk = !hbm_team  ? static_cast<WalkKernel>(wilson_walk_strata)
+                  : S->ring  ? static_cast<WalkKernel>(wilson_team_strata<true>)
+                             : static_cast<WalkKernel>(wilson_team_strata<false>);
+    else
+        S->walk = !hbm_team  ? static_cast<WalkKernel>(wilson_walk)
+                  : S->ring  ? static_cast<WalkKernel>(wilson_team<true>)
+                             : static_cast<WalkKernel>(wilson_team<false>);
     if (p->flags & RWC_SAMPLE_PERSISTENT) {
         int per_cu = 0;
         RWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->walk, kWave, 0));
@@ -510,8 +532,12 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
         S->grid_persistent = per_cu * device_cu_count();
     }
     if (S->nit_lds > 0) {
-        S->walk_lds = S->lds_ring ? static_cast<LdsKernel>(wilson_team_lds<true>)
-                                  : static_cast<LdsKernel>(wilson_team_lds<false>);
+        if (strat)
+            S->walk_lds = S->lds_ring ? static_cast<LdsKernel>(wilson_team_lds_strata<true>)
+                                      : static_cast<LdsKernel>(wilson_team_lds_strata<false>);
+        else
+            S->walk_lds = S->lds_ring ? static_cast<LdsKernel>(wilson_team_lds<true>)
+                                      : static_cast<LdsKernel>(wilson_team_lds<false>);
         S->lds_bytes = static_cast<size_t>(plan.lds_words) * 8;
         int per_cu = 0;
         RWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->walk_lds, kWave, S->lds_bytes));

@@ -3,9 +3,10 @@
 // tables they read.  Included by sampler.hip, which plans and launches them.
 //
 // RandomNeighbor(u) at the k-th departure from u in sample i of graph word g is
-// Philox4x32-10((k, u, i, g), seed).  A node's successive choices are therefore fixed in
-// advance, which makes the tree and every count independent of the order in which walks are
-// run (cycle popping), so results match the serial order of Algorithm 3 exactly.
+// Philox4x32-10((k, u, i, g), seed), optionally placed in its stratum (stratified_word).  A
+// node's successive choices are therefore fixed in advance, which makes the tree and every
+// count independent of the order in which walks are run (cycle popping), so results match the
+// serial order of Algorithm 3 exactly.
 #pragma once
 
 #include "common.hpp"
@@ -30,6 +31,7 @@ struct GraphArgs {
     int32_t T;              // tree slots (trees in flight) of this graph
     int32_t W;              // walkers per tree
     int32_t spread;         // each walker of a team takes starts from its own range
+    Strata strata;          // stack entries stratified over the call's samples (count >= 2)
 };
 
 struct Item {
@@ -47,7 +49,9 @@ struct DumpArgs {
 
 enum Phase : int { kScan = 0, kWalk = 1, kRetrace = 2, kDone = 3 };
 
-// Grows the tree of slot `slot` for absolute sample `sample` (one lane).
+// Grows the tree of slot `slot` for absolute sample `sample` (one lane).  kStrat: stack
+// entries stratified over the call's samples (stratified_word).
+template <bool kStrat>
 __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint64_t sample, uint64_t seed,
                                           bool want_hash, uint64_t& steps_out, uint64_t& hash_out,
                                           uint32_t& err_out) {
@@ -96,7 +100,8 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
                 rd = load_u4(q + 3);
                 rh_node = x;
             }
-            const uint64_t r = philox_x64(k, x, sw, gw, k0, k1);
+            uint64_t r = philox_x64(k, x, sw, gw, k0, k1);
+            if constexpr (kStrat) r = stratified_word(r, k, x, sw, gw, k0, k1, G.strata);
             const uint32_t y = choose_neighbor(r, [&](uint32_t i) { return rec_word(ra, rb, rc, rd, i); }, col, cdf);
             st[x] = st_make(y, k + 1);
             const uint64_t wy = st[y];
@@ -147,6 +152,7 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
 }
 
 // Batch b of graph g covers samples sample_begin + b*T_g + slot for slot in [0, T_g).
+template <bool kStrat>
 __device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t batch,
                                          int64_t sample_begin, int64_t l, uint64_t seed,
                                          uint64_t* __restrict__ tree_hash, uint64_t* __restrict__ total_steps,
@@ -158,7 +164,9 @@ __device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, c
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
     const bool active = slot < G.T && rel < l;
-    if (active) grow_tree(G, slot, static_cast<uint64_t>(sample_begin + rel), seed, tree_hash != nullptr, steps, h, err);
+    if (active)
+        grow_tree<kStrat>(G, slot, static_cast<uint64_t>(sample_begin + rel), seed, tree_hash != nullptr, steps, h,
+                          err);
     if (active) {
         if (tree_hash) tree_hash[static_cast<int64_t>(it.graph) * l + rel] = h;
         if (err) atomicOr(status, err);
@@ -171,13 +179,14 @@ __device__ __forceinline__ void run_item(const GraphArgs* __restrict__ graphs, c
 
 // One wave per work item (a block of 64 tree slots of one graph).  Persistent mode: a grid
 // sized to the resident capacity pops items from `queue` until the list is exhausted.
-__global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
-                                                     int32_t nitems, uint32_t* queue, int32_t batch,
-                                                     int64_t sample_begin, int64_t l, uint64_t seed,
-                                                     uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+template <bool kStrat>
+__device__ __forceinline__ void walk_items(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                           int32_t nitems, uint32_t* queue, int32_t batch, int64_t sample_begin,
+                                           int64_t l, uint64_t seed, uint64_t* tree_hash, uint64_t* total_steps,
+                                           uint32_t* status) {
     if (queue == nullptr) {
         if (static_cast<int32_t>(blockIdx.x) < nitems)
-            run_item(graphs, items[blockIdx.x], batch, sample_begin, l, seed, tree_hash, total_steps, status);
+            run_item<kStrat>(graphs, items[blockIdx.x], batch, sample_begin, l, seed, tree_hash, total_steps, status);
         return;
     }
     while (true) {
@@ -185,8 +194,24 @@ __global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict
         if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
         idx = __shfl(idx, 0, kWave);
         if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_item(graphs, items[idx], batch, sample_begin, l, seed, tree_hash, total_steps, status);
+        run_item<kStrat>(graphs, items[idx], batch, sample_begin, l, seed, tree_hash, total_steps, status);
     }
+}
+
+__global__ void __launch_bounds__(kWave) wilson_walk(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                                     int32_t nitems, uint32_t* queue, int32_t batch,
+                                                     int64_t sample_begin, int64_t l, uint64_t seed,
+                                                     uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    walk_items<false>(graphs, items, nitems, queue, batch, sample_begin, l, seed, tree_hash, total_steps, status);
+}
+
+// The same with stratified stack entries (a kernel of its own, so that the plain walk keeps
+// its register budget).
+__global__ void __launch_bounds__(kWave)
+    wilson_walk_strata(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items, int32_t nitems,
+                       uint32_t* queue, int32_t batch, int64_t sample_begin, int64_t l, uint64_t seed,
+                       uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    walk_items<true>(graphs, items, nitems, queue, batch, sample_begin, l, seed, tree_hash, total_steps, status);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -251,7 +276,7 @@ __device__ __forceinline__ bool st_cas(RWC_LDS uint64_t* p, uint64_t expected, u
 }
 
 // st: the tree's state words, in HBM (RWC_GLOBAL uint64_t*) or in LDS (RWC_LDS uint64_t*).
-template <bool kRing, class StatePtr>
+template <bool kRing, bool kStrat, class StatePtr>
 __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool active, uint64_t seed,
                           uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
                           bool want_hash, uint64_t& steps_out, uint64_t& hash_out, uint32_t& err_out) {
@@ -366,7 +391,8 @@ __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool
             if (rh_node != h) keep_record(h);
             wait_vm();
             k = hk;
-            const uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
+            uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
+            if constexpr (kStrat) r = stratified_word(r, k, h, sw, gw, k0, k1, G.strata);
             node = choose_neighbor(r, rec_at, col, cdf);
         } else if (mode == tStart) {
             node = j;
@@ -622,7 +648,7 @@ __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool
     err_out = err;
 }
 
-template <bool kRing>
+template <bool kRing, bool kStrat>
 __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ graphs, const Item it, int32_t batch,
                                               int64_t sample_begin, int64_t l, uint64_t seed,
                                               uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
@@ -636,7 +662,7 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
     const bool active = slot < G.T && rel < l;
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    grow_team<kRing>(G, global_ptr(G.state + static_cast<int64_t>(active ? slot : 0) * G.stride),
+    grow_team<kRing, kStrat>(G, global_ptr(G.state + static_cast<int64_t>(active ? slot : 0) * G.stride),
                      static_cast<uint64_t>(sample_begin + rel), active, seed, lds_path, lds_rec, tree_hash != nullptr,
                      steps, h, err);
     for (int off = W / 2; off > 0; off >>= 1) {
@@ -653,17 +679,16 @@ __device__ __forceinline__ void run_team_item(const GraphArgs* __restrict__ grap
 }
 
 // One wave per work item: 64 / W trees of one graph, W walkers each (W from the graph).
-template <bool kRing>
-__global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
-                                                     int32_t nitems, uint32_t* queue, int32_t batch,
-                                                     int64_t sample_begin, int64_t l, uint64_t seed,
-                                                     uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
-    __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
-    __shared__ uint4 lds_rec[4][kWave];
+template <bool kRing, bool kStrat>
+__device__ __forceinline__ void team_items(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                           int32_t nitems, uint32_t* queue, int32_t batch, int64_t sample_begin,
+                                           int64_t l, uint64_t seed, uint2 (*lds_path)[kWave],
+                                           uint4 (*lds_rec)[kWave], uint64_t* tree_hash, uint64_t* total_steps,
+                                           uint32_t* status) {
     if (queue == nullptr) {
         if (static_cast<int32_t>(blockIdx.x) < nitems)
-            run_team_item<kRing>(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_path,
-                                 lds_rec, tree_hash, total_steps, status);
+            run_team_item<kRing, kStrat>(graphs, items[blockIdx.x], batch, sample_begin, l, seed, lds_path,
+                                         lds_rec, tree_hash, total_steps, status);
         return;
     }
     while (true) {
@@ -671,9 +696,31 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
         if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
         idx = __shfl(idx, 0, kWave);
         if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_team_item<kRing>(graphs, items[idx], batch, sample_begin, l, seed, lds_path, lds_rec,
-                             tree_hash, total_steps, status);
+        run_team_item<kRing, kStrat>(graphs, items[idx], batch, sample_begin, l, seed, lds_path, lds_rec,
+                                     tree_hash, total_steps, status);
     }
+}
+
+template <bool kRing>
+__global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                                     int32_t nitems, uint32_t* queue, int32_t batch,
+                                                     int64_t sample_begin, int64_t l, uint64_t seed,
+                                                     uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
+    __shared__ uint4 lds_rec[4][kWave];
+    team_items<kRing, false>(graphs, items, nitems, queue, batch, sample_begin, l, seed, lds_path, lds_rec,
+                             tree_hash, total_steps, status);
+}
+
+template <bool kRing>
+__global__ void __launch_bounds__(kWave)
+    wilson_team_strata(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items, int32_t nitems,
+                       uint32_t* queue, int32_t batch, int64_t sample_begin, int64_t l, uint64_t seed,
+                       uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status) {
+    __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
+    __shared__ uint4 lds_rec[4][kWave];
+    team_items<kRing, true>(graphs, items, nitems, queue, batch, sample_begin, l, seed, lds_path, lds_rec,
+                            tree_hash, total_steps, status);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -684,7 +731,7 @@ __global__ void __launch_bounds__(kWave) wilson_team(const GraphArgs* __restrict
 // clears its LDS trees, grows them, then adds every node's departure count (and its square)
 // into the call's totals with one atomic per node and writes any requested parent dump.
 // ---------------------------------------------------------------------------------------
-template <bool kRing>
+template <bool kRing, bool kStrat>
 __device__ __forceinline__ void run_team_item_lds(const GraphArgs* __restrict__ graphs, const Item it,
                                                   int64_t sample_begin, int64_t l, uint64_t seed,
                                                   uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
@@ -709,8 +756,8 @@ __device__ __forceinline__ void run_team_item_lds(const GraphArgs* __restrict__ 
     __syncthreads();
     uint64_t steps = 0, h = 0;
     uint32_t err = 0;
-    grow_team<kRing>(G, st, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_path, lds_rec,
-                     tree_hash != nullptr, steps, h, err);
+    grow_team<kRing, kStrat>(G, st, static_cast<uint64_t>(sample_begin + rel), active, seed, lds_path, lds_rec,
+                             tree_hash != nullptr, steps, h, err);
     __syncthreads();
     if (active) {
         const int64_t off = node_off[it.graph];
@@ -746,6 +793,24 @@ __device__ __forceinline__ void run_team_item_lds(const GraphArgs* __restrict__ 
 
 // Persistent: a grid of resident waves pops items (graph, first sample) from `queue`.  The
 // dynamic LDS holds the state words of 64 / W trees of the largest graph of the call.
+template <bool kRing, bool kStrat>
+__device__ __forceinline__ void team_items_lds(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items,
+                                               int32_t nitems, uint32_t* queue, int64_t sample_begin, int64_t l,
+                                               uint64_t seed, const int64_t* __restrict__ node_off, uint64_t* counts,
+                                               uint64_t* counts_sq, int32_t* parents, const DumpArgs& dumps,
+                                               uint64_t* tree_hash, uint64_t* total_steps, uint32_t* status,
+                                               uint2 (*lds_path)[kWave], uint4 (*lds_rec)[kWave],
+                                               RWC_LDS uint64_t* lds_state) {
+    while (true) {
+        uint32_t idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
+        idx = __shfl(idx, 0, kWave);
+        if (idx >= static_cast<uint32_t>(nitems)) break;
+        run_team_item_lds<kRing, kStrat>(graphs, items[idx], sample_begin, l, seed, lds_path, lds_rec, lds_state,
+                                         node_off, counts, counts_sq, parents, dumps, tree_hash, total_steps, status);
+    }
+}
+
 template <bool kRing>
 __global__ void __launch_bounds__(kWave) wilson_team_lds(const GraphArgs* __restrict__ graphs,
                                                          const Item* __restrict__ items, int32_t nitems, uint32_t* queue,
@@ -756,15 +821,24 @@ __global__ void __launch_bounds__(kWave) wilson_team_lds(const GraphArgs* __rest
     __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
     __shared__ uint4 lds_rec[4][kWave];
     extern __shared__ uint64_t lds_state_raw[];
-    RWC_LDS uint64_t* lds_state = (RWC_LDS uint64_t*)lds_state_raw;
-    while (true) {
-        uint32_t idx = 0;
-        if (threadIdx.x == 0) idx = atomicAdd(queue, 1u);
-        idx = __shfl(idx, 0, kWave);
-        if (idx >= static_cast<uint32_t>(nitems)) break;
-        run_team_item_lds<kRing>(graphs, items[idx], sample_begin, l, seed, lds_path, lds_rec, lds_state, node_off,
-                                 counts, counts_sq, parents, dumps, tree_hash, total_steps, status);
-    }
+    team_items_lds<kRing, false>(graphs, items, nitems, queue, sample_begin, l, seed, node_off, counts, counts_sq,
+                                 parents, dumps, tree_hash, total_steps, status, lds_path, lds_rec,
+                                 (RWC_LDS uint64_t*)lds_state_raw);
+}
+
+template <bool kRing>
+__global__ void __launch_bounds__(kWave)
+    wilson_team_lds_strata(const GraphArgs* __restrict__ graphs, const Item* __restrict__ items, int32_t nitems,
+                           uint32_t* queue, int64_t sample_begin, int64_t l, uint64_t seed,
+                           const int64_t* __restrict__ node_off, uint64_t* counts, uint64_t* counts_sq,
+                           int32_t* parents, DumpArgs dumps, uint64_t* tree_hash, uint64_t* total_steps,
+                           uint32_t* status) {
+    __shared__ uint2 lds_path[kRing ? kPathBuf : 1][kWave];
+    __shared__ uint4 lds_rec[4][kWave];
+    extern __shared__ uint64_t lds_state_raw[];
+    team_items_lds<kRing, true>(graphs, items, nitems, queue, sample_begin, l, seed, node_off, counts, counts_sq,
+                                parents, dumps, tree_hash, total_steps, status, lds_path, lds_rec,
+                                (RWC_LDS uint64_t*)lds_state_raw);
 }
 
 }  // namespace
