@@ -73,11 +73,13 @@ uint64_t oracle_splitmix64(uint64_t z) { return splitmix64(z); }
  * sample i lies in stratum sigma(i) of [0, 2^64), where sigma is a permutation of 0 .. L-1
  * drawn for that entry alone:
  *   x     = the word above, from Philox on (k, u, i, g)
- *   a     = Philox4x32-10 on (k, u, 2^32 - 1, g): four round keys of a Feistel network P on
- *           [0, 4^h), h = max(1, ceil(ceil(log2 L) / 2)), round t: (l, r) -> (r, l xor
- *           (fmix32(r xor a_t) mod 2^h)), output l * 2^h + r
+ *   a     = Philox4x32-10 on (k, u, 2^32 - 1, g)
+ *   P     = a 4-round Feistel network on B = max(2, ceil(log2 L)) bits: the value is split
+ *           into a high part of p = floor(B/2) bits and a low part of q = B - p bits; a round
+ *           with key K maps (high, low) to (low, high xor (fmix32(low xor K) mod 2^p)) and
+ *           the two widths trade places; keys a0, a1, a0 xor rotl(a1, 16), a1 xor rotl(a0, 16)
  *   pi(i) = P(i), P applied again while the result is >= L (cycle walking, a permutation)
- *   s     = floor(b * L / 2^64), b = words 0, 1 of Philox4x32-10 on (k, u, 2^32 - 2, g)
+ *   s     = floor(b * L / 2^64), b = a2 + 2^32 a3
  *   sigma = (pi(i) + s) mod L
  *   word  = sigma * M + floor(x * M / 2^64),  M = floor(2^64 / L)
  * For one sample the entries stay independent and (up to the 2^-64 grid) uniform, because
@@ -94,16 +96,21 @@ static uint32_t fmix32(uint32_t h) {
     return h;
 }
 
-static uint64_t feistel4(uint64_t x, int half, const uint32_t key[4]) {
-    const uint64_t mask = ((uint64_t)1 << half) - 1;
-    uint64_t left = x >> half, right = x & mask;
+static uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+
+static uint64_t feistel4(uint64_t x, int bits, const uint32_t key[4]) {
+    int p = bits / 2, q = bits - p;                 /* widths of the high and low parts */
+    uint64_t high = x >> q, low = x & (((uint64_t)1 << q) - 1);
     for (int t = 0; t < 4; ++t) {
-        const uint64_t f = (uint64_t)fmix32((uint32_t)right ^ key[t]) & mask;
-        const uint64_t nl = right;
-        right = left ^ f;
-        left = nl;
+        const uint64_t f = (uint64_t)fmix32((uint32_t)low ^ key[t]) & (((uint64_t)1 << p) - 1);
+        const uint64_t new_low = high ^ f;          /* p bits */
+        high = low;                                 /* q bits */
+        low = new_low;
+        const int w = p;
+        p = q;
+        q = w;
     }
-    return (left << half) | right;
+    return (high << q) | low;
 }
 
 /* The 64-bit word of the k-th departure from u in sample `sample` of graph `graph`. */
@@ -114,19 +121,17 @@ static uint64_t stack_word(uint32_t k, int64_t u, uint64_t sample, uint32_t grap
     oracle_philox4x32_10(ctr, key, o);
     const uint64_t x = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
     if (strata < 2) return x;
-    uint32_t a[4], b[4];
+    uint32_t a[4];
     ctr[2] = 0xFFFFFFFFu;
     oracle_philox4x32_10(ctr, key, a);
-    ctr[2] = 0xFFFFFFFEu;
-    oracle_philox4x32_10(ctr, key, b);
-    int bits = 0;
+    const uint32_t round_keys[4] = {a[0], a[1], a[0] ^ rotl32(a[1], 16), a[1] ^ rotl32(a[0], 16)};
+    int bits = 2;
     while (((uint64_t)1 << bits) < strata) ++bits;
-    const int half = bits < 2 ? 1 : (bits + 1) / 2;
     uint64_t y = sample;
     do {
-        y = feistel4(y, half, a);
+        y = feistel4(y, bits, round_keys);
     } while (y >= strata);
-    const uint64_t bw = (uint64_t)b[0] | ((uint64_t)b[1] << 32);
+    const uint64_t bw = (uint64_t)a[2] | ((uint64_t)a[3] << 32);
     const uint64_t shift = (uint64_t)(((u128)bw * (u128)strata) >> 64);
     const uint64_t stratum = (y + shift) % strata;
     const uint64_t width = (uint64_t)((((u128)1) << 64) / (u128)strata);

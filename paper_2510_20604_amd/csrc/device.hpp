@@ -81,19 +81,20 @@ __device__ __forceinline__ uint4 philox4(uint32_t c0, uint32_t c1, uint32_t c2, 
 // Stratified stack entries: Latin hypercube sampling (McKay, Beckman, Conover 1979) of each
 // stack entry over the samples 0 .. L-1 of a call.  Entry (u, k) of sample i takes stratum
 // sigma(i) of [0, 2^64) split into L strata of width floor(2^64 / L), and its own Philox word
-// x places it inside the stratum.  sigma is a permutation of 0 .. L-1 keyed by the entry:
-// a 4-round Feistel network on [0, 4^h) (round keys: the four words of Philox on
-// (k, u, 2^32 - 1, g); round function the MurmurHash3 32-bit finaliser), walked until it
-// lands below L, then shifted by a uniform s = floor(b L / 2^64), b from Philox on
-// (k, u, 2^32 - 2, g).  The shift makes sigma(i) uniform for every i, so one sample's entries
+// x places it inside the stratum.  sigma is a permutation of 0 .. L-1 keyed by the entry
+// through one Philox call a on (k, u, 2^32 - 1, g): a 4-round unbalanced Feistel network on
+// B = max(2, ceil(log2 L)) bits (high part floor(B/2) bits, low part the rest; a round maps
+// (high, low) to (low, high xor (fmix32(low xor key) mod 2^|high|)), the widths trading
+// places; keys a0, a1, a0 xor rotl(a1, 16), a1 xor rotl(a0, 16); fmix32 is the MurmurHash3
+// 32-bit finaliser), walked until it lands below L, then shifted by s = floor(b L / 2^64),
+// b = a2 + 2^32 a3.  The shift makes sigma(i) uniform for every i, so one sample's entries
 // stay independent and uniform and every tree is still a Wilson tree; over the L samples each
-// entry takes every stratum once.  Needs i < L <= 2^31 (the two key counters are never a
-// sample's).
+// entry takes every stratum once.  Needs i < L <= 2^31 (the key counter is never a sample's).
 // ---------------------------------------------------------------------------------------
 struct Strata {
     uint64_t width;   // floor(2^64 / L)
     uint32_t count;   // L; below 2 the draws are not stratified
-    uint32_t half;    // h: the Feistel halves have h bits, 4^h >= L
+    uint32_t bits;    // B: the Feistel network permutes [0, 2^B), 2^B >= L
 };
 
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
@@ -108,27 +109,34 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 __device__ __forceinline__ uint64_t stratified_word(uint64_t x, uint32_t k, uint32_t u, uint32_t i, uint32_t g,
                                                     uint32_t k0, uint32_t k1, const Strata& S) {
     const uint4 a = philox4(k, u, 0xFFFFFFFFu, g, k0, k1);
-    const uint64_t b = philox_x64(k, u, 0xFFFFFFFEu, g, k0, k1);
-    const uint32_t half = S.half, mask = (1u << half) - 1u;
+    const uint32_t key2 = a.x ^ __builtin_rotateleft32(a.y, 16), key3 = a.y ^ __builtin_rotateleft32(a.x, 16);
+    const uint32_t p = S.bits >> 1, q = S.bits - p;   // widths of the high and low parts
+    const uint32_t mp = (1u << p) - 1u, mq = (1u << q) - 1u;
     // Cycle walking: i < L (the host checks every call's sample range) lies on its own cycle
-    // of the permutation of [0, 4^h), so a value below L comes back; each step lands there
-    // with probability above 1/4, so the cap is never reached in practice.  The clamp below
+    // of the permutation of [0, 2^B), so a value below L comes back; each step lands there
+    // with probability above 1/2, so the cap is never reached in practice.  The clamp below
     // keeps even an out-of-range index inside the row.
     uint32_t y = i;
     uint32_t walks = 0;
     do {
-        uint32_t left = y >> half, right = y & mask;
-        uint32_t t = left ^ (fmix32(right ^ a.x) & mask);
-        left = right; right = t;
-        t = left ^ (fmix32(right ^ a.y) & mask);
-        left = right; right = t;
-        t = left ^ (fmix32(right ^ a.z) & mask);
-        left = right; right = t;
-        t = left ^ (fmix32(right ^ a.w) & mask);
-        left = right; right = t;
-        y = (left << half) | right;
+        // rounds 1 and 3 see (p-bit high, q-bit low), rounds 2 and 4 (q-bit high, p-bit low)
+        uint32_t hi = y >> q, lo = y & mq;
+        uint32_t t = hi ^ (fmix32(lo ^ a.x) & mp);    // p bits
+        hi = lo;                                      // q bits
+        lo = t;
+        t = hi ^ (fmix32(lo ^ a.y) & mq);             // q bits
+        hi = lo;                                      // p bits
+        lo = t;
+        t = hi ^ (fmix32(lo ^ key2) & mp);
+        hi = lo;
+        lo = t;
+        t = hi ^ (fmix32(lo ^ key3) & mq);
+        hi = lo;
+        lo = t;
+        y = (hi << q) | lo;
     } while (y >= S.count && ++walks < (1u << 16));
     if (y >= S.count) y = 0;
+    const uint64_t b = static_cast<uint64_t>(a.z) | (static_cast<uint64_t>(a.w) << 32);
     uint32_t sigma = y + static_cast<uint32_t>(mulhi64(b, S.count));   // both < L <= 2^31
     if (sigma >= S.count) sigma -= S.count;
     return static_cast<uint64_t>(sigma) * S.width + mulhi64(x, S.width);

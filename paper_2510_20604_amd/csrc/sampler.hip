@@ -411,10 +411,10 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
 Strata make_strata(uint32_t L) {
     Strata S{0, 0, 0};
     if (L < 2) return S;
-    int bits = 0;
+    uint32_t bits = 2;
     while ((1ull << bits) < L) ++bits;
     S.count = L;
-    S.half = static_cast<uint32_t>(bits < 2 ? 1 : (bits + 1) / 2);
+    S.bits = bits;
     S.width = static_cast<uint64_t>((static_cast<unsigned __int128>(1) << 64) / L);
     return S;
 }

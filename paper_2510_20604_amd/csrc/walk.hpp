@@ -389,10 +389,12 @@ __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool
         uint32_t k = 0;
         if (mode == tWalk) {
             if (rh_node != h) keep_record(h);
-            wait_vm();
+            // the draw needs only (departure, head, sample): it runs while the record and the
+            // previous iteration's accesses are in flight, not after the wait
             k = hk;
             uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
             if constexpr (kStrat) r = stratified_word(r, k, h, sw, gw, k0, k1, G.strata);
+            wait_vm();
             node = choose_neighbor(r, rec_at, col, cdf);
         } else if (mode == tStart) {
             node = j;
