@@ -51,29 +51,41 @@ typedef enum rwc_status {
  * workspace given to rwc_build_csr, which must outlive every use of the struct. */
 typedef struct rwc_csr {
     int32_t n;             /* nodes                                                         */
-    int32_t pivot;         /* node of largest weighted degree, ties to the smallest id      */
+    int32_t pivot;         /* node of largest weighted degree, ties to the smallest id (an
+                              input id; its internal index is pivot_index)                  */
     int64_t m;             /* undirected edges (= input edges)                              */
     int64_t nnz;           /* 2m directed CSR entries                                       */
     int32_t weighted;      /* 1 if the graph was built with weights                         */
     int32_t max_degree;    /* largest number of neighbours                                  */
     double vol;            /* sum of weighted degrees (2m for unit weights)                 */
     uint64_t vol_fixed;    /* vol * 2^24, exact                                             */
+    /* The arrays below are in the graph's internal order (see node_id): row x, strength[x],
+       rec[16 x ..] and the ids in col and bfs_order are internal indices.  Every per-node
+       array a caller passes to or gets from the library is indexed by input id.           */
     int32_t* row_ptr;      /* [n + 1] CSR offsets                                           */
-    int32_t* col;          /* [nnz] neighbour ids, ascending within each row                */
+    int32_t* col;          /* [nnz] internal indices of the neighbours, ordered within each
+                              row by ascending input id                                     */
     float* weight;         /* [nnz] weight of each entry (1 for unweighted graphs)          */
     int32_t* edge_id;      /* [nnz] index of the input edge each entry came from            */
     uint64_t* cdf;         /* [nnz] inclusive prefix sums within each row of the integer
                               weights W_e = w_e * 2^24 (NULL for unweighted graphs)         */
     double* strength;      /* [n] weighted degree d_u                                       */
     uint32_t* rec;         /* [16 n] 64-byte node records: word 0 the degree, word 1 the row
-                              offset; unweighted rows: the first 14 neighbour ids in words
-                              2..15; weighted rows: the first 4 ids in words 2..5, the row's
-                              total (last CDF value) in words 6..7 and the first 4 CDF values
-                              in words 8..15; unused words are zero                         */
+                              offset, word 2 the node's input id; unweighted rows: the first
+                              13 neighbours in words 3..15; weighted rows: the first 3 in
+                              words 3..5, the row's total (last CDF value) in words 6..7 and
+                              the first 3 CDF values in words 8..13; unused words are zero  */
     int32_t* bfs_order;    /* [n] nodes in breadth-first order from the pivot: the order in
                               which walker teams take start nodes                          */
     int32_t bfs_depth;     /* largest hop distance from the pivot (its eccentricity)       */
     int32_t reserved;
+    int32_t* node_id;      /* [n] input id of internal index x                              */
+    int32_t* node_index;   /* [n] internal index of input id u                              */
+    int32_t pivot_index;   /* internal index of the pivot                                   */
+    int32_t internal_order;/* 1: nodes stored by descending weighted degree, ties by input
+                              id (graphs whose largest degree exceeds four times the mean);
+                              0: internal index = input id.  Placement only: no result
+                              depends on it                                                 */
 } rwc_csr;
 
 /* Bytes of workspace rwc_build_csr needs for n nodes and m edges (weighted != 0 if w will

@@ -41,7 +41,8 @@ class RwcCsr(ctypes.Structure):
                 ("max_degree", c_i32), ("vol", c_dbl), ("vol_fixed", c_u64), ("row_ptr", c_vp),
                 ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp),
                 ("rec", c_vp), ("bfs_order", c_vp), ("bfs_depth", c_i32),
-                ("reserved", c_i32)]
+                ("reserved", c_i32), ("node_id", c_vp), ("node_index", c_vp), ("pivot_index", c_i32),
+                ("internal_order", c_i32)]
 
 
 class SampleParams(ctypes.Structure):

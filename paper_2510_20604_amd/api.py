@@ -56,7 +56,8 @@ class Graph:
         check(L.rwc_build_csr(self.n, self.m, _ptr(self.src), _ptr(self.dst), _ptr(self.w), _ptr(self.ws),
                               self.ws.numel(), ctypes.byref(self.csr), _stream()), "rwc_build_csr")
 
-    # -- views of the device CSR (for tests and diagnostics) --
+    # -- views of the device CSR (for tests and diagnostics), in the graph's internal order:
+    # node_id()[x] is the input id of internal index x --
     def _view(self, addr: int, count: int, dtype: torch.dtype) -> torch.Tensor:
         off = addr - self.ws.data_ptr()
         nbytes = count * torch.empty(0, dtype=dtype).element_size()
@@ -96,6 +97,16 @@ class Graph:
 
     def bfs_order(self) -> torch.Tensor:
         return self._view(self.csr.bfs_order, self.n, torch.int32)
+
+    def node_id(self) -> torch.Tensor:
+        return self._view(self.csr.node_id, self.n, torch.int32)
+
+    def node_index(self) -> torch.Tensor:
+        return self._view(self.csr.node_index, self.n, torch.int32)
+
+    @property
+    def internal_order(self) -> int:
+        return int(self.csr.internal_order)
 
     def rec(self) -> torch.Tensor:
         return self._view(self.csr.rec, 16 * self.n, torch.int32)

@@ -144,14 +144,17 @@ __global__ void rank_nonzeros(int32_t n, int32_t rows_per_block, const double* _
     }
 }
 
+// Row u of Y is internal index u; g, rank and the probe keys use its input id node_id[u].
 __global__ void rhs_fill(int32_t n, int32_t R, ProbeSpec ps, const double* __restrict__ g,
-                         const double* __restrict__ d, const int32_t* __restrict__ rank, double* __restrict__ Y) {
+                         const int32_t* __restrict__ node_id, const double* __restrict__ d,
+                         const int32_t* __restrict__ rank, double* __restrict__ Y) {
     const int64_t total = static_cast<int64_t>(n) * R;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t u = i / R;
         const int32_t c = static_cast<int32_t>(i - u * R);
-        const double gu = g[u];
+        const int32_t id = node_id[u];
+        const double gu = g[id];
         double v = 0.0;
         if (c == 0) {
             v = gu;
@@ -159,10 +162,10 @@ __global__ void rhs_fill(int32_t n, int32_t R, ProbeSpec ps, const double* __res
             v = d[u];
         } else if (gu != 0.0) {
             if (ps.k == 0) {
-                if (rank[u] == c - 2) v = sqrt(fabs(gu));
+                if (rank[id] == c - 2) v = sqrt(fabs(gu));
             } else {
                 const int32_t first = class_first_column(ps, gu);
-                if (c >= first && c < first + ps.k) v = probe_entry(ps, gu, static_cast<uint32_t>(u), c - first);
+                if (c >= first && c < first + ps.k) v = probe_entry(ps, gu, static_cast<uint32_t>(id), c - first);
             }
         }
         Y[i] = v;
@@ -584,9 +587,10 @@ struct EdgeScalars {
 // trGL^ = sum_i c_i y_i^T L^+ y_i, with the probe entries y recomputed from g (the solve has
 // overwritten the right-hand sides).
 __global__ void scalar_partials(int32_t n, int32_t R, int32_t rows_per_block, ProbeSpec ps,
-                                const double* __restrict__ g, const int32_t* __restrict__ rank,
-                                const double* __restrict__ coef, const double* __restrict__ Z,
-                                const double* __restrict__ d, double* __restrict__ part) {
+                                const double* __restrict__ g, const int32_t* __restrict__ node_id,
+                                const int32_t* __restrict__ rank, const double* __restrict__ coef,
+                                const double* __restrict__ Z, const double* __restrict__ d,
+                                double* __restrict__ part) {
     __shared__ double lds[kBlock];
     const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_block;
     const int64_t hi = lo + rows_per_block < n ? lo + rows_per_block : n;
@@ -594,15 +598,16 @@ __global__ void scalar_partials(int32_t n, int32_t R, int32_t rows_per_block, Pr
     for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
         const double* zu = Z + u * R;
         q += d[u] * zu[1];
-        const double gu = g[u];
+        const int32_t id = node_id[u];
+        const double gu = g[id];
         if (gu == 0.0) continue;
         if (ps.k == 0) {
-            const int32_t c = 2 + rank[u];
+            const int32_t c = 2 + rank[id];
             t += coef[c] * (sqrt(fabs(gu)) * zu[c]);
         } else {
             const int32_t first = class_first_column(ps, gu);
             for (int32_t i = 0; i < ps.k; ++i)
-                t += coef[first + i] * (probe_entry(ps, gu, static_cast<uint32_t>(u), i) * zu[first + i]);
+                t += coef[first + i] * (probe_entry(ps, gu, static_cast<uint32_t>(id), i) * zu[first + i]);
         }
     }
     q = block_sum(q, lds);
@@ -738,7 +743,7 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     clear_error();
     if (!grad_rwc || !grad_w) return fail(RWC_ERR_INVALID_ARG, "grad_rwc and grad_w are required");
     RWC_CHECK(check_params(g, bp));
-    const int32_t n = g->n, v = g->pivot, k = bp->k;
+    const int32_t n = g->n, v = g->pivot_index, k = bp->k;
     const int32_t Rmax = static_cast<int32_t>(workspace_columns(bp));
     RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, Rmax).total));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -802,7 +807,8 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
         hipLaunchKernelGGL(rank_nonzeros, dim3(rblocks), dim3(kBlock), 0, s, n, rpb, grad_rwc, L.gbase, L.rank, L.coef);
     const int64_t nr = static_cast<int64_t>(n) * R;
     const unsigned flat = blocks_for(nr, kBlock) < 8192 ? blocks_for(nr, kBlock) : 8192;
-    hipLaunchKernelGGL(rhs_fill, dim3(flat), dim3(kBlock), 0, s, n, R, ps, grad_rwc, g->strength, L.rank, L.Y);
+    hipLaunchKernelGGL(rhs_fill, dim3(flat), dim3(kBlock), 0, s, n, R, ps, grad_rwc, g->node_id, g->strength, L.rank,
+                       L.Y);
 
     // one wave per row up to what the device holds at once: the SpMM is bound by the latency
     // of its row gathers, so every resident wave slot should hold one (4096 -> 6144 waves:
@@ -865,7 +871,7 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
                        L.colmean, 1.0 / n);
     hipLaunchKernelGGL(center_columns, dim3(flat), dim3(kBlock), 0, s, n, R, L.colmean, L.X);
     hipLaunchKernelGGL(scalar_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, ps, grad_rwc,
-                       L.rank, L.coef, L.X, g->strength, L.part);
+                       g->node_id, L.rank, L.coef, L.X, g->strength, L.part);
     hipLaunchKernelGGL(edge_scalars, dim3(1), dim3(kBlock), 0, s, static_cast<int32_t>(wave_blocks), L.part, L.es);
     const unsigned edge_blocks = blocks_for(g->nnz, kBlock) < 16384 ? blocks_for(g->nnz, kBlock) : 16384;
     hipLaunchKernelGGL(edge_gradient, dim3(edge_blocks), dim3(kBlock), 0, s, n, g->nnz, R, g->row_ptr, g->col,

@@ -149,15 +149,18 @@ __device__ __forceinline__ int32_t select_unweighted(uint64_t x, int32_t deg) {
     return static_cast<int32_t>(mulhi64(x, static_cast<uint64_t>(deg)));
 }
 
-// Node records (rwc_csr::rec): 16 x uint32 per node, 64-byte aligned.  Word 0 is the degree
-// and word 1 the row offset.  Unweighted rows store their first 14 neighbours in words 2..15
-// (position p in word 2 + p).  Weighted rows store the ids of their first 4 entries in words
-// 2..5, the row's total (its last CDF value) in words 6..7 and the CDF values of the first 4
-// entries in words 8..15.  Whatever degree the row has, these positions need no read of the
-// row itself.
+// Node records (rwc_csr::rec): 16 x uint32 per node (in the graph's internal order), 64-byte
+// aligned.  Word 0 is the degree, word 1 the row offset and word 2 the node's input id (the
+// id the generator is keyed on).  Unweighted rows store the internal indices of their first
+// 13 neighbours in words 3..15 (position p in word 3 + p).  Weighted rows store those of their
+// first 3 entries in words 3..5, the row's total (its last CDF value) in words 6..7 and the
+// CDF values of the first 3 entries in words 8..13.  Whatever degree the row has, these
+// positions need no read of the row itself.
 constexpr int kRecWords = 16;
-constexpr int kRecInline = 14;          // neighbours stored inline for unweighted rows
-constexpr int kRecInlineWeighted = 4;   // (id, cdf) pairs stored inline for weighted rows
+constexpr int kRecId = 2;               // word holding the node's input id
+constexpr int kRecFirst = 3;            // word of the first inline neighbour
+constexpr int kRecInline = 13;          // neighbours stored inline for unweighted rows
+constexpr int kRecInlineWeighted = 3;   // (id, cdf) pairs stored inline for weighted rows
 
 // SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014): the tree checksum term.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {

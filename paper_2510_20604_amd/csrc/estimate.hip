@@ -261,32 +261,35 @@ __global__ void pivot_partials(int32_t n, const double* __restrict__ d, const do
     }
 }
 
-__global__ void assemble(int32_t n, int32_t v, double vol, double l, const uint64_t* __restrict__ counts,
-                         const uint64_t* __restrict__ counts_sq, const double* __restrict__ d,
-                         const double* __restrict__ h, const Scalars* __restrict__ sc, double* __restrict__ rwc,
-                         double* __restrict__ se, double* __restrict__ hit) {
+// Thread per internal index u; the caller's arrays (counts in, RWC, standard errors and
+// hitting times out) are indexed by input id node_id[u].
+__global__ void assemble(int32_t n, int32_t v, double vol, double l, const int32_t* __restrict__ node_id,
+                         const uint64_t* __restrict__ counts, const uint64_t* __restrict__ counts_sq,
+                         const double* __restrict__ d, const double* __restrict__ h, const Scalars* __restrict__ sc,
+                         double* __restrict__ rwc, double* __restrict__ se, double* __restrict__ hit) {
     const double rv = sc->rwc_v;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const double t = static_cast<double>(counts[u]) / l;
+        const int64_t id = node_id[u];
+        const double t = static_cast<double>(counts[id]) / l;
         if (u == v) {
-            rwc[u] = rv;
+            rwc[id] = rv;
         } else {
             const double a = (vol * t) / d[u];
             const double b = 2.0 * h[u];
-            rwc[u] = (a - b) + rv;
+            rwc[id] = (a - b) + rv;
         }
-        if (hit) hit[u] = h[u];
+        if (hit) hit[id] = h[u];
         if (se) {
             double s = 0.0;
             if (u != v && l > 1.0) {
-                const double c1 = static_cast<double>(counts[u]);
-                const double c2 = static_cast<double>(counts_sq[u]);
+                const double c1 = static_cast<double>(counts[id]);
+                const double c2 = static_cast<double>(counts_sq[id]);
                 double var = (c2 - (c1 * c1) / l) / (l - 1.0);
                 var = var > 0.0 ? var : 0.0;
                 s = (vol / d[u]) * sqrt(var / l);
             }
-            se[u] = s;
+            se[id] = s;
         }
     }
 }
@@ -298,20 +301,22 @@ __global__ void assemble(int32_t n, int32_t v, double vol, double l, const uint6
 // and the forests' visit totals estimate d_u (M^-1)_uu by t~_u = C_u / l (as in Lemma 5.2 for
 // one root), so H_{S + u} ~ H_S - d_u h_u^2 / (vol t~_u).  Nodes of S keep H_S.
 __global__ void assemble_group(int32_t n, const uint32_t* __restrict__ gmask, double vol, double l,
-                               const uint64_t* __restrict__ counts, const double* __restrict__ d,
-                               const double* __restrict__ h, const Scalars* __restrict__ sc,
-                               double* __restrict__ marginal, double* __restrict__ hit, double* __restrict__ group) {
+                               const int32_t* __restrict__ node_id, const uint64_t* __restrict__ counts,
+                               const double* __restrict__ d, const double* __restrict__ h,
+                               const Scalars* __restrict__ sc, double* __restrict__ marginal, double* __restrict__ hit,
+                               double* __restrict__ group) {
     const double hs = sc->rwc_v;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t id = node_id[u];   // caller's arrays by input id
         if (u == 0) *group = hs;
-        if (hit) hit[u] = h[u];
+        if (hit) hit[id] = h[u];
         if (grounded(gmask, -1, u)) {
-            marginal[u] = hs;
+            marginal[id] = hs;
         } else {
-            const double t = static_cast<double>(counts[u]) / l;
+            const double t = static_cast<double>(counts[id]) / l;
             const double q = (d[u] * (h[u] * h[u])) / (vol * t);
-            marginal[u] = hs - q;
+            marginal[id] = hs - q;
         }
     }
 }
@@ -323,15 +328,16 @@ __global__ void clear_words(uint32_t* __restrict__ w, int64_t count) {
         w[i] = 0u;
 }
 
-__global__ void mark_roots(const int32_t* __restrict__ roots, int32_t nroots, int32_t n, uint32_t* __restrict__ gmask,
-                           WsHeader* header) {
+__global__ void mark_roots(const int32_t* __restrict__ roots, int32_t nroots, int32_t n,
+                           const int32_t* __restrict__ node_index, uint32_t* __restrict__ gmask, WsHeader* header) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nroots) return;
-    const int32_t r = roots[i];
-    if (r < 0 || r >= n) {
+    const int32_t id = roots[i];
+    if (id < 0 || id >= n) {
         atomicOr(&header->status, static_cast<uint32_t>(kErrNodeRange));
         return;
     }
+    const int32_t r = node_index[id];
     const uint32_t bit = 1u << (r & 31);
     if (atomicOr(&gmask[r >> 5], bit) & bit) atomicOr(&header->status, static_cast<uint32_t>(kErrDupRoot));
 }
@@ -465,15 +471,15 @@ extern "C" int rwc_estimate(const rwc_csr* g, const uint64_t* counts, const uint
     RWC_CHECK(check_workspace(ws, ws_bytes, carve_est(nullptr, n, false).total));
     EstLayout L = carve_est(ws, n, false);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int v = g->pivot;
+    const int v = g->pivot_index;
     const unsigned nb = blocks_for(n, kBlock) < kMaxBlocks ? blocks_for(n, kBlock) : kMaxBlocks;
     hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
     bool async = false;
     RWC_CHECK(pivot_solve(g, v, L, sp, iters, s, &async));
     hipLaunchKernelGGL(pivot_partials, dim3(nb), dim3(kBlock), 0, s, n, g->strength, L.x, L.part);
     hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol, 0.0);
-    hipLaunchKernelGGL(assemble, dim3(nb), dim3(kBlock), 0, s, n, v, g->vol, static_cast<double>(l), counts, counts_sq,
-                       g->strength, L.x, L.sc, rwc, stderr_out, hit);
+    hipLaunchKernelGGL(assemble, dim3(nb), dim3(kBlock), 0, s, n, v, g->vol, static_cast<double>(l), g->node_id, counts,
+                       counts_sq, g->strength, L.x, L.sc, rwc, stderr_out, hit);
     RWC_HIP(hipGetLastError());
     if (!async) RWC_HIP(hipStreamSynchronize(s));
     return RWC_OK;
@@ -503,7 +509,7 @@ extern "C" int rwc_estimate_group(const rwc_csr* g, const int32_t* roots, int32_
     hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
     hipLaunchKernelGGL(clear_words, dim3(blocks_for(L.mask_words, kBlock)), dim3(kBlock), 0, s, L.gmask, L.mask_words);
     hipLaunchKernelGGL(mark_roots, dim3(blocks_for(num_roots, kBlock)), dim3(kBlock), 0, s, roots, num_roots, n,
-                       L.gmask, L.header);
+                       g->node_index, L.gmask, L.header);
     if (!(sp && sp->check_every < 0)) {
         // host-checked mode: a bad root set would leave the system singular, so stop here
         WsHeader h{};
@@ -515,8 +521,8 @@ extern "C" int rwc_estimate_group(const rwc_csr* g, const int32_t* roots, int32_
     RWC_CHECK(pivot_solve(g, -1, L, sp, iters, s, &async));
     hipLaunchKernelGGL(pivot_partials, dim3(nb), dim3(kBlock), 0, s, n, g->strength, L.x, L.part);
     hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol, 0.0);
-    hipLaunchKernelGGL(assemble_group, dim3(nb), dim3(kBlock), 0, s, n, L.gmask, g->vol, static_cast<double>(l), counts,
-                       g->strength, L.x, L.sc, marginal, hit, group_rwc);
+    hipLaunchKernelGGL(assemble_group, dim3(nb), dim3(kBlock), 0, s, n, L.gmask, g->vol, static_cast<double>(l),
+                       g->node_id, counts, g->strength, L.x, L.sc, marginal, hit, group_rwc);
     RWC_HIP(hipGetLastError());
     if (!async) {
         // the root set is validated on the device: report it with the synchronous result

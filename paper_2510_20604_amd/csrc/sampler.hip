@@ -120,20 +120,27 @@ __global__ void zero_outputs(uint64_t* counts, uint64_t* counts_sq, int64_t tota
 // reported through the header (the trees of such a call are not sampled: init_state and the
 // walk still run, but the status tells the caller to discard the outputs).
 __global__ void build_rootmask(const int32_t* __restrict__ roots, int32_t nroots, int32_t n,
-                               uint32_t* __restrict__ rootmask, WsHeader* header) {
+                               const int32_t* __restrict__ node_index, uint32_t* __restrict__ rootmask,
+                               WsHeader* header) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nroots) return;
-    const int32_t r = roots[i];
-    if (r < 0 || r >= n) {
+    const int32_t id = roots[i];
+    if (id < 0 || id >= n) {
         atomicOr(&header->status, static_cast<uint32_t>(kErrNodeRange));
         return;
     }
+    const int32_t r = node_index[id];
     const uint32_t bit = 1u << (r & 31);
     const uint32_t old = atomicOr(&rootmask[r >> 5], bit);
     if (old & bit) atomicOr(&header->status, static_cast<uint32_t>(kErrDupRoot));
 }
 
 __global__ void reset_queue(uint32_t* queue) { *queue = 0; }
+
+// An explicit root arrives as an input id; its internal index is known on the device only.
+__global__ void resolve_root(GraphArgs* graphs, const int32_t* __restrict__ node_index, int32_t root_id) {
+    graphs[0].root = node_index[root_id];
+}
 
 // Folds the departure counts of batch `batch` into the per-node totals, writes the parent
 // dumps of this batch and, unless it is the last batch, resets the slots for the next one.  Thread per node, loop over slots: the reads and
@@ -150,9 +157,10 @@ __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t
         const int64_t first = static_cast<int64_t>(batch) * A.T;
         const int32_t used = static_cast<int32_t>(first >= l ? 0 : ((l - first) < A.T ? (l - first) : A.T));
         const bool root = is_root(A, x);
+        const int64_t id = A.node_id[x];   // outputs are indexed by input id
         for (int d = 0; d < dumps.count; ++d) {
             const uint64_t w = A.state[static_cast<int64_t>(dumps.slot[d]) * A.stride + x];
-            parents[static_cast<int64_t>(dumps.out[d]) * A.n + x] = root ? -1 : static_cast<int32_t>(st_next(w));
+            parents[static_cast<int64_t>(dumps.out[d]) * A.n + id] = root ? -1 : A.node_id[st_next(w)];
         }
         const uint64_t fresh = root ? kInTree : 0ull;
         uint64_t c1 = 0, c2 = 0;
@@ -175,8 +183,8 @@ __global__ void reduce_batch(const GraphArgs* __restrict__ graphs, const int64_t
             c2 += square_count(c);
             if (reset) A.state[static_cast<int64_t>(t) * A.stride + x] = fresh;
         }
-        if (counts) counts[gx] += c1;
-        if (counts_sq) counts_sq[gx] += c2;
+        if (counts) counts[node_off[g] + id] += c1;
+        if (counts_sq) counts_sq[node_off[g] + id] += c2;
     }
 }
 
@@ -460,7 +468,9 @@ int make_setup(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p, voi
         hg[g].guard = steps;
         hg[g].rootmask = (g == 0 && p->num_roots > 0) ? S->L.rootmask : nullptr;
         hg[g].n = graphs[g].n;
-        hg[g].root = (p->root >= 0) ? p->root : graphs[g].pivot;
+        hg[g].node_id = graphs[g].node_id;
+        hg[g].node_index = graphs[g].node_index;
+        hg[g].root = (p->root >= 0) ? -1 : graphs[g].pivot_index;   // an explicit root: resolve_root
         hg[g].graph_word = p->graph_index_base + static_cast<uint32_t>(g);
         hg[g].T = plan.T[g];
         hg[g].W = plan.W[g];
@@ -716,7 +726,8 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
                            nroots > 0 ? L.mask_words : int64_t{0});
         if (nroots > 0)
             hipLaunchKernelGGL(build_rootmask, dim3(blocks_for(nroots, 256)), dim3(256), 0, ls, p->roots, nroots,
-                               graphs[0].n, L.rootmask, L.header);
+                               graphs[0].n, graphs[0].node_index, L.rootmask, L.header);
+        if (p->root >= 0) hipLaunchKernelGGL(resolve_root, dim3(1), dim3(1), 0, ls, L.graphs, graphs[0].node_index, p->root);
         hipLaunchKernelGGL(init_state, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G, plan.total_nodes);
         for (int32_t b = 0; b < plan.batches; ++b) {
             // every graph runs its samples [b*T_g, (b+1)*T_g); graphs with fewer batches idle

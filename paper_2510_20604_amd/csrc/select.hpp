@@ -16,12 +16,13 @@ __device__ __forceinline__ uint32_t rec_word(const uint4& a, const uint4& b, con
     return s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
 }
 
-// RandomNeighbor (Algorithm 3): the neighbour id chosen at a node by the 64 random bits x,
-// read from the node's record wherever it holds the answer.  rec(i) returns word i of the
-// record, already local (registers or LDS).  Unweighted: position floor(x deg / 2^64), inline
-// below kRecInline.  Weighted: the first position k with floor(x S / 2^64) < cdf[k], S the
-// row's total; the record's four CDF values settle it without a read of the row whenever r
-// falls below the fourth, else a binary search over the rest of the row's CDF does.
+// RandomNeighbor (Algorithm 3): the neighbour chosen at a node by the 64 random bits x (its
+// internal index), read from the node's record wherever it holds the answer.  rec(i) returns
+// word i of the record, already local (registers or LDS).  Rows list their neighbours by
+// ascending input id.  Unweighted: position floor(x deg / 2^64), inline below kRecInline.
+// Weighted: the first position k with floor(x S / 2^64) < cdf[k], S the row's total; the
+// record's three CDF values settle it without a read of the row whenever r falls below the
+// third, else a binary search over the rest of the row's CDF does.
 template <class Rec>
 __device__ __forceinline__ uint32_t choose_neighbor(uint64_t x, Rec rec, const RWC_GLOBAL int32_t* col,
                                                     const RWC_GLOBAL uint64_t* cdf) {
@@ -30,7 +31,7 @@ __device__ __forceinline__ uint32_t choose_neighbor(uint64_t x, Rec rec, const R
     uint32_t pos;
     if (cdf == nullptr) {
         pos = static_cast<uint32_t>(select_unweighted(x, static_cast<int32_t>(deg)));
-        if (pos < static_cast<uint32_t>(kRecInline)) return rec(2u + pos);
+        if (pos < static_cast<uint32_t>(kRecInline)) return rec(static_cast<uint32_t>(kRecFirst) + pos);
     } else {
         const uint64_t total = rec(6) | (static_cast<uint64_t>(rec(7)) << 32);
         const uint64_t r = mulhi64(x, total);
@@ -46,7 +47,7 @@ __device__ __forceinline__ uint32_t choose_neighbor(uint64_t x, Rec rec, const R
 #pragma unroll
             for (int i = 0; i < kRecInlineWeighted - 1; ++i)
                 pos += (static_cast<uint32_t>(i) < lim && c[i] <= r) ? 1u : 0u;
-            return rec(2u + pos);
+            return rec(static_cast<uint32_t>(kRecFirst) + pos);
         }
         int32_t lo = kRecInlineWeighted, hi = static_cast<int32_t>(deg) - 1;
         while (lo < hi) {

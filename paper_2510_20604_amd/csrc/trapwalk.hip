@@ -23,6 +23,7 @@ struct TrapArgs {
     const int32_t* col;
     const uint64_t* cdf;
     const uint4* rec;
+    const int32_t* node_index;   // internal index of each input id
     uint64_t* counts;
     uint64_t* counts_sq;
     uint64_t* total_steps;
@@ -33,7 +34,7 @@ struct TrapArgs {
     int64_t walk_begin;
     uint64_t seed;
     int32_t n;
-    int32_t trap;
+    int32_t trap;                // input id
     uint32_t graph_word;
 };
 
@@ -61,8 +62,11 @@ __global__ void __launch_bounds__(kWave) trap_walks(TrapArgs A) {
     const uint64_t starts = static_cast<uint64_t>(A.n - 1);
     // the walk counter is 64 bits wide: two 32-bit words updated by one 64-bit atomic
     auto* q64 = reinterpret_cast<unsigned long long*>(A.queue);
+    // walks are enumerated and keyed by input ids (u); the walk itself moves over internal
+    // indices (x, y; xs the start's, trap_x the trap's)
+    const uint32_t trap_x = static_cast<uint32_t>(A.node_index[A.trap]);
     bool busy = false, done = false;
-    uint32_t u = 0, x = 0, count = 0;
+    uint32_t u = 0, x = 0, xs = 0, count = 0;
     uint32_t i = 0;
     uint64_t s = 0, steps = 0;
     uint32_t err = 0;
@@ -81,7 +85,8 @@ __global__ void __launch_bounds__(kWave) trap_walks(TrapArgs A) {
                     const uint64_t j = w % starts;
                     i = static_cast<uint32_t>(static_cast<uint64_t>(A.walk_begin) + w / starts);
                     u = static_cast<uint32_t>(j) + (static_cast<int64_t>(j) >= A.trap ? 1u : 0u);
-                    x = u;
+                    xs = static_cast<uint32_t>(A.node_index[u]);
+                    x = xs;
                     s = 0;
                     count = 1;
                     busy = true;
@@ -97,7 +102,7 @@ __global__ void __launch_bounds__(kWave) trap_walks(TrapArgs A) {
             const uint64_t r = philox_x64(static_cast<uint32_t>(s), u, i, A.graph_word, k0, k1);
             const uint32_t y = choose_neighbor(r, [&](uint32_t t) { return rec_word(ra, rb, rc, rd, t); }, col, cdf);
             ++s;
-            if (y == static_cast<uint32_t>(A.trap)) {
+            if (y == trap_x) {
                 atomicAdd(reinterpret_cast<unsigned long long*>(&A.counts[u]), static_cast<unsigned long long>(count));
                 if (A.counts_sq)
                     atomicAdd(reinterpret_cast<unsigned long long*>(&A.counts_sq[u]),
@@ -109,7 +114,7 @@ __global__ void __launch_bounds__(kWave) trap_walks(TrapArgs A) {
                 steps += s;
                 busy = false;
             } else {
-                count += (y == u) ? 1u : 0u;
+                count += (y == xs) ? 1u : 0u;
                 x = y;
             }
         }
@@ -171,6 +176,7 @@ extern "C" int rwc_sample_trap_walks(const rwc_csr* g, const rwc_trap_params* p,
     A.col = g->col;
     A.cdf = g->weighted ? g->cdf : nullptr;
     A.rec = reinterpret_cast<const uint4*>(g->rec);
+    A.node_index = g->node_index;
     A.counts = counts;
     A.counts_sq = counts_sq;
     A.total_steps = total_steps;

@@ -3,7 +3,8 @@
 // tables they read.  Included by sampler.hip, which plans and launches them.
 //
 // RandomNeighbor(u) at the k-th departure from u in sample i of graph word g is
-// Philox4x32-10((k, u, i, g), seed), optionally placed in its stratum (stratified_word).  A
+// Philox4x32-10((k, u, i, g), seed), optionally placed in its stratum (stratified_word), with
+// u the node's input id (record word kRecId); the kernels address memory by internal index.  A
 // node's successive choices are therefore fixed in advance, which makes the tree and every
 // count independent of the order in which walks are run (cycle popping), so results match the
 // serial order of Algorithm 3 exactly.
@@ -24,7 +25,10 @@ struct GraphArgs {
     uint64_t* state;        // [T][stride]
     int64_t stride;         // words per tree slot (n rounded up to a multiple of 8)
     uint64_t guard;         // per-tree step guard (one walker) or iteration guard (team)
-    const uint32_t* rootmask;   // bitmap of the root set (n bits), or null: the root is `root`
+    const int32_t* node_id;     // input id of each internal index (keys, checksums, outputs)
+    const int32_t* node_index;  // internal index of each input id
+    const uint32_t* rootmask;   // bitmap of the root set (n bits, internal indices), or null:
+                                // the root is `root` (an internal index)
     int32_t n;
     int32_t root;
     uint32_t graph_word;
@@ -100,8 +104,9 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
                 rd = load_u4(q + 3);
                 rh_node = x;
             }
-            uint64_t r = philox_x64(k, x, sw, gw, k0, k1);
-            if constexpr (kStrat) r = stratified_word(r, k, x, sw, gw, k0, k1, G.strata);
+            const uint32_t xid = rec_word(ra, rb, rc, rd, kRecId);
+            uint64_t r = philox_x64(k, xid, sw, gw, k0, k1);
+            if constexpr (kStrat) r = stratified_word(r, k, xid, sw, gw, k0, k1, G.strata);
             const uint32_t y = choose_neighbor(r, [&](uint32_t i) { return rec_word(ra, rb, rc, rd, i); }, col, cdf);
             st[x] = st_make(y, k + 1);
             const uint64_t wy = st[y];
@@ -137,7 +142,7 @@ __device__ __forceinline__ void grow_tree(const GraphArgs& G, int32_t slot, uint
                 const uint64_t w = st[x];
                 const uint32_t p = st_next(w);
                 st[x] = w | kInTree;
-                if (want_hash) h += splitmix64((static_cast<uint64_t>(x) << 32) | p);
+                if (want_hash) h += splitmix64((static_cast<uint64_t>(G.node_id[x]) << 32) | G.node_id[p]);
                 x = p;
                 if (++retr > static_cast<uint32_t>(n)) {
                     err |= kErrRetrace;
@@ -389,12 +394,11 @@ __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool
         uint32_t k = 0;
         if (mode == tWalk) {
             if (rh_node != h) keep_record(h);
-            // the draw needs only (departure, head, sample): it runs while the record and the
-            // previous iteration's accesses are in flight, not after the wait
-            k = hk;
-            uint64_t r = philox_x64(k, h, sw, gw, k0, k1);
-            if constexpr (kStrat) r = stratified_word(r, k, h, sw, gw, k0, k1, G.strata);
             wait_vm();
+            k = hk;
+            const uint32_t hid = rec_at(kRecId);   // the head's input id keys its stack
+            uint64_t r = philox_x64(k, hid, sw, gw, k0, k1);
+            if constexpr (kStrat) r = stratified_word(r, k, hid, sw, gw, k0, k1, G.strata);
             node = choose_neighbor(r, rec_at, col, cdf);
         } else if (mode == tStart) {
             node = j;
@@ -485,7 +489,8 @@ __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool
                 // chase of the path prefix older than the ring: mark it INTREE
                 st_node = c;
                 st_word = (w & ~(kOwned | (0x3Full << 56))) | kInTree;
-                if (want_hash) hsum += splitmix64((static_cast<uint64_t>(c) << 32) | st_next(w));
+                if (want_hash)
+                    hsum += splitmix64((static_cast<uint64_t>(G.node_id[c]) << 32) | G.node_id[st_next(w)]);
                 if (st_next(w) == cstop)
                     mode = tIdle;
                 else
@@ -565,7 +570,8 @@ __device__ void grow_team(const GraphArgs& G, StatePtr st, uint64_t sample, bool
                 ring_attach = true;
                 if (want_hash)
                     for (uint32_t d = 0; d < nbuf; ++d)
-                        hsum += splitmix64((static_cast<uint64_t>(buf(d)) << 32) | (d == 0 ? act_v : buf(d - 1)));
+                        hsum += splitmix64((static_cast<uint64_t>(G.node_id[buf(d)]) << 32) |
+                                           G.node_id[d == 0 ? act_v : buf(d - 1)]);
                 cstop = buf(nbuf - 1);
                 if (cstop == j) mode = tIdle;
             }
@@ -769,14 +775,15 @@ __device__ __forceinline__ void run_team_item_lds(const GraphArgs* __restrict__ 
         for (int32_t x = static_cast<int32_t>(tl); x < n; x += W) {
             const uint64_t w = st[x];
             const uint32_t c = st_cnt(w);
+            const int64_t id = G.node_id[x];   // outputs are indexed by input id
             if (c) {
-                atomicAdd(reinterpret_cast<unsigned long long*>(&counts[off + x]), static_cast<unsigned long long>(c));
+                atomicAdd(reinterpret_cast<unsigned long long*>(&counts[off + id]), static_cast<unsigned long long>(c));
                 if (counts_sq)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&counts_sq[off + x]),
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&counts_sq[off + id]),
                               static_cast<unsigned long long>(square_count(c)));
             }
             if (dump_out >= 0)
-                parents[static_cast<int64_t>(dump_out) * n + x] = is_root(x) ? -1 : static_cast<int32_t>(st_next(w));
+                parents[static_cast<int64_t>(dump_out) * n + id] = is_root(x) ? -1 : G.node_id[st_next(w)];
         }
     }
     for (int off = W / 2; off > 0; off >>= 1) {

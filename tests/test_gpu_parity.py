@@ -48,52 +48,75 @@ def _u64(t):
 
 @pytest.mark.parametrize("name", CASES)
 def test_csr_matches_oracle(name):
+    """The device CSR in its internal order against the oracle's CSR in input order: the order
+    (descending weighted degree, ties by id, on heavy-tailed graphs; else the identity), every
+    row mapped through it, the records, the start order and the edge ids."""
     g = _case(name)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     o = W.OracleCSR(g.n, g.src, g.dst, g.w)
-    np.testing.assert_array_equal(Gd.row_ptr().cpu().numpy(), o.row_ptr)
-    np.testing.assert_array_equal(Gd.col().cpu().numpy(), o.col)
-    np.testing.assert_array_equal(Gd.strength().cpu().numpy(), o.strength)
+    nid = Gd.node_id().cpu().numpy()
+    nix = Gd.node_index().cpu().numpy()
+    np.testing.assert_array_equal(np.sort(nid), np.arange(g.n))
+    np.testing.assert_array_equal(nix[nid], np.arange(g.n))
+    deg_in = np.diff(o.row_ptr)
+    heavy = int(deg_in.max()) * g.n > 8 * g.m
+    assert Gd.internal_order == int(heavy)
+    if heavy:
+        want = np.lexsort((np.arange(g.n), -o.strength))
+        np.testing.assert_array_equal(nid, want)
+    else:
+        np.testing.assert_array_equal(nid, np.arange(g.n))
     assert Gd.pivot == o.pivot
+    assert int(Gd.csr.pivot_index) == int(nix[o.pivot])
     assert Gd.vol == o.vol
+    deg = deg_in[nid]
+    row_ptr = Gd.row_ptr().cpu().numpy()
+    np.testing.assert_array_equal(row_ptr, np.concatenate([[0], np.cumsum(deg)]))
+    col = Gd.col().cpu().numpy()
+    # internal row x holds input node nid[x]'s row, neighbours by ascending input id
+    perm = np.concatenate([np.arange(o.row_ptr[p], o.row_ptr[p + 1]) for p in nid]) if g.n else np.zeros(0, int)
+    np.testing.assert_array_equal(nid[col], o.col[perm])
+    np.testing.assert_array_equal(Gd.strength().cpu().numpy(), o.strength[nid])
     if g.w is not None:
-        np.testing.assert_array_equal(_u64(Gd.cdf()), o.cdf)
-        np.testing.assert_array_equal(Gd.weight().cpu().numpy().astype(np.float64), o.weight)
-    # 64-byte node records: degree, row offset, inline neighbours (and CDF values with the
-    # row's total); unused words are zero
+        np.testing.assert_array_equal(_u64(Gd.cdf()), o.cdf[perm])
+        np.testing.assert_array_equal(Gd.weight().cpu().numpy().astype(np.float64), o.weight[perm])
+    # 64-byte node records: degree, row offset, input id, inline neighbours (and CDF values with
+    # the row's total); unused words are zero
     rec = Gd.rec().cpu().numpy().reshape(g.n, 16).view(np.uint32)
-    deg = np.diff(o.row_ptr)
     np.testing.assert_array_equal(rec[:, 0], deg)
-    np.testing.assert_array_equal(rec[:, 1], o.row_ptr[:-1])
-    inline = 4 if g.w is not None else 14
+    np.testing.assert_array_equal(rec[:, 1], row_ptr[:-1])
+    np.testing.assert_array_equal(rec[:, 2], nid)
+    inline = 3 if g.w is not None else 13
     lo32 = np.uint64(0xFFFFFFFF)
-    for u in range(0, g.n, max(1, g.n // 200)):
-        b, k = o.row_ptr[u], min(deg[u], inline)
+    cdf = _u64(Gd.cdf()) if g.w is not None else None
+    for x in range(0, g.n, max(1, g.n // 200)):
+        b, k = row_ptr[x], min(deg[x], inline)
         want = np.zeros(16, dtype=np.uint32)
-        want[0], want[1] = deg[u], b
-        want[2:2 + k] = o.col[b:b + k]
+        want[0], want[1], want[2] = deg[x], b, nid[x]
+        want[3:3 + k] = col[b:b + k]
         if g.w is not None:
-            c = o.cdf[b:b + k].astype(np.uint64)
+            c = cdf[b:b + k].astype(np.uint64)
             want[8:8 + 2 * k:2] = (c & lo32).astype(np.uint32)
             want[9:9 + 2 * k:2] = (c >> np.uint64(32)).astype(np.uint32)
-            total = np.uint64(o.cdf[o.row_ptr[u + 1] - 1])
+            total = np.uint64(cdf[row_ptr[x + 1] - 1])
             want[6], want[7] = np.uint32(total & lo32), np.uint32(total >> np.uint64(32))
-        np.testing.assert_array_equal(rec[u], want, err_msg=f"record of node {u}")
-    # breadth-first start order: a permutation starting at the pivot, distances non-decreasing
+        np.testing.assert_array_equal(rec[x], want, err_msg=f"record of internal node {x}")
+    # breadth-first start order (internal indices): a permutation starting at the pivot,
+    # distances non-decreasing
     order = Gd.bfs_order().cpu().numpy()
     np.testing.assert_array_equal(np.sort(order), np.arange(g.n))
-    assert order[0] == o.pivot
+    assert order[0] == nix[o.pivot]
     import scipy.sparse as sp
     import scipy.sparse.csgraph as csg
     A = sp.csr_matrix((np.ones(o.col.shape[0]), o.col, o.row_ptr), shape=(g.n, g.n))
     dist = csg.shortest_path(A, unweighted=True, indices=o.pivot)
-    assert np.all(np.diff(dist[order]) >= 0)
+    assert np.all(np.diff(dist[nid[order]]) >= 0)
     assert Gd.csr.bfs_depth == int(dist.max())        # the pivot's eccentricity
     # edge_id maps every entry back to an input edge with matching endpoints
     eid = Gd.edge_id().cpu().numpy()
-    rows = np.repeat(np.arange(g.n), np.diff(o.row_ptr))
+    rows = np.repeat(nid, deg)
     a, b = g.src[eid], g.dst[eid]
-    assert np.all(((a == rows) & (b == o.col)) | ((b == rows) & (a == o.col)))
+    assert np.all(((a == rows) & (b == nid[col])) | ((b == rows) & (a == nid[col])))
 
 
 @pytest.mark.parametrize("bad,code", [("self_loop", -3), ("dup", -4), ("range", -2), ("weight", -5),
