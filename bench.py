@@ -40,12 +40,13 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILES = {"rmat23": os.path.join(ROOT, "profiles", "wilson_team_rmat23_traffic.json"),
                  "ba1m": os.path.join(ROOT, "profiles", "wilson_team_ba1m_traffic.json")}
 SAMPLER_SOURCES = ("paper_2510_20604_amd/csrc/walk.hpp", "paper_2510_20604_amd/csrc/select.hpp",
-                   "paper_2510_20604_amd/csrc/device.hpp")
+                   "paper_2510_20604_amd/csrc/device.hpp", "paper_2510_20604_amd/csrc/csr_build.hip")
 
 
 def sampler_code_sha256() -> str:
-    """SHA-256 of the walk kernel's sources with comments removed and whitespace collapsed: the
-    committed counters stay valid exactly while the code they were taken on is unchanged."""
+    """SHA-256 of the walk kernel's sources and of the CSR build (which decides the node order in
+    memory), comments removed and whitespace collapsed: the committed counters stay valid
+    exactly while the code they were taken on is unchanged."""
     import hashlib
     import re
     h = hashlib.sha256()
