@@ -44,7 +44,8 @@ typedef enum rwc_status {
     RWC_ERR_STEP_LIMIT = -9,       /* a tree needed more walk steps than max_steps_per_tree  */
     RWC_ERR_COUNT_OVERFLOW = -10,  /* a node departed 2^24 times within one tree             */
     RWC_ERR_NOT_CONVERGED = -11,   /* the pivot/adjoint solve missed its tolerance           */
-    RWC_ERR_HIP = -12              /* a HIP runtime call failed                              */
+    RWC_ERR_HIP = -12,             /* a HIP runtime call failed                              */
+    RWC_ERR_BREAKDOWN = -13        /* FastChol: a non-positive pivot in the incomplete factor */
 } rwc_status;
 
 /* A graph in device memory, produced by rwc_build_csr.  All pointers point into the
@@ -451,6 +452,51 @@ int rwc_backward_workspace(const rwc_csr* g, const rwc_backward_params* bp, size
  * check_every iterations). */
 int rwc_backward(const rwc_csr* g, const double* grad_rwc_dev, const rwc_backward_params* bp,
                  double* grad_w_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * FastChol (Section 4, Algorithm 2): the matrix-factorisation estimate of diag(calL_v^{-1}),
+ * the second of the paper's two algorithms, on the GPU.
+ *
+ * 1. IChol(calL_v, delta) (Lemma 4.1): incomplete Cholesky of the grounded normalised
+ *    Laplacian (pivot v removed, columns in ascending input id), left-looking; an off-diagonal
+ *    entry x of column j is kept when |x| >= delta * ||calL_v(j:N, j)||_1 (the threshold rule of
+ *    the ICT variant of MATLAB's ichol, which the paper's experiments use with delta = 1e-4).
+ * 2. The sparse approximate inverse S~ of the factor, right to left (Lemma 4.3's recursion
+ *    over a sliding window of w_u = min(floor(w_s (1 + d_u / d_max)), N) later columns), each
+ *    column of more than zeta nonzeros cut to the shortest prefix, by decreasing magnitude,
+ *    whose dropped tail has 1-norm <= eps_p times the column's (Algorithm 2's sparsification);
+ *    tau~_u = ||S~(:, u)||^2 (Section 4: (calL_v^{-1})_uu ~ ||R^{-1} e_u||^2).
+ * Both are chains of dependent columns; one wave runs each, column by column, in the serial
+ * algorithm's order of floating-point operations.  Feed tau~ to rwc_estimate_diag for RWC.
+ * ------------------------------------------------------------------------------------- */
+typedef struct rwc_fastchol_params {
+    double droptol;            /* IChol drop tolerance delta (>= 0; the paper uses 1e-4)         */
+    double window;             /* base window width w_s (>= 1)                                   */
+    double eps_p;              /* sparsification tolerance (>= 0)                                */
+    int32_t zeta;              /* columns of at most zeta nonzeros are kept whole (>= 0)         */
+    int32_t reserved;
+    int64_t factor_capacity;   /* entries of the factor the workspace holds (>= n - 1); a factor
+                                  that needs more stops with RWC_ERR_TOO_LARGE                */
+    int64_t inverse_capacity;  /* entries of S~ the workspace holds                          */
+} rwc_fastchol_params;
+
+int rwc_fastchol_workspace(const rwc_csr* g, const rwc_fastchol_params* p, size_t* bytes);
+
+/* tau_dev: double [n] output by input id (0 at the pivot).  Stream-ordered: the call enqueues
+ * three single-wave kernels and returns; rwc_workspace_status reports RWC_ERR_TOO_LARGE (a
+ * pool, or a column's 4096-entry ordering buffer, was too small) or RWC_ERR_BREAKDOWN (a
+ * non-positive pivot), after which tau_dev is meaningless. */
+int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, double* tau_dev, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* Entries of the factor and of S~ the last rwc_fastchol on `ws` produced (synchronises). */
+int rwc_fastchol_sizes(const void* ws, int64_t* factor_entries, int64_t* inverse_entries, void* stream);
+
+/* AppRWC (Algorithm 1) from an estimate of diag(calL_v^{-1}) itself (FastChol's tau~) instead
+ * of visit totals: rwc_estimate with t~ = diag_dev (double [n] by input id; the pivot's entry is
+ * not read).  Same workspace, parameters, outputs and synchronisation as rwc_estimate. */
+int rwc_estimate_diag(const rwc_csr* g, const double* diag_dev, const rwc_solve_params* sp, double* rwc_dev,
+                      double* hit_dev, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
 const char* rwc_status_string(int status);
 /* Copies the calling thread's last error detail into buf (NUL-terminated); returns its

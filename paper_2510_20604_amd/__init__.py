@@ -10,6 +10,6 @@ from . import _lib
 _lib.lib()  # load librwc.so now: fail loudly at import, never later on a silent path
 
 from .api import (Graph, RWCFunction, as_uint64, autotune, autotune_batch, backward, dense_g, estimate,  # noqa: F401,E402
-                  estimate_group, prepare_sampling, random_walk_centrality, release_cached_graphs,
-                  sample_forests, sample_trap_walks, workspace_status)
+                  estimate_diag, estimate_group, fastchol, prepare_sampling, random_walk_centrality,
+                  release_cached_graphs, sample_forests, sample_trap_walks, workspace_status)
 from ._lib import RWCError  # noqa: F401,E402

@@ -32,7 +32,7 @@ STATUS = {
     0: "RWC_OK", -1: "RWC_ERR_INVALID_ARG", -2: "RWC_ERR_NODE_RANGE", -3: "RWC_ERR_SELF_LOOP",
     -4: "RWC_ERR_DUP_EDGE", -5: "RWC_ERR_WEIGHT_RANGE", -6: "RWC_ERR_DISCONNECTED",
     -7: "RWC_ERR_TOO_LARGE", -8: "RWC_ERR_WORKSPACE", -9: "RWC_ERR_STEP_LIMIT",
-    -10: "RWC_ERR_COUNT_OVERFLOW", -11: "RWC_ERR_NOT_CONVERGED", -12: "RWC_ERR_HIP",
+    -10: "RWC_ERR_COUNT_OVERFLOW", -11: "RWC_ERR_NOT_CONVERGED", -12: "RWC_ERR_HIP", -13: "RWC_ERR_BREAKDOWN",
 }
 
 
@@ -82,6 +82,11 @@ class BackwardParams(ctypes.Structure):
                 ("max_support", c_i32)]
 
 
+class FastcholParams(ctypes.Structure):
+    _fields_ = [("droptol", c_dbl), ("window", c_dbl), ("eps_p", c_dbl), ("zeta", c_i32), ("reserved", c_i32),
+                ("factor_capacity", c_i64), ("inverse_capacity", c_i64)]
+
+
 # (name, restype, argtypes) for every entry point declared in include/*.h
 SIGNATURES = [
     ("rwc_build_csr_workspace", c_i32, [c_i32, c_i64, c_i32, ctypes.POINTER(c_sz)]),
@@ -107,6 +112,11 @@ SIGNATURES = [
     ("rwc_estimate_group_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(c_sz)]),
     ("rwc_estimate_group", c_i32, [ctypes.POINTER(RwcCsr), c_vp, c_i32, c_vp, c_i64, ctypes.POINTER(SolveParams),
                                    c_vp, c_vp, c_vp, ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_estimate_diag", c_i32, [ctypes.POINTER(RwcCsr), c_vp, ctypes.POINTER(SolveParams), c_vp, c_vp,
+                                  ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),
+    ("rwc_fastchol_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(FastcholParams), ctypes.POINTER(c_sz)]),
+    ("rwc_fastchol", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(FastcholParams), c_vp, c_vp, c_sz, c_vp]),
+    ("rwc_fastchol_sizes", c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), c_vp]),
     ("rwc_backward_workspace", c_i32, [ctypes.POINTER(RwcCsr), ctypes.POINTER(BackwardParams), ctypes.POINTER(c_sz)]),
     ("rwc_backward", c_i32, [ctypes.POINTER(RwcCsr), c_vp, ctypes.POINTER(BackwardParams), c_vp,
                              ctypes.POINTER(c_i32), c_vp, c_sz, c_vp]),

@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (BackwardParams, BatchTuneResult, RwcCsr, SampleOutputs, SampleParams, SolveParams, TrapParams,
+from ._lib import (BackwardParams, BatchTuneResult, FastcholParams, RwcCsr, SampleOutputs, SampleParams, SolveParams,
+                   TrapParams,
                    TuneResult, check)
 
 
@@ -386,6 +387,53 @@ def estimate(graph: Graph, counts: torch.Tensor, l: int, counts_sq: torch.Tensor
                          _ptr(ws), ws.numel(), _stream()),
           "rwc_estimate")
     return {**out, "iters": iters.value, "workspace": ws}
+
+
+def estimate_diag(graph: Graph, diag: torch.Tensor, tol: float = 1e-12, max_iter: int = 0,
+                  want_hit: bool = True) -> dict:
+    """RWC from an estimate of diag(calL_v^{-1}) by input id (FastChol's tau~): rwc_estimate_diag."""
+    L = _lib.lib()
+    dev = graph.device
+    size = ctypes.c_size_t()
+    check(L.rwc_estimate_workspace(ctypes.byref(graph.csr), ctypes.byref(size)), "rwc_estimate_workspace")
+    ws = _workspace(size.value, dev)
+    rwc = torch.empty(graph.n, dtype=torch.float64, device=dev)
+    hit = torch.empty(graph.n, dtype=torch.float64, device=dev) if want_hit else None
+    sp = SolveParams(tol=tol, max_iter=max_iter, check_every=0)
+    iters = ctypes.c_int32()
+    check(L.rwc_estimate_diag(ctypes.byref(graph.csr), _ptr(diag), ctypes.byref(sp), _ptr(rwc), _ptr(hit),
+                              ctypes.byref(iters), _ptr(ws), ws.numel(), _stream()), "rwc_estimate_diag")
+    return {"rwc": rwc, "hit": hit, "iters": iters.value}
+
+
+def fastchol(graph: Graph, droptol: float = 1e-4, window: float = 16.0, zeta: int = 16, eps_p: float = 1e-3,
+             factor_capacity: int | None = None, inverse_capacity: int | None = None, sync: bool = True) -> dict:
+    """FastChol's tau~ (rwc_fastchol): the estimate of diag(calL_v^{-1}) by input id from the
+    threshold incomplete Cholesky factor and its windowed, sparsified inverse (Section 4,
+    Algorithm 2).  The pools default to 512 (n - 1) entries each for the factor and for S~, at
+    most a full triangle.  With sync=True waits, raises on a device-side error and
+    also returns the number of entries of the factor and of S~."""
+    L = _lib.lib()
+    dev = graph.device
+    n1 = graph.n - 1
+    tri = n1 * (n1 + 1) // 2
+    p = FastcholParams(droptol=float(droptol), window=float(window), eps_p=float(eps_p), zeta=int(zeta),
+                       factor_capacity=int(factor_capacity if factor_capacity is not None else min(512 * n1, tri)),
+                       inverse_capacity=int(inverse_capacity if inverse_capacity is not None else min(512 * n1, tri)))
+    size = ctypes.c_size_t()
+    check(L.rwc_fastchol_workspace(ctypes.byref(graph.csr), ctypes.byref(p), ctypes.byref(size)),
+          "rwc_fastchol_workspace")
+    ws = _workspace(size.value, dev)
+    tau = torch.empty(graph.n, dtype=torch.float64, device=dev)
+    check(L.rwc_fastchol(ctypes.byref(graph.csr), ctypes.byref(p), _ptr(tau), _ptr(ws), ws.numel(), _stream()),
+          "rwc_fastchol")
+    res = {"tau": tau, "workspace": ws}
+    if sync:
+        check(L.rwc_workspace_status(_ptr(ws), _stream()), "rwc_fastchol (device status)")
+        fe, ie = ctypes.c_int64(), ctypes.c_int64()
+        check(L.rwc_fastchol_sizes(_ptr(ws), ctypes.byref(fe), ctypes.byref(ie), _stream()), "rwc_fastchol_sizes")
+        res["factor_entries"], res["inverse_entries"] = fe.value, ie.value
+    return res
 
 
 def estimate_group(graph: Graph, roots, counts: torch.Tensor, l: int, tol: float = 1e-12, max_iter: int = 0,

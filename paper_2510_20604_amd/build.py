@@ -17,10 +17,11 @@ OUT = os.path.join(PKG, "librwc.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["common.cpp", "csr_build.hip", "sampler.hip", "trapwalk.hip", "estimate.hip", "backward.hip",
+           "fastchol.hip",
            "probe.hip", "autotune.cpp"]
 # Translation units whose floating-point results are compared against FP64 references:
 # no fused multiply-add contraction.
-NO_CONTRACT = {"estimate.hip", "backward.hip"}
+NO_CONTRACT = {"estimate.hip", "backward.hip", "fastchol.hip"}
 
 ARCH = "gfx950"
 COMMON = [

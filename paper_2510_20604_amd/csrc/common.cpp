@@ -42,6 +42,9 @@ int device_error_to_status(uint32_t bits) {
         return fail(RWC_ERR_WEIGHT_RANGE, "the total weight times 2^24 reaches 2^64 (fixed-point overflow)");
     if (bits & kErrDupRoot) return fail(RWC_ERR_INVALID_ARG, "the root set lists a node twice");
     if (bits & kErrNonFinite) return fail(RWC_ERR_INVALID_ARG, "an input value is not finite");
+    if (bits & kErrCapacity)
+        return fail(RWC_ERR_TOO_LARGE, "the factor or inverse pool, or a column's sort buffer, is full");
+    if (bits & kErrPivot) return fail(RWC_ERR_BREAKDOWN, "the incomplete factorization met a non-positive pivot");
     if (bits & kErrNotConverged)
         return fail(RWC_ERR_NOT_CONVERGED, "the solve missed its tolerance within max_iter iterations");
     if (bits & kErrStepLimit)

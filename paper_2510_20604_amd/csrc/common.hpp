@@ -82,6 +82,8 @@ enum DeviceError : uint32_t {
     kErrNotConverged = 1u << 10,
     kErrDupRoot = 1u << 11,
     kErrNonFinite = 1u << 12,
+    kErrCapacity = 1u << 13,    // a FastChol pool or a column's sort buffer is full
+    kErrPivot = 1u << 14,       // a non-positive pivot in the incomplete factorization
 };
 
 int device_error_to_status(uint32_t bits);

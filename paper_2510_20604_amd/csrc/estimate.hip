@@ -294,6 +294,26 @@ __global__ void assemble(int32_t n, int32_t v, double vol, double l, const int32
     }
 }
 
+// Eq. (3) from a given estimate of diag(calL_v^{-1}) (FastChol's tau~), by input id.
+__global__ void assemble_diag(int32_t n, int32_t v, double vol, const int32_t* __restrict__ node_id,
+                              const double* __restrict__ diag, const double* __restrict__ d,
+                              const double* __restrict__ h, const Scalars* __restrict__ sc, double* __restrict__ rwc,
+                              double* __restrict__ hit) {
+    const double rv = sc->rwc_v;
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t id = node_id[u];
+        if (u == v) {
+            rwc[id] = rv;
+        } else {
+            const double a = (vol * diag[id]) / d[u];
+            const double b = 2.0 * h[u];
+            rwc[id] = (a - b) + rv;
+        }
+        if (hit) hit[id] = h[u];
+    }
+}
+
 // Group RWC of a root set S (hitting time to the set, H_S = sum_u pi_u h_u with h solving the
 // system grounded at S) and, for every node u, the estimate of H_{S + u} from the S-rooted
 // forests: removing u from the grounded system is a rank-one update, so with M = L_S,
@@ -480,6 +500,29 @@ extern "C" int rwc_estimate(const rwc_csr* g, const uint64_t* counts, const uint
     hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol, 0.0);
     hipLaunchKernelGGL(assemble, dim3(nb), dim3(kBlock), 0, s, n, v, g->vol, static_cast<double>(l), g->node_id, counts,
                        counts_sq, g->strength, L.x, L.sc, rwc, stderr_out, hit);
+    RWC_HIP(hipGetLastError());
+    if (!async) RWC_HIP(hipStreamSynchronize(s));
+    return RWC_OK;
+}
+
+extern "C" int rwc_estimate_diag(const rwc_csr* g, const double* diag, const rwc_solve_params* sp, double* rwc,
+                                 double* hit, int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!g || !diag || !rwc) return fail(RWC_ERR_INVALID_ARG, "g, diag and rwc must not be null");
+    RWC_CHECK(check_solve_params(sp));
+    const int32_t n = g->n;
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_est(nullptr, n, false).total));
+    EstLayout L = carve_est(ws, n, false);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int v = g->pivot_index;
+    const unsigned nb = blocks_for(n, kBlock) < kMaxBlocks ? blocks_for(n, kBlock) : kMaxBlocks;
+    hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
+    bool async = false;
+    RWC_CHECK(pivot_solve(g, v, L, sp, iters, s, &async));
+    hipLaunchKernelGGL(pivot_partials, dim3(nb), dim3(kBlock), 0, s, n, g->strength, L.x, L.part);
+    hipLaunchKernelGGL(scalars_step, dim3(1), dim3(kBlock), 0, s, L.part, static_cast<int>(nb), L.sc, 3, g->vol, 0.0);
+    hipLaunchKernelGGL(assemble_diag, dim3(nb), dim3(kBlock), 0, s, n, v, g->vol, g->node_id, diag, g->strength, L.x,
+                       L.sc, rwc, hit);
     RWC_HIP(hipGetLastError());
     if (!async) RWC_HIP(hipStreamSynchronize(s));
     return RWC_OK;

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_more_than_one_gpu_exits_with_a_message():
-    for cfg in ("ba1m", "batch256", "grad100k", "rmat23", "trap", "group", "strata"):
+    for cfg in ("ba1m", "batch256", "grad100k", "rmat23", "trap", "group", "strata", "fastchol"):
         out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--config", cfg],
                              capture_output=True, text=True, timeout=120)
         assert out.returncode == 2
