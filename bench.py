@@ -666,8 +666,9 @@ def fastchol_main(args):
     """FastChol (Section 4, Algorithm 2) on the GPU: the threshold incomplete Cholesky factor
     (delta = 1e-4, columns in input order) and its windowed, sparsified inverse (w_s = zeta =
     ceil(log2 n), eps_p = 1e-3), then the same AppRWC assembly.  Per graph with stored exact RWC:
-    the device time of both chains and the assembly, the MRE, the factor's size, and the serial
-    oracle's time on the host beside it."""
+    the device time of the estimate (dense right-looking IChol, the default at these sizes) and of
+    the assembly, the left-looking one-wave chain timed beside it (same bits), the MRE, the
+    factor's size, and the serial oracle's time on the host."""
     import torch
     import paper_2510_20604_amd as P
     import rwcgen
@@ -688,8 +689,14 @@ def fastchol_main(args):
         gpu_s = time.perf_counter() - t0
         rwc = e["rwc"].cpu().numpy()
         mre = float(np.mean(np.abs(rwc[nodes] - exact) / exact))
+        t0 = time.perf_counter()
+        rc = P.fastchol(G, method="chain", **kw)
+        torch.cuda.synchronize()
+        chain_s = time.perf_counter() - t0
         item = {"workload": desc, "n": g.n, "m": g.m, "params": kw, "gpu_ms": round(1e3 * gpu_s, 2), "mre": mre,
-                "factor_entries": r["factor_entries"], "inverse_entries": r["inverse_entries"]}
+                "factor_entries": r["factor_entries"], "inverse_entries": r["inverse_entries"],
+                "ichol_method": "dense", "chain_ms": round(1e3 * chain_s, 2),
+                "chain_tau_bit_identical": bool(torch.equal(rc["tau"], r["tau"]))}
         if not args.no_cpu_baseline:
             from oracle import fastchol as OF
             t1 = time.perf_counter()

@@ -469,12 +469,22 @@ int rwc_backward(const rwc_csr* g, const double* grad_rwc_dev, const rwc_backwar
  * Both are chains of dependent columns; one wave runs each, column by column, in the serial
  * algorithm's order of floating-point operations.  Feed tau~ to rwc_estimate_diag for RWC.
  * ------------------------------------------------------------------------------------- */
+/* How rwc_fastchol factors calL_v; both give the same factor bit for bit.
+ *   RWC_FASTCHOL_DENSE: right-looking on an (n-1) x (n-1) double array in the workspace, one
+ *     launch per column, the column's updates spread over the GPU (n - 1 <= 2^20);
+ *   RWC_FASTCHOL_CHAIN: left-looking on one wave, sparse throughout (any n; a column may reach
+ *     at most 4096 kept entries);
+ *   RWC_FASTCHOL_AUTO: DENSE while the array is at most 8 GiB ((n-1) <= 32768), else CHAIN. */
+#define RWC_FASTCHOL_AUTO 0
+#define RWC_FASTCHOL_CHAIN 1
+#define RWC_FASTCHOL_DENSE 2
+
 typedef struct rwc_fastchol_params {
     double droptol;            /* IChol drop tolerance delta (>= 0; the paper uses 1e-4)         */
     double window;             /* base window width w_s (>= 1)                                   */
     double eps_p;              /* sparsification tolerance (>= 0)                                */
     int32_t zeta;              /* columns of at most zeta nonzeros are kept whole (>= 0)         */
-    int32_t reserved;
+    int32_t method;            /* RWC_FASTCHOL_AUTO, _CHAIN or _DENSE                            */
     int64_t factor_capacity;   /* entries of the factor the workspace holds (>= n - 1); a factor
                                   that needs more stops with RWC_ERR_TOO_LARGE                */
     int64_t inverse_capacity;  /* entries of S~ the workspace holds                          */
@@ -483,9 +493,11 @@ typedef struct rwc_fastchol_params {
 int rwc_fastchol_workspace(const rwc_csr* g, const rwc_fastchol_params* p, size_t* bytes);
 
 /* tau_dev: double [n] output by input id (0 at the pivot).  Stream-ordered: the call enqueues
- * three single-wave kernels and returns; rwc_workspace_status reports RWC_ERR_TOO_LARGE (a
- * pool, or a column's 4096-entry ordering buffer, was too small) or RWC_ERR_BREAKDOWN (a
- * non-positive pivot), after which tau_dev is meaningless. */
+ * its kernels (three single-wave ones for CHAIN; n + 3 for DENSE) and returns;
+ * rwc_workspace_status reports RWC_ERR_TOO_LARGE (a pool, or a column's 4096-entry ordering
+ * buffer, was too small) or RWC_ERR_BREAKDOWN (a non-positive pivot), after which tau_dev is
+ * meaningless.  RWC_ERR_INVALID_ARG for an unknown method, RWC_ERR_TOO_LARGE for DENSE past
+ * 2^20 columns. */
 int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, double* tau_dev, void* ws, size_t ws_bytes,
                  void* stream);
 

@@ -26,6 +26,10 @@ RWC_SAMPLE_NO_PATH_RING = 128
 RWC_SAMPLE_ID_STARTS = 256
 RWC_SAMPLE_NO_LDS_STATE = 512
 
+RWC_FASTCHOL_AUTO = 0   # rwc_fastchol_params.method
+RWC_FASTCHOL_CHAIN = 1
+RWC_FASTCHOL_DENSE = 2
+
 RWC_SOLVE_STREAM_ORDERED = -1   # rwc_solve_params.check_every value selecting stream-ordered mode
 
 STATUS = {
@@ -83,7 +87,7 @@ class BackwardParams(ctypes.Structure):
 
 
 class FastcholParams(ctypes.Structure):
-    _fields_ = [("droptol", c_dbl), ("window", c_dbl), ("eps_p", c_dbl), ("zeta", c_i32), ("reserved", c_i32),
+    _fields_ = [("droptol", c_dbl), ("window", c_dbl), ("eps_p", c_dbl), ("zeta", c_i32), ("method", c_i32),
                 ("factor_capacity", c_i64), ("inverse_capacity", c_i64)]
 
 

@@ -406,18 +406,28 @@ def estimate_diag(graph: Graph, diag: torch.Tensor, tol: float = 1e-12, max_iter
     return {"rwc": rwc, "hit": hit, "iters": iters.value}
 
 
+FASTCHOL_METHODS = {"auto": _lib.RWC_FASTCHOL_AUTO, "chain": _lib.RWC_FASTCHOL_CHAIN,
+                    "dense": _lib.RWC_FASTCHOL_DENSE}
+
+
 def fastchol(graph: Graph, droptol: float = 1e-4, window: float = 16.0, zeta: int = 16, eps_p: float = 1e-3,
-             factor_capacity: int | None = None, inverse_capacity: int | None = None, sync: bool = True) -> dict:
+             factor_capacity: int | None = None, inverse_capacity: int | None = None, sync: bool = True,
+             method: str = "auto") -> dict:
     """FastChol's tau~ (rwc_fastchol): the estimate of diag(calL_v^{-1}) by input id from the
     threshold incomplete Cholesky factor and its windowed, sparsified inverse (Section 4,
     Algorithm 2).  The pools default to 512 (n - 1) entries each for the factor and for S~, at
-    most a full triangle.  With sync=True waits, raises on a device-side error and
-    also returns the number of entries of the factor and of S~."""
+    most a full triangle.  method: "dense" (right-looking IChol on an (n-1)^2 array), "chain"
+    (left-looking on one wave) or "auto" (dense up to 8 GiB); both give the same bits.  With
+    sync=True waits, raises on a device-side error and also returns the number of entries of
+    the factor and of S~."""
     L = _lib.lib()
     dev = graph.device
     n1 = graph.n - 1
     tri = n1 * (n1 + 1) // 2
+    if method not in FASTCHOL_METHODS:
+        raise ValueError(f"method must be one of {sorted(FASTCHOL_METHODS)}")
     p = FastcholParams(droptol=float(droptol), window=float(window), eps_p=float(eps_p), zeta=int(zeta),
+                       method=FASTCHOL_METHODS[method],
                        factor_capacity=int(factor_capacity if factor_capacity is not None else min(512 * n1, tri)),
                        inverse_capacity=int(inverse_capacity if inverse_capacity is not None else min(512 * n1, tri)))
     size = ctypes.c_size_t()

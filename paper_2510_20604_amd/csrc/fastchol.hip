@@ -14,11 +14,17 @@
 //    most eps_p ||S*(:, u)||_1; tau~_u = ||S~(:, u)||^2.
 //
 // Both recursions are chains: column j needs every earlier column its row reaches (IChol) and
-// column u every later column in its window (the inverse).  One wave runs each chain column by
-// column, its lanes over the column's entries.  Every floating-point operation happens in the
-// order the serial algorithm performs it (updates in ascending k, norms and tails summed one
-// entry at a time, sorts by total orders), so the factor, S~ and tau~ are the serial ones bit
-// for bit.
+// column u every later column in its window (the inverse).  The inverse runs on one wave, column
+// by column, its lanes over the column's entries.  IChol has two forms with the same result:
+//   - dense (the default while the (n-1)^2 matrix fits): right-looking on an N x N array in
+//     HBM; step k forms column k of R and subtracts R(i, k) R(j, k) from every kept pair, those
+//     pairs spread over the whole GPU, one launch per step;
+//   - chain: left-looking on one wave, sparse throughout, for any size.
+// Every floating-point operation happens in the order the serial algorithm performs it (each
+// entry's updates in ascending k, norms and tails summed one entry at a time, sorts by total
+// orders), so the factor, S~ and tau~ are the serial ones bit for bit.
+#include <algorithm>
+
 #include "common.hpp"
 #include "device.hpp"
 
@@ -45,6 +51,7 @@ struct FcArgs {
     int32_t* r_row;
     double* r_val;
     int32_t* r_colof;   // column of the entry at each position
+    int64_t* r_colend;  // end of that column (r_ptr[column + 1]), so a row-list link needs no more
     int64_t* r_next;    // next entry of the same row (row lists in ascending column), -1 at the end
     int64_t* head;      // first and last entry of each row
     int64_t* tail;
@@ -60,21 +67,27 @@ struct FcArgs {
     int32_t* stamp;
     int32_t* touched;   // [N] the rows a column has reached, in the order reached
     double* dmax;
+    double* dense;      // dense IChol: S, N x N column-major (lower triangle used)
+    double* colnorm;    // dense IChol: ||A(j:N, j)||_1 per column
     double* tau;        // [n] output by input id
     WsHeader* header;
     int64_t* counters;  // [2]: entries of R and of S~
 };
 
 // Words one lane writes and another reads later (the dense accumulator, its stamps and the row
-// lists): relaxed work-group-scope atomics, as for the walk kernels' tree state.
+// lists): relaxed atomics.  Each kernel here is a single wave, so their scope is the wavefront,
+// and so is the scope of wave_order(): a wave's vector memory operations are performed in the
+// order it issues them, so ordering them needs no wait for the memory system, only that the
+// compiler keep them in program order.
 template <class T>
 __device__ __forceinline__ T ld(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 template <class T>
 __device__ __forceinline__ void st(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
+__device__ __forceinline__ void wave_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 __device__ __forceinline__ int32_t node_of_column(int32_t j, int32_t v) { return j + (j >= v ? 1 : 0); }
 __device__ __forceinline__ int32_t column_of_node(int32_t u, int32_t v) { return u - (u > v ? 1 : 0); }
@@ -148,6 +161,74 @@ __global__ void __launch_bounds__(kWave) fc_begin(FcArgs A) {
     for (int64_t u = lane; u < A.n; u += kWave) A.tau[u] = 0.0;
 }
 
+// One link of a row list in IChol's left-looking update: entry e = R(j, k), the next entry of
+// row j, the end of column k, and kSpan entries of column k's suffix from some position p0 (lane
+// l holds positions p0 + b kWave + l, clamped to written positions for the load).
+constexpr int kBatch = 4;
+constexpr int kSpan = kBatch * kWave;
+struct Link {
+    int64_t e, next, end;
+    double rjk;
+    int32_t row[kBatch];
+    double val[kBatch];
+};
+
+__device__ __forceinline__ void load_span(const FcArgs& A, int64_t p0, int64_t rp, Link& L) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+        const int64_t p = p0 + b * kWave + lane;
+        const int64_t pc = p < rp ? p : rp - 1;
+        L.row[b] = A.r_row[pc];
+        L.val[b] = A.r_val[pc];
+    }
+}
+
+// Starts the loads of the link at e; e outside [0, rp) ends the list (L.e = -1).
+__device__ __forceinline__ Link open_link(const FcArgs& A, int64_t e, int64_t rp) {
+    Link L;
+    if (e < 0 || e >= rp) {
+        L.e = -1;
+        return L;
+    }
+    L.e = e;
+    L.next = ld(&A.r_next[e]);
+    L.rjk = A.r_val[e];
+    L.end = A.r_colend[e];
+    load_span(A, e, rp, L);
+    return L;
+}
+
+// acc[i] -= R(i, k) R(j, k) for the loaded span's rows i < L.end; rows reached for the first time
+// in this column start from 0 and join the touched list.  The rows of one column are distinct,
+// so the span's loads of stamps and accumulators all precede its stores.
+__device__ __forceinline__ void update(const FcArgs& A, int64_t p0, const Link& L, int32_t stamp, uint32_t& nt) {
+    const int lane = threadIdx.x;
+    int32_t i[kBatch], sg[kBatch];
+    double cur[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+        i[b] = p0 + b * kWave + lane < L.end ? L.row[b] : -1;
+        const int32_t ic = i[b] >= 0 ? i[b] : L.row[0];   // a valid address for every lane
+        sg[b] = ld(&A.stamp[ic]);
+        cur[b] = ld(&A.acc[ic]);
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+        const bool fresh = i[b] >= 0 && sg[b] != stamp;
+        uint32_t cnt = 0;
+        const uint32_t r = rank_of(fresh, cnt);
+        if (fresh) {
+            st(&A.stamp[i[b]], stamp);
+            st(&A.touched[nt + r], i[b]);   // distinct rows below N: nt never passes N
+            cur[b] = 0.0;
+        }
+        nt += cnt;
+        if (i[b] >= 0) st(&A.acc[i[b]], cur[b] - L.val[b] * L.rjk);
+    }
+    wave_order();
+}
+
 // IChol, one wave.
 __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
     __shared__ int32_t krow[kSortCap];   // the entries a column keeps, ordered by row here
@@ -203,47 +284,37 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
             if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
             return;
         }
-        __threadfence_block();
+        wave_order();
         // left-looking update: every earlier column k with R(j, k) != 0, ascending k (a row has
-        // at most j entries left of the diagonal: the guard stops a corrupt list)
+        // at most j entries left of the diagonal: the guard stops a corrupt list).  Pipelined by
+        // one link: the next link's entry, its column end and the first kSpan entries of its
+        // column suffix are loaded before this link's accumulator update, so a link costs about
+        // one memory round trip (the accumulator's) instead of four.
         int64_t links = 0;
-        for (int64_t e = ld(&A.head[j]); e >= 0 && e < rp; e = ld(&A.r_next[e])) {
+        Link cur = open_link(A, ld(&A.head[j]), rp);
+        while (cur.e >= 0) {
             if (++links > j) {
                 full = true;
                 break;
             }
-            const int32_t k = A.r_colof[e];
-            const double rjk = A.r_val[e];
-            const int64_t kend = A.r_ptr[k + 1];
-            for (int64_t p0 = e; p0 < kend; p0 += kWave) {
-                const int64_t p = p0 + lane;
-                int32_t i = -1;
-                double rik = 0.0;
-                bool fresh = false;
-                if (p < kend) {
-                    i = A.r_row[p];
-                    rik = A.r_val[p];
-                    fresh = ld(&A.stamp[i]) != stamp;
-                }
-                uint32_t cnt = 0;
-                const uint32_t r = rank_of(fresh, cnt);
-                double cur = 0.0;
-                if (fresh) {
-                    st(&A.stamp[i], stamp);
-                    st(&touched[nt + r], i);   // distinct rows below N: nt never passes N
-                } else if (i >= 0) {
-                    cur = ld(&A.acc[i]);
-                }
-                nt += cnt;
-                if (i >= 0) st(&A.acc[i], cur - rik * rjk);
+            const Link nxt = open_link(A, cur.next, rp);
+            // a suffix longer than kSpan: each further span is loaded before the previous one
+            // is applied
+            for (int64_t p0 = cur.e;; p0 += kSpan) {
+                const bool more = p0 + kSpan < cur.end;
+                Link span = cur;
+                if (more) load_span(A, p0 + kSpan, rp, span);
+                update(A, p0, cur, stamp, nt);
+                if (!more) break;
+                cur = span;
             }
-            __threadfence_block();
+            cur = nxt;
         }
         if (full) {
             if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
             return;
         }
-        __threadfence_block();
+        wave_order();
         const double wjj = ld(&A.acc[j]);
         if (!(wjj > 0.0)) {
             if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrPivot));
@@ -254,26 +325,32 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
         // appended after the diagonal
         const double thr = A.droptol * colnorm;
         uint32_t kept = 0;
-        for (uint32_t t0 = 0; t0 < nt; t0 += kWave) {
-            const uint32_t t = t0 + lane;
-            int32_t i = -1;
-            double xv = 0.0;
-            if (t < nt) {
-                i = ld(&touched[t]);
-                if (i != j) xv = ld(&A.acc[i]) / piv;
+        for (uint32_t t0 = 0; t0 < nt && !full; t0 += kSpan) {
+            int32_t i[kBatch];
+            double xv[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const uint32_t t = t0 + b * kWave + lane;
+                i[b] = t < nt ? ld(&touched[t < nt ? t : 0]) : -1;
             }
-            const bool keep = i >= 0 && i != j && xv != 0.0 && fabs(xv) >= thr;
-            uint32_t cnt = 0;
-            const uint32_t r = rank_of(keep, cnt);
-            if (kept + cnt > static_cast<uint32_t>(kSortCap)) {
-                full = true;
-                break;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) xv[b] = ld(&A.acc[i[b] >= 0 ? i[b] : j]);
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const double x = xv[b] / piv;
+                const bool keep = i[b] >= 0 && i[b] != j && x != 0.0 && fabs(x) >= thr;
+                uint32_t cnt = 0;
+                const uint32_t r = rank_of(keep, cnt);
+                if (kept + cnt > static_cast<uint32_t>(kSortCap)) {
+                    full = true;
+                    break;
+                }
+                if (keep) {
+                    krow[kept + r] = i[b];
+                    kval[kept + r] = x;
+                }
+                kept += cnt;
             }
-            if (keep) {
-                krow[kept + r] = i;
-                kval[kept + r] = xv;
-            }
-            kept += cnt;
         }
         if (full || rp + 1 + static_cast<int64_t>(kept) > A.r_cap) {
             if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
@@ -281,10 +358,12 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
         }
         wave_sort(kval, krow, static_cast<int32_t>(kept),
                   [](double, int32_t ra, double, int32_t rb) { return ra < rb; });
+        const int64_t colend = rp + 1 + static_cast<int64_t>(kept);
         if (lane == 0) {
             A.r_row[rp] = j;
             A.r_val[rp] = piv;
             A.r_colof[rp] = j;
+            A.r_colend[rp] = colend;
             st(&A.r_next[rp], int64_t{-1});
         }
         for (uint32_t t = lane; t < kept; t += kWave) {
@@ -293,6 +372,7 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
             A.r_row[pos] = i;
             A.r_val[pos] = kval[t];
             A.r_colof[pos] = j;
+            A.r_colend[pos] = colend;
             st(&A.r_next[pos], int64_t{-1});
             // append to row i's list (each lane a different row)
             const int64_t last = ld(&A.tail[i]);
@@ -304,10 +384,203 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
         }
         rp += 1 + kept;
         if (lane == 0) A.r_ptr[j + 1] = rp;
-        __threadfence_block();
+        wave_order();
         __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) A.counters[0] = rp;
+}
+
+// ---- IChol, dense right-looking ----
+// S starts as the lower triangle of calL_v.  Step k takes column k of S after steps 0..k-1: its
+// pivot and the entries that pass the drop rule become column k of R, and every kept pair
+// i >= j loses R(i, k) R(j, k) from S(i, j).  Each S(i, j) meets its updates in ascending k, as
+// in the left-looking chain, so the two forms give the same factor bit for bit.
+constexpr int kDenseBlock = 1024;
+constexpr int kDenseWaves = kDenseBlock / kWave;
+constexpr int kDenseRows = 4;    // rows per lane in one round of a column's compaction
+constexpr int kDenseGrid = 256;  // workgroups of a step
+constexpr int kDenseItems = 4;   // (column, 64-row chunk) items a wave loads at once
+
+__global__ void fc_dense_clear(double* p, int64_t count) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0.0;
+}
+
+// S = the lower triangle of calL_v (S must be zero) and colnorm[j] = ||A(j:N, j)||_1 summed down
+// the column from the diagonal, as the chain sums it.  One wave per column.
+__global__ void __launch_bounds__(256) fc_dense_scatter(FcArgs A) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t N = A.N, v = A.v;
+    const int32_t waves = static_cast<int32_t>(blockDim.x / kWave);
+    for (int32_t j = blockIdx.x * waves + threadIdx.x / kWave; j < N; j += gridDim.x * waves) {
+        const int32_t u = node_of_column(j, v);
+        const int32_t x = A.node_index[u];
+        const double du = A.strength[x];
+        const int32_t beg = A.row_ptr[x], end = A.row_ptr[x + 1];
+        double* Sj = A.dense + static_cast<int64_t>(j) * N;
+        if (lane == 0) Sj[j] = 1.0;
+        double colnorm = 1.0;
+        for (int32_t b0 = beg; b0 < end; b0 += kWave) {
+            const int32_t k = b0 + lane;
+            int32_t i = -1;
+            double a = 0.0;
+            if (k < end) {
+                const int32_t y = A.col[k];
+                const int32_t yid = A.node_id[y];
+                if (yid > u && yid != v) {
+                    i = column_of_node(yid, v);
+                    a = -static_cast<double>(A.weight[k]) / sqrt(du * A.strength[y]);
+                    Sj[i] = a;
+                }
+            }
+            for (int l = 0; l < kWave; ++l) {
+                const double al = __shfl(a, l, kWave);
+                const int32_t il = __shfl(i, l, kWave);
+                if (il >= 0) colnorm += fabs(al);
+            }
+        }
+        if (lane == 0) A.colnorm[j] = colnorm;
+    }
+}
+
+// Column j of R from column j of S: the pivot sqrt(S(j, j)), then the rows i > j whose
+// x = S(i, j) / pivot is nonzero with |x| >= droptol colnorm[j], ascending, from r_ptr[j].  One
+// workgroup; rounds of kDenseBlock * kDenseRows rows, wave w taking a contiguous block of each.
+__device__ void dense_column(const FcArgs& A, int32_t j, uint32_t* wave_count) {
+    const int64_t N = A.N;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const double* Sj = A.dense + static_cast<int64_t>(j) * N;
+    const double wjj = Sj[j];
+    if (!(wjj > 0.0)) {
+        if (threadIdx.x == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrPivot));
+        return;
+    }
+    const double piv = sqrt(wjj);
+    const double thr = A.droptol * A.colnorm[j];
+    const int64_t rp = A.r_ptr[j];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    int64_t kept = 0;
+    for (int64_t base = j + 1; base < N; base += static_cast<int64_t>(kDenseBlock) * kDenseRows) {
+        double xv[kDenseRows];
+        uint64_t m[kDenseRows];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int q = 0; q < kDenseRows; ++q) {
+            const int64_t i = base + static_cast<int64_t>(wave * kDenseRows + q) * kWave + lane;
+            xv[q] = i < N ? Sj[i] / piv : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kDenseRows; ++q) {
+            const int64_t i = base + static_cast<int64_t>(wave * kDenseRows + q) * kWave + lane;
+            m[q] = __ballot(i < N && xv[q] != 0.0 && fabs(xv[q]) >= thr);
+            cnt += static_cast<uint32_t>(__popcll(m[q]));
+        }
+        if (lane == 0) wave_count[wave] = cnt;
+        __syncthreads();
+        int64_t off = 0, total = 0;
+        for (int w = 0; w < kDenseWaves; ++w) {
+            const uint32_t c = wave_count[w];
+            off += w < wave ? c : 0;
+            total += c;
+        }
+        if (rp + 1 + kept + total > A.r_cap) {   // uniform: every thread read the same counts
+            if (threadIdx.x == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
+            return;
+        }
+        int64_t pos = rp + 1 + kept + off;
+#pragma unroll
+        for (int q = 0; q < kDenseRows; ++q) {
+            const int64_t i = base + static_cast<int64_t>(wave * kDenseRows + q) * kWave + lane;
+            if ((m[q] >> lane) & 1ull) {
+                const int64_t at = pos + __popcll(m[q] & below);
+                A.r_row[at] = static_cast<int32_t>(i);
+                A.r_val[at] = xv[q];
+            }
+            pos += __popcll(m[q]);
+        }
+        kept += total;
+        __syncthreads();   // wave_count is rewritten by the next round
+    }
+    if (threadIdx.x == 0) {
+        A.r_row[rp] = j;
+        A.r_val[rp] = piv;
+        A.r_ptr[j + 1] = rp + 1 + kept;
+        A.counters[0] = rp + 1 + kept;
+    }
+}
+
+// Step k >= 0 subtracts R(i, k) R(j, k) from S(i, j) for the kept pairs of column k; workgroup 0
+// takes the pairs in column j = first kept row (the only column step k + 1 reads, when that row
+// is k + 1) and then forms column k + 1 of R.  k = -1 forms column 0 only.
+__global__ void __launch_bounds__(kDenseBlock) fc_dense_step(FcArgs A, int32_t k) {
+    __shared__ uint32_t wave_count[kDenseWaves];
+    __shared__ uint32_t status;
+    const int64_t N = A.N;
+    if (threadIdx.x == 0) status = __hip_atomic_load(&A.header->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (status != 0) return;
+    if (k >= 0) {
+        const int64_t rp = A.r_ptr[k];
+        const int32_t c = static_cast<int32_t>(A.r_ptr[k + 1] - rp - 1);   // kept entries below the pivot
+        const int32_t* rr = A.r_row + rp + 1;
+        const double* rv = A.r_val + rp + 1;
+        if (blockIdx.x == 0) {
+            if (c > 0) {
+                double* Sb = A.dense + static_cast<int64_t>(rr[0]) * N;
+                const double x0 = rv[0];
+                for (int32_t a = threadIdx.x; a < c; a += kDenseBlock) {
+                    const int32_t ra = rr[a];
+                    Sb[ra] = Sb[ra] - rv[a] * x0;
+                }
+            }
+        } else if (c > 1) {
+            // columns b = 1 .. c-1 in items (h, b): rows a in [b + 64 h, min(b + 64 h + 64, c)).
+            // Items are numbered h-major: chunk h has the c - 1 - 64 h columns b < c - 64 h.
+            const int lane = threadIdx.x & (kWave - 1);
+            const int64_t gw = static_cast<int64_t>(blockIdx.x - 1) * kDenseWaves + threadIdx.x / kWave;
+            const int64_t nw = static_cast<int64_t>(gridDim.x - 1) * kDenseWaves;
+            int64_t items = 0;
+            for (int32_t h = 0; c - 1 - 64 * h > 0; ++h) items += c - 1 - 64 * h;
+            for (int64_t t0 = gw; t0 < items; t0 += nw * kDenseItems) {
+                int32_t ra[kDenseItems], rb[kDenseItems];
+                double xa[kDenseItems], xb[kDenseItems], sv[kDenseItems];
+                bool on[kDenseItems];
+#pragma unroll
+                for (int q = 0; q < kDenseItems; ++q) {
+                    int64_t t = t0 + q * nw;
+                    on[q] = false;
+                    ra[q] = rb[q] = 0;
+                    xa[q] = xb[q] = 0.0;
+                    if (t < items) {
+                        int32_t h = 0;
+                        while (t >= c - 1 - 64 * h) {   // wave-uniform
+                            t -= c - 1 - 64 * h;
+                            ++h;
+                        }
+                        const int32_t b = 1 + static_cast<int32_t>(t);
+                        const int32_t a = b + 64 * h + lane;
+                        rb[q] = rr[b];
+                        xb[q] = rv[b];
+                        if (a < c) {
+                            on[q] = true;
+                            ra[q] = rr[a];
+                            xa[q] = rv[a];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kDenseItems; ++q)
+                    if (on[q]) sv[q] = A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]];
+#pragma unroll
+                for (int q = 0; q < kDenseItems; ++q)
+                    if (on[q]) A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]] = sv[q] - xa[q] * xb[q];
+            }
+        }
+    }
+    if (blockIdx.x != 0 || k + 1 >= N) return;
+    __syncthreads();   // workgroup 0's updates of column k + 1 are visible to all its waves
+    dense_column(A, k + 1, wave_count);
 }
 
 // The windowed, sparsified inverse and tau~, one wave, right to left.
@@ -335,7 +608,7 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
             st(&A.stamp[u], stamp);
             st(&touched[0], u);
         }
-        __threadfence_block();
+        wave_order();
         bool full = false;
         for (int64_t p = c0 + 1; p < c1; ++p) {
             const int32_t i = A.r_row[p];
@@ -365,14 +638,14 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
                 nt += cnt;
                 if (r >= 0) st(&A.acc[r], cur - coef * sv);
             }
-            __threadfence_block();
+            wave_order();
             if (full) break;
         }
         if (full) {
             if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
             return;
         }
-        __threadfence_block();
+        wave_order();
         // the nonzeros of S*(:, u)
         uint32_t nz = 0;
         for (uint32_t t0 = 0; t0 < nt; t0 += kWave) {
@@ -442,7 +715,7 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
             A.tau[node] = t2;
         }
         sp += keep;
-        __threadfence_block();
+        wave_order();
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
     }
@@ -453,13 +726,24 @@ struct FcLayout {
     WsHeader* header;
     int64_t* counters;
     double* dmax;
-    int64_t *r_ptr, *r_next, *head, *tail, *s_start;
+    int64_t *r_ptr, *r_next, *r_colend, *head, *tail, *s_start;
     int32_t *r_row, *r_colof, *s_len, *s_row, *stamp, *touched;
-    double *r_val, *s_val, *acc;
+    double *r_val, *s_val, *acc, *colnorm, *dense;
     size_t total;
 };
 
-FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap) {
+// Dense IChol needs (n - 1)^2 doubles; the automatic choice takes it up to this many bytes.
+constexpr uint64_t kDenseAutoBytes = uint64_t{8} << 30;
+constexpr int64_t kDenseMaxColumns = int64_t{1} << 20;
+
+bool use_dense(const rwc_fastchol_params* p, int32_t n) {
+    const uint64_t N = static_cast<uint64_t>(n - 1);
+    if (p->method == RWC_FASTCHOL_DENSE) return true;
+    if (p->method == RWC_FASTCHOL_CHAIN) return false;
+    return N * N * sizeof(double) <= kDenseAutoBytes;
+}
+
+FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense) {
     Carver c(ws);
     FcLayout L{};
     const int64_t N = n - 1;
@@ -478,8 +762,13 @@ FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap) {
     L.r_colof = c.take<int32_t>(r_cap);
     L.r_val = c.take<double>(r_cap);
     L.r_next = c.take<int64_t>(r_cap);
+    L.r_colend = c.take<int64_t>(r_cap);
     L.s_row = c.take<int32_t>(s_cap);
     L.s_val = c.take<double>(s_cap);
+    if (dense) {
+        L.colnorm = c.take<double>(N);
+        L.dense = c.take<double>(static_cast<size_t>(N) * static_cast<size_t>(N));
+    }
     L.total = c.used();
     return L;
 }
@@ -491,6 +780,10 @@ int check_fc(const rwc_csr* g, const rwc_fastchol_params* p) {
         return fail(RWC_ERR_INVALID_ARG, "droptol and eps_p must be >= 0, window >= 1, zeta >= 0");
     if (p->factor_capacity < g->n - 1 || p->inverse_capacity < 0)
         return fail(RWC_ERR_INVALID_ARG, "factor_capacity must be at least n - 1 and inverse_capacity >= 0");
+    if (p->method != RWC_FASTCHOL_AUTO && p->method != RWC_FASTCHOL_CHAIN && p->method != RWC_FASTCHOL_DENSE)
+        return fail(RWC_ERR_INVALID_ARG, "method must be RWC_FASTCHOL_AUTO, _CHAIN or _DENSE");
+    if (p->method == RWC_FASTCHOL_DENSE && g->n - 1 > kDenseMaxColumns)
+        return fail(RWC_ERR_TOO_LARGE, "dense IChol takes at most %lld columns", static_cast<long long>(kDenseMaxColumns));
     return RWC_OK;
 }
 
@@ -503,7 +796,7 @@ extern "C" int rwc_fastchol_workspace(const rwc_csr* g, const rwc_fastchol_param
     clear_error();
     if (!bytes) return fail(RWC_ERR_INVALID_ARG, "bytes is null");
     RWC_CHECK(check_fc(g, p));
-    *bytes = carve_fc(nullptr, g->n, p->factor_capacity, p->inverse_capacity).total;
+    *bytes = carve_fc(nullptr, g->n, p->factor_capacity, p->inverse_capacity, use_dense(p, g->n)).total;
     return RWC_OK;
 }
 
@@ -512,8 +805,10 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     clear_error();
     RWC_CHECK(check_fc(g, p));
     if (!tau) return fail(RWC_ERR_INVALID_ARG, "tau is required");
-    RWC_CHECK(check_workspace(ws, ws_bytes, carve_fc(nullptr, g->n, p->factor_capacity, p->inverse_capacity).total));
-    FcLayout L = carve_fc(ws, g->n, p->factor_capacity, p->inverse_capacity);
+    const bool dense = use_dense(p, g->n);
+    RWC_CHECK(check_workspace(ws, ws_bytes,
+                              carve_fc(nullptr, g->n, p->factor_capacity, p->inverse_capacity, dense).total));
+    FcLayout L = carve_fc(ws, g->n, p->factor_capacity, p->inverse_capacity, dense);
     FcArgs A{};
     A.row_ptr = g->row_ptr;
     A.col = g->col;
@@ -533,6 +828,7 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     A.r_val = L.r_val;
     A.r_colof = L.r_colof;
     A.r_next = L.r_next;
+    A.r_colend = L.r_colend;
     A.head = L.head;
     A.tail = L.tail;
     A.r_cap = p->factor_capacity;
@@ -545,12 +841,26 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     A.stamp = L.stamp;
     A.touched = L.touched;
     A.dmax = L.dmax;
+    A.dense = L.dense;
+    A.colnorm = L.colnorm;
     A.tau = tau;
     A.header = L.header;
     A.counters = L.counters;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(fc_begin, dim3(1), dim3(kWave), 0, s, A);
-    hipLaunchKernelGGL(fc_ichol, dim3(1), dim3(kWave), 0, s, A);
+    if (dense) {
+        const int64_t N = g->n - 1;
+        const int64_t cells = N * N;
+        hipLaunchKernelGGL(fc_dense_clear, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(cells, 256), 8192))),
+                           dim3(256), 0, s, L.dense, cells);
+        hipLaunchKernelGGL(fc_dense_scatter, dim3(blocks_for(N, 256 / kWave)), dim3(256), 0, s, A);
+        // one launch per step: step k reads what every workgroup of step k - 1 wrote
+        for (int64_t k = -1; k + 1 < N; ++k)
+            hipLaunchKernelGGL(fc_dense_step, dim3(k < 0 ? 1 : kDenseGrid), dim3(kDenseBlock), 0, s, A,
+                               static_cast<int32_t>(k));
+    } else {
+        hipLaunchKernelGGL(fc_ichol, dim3(1), dim3(kWave), 0, s, A);
+    }
     hipLaunchKernelGGL(fc_inverse, dim3(1), dim3(kWave), 0, s, A);
     RWC_HIP(hipGetLastError());
     return RWC_OK;
@@ -559,7 +869,7 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
 extern "C" int rwc_fastchol_sizes(const void* ws, int64_t* factor_entries, int64_t* inverse_entries, void* stream) {
     clear_error();
     if (!ws || !factor_entries || !inverse_entries) return fail(RWC_ERR_INVALID_ARG, "ws and outputs are required");
-    FcLayout L = carve_fc(const_cast<void*>(ws), 2, 1, 0);
+    FcLayout L = carve_fc(const_cast<void*>(ws), 2, 1, 0, false);
     int64_t c[2] = {0, 0};
     hipStream_t s = static_cast<hipStream_t>(stream);
     RWC_HIP(hipMemcpyAsync(c, L.counters, sizeof(c), hipMemcpyDeviceToHost, s));

@@ -201,3 +201,36 @@ def test_estimate_rejects_bad_modes_before_device_work():
                                 ws.value, None) == -1
         assert lib.rwc_estimate_group(ctypes.byref(g), 8, 3, 8, 10, ctypes.byref(sp), 8, 8, None, ctypes.byref(it),
                                       256, size.value, None) == -1
+
+
+def test_fastchol_method_and_dense_workspace():
+    """rwc_fastchol_params.method: AUTO takes the dense form while (n-1)^2 doubles fit 8 GiB,
+    DENSE adds exactly that array (and a norm per column) to CHAIN's workspace, and an unknown
+    method or a dense request past 2^20 columns is refused before any device work."""
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    assert (_lib.RWC_FASTCHOL_AUTO, _lib.RWC_FASTCHOL_CHAIN, _lib.RWC_FASTCHOL_DENSE) == (0, 1, 2)
+    hdr = open(os.path.join(ROOT, "include", "rwc.h")).read()
+    for name, val in (("AUTO", 0), ("CHAIN", 1), ("DENSE", 2)):
+        assert re.search(rf"#define RWC_FASTCHOL_{name} {val}\b", hdr)
+
+    def ws(n, method):
+        g = _lib.RwcCsr(n=n, pivot=0, m=4 * n, nnz=8 * n, weighted=0, row_ptr=8, col=8, rec=8, node_id=8,
+                        node_index=8, strength=8)
+        p = _lib.FastcholParams(droptol=1e-4, window=16.0, eps_p=1e-3, zeta=16, method=method,
+                                factor_capacity=64 * n, inverse_capacity=64 * n)
+        size = ctypes.c_size_t()
+        rc = lib.rwc_fastchol_workspace(ctypes.byref(g), ctypes.byref(p), ctypes.byref(size))
+        return rc, size.value
+
+    rc, chain = ws(1001, _lib.RWC_FASTCHOL_CHAIN)
+    assert rc == 0
+    rc, dense = ws(1001, _lib.RWC_FASTCHOL_DENSE)
+    assert rc == 0
+    assert 1000 * 1000 * 8 + 1000 * 8 <= dense - chain <= 1000 * 1000 * 8 + 1000 * 8 + 2 * 256
+    assert ws(1001, _lib.RWC_FASTCHOL_AUTO) == (0, dense)
+    big = 40001   # (n-1)^2 doubles = 12.8 GB > 8 GiB: AUTO takes the chain
+    assert ws(big, _lib.RWC_FASTCHOL_AUTO) == ws(big, _lib.RWC_FASTCHOL_CHAIN)
+    assert ws(1001, 3)[0] == -1
+    assert ws(1001, -1)[0] == -1
+    assert ws((1 << 20) + 2, _lib.RWC_FASTCHOL_DENSE)[0] == -7

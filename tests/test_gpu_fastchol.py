@@ -1,8 +1,9 @@
 """FastChol (Section 4, Algorithm 2) on the GPU against the oracle.
 
-The GPU runs the serial algorithm's floating-point operations in the serial order (left-looking
-updates in ascending column, norms and tails summed one entry at a time, the same total orders
-for sorting), so tau~, the factor's size and S~'s size must equal the oracle's exactly.  With no
+The GPU runs the serial algorithm's floating-point operations in the serial order (each entry's
+updates in ascending column, in the left-looking chain and in the dense right-looking form alike;
+norms and tails summed one entry at a time; the same total orders for sorting), so tau~, the
+factor's size and S~'s size must equal the oracle's exactly, for both IChol methods.  With no
 dropping, a full window and no sparsification tau~ is diag(calL_v^{-1}) and RWC is exact.
 """
 import numpy as np
@@ -51,15 +52,30 @@ def _oracle(g, v, droptol, ws, zeta, eps_p):
 PARAMS = [(1e-4, 16.0, 16, 1e-3), (0.05, 4.0, 2, 0.05), (1e-3, 2.0, 0, 0.02)]
 
 
+@pytest.mark.parametrize("method", ["chain", "dense"])
 @pytest.mark.parametrize("params", PARAMS)
 @pytest.mark.parametrize("name", ["er300", "er1000_w", "ba2000", "grid", "path", "star"])
-def test_fastchol_matches_oracle_bit_for_bit(name, params):
+def test_fastchol_matches_oracle_bit_for_bit(name, params, method):
     g = _graph(name)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     tau, fnz, snz = _oracle(g, Gd.pivot, *params)
     droptol, ws, zeta, eps_p = params
     r = P.fastchol(Gd, droptol=droptol, window=ws, zeta=zeta, eps_p=eps_p, factor_capacity=fnz + 16,
-                   inverse_capacity=snz + 16)
+                   inverse_capacity=snz + 16, method=method)
+    assert r["factor_entries"] == fnz
+    assert r["inverse_entries"] == snz
+    np.testing.assert_array_equal(r["tau"].cpu().numpy(), tau)
+
+
+def test_dense_matches_oracle_on_ba20k():
+    """The bench's BA(20000, 5) with its parameters: the dense form (the default at this size,
+    19 999 launches, columns of up to thousands of kept entries spread over 255 workgroups)
+    against the oracle, bit for bit."""
+    g = G.barabasi_albert(20000, 5, 1002)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    lg = 15
+    tau, fnz, snz = _oracle(g, Gd.pivot, 1e-4, float(lg), lg, 1e-3)
+    r = P.fastchol(Gd, droptol=1e-4, window=float(lg), zeta=lg, eps_p=1e-3, method="dense")
     assert r["factor_entries"] == fnz
     assert r["inverse_entries"] == snz
     np.testing.assert_array_equal(r["tau"].cpu().numpy(), tau)
@@ -101,6 +117,9 @@ def test_small_pools_are_reported():
     assert ei.value.status == -7
     with pytest.raises(P.RWCError) as ei:
         P.fastchol(Gd, inverse_capacity=10)
+    assert ei.value.status == -7
+    with pytest.raises(P.RWCError) as ei:
+        P.fastchol(Gd, factor_capacity=g.n - 1, method="chain")
     assert ei.value.status == -7
     with pytest.raises(P.RWCError) as ei:
         P.fastchol(Gd, window=0.5)
