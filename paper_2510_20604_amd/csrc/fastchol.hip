@@ -69,6 +69,14 @@ struct FcArgs {
     double* dmax;
     double* dense;      // dense IChol: S, N x N column-major (lower triangle used)
     double* colnorm;    // dense IChol: ||A(j:N, j)||_1 per column
+    double* xk;         // dense IChol: R(i, j) of the last column j that kept row i ...
+    int32_t* xstamp;    // ... and that j (-1 before any)
+    int32_t* stage_row; // dense IChol, two columns by parity: each forming workgroup's kept
+    double* stage_val;  // entries (rows ascending), stage_cap per workgroup ...
+    uint32_t* stage_cnt;  // ... their counts [2][kFormGroups] ...
+    double* stage_piv;    // ... the pivot [2] ...
+    int32_t* stage_first; // ... and whether row j + 1 was kept [2]
+    int64_t stage_cap;
     double* tau;        // [n] output by input id
     WsHeader* header;
     int64_t* counters;  // [2]: entries of R and of S~
@@ -395,19 +403,25 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
 // pivot and the entries that pass the drop rule become column k of R, and every kept pair
 // i >= j loses R(i, k) R(j, k) from S(i, j).  Each S(i, j) meets its updates in ascending k, as
 // in the left-looking chain, so the two forms give the same factor bit for bit.
+//
+// Launch k forms column k + 1 of R on kFormGroups workgroups, each over a contiguous range of its
+// rows, into a staging area (two columns, by parity); the other workgroups apply step k's pairs,
+// reading column k from the staging area, and one of them copies it, in row order, into the
+// compact factor.
 constexpr int kDenseBlock = 1024;
 constexpr int kDenseWaves = kDenseBlock / kWave;
-constexpr int kDenseRows = 4;    // rows per lane in one round of a column's compaction
-constexpr int kDenseGrid = 256;  // workgroups of a step
-constexpr int kDenseItems = 4;   // (column, 64-row chunk) items a wave loads at once
+constexpr int kFormGroups = 16;   // workgroups forming a column
+constexpr int kFormRows = 4;      // rows per thread in one round of a workgroup's range
+constexpr int kDenseGrid = 256;   // workgroups of a launch
+constexpr int kDenseItems = 4;    // (column, 64-row chunk) items a wave loads at once
 
-__global__ void fc_dense_clear(double* p, int64_t count) {
+__global__ void fc_dense_clear(uint64_t* p, int64_t count) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        p[i] = 0.0;
+        p[i] = 0;
 }
 
-// S = the lower triangle of calL_v (S must be zero) and colnorm[j] = ||A(j:N, j)||_1 summed down
+// S = the lower triangle of calL_v (S must be zero), and colnorm[j] = ||A(j:N, j)||_1 summed down
 // the column from the diagonal, as the chain sums it.  One wave per column.
 __global__ void __launch_bounds__(256) fc_dense_scatter(FcArgs A) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -419,7 +433,10 @@ __global__ void __launch_bounds__(256) fc_dense_scatter(FcArgs A) {
         const double du = A.strength[x];
         const int32_t beg = A.row_ptr[x], end = A.row_ptr[x + 1];
         double* Sj = A.dense + static_cast<int64_t>(j) * N;
-        if (lane == 0) Sj[j] = 1.0;
+        if (lane == 0) {
+            Sj[j] = 1.0;
+            A.xstamp[j] = -1;
+        }
         double colnorm = 1.0;
         for (int32_t b0 = beg; b0 < end; b0 += kWave) {
             const int32_t k = b0 + lane;
@@ -444,143 +461,195 @@ __global__ void __launch_bounds__(256) fc_dense_scatter(FcArgs A) {
     }
 }
 
-// Column j of R from column j of S: the pivot sqrt(S(j, j)), then the rows i > j whose
-// x = S(i, j) / pivot is nonzero with |x| >= droptol colnorm[j], ascending, from r_ptr[j].  One
-// workgroup; rounds of kDenseBlock * kDenseRows rows, wave w taking a contiguous block of each.
-__device__ void dense_column(const FcArgs& A, int32_t j, uint32_t* wave_count) {
+// Part p of column j of R.  Step j - 1's update of column j (the pairs (i, j) with R(j, j-1) != 0)
+// is applied here, on the loaded values, and never stored: nothing reads column j of S
+// afterwards.  xk/xstamp give R(i, j-1) by row.  The pivot is sqrt(S(j, j)); this workgroup's
+// rows i (a contiguous range of j + 1 .. N - 1) whose x = S(i, j) / pivot is nonzero with
+// |x| >= droptol colnorm[j] go, ascending, to its staging slots, and become xk/xstamp for column
+// j + 1.  Rows are read q-major: round r, slot q, thread t reads row base + q * kDenseBlock + t.
+__device__ void form_part(const FcArgs& A, int32_t j, int p, uint32_t* counts /* [kFormRows][kDenseWaves] */) {
     const int64_t N = A.N;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const double* Sj = A.dense + static_cast<int64_t>(j) * N;
-    const double wjj = Sj[j];
-    if (!(wjj > 0.0)) {
-        if (threadIdx.x == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrPivot));
+    const int64_t M = N - 1 - j;
+    const int64_t R = (M + kFormGroups - 1) / kFormGroups;
+    const int64_t lo = j + 1 + p * R;
+    const int64_t hi = lo + R < N ? lo + R : N;
+    const int par = j & 1;
+    int32_t* srow = A.stage_row + (static_cast<int64_t>(par) * kFormGroups + p) * A.stage_cap;
+    double* sval = A.stage_val + (static_cast<int64_t>(par) * kFormGroups + p) * A.stage_cap;
+    double wjj = Sj[j];
+    const int32_t xsj = A.xstamp[j];
+    const double xkj = A.xk[j];
+    const double thr = A.droptol * A.colnorm[j];
+    const bool upd = j > 0 && xsj == j - 1;
+    const double x0 = upd ? xkj : 0.0;   // R(j, j - 1), 0 when column j - 1 dropped row j
+    if (upd) wjj = wjj - x0 * x0;
+    const bool bad = !(wjj > 0.0);
+    const double piv = sqrt(wjj);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    uint32_t kept = 0;
+    bool first_kept = false;
+    for (int64_t base = lo; base < hi; base += static_cast<int64_t>(kDenseBlock) * kFormRows) {
+        double xv[kFormRows], xo[kFormRows];
+        int32_t xs[kFormRows];
+#pragma unroll
+        for (int q = 0; q < kFormRows; ++q) {
+            const int64_t i = base + q * kDenseBlock + threadIdx.x;
+            const int64_t ic = i < hi ? i : j;   // a valid address for every thread
+            xv[q] = Sj[ic];
+            xs[q] = A.xstamp[ic];
+            xo[q] = A.xk[ic];
+        }
+        if (bad) break;   // uniform
+        uint64_t km[kFormRows];
+#pragma unroll
+        for (int q = 0; q < kFormRows; ++q) {
+            const int64_t i = base + q * kDenseBlock + threadIdx.x;
+            const double sv = upd && xs[q] == j - 1 ? xv[q] - xo[q] * x0 : xv[q];
+            xv[q] = i < hi ? sv / piv : 0.0;
+            const bool keep = i < hi && xv[q] != 0.0 && fabs(xv[q]) >= thr;
+            if (i == j + 1) first_kept = keep;
+            km[q] = __ballot(keep);
+            if (lane == 0) counts[q * kDenseWaves + wave] = static_cast<uint32_t>(__popcll(km[q]));
+        }
+        __syncthreads();
+        uint32_t at[kFormRows], round = 0;
+#pragma unroll
+        for (int q = 0; q < kFormRows; ++q) {
+            uint32_t before = 0, all = 0;
+            for (int w = 0; w < kDenseWaves; ++w) {
+                const uint32_t c = counts[q * kDenseWaves + w];
+                before += w < wave ? c : 0;
+                all += c;
+            }
+            at[q] = kept + round + before;
+            round += all;
+        }
+#pragma unroll
+        for (int q = 0; q < kFormRows; ++q) {
+            if ((km[q] >> lane) & 1ull) {
+                const uint32_t pos = at[q] + static_cast<uint32_t>(__popcll(km[q] & below));
+                const int32_t i = static_cast<int32_t>(base + q * kDenseBlock + threadIdx.x);
+                srow[pos] = i;
+                sval[pos] = xv[q];
+                A.xk[i] = xv[q];   // this thread read row i's old mark above
+                A.xstamp[i] = j;
+            }
+        }
+        kept += round;
+        __syncthreads();   // counts are rewritten by the next round
+    }
+    if (bad) {
+        if (p == 0 && threadIdx.x == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrPivot));
         return;
     }
-    const double piv = sqrt(wjj);
-    const double thr = A.droptol * A.colnorm[j];
-    const int64_t rp = A.r_ptr[j];
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    int64_t kept = 0;
-    for (int64_t base = j + 1; base < N; base += static_cast<int64_t>(kDenseBlock) * kDenseRows) {
-        double xv[kDenseRows];
-        uint64_t m[kDenseRows];
-        uint32_t cnt = 0;
-#pragma unroll
-        for (int q = 0; q < kDenseRows; ++q) {
-            const int64_t i = base + static_cast<int64_t>(wave * kDenseRows + q) * kWave + lane;
-            xv[q] = i < N ? Sj[i] / piv : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < kDenseRows; ++q) {
-            const int64_t i = base + static_cast<int64_t>(wave * kDenseRows + q) * kWave + lane;
-            m[q] = __ballot(i < N && xv[q] != 0.0 && fabs(xv[q]) >= thr);
-            cnt += static_cast<uint32_t>(__popcll(m[q]));
-        }
-        if (lane == 0) wave_count[wave] = cnt;
-        __syncthreads();
-        int64_t off = 0, total = 0;
-        for (int w = 0; w < kDenseWaves; ++w) {
-            const uint32_t c = wave_count[w];
-            off += w < wave ? c : 0;
-            total += c;
-        }
-        if (rp + 1 + kept + total > A.r_cap) {   // uniform: every thread read the same counts
-            if (threadIdx.x == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
-            return;
-        }
-        int64_t pos = rp + 1 + kept + off;
-#pragma unroll
-        for (int q = 0; q < kDenseRows; ++q) {
-            const int64_t i = base + static_cast<int64_t>(wave * kDenseRows + q) * kWave + lane;
-            if ((m[q] >> lane) & 1ull) {
-                const int64_t at = pos + __popcll(m[q] & below);
-                A.r_row[at] = static_cast<int32_t>(i);
-                A.r_val[at] = xv[q];
-            }
-            pos += __popcll(m[q]);
-        }
-        kept += total;
-        __syncthreads();   // wave_count is rewritten by the next round
-    }
-    if (threadIdx.x == 0) {
-        A.r_row[rp] = j;
-        A.r_val[rp] = piv;
-        A.r_ptr[j + 1] = rp + 1 + kept;
-        A.counters[0] = rp + 1 + kept;
+    if (threadIdx.x == 0) A.stage_cnt[par * kFormGroups + p] = kept;
+    if (p == 0 && threadIdx.x == 0) {
+        A.stage_piv[par] = piv;
+        A.stage_first[par] = first_kept ? 1 : 0;   // thread 0 of part 0 holds row j + 1
     }
 }
 
-// Step k >= 0 subtracts R(i, k) R(j, k) from S(i, j) for the kept pairs of column k; workgroup 0
-// takes the pairs in column j = first kept row (the only column step k + 1 reads, when that row
-// is k + 1) and then forms column k + 1 of R.  k = -1 forms column 0 only.
+// The staged column k: entry a of its kept rows (ascending) from the parts' counts.
+struct Staged {
+    uint32_t pre[kFormGroups + 1];
+    const int32_t* row;
+    const double* val;
+    int64_t cap;
+    __device__ __forceinline__ int64_t slot(int32_t a) const {
+        int p = 0;
+#pragma unroll
+        for (int q = 1; q < kFormGroups; ++q) p += static_cast<uint32_t>(a) >= pre[q] ? 1 : 0;
+        return p * cap + (a - static_cast<int32_t>(pre[p]));
+    }
+};
+
+// Launch k: workgroups 0 .. kFormGroups-1 form column k + 1; the others subtract R(i, k) R(j, k)
+// from S(i, j) for the kept pairs of column k, except in column k + 1 (which the forming
+// workgroups update as they read it), and the first of them copies column k into the factor.
 __global__ void __launch_bounds__(kDenseBlock) fc_dense_step(FcArgs A, int32_t k) {
-    __shared__ uint32_t wave_count[kDenseWaves];
-    __shared__ uint32_t status;
+    __shared__ uint32_t counts[kFormRows * kDenseWaves];
     const int64_t N = A.N;
-    if (threadIdx.x == 0) status = __hip_atomic_load(&A.header->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (status != 0) return;
-    if (k >= 0) {
+    // status is only written by the forming workgroup 0 and the copying workgroup after their
+    // threads have all read it: uniform within each workgroup
+    if (__hip_atomic_load(&A.header->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    if (blockIdx.x < kFormGroups) {
+        if (k + 1 < N) form_part(A, k + 1, blockIdx.x, counts);
+        return;
+    }
+    const int par = k & 1;
+    Staged st;
+    st.pre[0] = 0;
+#pragma unroll
+    for (int q = 0; q < kFormGroups; ++q) st.pre[q + 1] = st.pre[q] + A.stage_cnt[par * kFormGroups + q];
+    st.row = A.stage_row + static_cast<int64_t>(par) * kFormGroups * A.stage_cap;
+    st.val = A.stage_val + static_cast<int64_t>(par) * kFormGroups * A.stage_cap;
+    st.cap = A.stage_cap;
+    const int32_t c = static_cast<int32_t>(st.pre[kFormGroups]);   // kept entries below the pivot
+    if (blockIdx.x == kFormGroups) {
+        // column k of the factor: the pivot, then the kept rows ascending
         const int64_t rp = A.r_ptr[k];
-        const int32_t c = static_cast<int32_t>(A.r_ptr[k + 1] - rp - 1);   // kept entries below the pivot
-        const int32_t* rr = A.r_row + rp + 1;
-        const double* rv = A.r_val + rp + 1;
-        if (blockIdx.x == 0) {
-            if (c > 0) {
-                double* Sb = A.dense + static_cast<int64_t>(rr[0]) * N;
-                const double x0 = rv[0];
-                for (int32_t a = threadIdx.x; a < c; a += kDenseBlock) {
-                    const int32_t ra = rr[a];
-                    Sb[ra] = Sb[ra] - rv[a] * x0;
-                }
-            }
-        } else if (c > 1) {
-            // columns b = 1 .. c-1 in items (h, b): rows a in [b + 64 h, min(b + 64 h + 64, c)).
-            // Items are numbered h-major: chunk h has the c - 1 - 64 h columns b < c - 64 h.
-            const int lane = threadIdx.x & (kWave - 1);
-            const int64_t gw = static_cast<int64_t>(blockIdx.x - 1) * kDenseWaves + threadIdx.x / kWave;
-            const int64_t nw = static_cast<int64_t>(gridDim.x - 1) * kDenseWaves;
-            int64_t items = 0;
-            for (int32_t h = 0; c - 1 - 64 * h > 0; ++h) items += c - 1 - 64 * h;
-            for (int64_t t0 = gw; t0 < items; t0 += nw * kDenseItems) {
-                int32_t ra[kDenseItems], rb[kDenseItems];
-                double xa[kDenseItems], xb[kDenseItems], sv[kDenseItems];
-                bool on[kDenseItems];
-#pragma unroll
-                for (int q = 0; q < kDenseItems; ++q) {
-                    int64_t t = t0 + q * nw;
-                    on[q] = false;
-                    ra[q] = rb[q] = 0;
-                    xa[q] = xb[q] = 0.0;
-                    if (t < items) {
-                        int32_t h = 0;
-                        while (t >= c - 1 - 64 * h) {   // wave-uniform
-                            t -= c - 1 - 64 * h;
-                            ++h;
-                        }
-                        const int32_t b = 1 + static_cast<int32_t>(t);
-                        const int32_t a = b + 64 * h + lane;
-                        rb[q] = rr[b];
-                        xb[q] = rv[b];
-                        if (a < c) {
-                            on[q] = true;
-                            ra[q] = rr[a];
-                            xa[q] = rv[a];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kDenseItems; ++q)
-                    if (on[q]) sv[q] = A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]];
-#pragma unroll
-                for (int q = 0; q < kDenseItems; ++q)
-                    if (on[q]) A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]] = sv[q] - xa[q] * xb[q];
-            }
+        if (rp + 1 + c > A.r_cap) {
+            if (threadIdx.x == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
+            return;
+        }
+        for (int32_t a = threadIdx.x; a < c; a += kDenseBlock) {
+            const int64_t sl = st.slot(a);
+            A.r_row[rp + 1 + a] = st.row[sl];
+            A.r_val[rp + 1 + a] = st.val[sl];
+        }
+        if (threadIdx.x == 0) {
+            A.r_row[rp] = k;
+            A.r_val[rp] = A.stage_piv[par];
+            A.r_ptr[k + 1] = rp + 1 + c;
+            A.counters[0] = rp + 1 + c;
         }
     }
-    if (blockIdx.x != 0 || k + 1 >= N) return;
-    __syncthreads();   // workgroup 0's updates of column k + 1 are visible to all its waves
-    dense_column(A, k + 1, wave_count);
+    const int32_t b_lo = A.stage_first[par];   // 1: row k + 1 was kept, column k + 1 is being formed
+    // columns b = b_lo .. c-1 in items (h, b): rows a in [b + 64 h, min(b + 64 h + 64, c)).
+    // Items are numbered h-major: chunk h has the c - b_lo - 64 h columns b < c - 64 h.
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t gw = static_cast<int64_t>(blockIdx.x - kFormGroups) * kDenseWaves + threadIdx.x / kWave;
+    const int64_t nw = static_cast<int64_t>(gridDim.x - kFormGroups) * kDenseWaves;
+    int64_t items = 0;
+    for (int32_t h = 0; c - b_lo - 64 * h > 0; ++h) items += c - b_lo - 64 * h;
+    for (int64_t t0 = gw; t0 < items; t0 += nw * kDenseItems) {
+        int32_t ra[kDenseItems], rb[kDenseItems];
+        double xa[kDenseItems], xb[kDenseItems], sv[kDenseItems];
+        bool on[kDenseItems];
+#pragma unroll
+        for (int q = 0; q < kDenseItems; ++q) {
+            int64_t t = t0 + q * nw;
+            on[q] = false;
+            ra[q] = rb[q] = 0;
+            xa[q] = xb[q] = 0.0;
+            if (t < items) {
+                int32_t h = 0;
+                while (t >= c - b_lo - 64 * h) {   // wave-uniform
+                    t -= c - b_lo - 64 * h;
+                    ++h;
+                }
+                const int32_t b = b_lo + static_cast<int32_t>(t);
+                const int32_t a = b + 64 * h + lane;
+                const int64_t sb = st.slot(b);
+                rb[q] = st.row[sb];
+                xb[q] = st.val[sb];
+                if (a < c) {
+                    const int64_t sa = st.slot(a);
+                    on[q] = true;
+                    ra[q] = st.row[sa];
+                    xa[q] = st.val[sa];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kDenseItems; ++q)
+            if (on[q]) sv[q] = A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]];
+#pragma unroll
+        for (int q = 0; q < kDenseItems; ++q)
+            if (on[q]) A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]] = sv[q] - xa[q] * xb[q];
+    }
 }
 
 // The windowed, sparsified inverse and tau~, one wave, right to left.
@@ -728,7 +797,14 @@ struct FcLayout {
     double* dmax;
     int64_t *r_ptr, *r_next, *r_colend, *head, *tail, *s_start;
     int32_t *r_row, *r_colof, *s_len, *s_row, *stamp, *touched;
-    double *r_val, *s_val, *acc, *colnorm, *dense;
+    double *r_val, *s_val, *acc, *colnorm, *xk, *dense;
+    int32_t* xstamp;
+    int32_t* stage_row;
+    double* stage_val;
+    uint32_t* stage_cnt;
+    double* stage_piv;
+    int32_t* stage_first;
+    int64_t stage_cap;
     size_t total;
 };
 
@@ -767,6 +843,15 @@ FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense)
     L.s_val = c.take<double>(s_cap);
     if (dense) {
         L.colnorm = c.take<double>(N);
+        L.xk = c.take<double>(N);
+        L.xstamp = c.take<int32_t>(N);
+        const size_t cap = static_cast<size_t>((N - 1 + kFormGroups - 1) / kFormGroups + 1);
+        L.stage_row = c.take<int32_t>(2 * kFormGroups * cap);
+        L.stage_val = c.take<double>(2 * kFormGroups * cap);
+        L.stage_cnt = c.take<uint32_t>(2 * kFormGroups);
+        L.stage_piv = c.take<double>(2);
+        L.stage_first = c.take<int32_t>(2);
+        L.stage_cap = static_cast<int64_t>(cap);
         L.dense = c.take<double>(static_cast<size_t>(N) * static_cast<size_t>(N));
     }
     L.total = c.used();
@@ -843,6 +928,14 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     A.dmax = L.dmax;
     A.dense = L.dense;
     A.colnorm = L.colnorm;
+    A.xk = L.xk;
+    A.xstamp = L.xstamp;
+    A.stage_row = L.stage_row;
+    A.stage_val = L.stage_val;
+    A.stage_cnt = L.stage_cnt;
+    A.stage_piv = L.stage_piv;
+    A.stage_first = L.stage_first;
+    A.stage_cap = L.stage_cap;
     A.tau = tau;
     A.header = L.header;
     A.counters = L.counters;
@@ -852,11 +945,12 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
         const int64_t N = g->n - 1;
         const int64_t cells = N * N;
         hipLaunchKernelGGL(fc_dense_clear, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(cells, 256), 8192))),
-                           dim3(256), 0, s, L.dense, cells);
+                           dim3(256), 0, s, reinterpret_cast<uint64_t*>(L.dense), cells);
         hipLaunchKernelGGL(fc_dense_scatter, dim3(blocks_for(N, 256 / kWave)), dim3(256), 0, s, A);
-        // one launch per step: step k reads what every workgroup of step k - 1 wrote
-        for (int64_t k = -1; k + 1 < N; ++k)
-            hipLaunchKernelGGL(fc_dense_step, dim3(k < 0 ? 1 : kDenseGrid), dim3(kDenseBlock), 0, s, A,
+        // one launch per step: launch k reads what every workgroup of launch k - 1 wrote; the
+        // last one only copies column N - 1 into the factor
+        for (int64_t k = -1; k < N; ++k)
+            hipLaunchKernelGGL(fc_dense_step, dim3(k < 0 ? kFormGroups : kDenseGrid), dim3(kDenseBlock), 0, s, A,
                                static_cast<int32_t>(k));
     } else {
         hipLaunchKernelGGL(fc_ichol, dim3(1), dim3(kWave), 0, s, A);

@@ -205,8 +205,10 @@ def test_estimate_rejects_bad_modes_before_device_work():
 
 def test_fastchol_method_and_dense_workspace():
     """rwc_fastchol_params.method: AUTO takes the dense form while (n-1)^2 doubles fit 8 GiB,
-    DENSE adds exactly that array (and a norm per column) to CHAIN's workspace, and an unknown
-    method or a dense request past 2^20 columns is refused before any device work."""
+    DENSE adds exactly that array, three per-column words (norm, kept value, its column) and
+    the staging area of two columns (16 parts of ceil((n-2)/16) + 1 entries each, with counts,
+    pivots and flags) to CHAIN's workspace, and an unknown method or a dense request past 2^20
+    columns is refused before any device work."""
     from paper_2510_20604_amd import _lib
     lib = _lib.load()
     assert (_lib.RWC_FASTCHOL_AUTO, _lib.RWC_FASTCHOL_CHAIN, _lib.RWC_FASTCHOL_DENSE) == (0, 1, 2)
@@ -227,7 +229,9 @@ def test_fastchol_method_and_dense_workspace():
     assert rc == 0
     rc, dense = ws(1001, _lib.RWC_FASTCHOL_DENSE)
     assert rc == 0
-    assert 1000 * 1000 * 8 + 1000 * 8 <= dense - chain <= 1000 * 1000 * 8 + 1000 * 8 + 2 * 256
+    cap = -(-999 // 16) + 1
+    extra = 1000 * 1000 * 8 + 1000 * (8 + 8 + 4) + 2 * 16 * cap * (4 + 8) + 2 * 16 * 4 + 2 * 8 + 2 * 4
+    assert extra <= dense - chain <= extra + 9 * 256
     assert ws(1001, _lib.RWC_FASTCHOL_AUTO) == (0, dense)
     big = 40001   # (n-1)^2 doubles = 12.8 GB > 8 GiB: AUTO takes the chain
     assert ws(big, _lib.RWC_FASTCHOL_AUTO) == ws(big, _lib.RWC_FASTCHOL_CHAIN)
