@@ -50,7 +50,6 @@ struct FcArgs {
     int64_t* r_ptr;
     int32_t* r_row;
     double* r_val;
-    int32_t* r_colof;   // column of the entry at each position
     int64_t* r_colend;  // end of that column (r_ptr[column + 1]), so a row-list link needs no more
     int64_t* r_next;    // next entry of the same row (row lists in ascending column), -1 at the end
     int64_t* head;      // first and last entry of each row
@@ -162,8 +161,10 @@ __global__ void __launch_bounds__(kWave) fc_begin(FcArgs A) {
     }
     if (lane == 0) *A.dmax = m;
     for (int64_t i = lane; i < A.N; i += kWave) {
-        st(&A.head[i], int64_t{-1});
-        st(&A.tail[i], int64_t{-1});
+        if (A.head) {   // the chain's row lists (absent for the dense factor)
+            st(&A.head[i], int64_t{-1});
+            st(&A.tail[i], int64_t{-1});
+        }
         st(&A.stamp[i], 0);
     }
     for (int64_t u = lane; u < A.n; u += kWave) A.tau[u] = 0.0;
@@ -370,7 +371,6 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
         if (lane == 0) {
             A.r_row[rp] = j;
             A.r_val[rp] = piv;
-            A.r_colof[rp] = j;
             A.r_colend[rp] = colend;
             st(&A.r_next[rp], int64_t{-1});
         }
@@ -379,7 +379,6 @@ __global__ void __launch_bounds__(kWave) fc_ichol(FcArgs A) {
             const int64_t pos = rp + 1 + t;
             A.r_row[pos] = i;
             A.r_val[pos] = kval[t];
-            A.r_colof[pos] = j;
             A.r_colend[pos] = colend;
             st(&A.r_next[pos], int64_t{-1});
             // append to row i's list (each lane a different row)
@@ -571,13 +570,14 @@ struct Staged {
 __global__ void __launch_bounds__(kDenseBlock) fc_dense_step(FcArgs A, int32_t k) {
     __shared__ uint32_t counts[kFormRows * kDenseWaves];
     const int64_t N = A.N;
-    // status is only written by the forming workgroup 0 and the copying workgroup after their
-    // threads have all read it: uniform within each workgroup
-    if (__hip_atomic_load(&A.header->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    // Forming a column reads no status (its barriers need every wave of the workgroup; after an
+    // error it only fills the staging area, which nothing uses); the other workgroups, which
+    // have no barriers, stop once an earlier launch or this one has reported one.
     if (blockIdx.x < kFormGroups) {
         if (k + 1 < N) form_part(A, k + 1, blockIdx.x, counts);
         return;
     }
+    if (__hip_atomic_load(&A.header->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     const int par = k & 1;
     Staged st;
     st.pre[0] = 0;
@@ -796,7 +796,7 @@ struct FcLayout {
     int64_t* counters;
     double* dmax;
     int64_t *r_ptr, *r_next, *r_colend, *head, *tail, *s_start;
-    int32_t *r_row, *r_colof, *s_len, *s_row, *stamp, *touched;
+    int32_t *r_row, *s_len, *s_row, *stamp, *touched;
     double *r_val, *s_val, *acc, *colnorm, *xk, *dense;
     int32_t* xstamp;
     int32_t* stage_row;
@@ -827,21 +827,21 @@ FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense)
     L.counters = c.take<int64_t>(2);
     L.dmax = c.take<double>(1);
     L.r_ptr = c.take<int64_t>(N + 1);
-    L.head = c.take<int64_t>(N);
-    L.tail = c.take<int64_t>(N);
     L.s_start = c.take<int64_t>(N);
     L.s_len = c.take<int32_t>(N);
     L.stamp = c.take<int32_t>(N);
     L.touched = c.take<int32_t>(N);
     L.acc = c.take<double>(N);
     L.r_row = c.take<int32_t>(r_cap);
-    L.r_colof = c.take<int32_t>(r_cap);
     L.r_val = c.take<double>(r_cap);
-    L.r_next = c.take<int64_t>(r_cap);
-    L.r_colend = c.take<int64_t>(r_cap);
     L.s_row = c.take<int32_t>(s_cap);
     L.s_val = c.take<double>(s_cap);
-    if (dense) {
+    if (!dense) {   // the chain's row lists
+        L.head = c.take<int64_t>(N);
+        L.tail = c.take<int64_t>(N);
+        L.r_next = c.take<int64_t>(r_cap);
+        L.r_colend = c.take<int64_t>(r_cap);
+    } else {
         L.colnorm = c.take<double>(N);
         L.xk = c.take<double>(N);
         L.xstamp = c.take<int32_t>(N);
@@ -911,7 +911,6 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     A.r_ptr = L.r_ptr;
     A.r_row = L.r_row;
     A.r_val = L.r_val;
-    A.r_colof = L.r_colof;
     A.r_next = L.r_next;
     A.r_colend = L.r_colend;
     A.head = L.head;

@@ -205,9 +205,10 @@ def test_estimate_rejects_bad_modes_before_device_work():
 
 def test_fastchol_method_and_dense_workspace():
     """rwc_fastchol_params.method: AUTO takes the dense form while (n-1)^2 doubles fit 8 GiB,
-    DENSE adds exactly that array, three per-column words (norm, kept value, its column) and
-    the staging area of two columns (16 parts of ceil((n-2)/16) + 1 entries each, with counts,
-    pivots and flags) to CHAIN's workspace, and an unknown method or a dense request past 2^20
+    DENSE holds that array, three per-column words (norm, kept value, its column) and the
+    staging area of two columns (16 parts of ceil((n-2)/16) + 1 entries each, with counts,
+    pivots and flags) where CHAIN holds its row lists (first and last entry per row, next entry
+    and column end per factor entry), and an unknown method or a dense request past 2^20
     columns is refused before any device work."""
     from paper_2510_20604_amd import _lib
     lib = _lib.load()
@@ -229,9 +230,10 @@ def test_fastchol_method_and_dense_workspace():
     assert rc == 0
     rc, dense = ws(1001, _lib.RWC_FASTCHOL_DENSE)
     assert rc == 0
-    cap = -(-999 // 16) + 1
-    extra = 1000 * 1000 * 8 + 1000 * (8 + 8 + 4) + 2 * 16 * cap * (4 + 8) + 2 * 16 * 4 + 2 * 8 + 2 * 4
-    assert extra <= dense - chain <= extra + 9 * 256
+    N, r_cap, cap = 1000, 64 * 1001, -(-999 // 16) + 1
+    dense_only = N * N * 8 + N * (8 + 8 + 4) + 2 * 16 * cap * (4 + 8) + 2 * 16 * 4 + 2 * 8 + 2 * 4
+    chain_only = N * (8 + 8) + r_cap * (8 + 8)
+    assert abs((dense - chain) - (dense_only - chain_only)) <= 13 * 256
     assert ws(1001, _lib.RWC_FASTCHOL_AUTO) == (0, dense)
     big = 40001   # (n-1)^2 doubles = 12.8 GB > 8 GiB: AUTO takes the chain
     assert ws(big, _lib.RWC_FASTCHOL_AUTO) == ws(big, _lib.RWC_FASTCHOL_CHAIN)
