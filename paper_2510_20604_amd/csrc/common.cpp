@@ -53,6 +53,8 @@ int device_error_to_status(uint32_t bits) {
         return fail(RWC_ERR_COUNT_OVERFLOW, "a node departed 2^24 times within one tree");
     if (bits & kErrProtocol)
         return fail(RWC_ERR_HIP, "multi-walker protocol invariant violated (device bits 0x%x)", bits);
+    if (bits & kErrWait)
+        return fail(RWC_ERR_HIP, "a FastChol inverse column waited too long for a column it reads");
     if (bits & kErrRetrace)
         return fail(RWC_ERR_STEP_LIMIT, "loop-erased path retrace exceeded n nodes");
     return fail(RWC_ERR_HIP, "unknown device error bits 0x%x", bits);

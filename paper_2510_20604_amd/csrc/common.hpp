@@ -84,6 +84,7 @@ enum DeviceError : uint32_t {
     kErrNonFinite = 1u << 12,
     kErrCapacity = 1u << 13,    // a FastChol pool or a column's sort buffer is full
     kErrPivot = 1u << 14,       // a non-positive pivot in the incomplete factorization
+    kErrWait = 1u << 15,        // a FastChol inverse column outwaited its spin limit
 };
 
 int device_error_to_status(uint32_t bits);

@@ -64,7 +64,11 @@ struct FcArgs {
     // dense accumulators with stamps (entry i is live in column c when stamp[i] == c + 1)
     double* acc;
     int32_t* stamp;
-    int32_t* touched;   // [N] the rows a column has reached, in the order reached
+    int32_t* touched;   // [N] the rows a column has reached, in the order reached (the inverse:
+                        // acc, stamp and touched hold one slice of N per wave)
+    int32_t* done;      // [N] the inverse: column published
+    double* inv_val;    // the inverse: per wave, kSortCap entries to order a large column in
+    int32_t* inv_row;
     double* dmax;
     double* dense;      // dense IChol: S, N x N column-major (lower triangle used)
     double* colnorm;    // dense IChol: ||A(j:N, j)||_1 per column
@@ -117,6 +121,7 @@ __device__ void wave_sort(double* val, int32_t* row, int32_t len, Less less) {
         val[i] = 0.0;
         row[i] = 0x7FFFFFFF;
     }
+    wave_order();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the wave's LDS writes are done
     __builtin_amdgcn_wave_barrier();
     for (int32_t k = 2; k <= size; k <<= 1) {
@@ -138,10 +143,17 @@ __device__ void wave_sort(double* val, int32_t* row, int32_t len, Less less) {
                     }
                 }
             }
+            wave_order();   // the buffers may be in global memory: keep the stages in order
             __builtin_amdgcn_s_waitcnt(0xc07f);
             __builtin_amdgcn_wave_barrier();
         }
     }
+}
+
+__global__ void fill_i32(int32_t* p, int64_t count, int32_t value) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = value;
 }
 
 __global__ void __launch_bounds__(kWave) fc_begin(FcArgs A) {
@@ -160,12 +172,11 @@ __global__ void __launch_bounds__(kWave) fc_begin(FcArgs A) {
         m = o > m ? o : m;
     }
     if (lane == 0) *A.dmax = m;
-    for (int64_t i = lane; i < A.N; i += kWave) {
-        if (A.head) {   // the chain's row lists (absent for the dense factor)
+    if (A.head) {   // the chain's row lists (absent for the dense factor)
+        for (int64_t i = lane; i < A.N; i += kWave) {
             st(&A.head[i], int64_t{-1});
             st(&A.tail[i], int64_t{-1});
         }
-        st(&A.stamp[i], 0);
     }
     for (int64_t u = lane; u < A.n; u += kWave) A.tau[u] = 0.0;
 }
@@ -652,18 +663,51 @@ __global__ void __launch_bounds__(kDenseBlock) fc_dense_step(FcArgs A, int32_t k
     }
 }
 
-// The windowed, sparsified inverse and tau~, one wave, right to left.
-__global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
-    __shared__ double val[kSortCap];
-    __shared__ int32_t row[kSortCap];
-    __shared__ int32_t kept_count;
-    int32_t* touched = A.touched;
-    const int lane = threadIdx.x;
+// The windowed, sparsified inverse and tau~.  Column u needs exactly the later columns i of its
+// window with R(i, u) != 0, which are few (0.9 on average on BA(20000, 5)), so the columns form a
+// shallow DAG: kInvWaves waves of one workgroup take columns in descending order from a counter
+// and each waits, on a done flag, for the columns it reads.  The wave holding the largest
+// unfinished column never waits, so every wave finishes; a wait that outlasts kInvSpinLimit
+// naps, or any error, stops the kernel.  Each wave has its own accumulator, stamps and touched
+// list (a slice of N of each), and orders a column in LDS when it has at most kInvLds nonzeros,
+// else in its own kSortCap-entry slice of global scratch.  A column's arithmetic is the serial
+// one; only its place in the S~ pool depends on the schedule.
+constexpr int kInvWaves = 8;
+constexpr int kInvLds = 512;
+constexpr int64_t kInvSpinLimit = int64_t{1} << 26;
+
+__global__ void __launch_bounds__(kInvWaves * kWave) fc_inverse(FcArgs A) {
+    __shared__ double lval[kInvWaves][kInvLds];
+    __shared__ int32_t lrow[kInvWaves][kInvLds];
+    __shared__ int32_t kept_count[kInvWaves];
+    __shared__ int32_t next_col;
+    __shared__ unsigned long long pool;
+    __shared__ int32_t abort_all;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int32_t N = A.N, v = A.v;
-    if (A.header->status != 0) return;   // the factor is incomplete
+    if (threadIdx.x == 0) {
+        next_col = 0;
+        pool = 0;
+        abort_all = A.header->status != 0 ? 1 : 0;   // the factor is incomplete
+    }
+    __syncthreads();
     const double dmax = *A.dmax;
-    int64_t sp = 0;
-    for (int32_t u = N - 1; u >= 0; --u) {
+    double* acc = A.acc + static_cast<int64_t>(wave) * N;
+    int32_t* stamps = A.stamp + static_cast<int64_t>(wave) * N;
+    int32_t* touched = A.touched + static_cast<int64_t>(wave) * N;
+    // a wave stops on an error of its own or of another wave
+    auto fail = [&](uint32_t code) {
+        if (lane == 0) {
+            atomicOr(&A.header->status, code);
+            __hip_atomic_store(&abort_all, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+    while (__hip_atomic_load(&abort_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+        int32_t t = 0;
+        if (lane == 0) t = atomicAdd(&next_col, 1);
+        t = __shfl(t, 0, kWave);
+        if (t >= N) break;
+        const int32_t u = N - 1 - t;
         const int32_t stamp = -(u + 1);   // negative stamps: the factor's are positive
         const int32_t node = node_of_column(u, v);
         const int32_t x = A.node_index[node];
@@ -673,15 +717,26 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
         if (w > N) w = N;
         uint32_t nt = 1;
         if (lane == 0) {
-            st(&A.acc[u], 1.0 / ruu);
-            st(&A.stamp[u], stamp);
+            st(&acc[u], 1.0 / ruu);
+            st(&stamps[u], stamp);
             st(&touched[0], u);
         }
         wave_order();
-        bool full = false;
-        for (int64_t p = c0 + 1; p < c1; ++p) {
+        bool stop = false;
+        for (int64_t p = c0 + 1; p < c1 && !stop; ++p) {
             const int32_t i = A.r_row[p];
             if (i > u + w) break;
+            // column i of S~ is read once its wave has published it
+            int64_t spins = 0;
+            while (__hip_atomic_load(&A.done[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+                if (__hip_atomic_load(&abort_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0 ||
+                    ++spins > kInvSpinLimit) {
+                    stop = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (stop) break;
             const double coef = A.r_val[p] / ruu;
             const int64_t s0 = A.s_start[i];
             const int32_t sl = A.s_len[i];
@@ -693,37 +748,41 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
                 if (q < sl) {
                     r = A.s_row[s0 + q];
                     sv = A.s_val[s0 + q];
-                    fresh = ld(&A.stamp[r]) != stamp;
+                    fresh = ld(&stamps[r]) != stamp;
                 }
                 uint32_t cnt = 0;
                 const uint32_t rk = rank_of(fresh, cnt);
                 double cur = 0.0;
                 if (fresh) {
-                    st(&A.stamp[r], stamp);
+                    st(&stamps[r], stamp);
                     st(&touched[nt + rk], r);   // distinct rows below N
                 } else if (r >= 0) {
-                    cur = ld(&A.acc[r]);
+                    cur = ld(&acc[r]);
                 }
                 nt += cnt;
-                if (r >= 0) st(&A.acc[r], cur - coef * sv);
+                if (r >= 0) st(&acc[r], cur - coef * sv);
             }
             wave_order();
-            if (full) break;
         }
-        if (full) {
-            if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
-            return;
+        if (stop) {
+            if (__hip_atomic_load(&abort_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+                fail(static_cast<uint32_t>(kErrWait));   // a wait ran out (not expected)
+            break;
         }
         wave_order();
-        // the nonzeros of S*(:, u)
+        // the nonzeros of S*(:, u), in LDS when they fit, else in this wave's global scratch
+        const bool small = nt <= static_cast<uint32_t>(kInvLds);
+        double* val = small ? lval[wave] : A.inv_val + static_cast<int64_t>(wave) * kSortCap;
+        int32_t* row = small ? lrow[wave] : A.inv_row + static_cast<int64_t>(wave) * kSortCap;
         uint32_t nz = 0;
+        bool full = false;
         for (uint32_t t0 = 0; t0 < nt; t0 += kWave) {
-            const uint32_t t = t0 + lane;
+            const uint32_t tt = t0 + lane;
             int32_t r = -1;
             double a = 0.0;
-            if (t < nt) {
-                r = ld(&touched[t]);
-                a = ld(&A.acc[r]);
+            if (tt < nt) {
+                r = ld(&touched[tt]);
+                a = ld(&acc[r]);
             }
             const bool live = r >= 0 && a != 0.0;
             uint32_t cnt = 0;
@@ -739,9 +798,10 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
             nz += cnt;
         }
         if (full) {
-            if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
-            return;
+            fail(static_cast<uint32_t>(kErrCapacity));
+            break;
         }
+        wave_order();
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
         int32_t keep = static_cast<int32_t>(nz);
@@ -753,42 +813,49 @@ __global__ void __launch_bounds__(kWave) fc_inverse(FcArgs A) {
             // the 1-norm in sorted order, then the tail grown from the smallest entry
             if (lane == 0) {
                 double l1 = 0.0;
-                for (int32_t t = 0; t < static_cast<int32_t>(nz); ++t) l1 += fabs(val[t]);
+                for (int32_t k = 0; k < static_cast<int32_t>(nz); ++k) l1 += fabs(val[k]);
                 double tail = 0.0;
                 int32_t k = static_cast<int32_t>(nz);
                 while (k > 0 && tail + fabs(val[k - 1]) <= A.eps_p * l1) {
                     tail += fabs(val[k - 1]);
                     --k;
                 }
-                kept_count = k;   // hand the count to the other lanes through LDS
+                kept_count[wave] = k;   // hand the count to the other lanes through LDS
             }
             __builtin_amdgcn_s_waitcnt(0xc07f);
             __builtin_amdgcn_wave_barrier();
-            keep = kept_count;
+            keep = kept_count[wave];
             __builtin_amdgcn_wave_barrier();
         }
         wave_sort(val, row, keep, [](double, int32_t ra, double, int32_t rb) { return ra < rb; });
+        unsigned long long at = 0;
+        if (lane == 0) at = atomicAdd(&pool, static_cast<unsigned long long>(keep));
+        const int64_t sp = static_cast<int64_t>(__shfl(at, 0, kWave));
         if (sp + keep > A.s_cap) {
-            if (lane == 0) atomicOr(&A.header->status, static_cast<uint32_t>(kErrCapacity));
-            return;
+            fail(static_cast<uint32_t>(kErrCapacity));
+            break;
         }
-        for (int32_t t = lane; t < keep; t += kWave) {
-            A.s_row[sp + t] = row[t];
-            A.s_val[sp + t] = val[t];
+        for (int32_t k = lane; k < keep; k += kWave) {
+            A.s_row[sp + k] = row[k];
+            A.s_val[sp + k] = val[k];
         }
         if (lane == 0) {
             double t2 = 0.0;
-            for (int32_t t = 0; t < keep; ++t) t2 += val[t] * val[t];
+            for (int32_t k = 0; k < keep; ++k) t2 += val[k] * val[k];
             A.s_start[u] = sp;
             A.s_len[u] = keep;
             A.tau[node] = t2;
         }
-        sp += keep;
+        // every lane's stores of column u are done before the flag that publishes it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) __hip_atomic_store(&A.done[u], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         wave_order();
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
     }
-    if (lane == 0) A.counters[1] = sp;
+    __syncthreads();
+    if (threadIdx.x == 0 && abort_all == 0) A.counters[1] = static_cast<int64_t>(pool);
 }
 
 struct FcLayout {
@@ -796,7 +863,8 @@ struct FcLayout {
     int64_t* counters;
     double* dmax;
     int64_t *r_ptr, *r_next, *r_colend, *head, *tail, *s_start;
-    int32_t *r_row, *s_len, *s_row, *stamp, *touched;
+    int32_t *r_row, *s_len, *s_row, *stamp, *touched, *done, *inv_row;
+    double* inv_val;
     double *r_val, *s_val, *acc, *colnorm, *xk, *dense;
     int32_t* xstamp;
     int32_t* stage_row;
@@ -829,9 +897,12 @@ FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense)
     L.r_ptr = c.take<int64_t>(N + 1);
     L.s_start = c.take<int64_t>(N);
     L.s_len = c.take<int32_t>(N);
-    L.stamp = c.take<int32_t>(N);
-    L.touched = c.take<int32_t>(N);
-    L.acc = c.take<double>(N);
+    L.stamp = c.take<int32_t>(kInvWaves * N);
+    L.touched = c.take<int32_t>(kInvWaves * N);
+    L.acc = c.take<double>(kInvWaves * N);
+    L.done = c.take<int32_t>(N);
+    L.inv_val = c.take<double>(kInvWaves * kSortCap);
+    L.inv_row = c.take<int32_t>(kInvWaves * kSortCap);
     L.r_row = c.take<int32_t>(r_cap);
     L.r_val = c.take<double>(r_cap);
     L.s_row = c.take<int32_t>(s_cap);
@@ -924,6 +995,9 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     A.acc = L.acc;
     A.stamp = L.stamp;
     A.touched = L.touched;
+    A.done = L.done;
+    A.inv_val = L.inv_val;
+    A.inv_row = L.inv_row;
     A.dmax = L.dmax;
     A.dense = L.dense;
     A.colnorm = L.colnorm;
@@ -940,6 +1014,11 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     A.counters = L.counters;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(fc_begin, dim3(1), dim3(kWave), 0, s, A);
+    {
+        const int64_t N = g->n - 1;
+        hipLaunchKernelGGL(fill_i32, dim3(blocks_for(kInvWaves * N, 256)), dim3(256), 0, s, L.stamp, kInvWaves * N, 0);
+        hipLaunchKernelGGL(fill_i32, dim3(blocks_for(N, 256)), dim3(256), 0, s, L.done, N, 0);
+    }
     if (dense) {
         const int64_t N = g->n - 1;
         const int64_t cells = N * N;
@@ -954,7 +1033,7 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     } else {
         hipLaunchKernelGGL(fc_ichol, dim3(1), dim3(kWave), 0, s, A);
     }
-    hipLaunchKernelGGL(fc_inverse, dim3(1), dim3(kWave), 0, s, A);
+    hipLaunchKernelGGL(fc_inverse, dim3(1), dim3(kInvWaves * kWave), 0, s, A);
     RWC_HIP(hipGetLastError());
     return RWC_OK;
 }
