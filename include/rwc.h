@@ -493,7 +493,7 @@ typedef struct rwc_fastchol_params {
 int rwc_fastchol_workspace(const rwc_csr* g, const rwc_fastchol_params* p, size_t* bytes);
 
 /* tau_dev: double [n] output by input id (0 at the pivot).  Stream-ordered: the call enqueues
- * its kernels (three single-wave ones for CHAIN; n + 3 for DENSE) and returns;
+ * its kernels (five for CHAIN, n + 6 for DENSE; the inverse is one workgroup) and returns;
  * rwc_workspace_status reports RWC_ERR_TOO_LARGE (a pool, or a column's 4096-entry ordering
  * buffer, was too small) or RWC_ERR_BREAKDOWN (a non-positive pivot), after which tau_dev is
  * meaningless.  RWC_ERR_INVALID_ARG for an unknown method, RWC_ERR_TOO_LARGE for DENSE past

@@ -14,12 +14,14 @@
 //    most eps_p ||S*(:, u)||_1; tau~_u = ||S~(:, u)||^2.
 //
 // Both recursions are chains: column j needs every earlier column its row reaches (IChol) and
-// column u every later column in its window (the inverse).  The inverse runs on one wave, column
-// by column, its lanes over the column's entries.  IChol has two forms with the same result:
+// column u the later columns of its window with a factor entry (the inverse).  IChol has two
+// forms with the same result:
 //   - dense (the default while the (n-1)^2 matrix fits): right-looking on an N x N array in
-//     HBM; step k forms column k of R and subtracts R(i, k) R(j, k) from every kept pair, those
-//     pairs spread over the whole GPU, one launch per step;
+//     HBM; launch k forms column k + 1 of R on 16 workgroups while the others subtract
+//     R(i, k) R(j, k) for step k's kept pairs, one launch per step;
 //   - chain: left-looking on one wave, sparse throughout, for any size.
+// The inverse's columns form a shallow dependency DAG, which eight waves of one workgroup run,
+// each column on one wave with its lanes over the column's entries.
 // Every floating-point operation happens in the order the serial algorithm performs it (each
 // entry's updates in ascending k, norms and tails summed one entry at a time, sorts by total
 // orders), so the factor, S~ and tau~ are the serial ones bit for bit.
