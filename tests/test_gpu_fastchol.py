@@ -124,3 +124,19 @@ def test_small_pools_are_reported():
     with pytest.raises(P.RWCError) as ei:
         P.fastchol(Gd, window=0.5)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("method", ["chain", "dense"])
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_fastchol_on_the_smallest_graphs(n, method):
+    """One, two and three columns (a single edge, the 3- and 4-node paths): the first launch is
+    also the last column, the staging and the inverse's schedule hold one entry; and the 3-node
+    star, whose pivot is the centre, leaves two columns without any off-diagonal entry."""
+    for g in (G.path_graph(n), G.star_graph(n)) if n == 3 else (G.path_graph(n),):
+        Gd = P.Graph(g.n, g.src, g.dst, g.w)
+        tau, fnz, snz = _oracle(g, Gd.pivot, 1e-4, 2.0, 1, 1e-3)
+        r = P.fastchol(Gd, droptol=1e-4, window=2.0, zeta=1, eps_p=1e-3, method=method)
+        assert r["factor_entries"] == fnz
+        assert r["inverse_entries"] == snz
+        np.testing.assert_array_equal(r["tau"].cpu().numpy(), tau)
+        assert tau[Gd.pivot] == 0.0
