@@ -474,7 +474,7 @@ int rwc_backward(const rwc_csr* g, const double* grad_rwc_dev, const rwc_backwar
  *     launch per column, the column's updates spread over the GPU (n - 1 <= 2^20);
  *   RWC_FASTCHOL_CHAIN: left-looking on one wave, sparse throughout (any n; a column may reach
  *     at most 4096 kept entries);
- *   RWC_FASTCHOL_AUTO: DENSE while the array is at most 8 GiB ((n-1) <= 32768), else CHAIN. */
+ *   RWC_FASTCHOL_AUTO: DENSE while the array is at most 32 GiB ((n-1) <= 65536), else CHAIN. */
 #define RWC_FASTCHOL_AUTO 0
 #define RWC_FASTCHOL_CHAIN 1
 #define RWC_FASTCHOL_DENSE 2

@@ -417,7 +417,7 @@ def fastchol(graph: Graph, droptol: float = 1e-4, window: float = 16.0, zeta: in
     threshold incomplete Cholesky factor and its windowed, sparsified inverse (Section 4,
     Algorithm 2).  The pools default to 512 (n - 1) entries each for the factor and for S~, at
     most a full triangle.  method: "dense" (right-looking IChol on an (n-1)^2 array), "chain"
-    (left-looking on one wave) or "auto" (dense up to 8 GiB); both give the same bits.  With
+    (left-looking on one wave) or "auto" (dense up to 32 GiB); both give the same bits.  With
     sync=True waits, raises on a device-side error and also returns the number of entries of
     the factor and of S~."""
     L = _lib.lib()

@@ -204,7 +204,7 @@ def test_estimate_rejects_bad_modes_before_device_work():
 
 
 def test_fastchol_method_and_dense_workspace():
-    """rwc_fastchol_params.method: AUTO takes the dense form while (n-1)^2 doubles fit 8 GiB,
+    """rwc_fastchol_params.method: AUTO takes the dense form while (n-1)^2 doubles fit 32 GiB,
     DENSE holds that array, three per-column words (norm, kept value, its column) and the
     staging area of two columns (16 parts of ceil((n-2)/16) + 1 entries each, with counts,
     pivots and flags) where CHAIN holds its row lists (first and last entry per row, next entry
@@ -235,8 +235,10 @@ def test_fastchol_method_and_dense_workspace():
     chain_only = N * (8 + 8) + r_cap * (8 + 8)
     assert abs((dense - chain) - (dense_only - chain_only)) <= 13 * 256
     assert ws(1001, _lib.RWC_FASTCHOL_AUTO) == (0, dense)
-    big = 40001   # (n-1)^2 doubles = 12.8 GB > 8 GiB: AUTO takes the chain
+    big = 65538   # (n-1)^2 doubles just past 32 GiB: AUTO takes the chain
     assert ws(big, _lib.RWC_FASTCHOL_AUTO) == ws(big, _lib.RWC_FASTCHOL_CHAIN)
+    edge = 65537  # exactly 32 GiB: still dense
+    assert ws(edge, _lib.RWC_FASTCHOL_AUTO) == ws(edge, _lib.RWC_FASTCHOL_DENSE)
     assert ws(1001, 3)[0] == -1
     assert ws(1001, -1)[0] == -1
     assert ws((1 << 20) + 2, _lib.RWC_FASTCHOL_DENSE)[0] == -7
