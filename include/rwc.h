@@ -78,8 +78,10 @@ typedef struct rwc_csr {
                               the first 3 CDF values in words 8..13; unused words are zero  */
     int32_t* bfs_order;    /* [n] nodes in breadth-first order from the pivot: the order in
                               which walker teams take start nodes                          */
-    int32_t bfs_depth;     /* largest hop distance from the pivot (its eccentricity)       */
-    int32_t reserved;
+    int32_t bfs_depth;     /* largest hop distance from the pivot (its eccentricity in its
+                              component)                                                    */
+    int32_t components;    /* connected components (1 unless built with
+                              RWC_BUILD_ALLOW_DISCONNECTED)                                 */
     int32_t* node_id;      /* [n] input id of internal index x                              */
     int32_t* node_index;   /* [n] internal index of input id u                              */
     int32_t pivot_index;   /* internal index of the pivot                                   */
@@ -87,6 +89,8 @@ typedef struct rwc_csr {
                               id (graphs whose largest degree exceeds four times the mean);
                               0: internal index = input id.  Placement only: no result
                               depends on it                                                 */
+    int32_t* component;    /* [n] by input id: the smallest input id of the node's
+                              connected component                                           */
 } rwc_csr;
 
 /* Bytes of workspace rwc_build_csr needs for n nodes and m edges (weighted != 0 if w will
@@ -103,6 +107,26 @@ int rwc_csr_persistent_bytes(int32_t n, int64_t m, int32_t weighted, size_t* byt
  * Synchronises `stream` before returning (it reads back a status word and the scalars). */
 int rwc_build_csr(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* dst_dev,
                   const float* w_dev, void* ws, size_t ws_bytes, rwc_csr* out, void* stream);
+
+/* Build flags. */
+#define RWC_BUILD_ALLOW_DISCONNECTED 1u  /* accept several connected components (isolated nodes
+                                            included) for forests rooted at a set that meets
+                                            every component (Conclusion: groups of nodes; one
+                                            root per component makes every walk end): the CSR
+                                            records `components` and `component`, bfs_order
+                                            lists the pivot's component first, then the other
+                                            nodes in internal order.  Calls that need a
+                                            connected graph (a single root: the pivot estimate,
+                                            trap walks, FastChol, the adjoint, the autotuners
+                                            and unrooted sampling) return RWC_ERR_DISCONNECTED
+                                            for such a CSR; a root set that misses a component
+                                            is reported by the device as RWC_ERR_DISCONNECTED */
+
+/* rwc_build_csr with flags (0 or RWC_BUILD_ALLOW_DISCONNECTED; other bits are
+ * RWC_ERR_INVALID_ARG).  rwc_build_csr(...) is rwc_build_csr_ex(..., 0, ...). */
+int rwc_build_csr_ex(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* dst_dev,
+                     const float* w_dev, uint32_t flags, void* ws, size_t ws_bytes, rwc_csr* out,
+                     void* stream);
 
 /* Sampling flags. */
 #define RWC_SAMPLE_ACCUMULATE    1u  /* add to counts / counts_sq / total_steps instead of

@@ -15,6 +15,8 @@ c_i32, c_i64, c_u32, c_u64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64,
                                                  ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p,
                                                  ctypes.c_size_t)
 
+RWC_BUILD_ALLOW_DISCONNECTED = 1
+
 RWC_SAMPLE_ACCUMULATE = 1
 RWC_SAMPLE_PERSISTENT = 2
 RWC_SAMPLE_GRAPH_CAPTURE = 4
@@ -45,8 +47,8 @@ class RwcCsr(ctypes.Structure):
                 ("max_degree", c_i32), ("vol", c_dbl), ("vol_fixed", c_u64), ("row_ptr", c_vp),
                 ("col", c_vp), ("weight", c_vp), ("edge_id", c_vp), ("cdf", c_vp), ("strength", c_vp),
                 ("rec", c_vp), ("bfs_order", c_vp), ("bfs_depth", c_i32),
-                ("reserved", c_i32), ("node_id", c_vp), ("node_index", c_vp), ("pivot_index", c_i32),
-                ("internal_order", c_i32)]
+                ("components", c_i32), ("node_id", c_vp), ("node_index", c_vp), ("pivot_index", c_i32),
+                ("internal_order", c_i32), ("component", c_vp)]
 
 
 class SampleParams(ctypes.Structure):
@@ -96,6 +98,7 @@ SIGNATURES = [
     ("rwc_build_csr_workspace", c_i32, [c_i32, c_i64, c_i32, ctypes.POINTER(c_sz)]),
     ("rwc_csr_persistent_bytes", c_i32, [c_i32, c_i64, c_i32, ctypes.POINTER(c_sz)]),
     ("rwc_build_csr", c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, ctypes.POINTER(RwcCsr), c_vp]),
+    ("rwc_build_csr_ex", c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp, c_u32, c_vp, c_sz, ctypes.POINTER(RwcCsr), c_vp]),
     ("rwc_sample_forests_workspace", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),
                                              ctypes.POINTER(c_sz)]),
     ("rwc_sample_forests", c_i32, [ctypes.POINTER(RwcCsr), c_i32, ctypes.POINTER(SampleParams),

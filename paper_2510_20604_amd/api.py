@@ -39,9 +39,12 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 class Graph:
-    """An undirected graph built on the device by rwc_build_csr."""
+    """An undirected graph built on the device by rwc_build_csr_ex.  allow_disconnected=True
+    accepts several connected components (RWC_BUILD_ALLOW_DISCONNECTED): such a graph is for
+    forests rooted at a set that meets every component and the group estimate; the pivot
+    estimate, trap walks, FastChol, the adjoint and unrooted sampling refuse it."""
 
-    def __init__(self, n: int, src, dst, w=None, device: str | torch.device = "cuda"):
+    def __init__(self, n: int, src, dst, w=None, device: str | torch.device = "cuda", allow_disconnected: bool = False):
         L = _lib.lib()
         self.device = torch.device(device)
         self.src = _dev_tensor(src, torch.int32, self.device)
@@ -54,8 +57,9 @@ class Graph:
               "rwc_build_csr_workspace")
         self.ws = _workspace(size.value, self.device)
         self.csr = RwcCsr()
-        check(L.rwc_build_csr(self.n, self.m, _ptr(self.src), _ptr(self.dst), _ptr(self.w), _ptr(self.ws),
-                              self.ws.numel(), ctypes.byref(self.csr), _stream()), "rwc_build_csr")
+        flags = _lib.RWC_BUILD_ALLOW_DISCONNECTED if allow_disconnected else 0
+        check(L.rwc_build_csr_ex(self.n, self.m, _ptr(self.src), _ptr(self.dst), _ptr(self.w), flags, _ptr(self.ws),
+                                 self.ws.numel(), ctypes.byref(self.csr), _stream()), "rwc_build_csr_ex")
 
     # -- views of the device CSR (for tests and diagnostics), in the graph's internal order:
     # node_id()[x] is the input id of internal index x --
@@ -108,6 +112,14 @@ class Graph:
     @property
     def internal_order(self) -> int:
         return int(self.csr.internal_order)
+
+    @property
+    def components(self) -> int:
+        return int(self.csr.components)
+
+    def component(self) -> torch.Tensor:
+        """[n] by input id: the smallest input id of each node's connected component."""
+        return self._view(self.csr.component, self.n, torch.int32)
 
     def rec(self) -> torch.Tensor:
         return self._view(self.csr.rec, 16 * self.n, torch.int32)

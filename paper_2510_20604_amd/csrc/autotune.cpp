@@ -147,6 +147,7 @@ extern "C" int rwc_autotune_sampler(const rwc_csr* g, const rwc_sample_params* p
     clear_error();
     if (!g || !p || !out || p->num_samples < 1 || budget_bytes <= 0)
         return fail(RWC_ERR_INVALID_ARG, "g, p and out are required; num_samples and budget must be positive");
+    RWC_CHECK(require_connected(g, "rwc_autotune_sampler"));
     const ClassKey key = class_of(g, p->num_samples);
     {
         std::lock_guard<std::mutex> lock(g_mu);
@@ -315,6 +316,7 @@ extern "C" int rwc_autotune_batch(const rwc_csr* graphs, int32_t G, const rwc_sa
     clear_error();
     if (!graphs || !p || !out || G < 1 || p->num_samples < 1)
         return fail(RWC_ERR_INVALID_ARG, "graphs, p and out are required; num_graphs and num_samples must be positive");
+    for (int32_t g = 0; g < G; ++g) RWC_CHECK(require_connected(&graphs[g], "rwc_autotune_batch"));
     int64_t nnz = 0;
     for (int32_t g = 0; g < G; ++g) nnz += graphs[g].nnz;
     const BatchKey key{G, sum_nodes(graphs, G), nnz, probe_samples(p->num_samples)};

@@ -743,6 +743,7 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     clear_error();
     if (!grad_rwc || !grad_w) return fail(RWC_ERR_INVALID_ARG, "grad_rwc and grad_w are required");
     RWC_CHECK(check_params(g, bp));
+    RWC_CHECK(require_connected(g, "rwc_backward"));
     const int32_t n = g->n, v = g->pivot_index, k = bp->k;
     const int32_t Rmax = static_cast<int32_t>(workspace_columns(bp));
     RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, Rmax).total));

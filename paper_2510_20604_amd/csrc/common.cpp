@@ -53,6 +53,8 @@ int device_error_to_status(uint32_t bits) {
         return fail(RWC_ERR_COUNT_OVERFLOW, "a node departed 2^24 times within one tree");
     if (bits & kErrProtocol)
         return fail(RWC_ERR_HIP, "multi-walker protocol invariant violated (device bits 0x%x)", bits);
+    if (bits & kErrUncovered)
+        return fail(RWC_ERR_DISCONNECTED, "the root set misses a connected component of the graph");
     if (bits & kErrWait)
         return fail(RWC_ERR_HIP, "a FastChol inverse column waited too long for a column it reads");
     if (bits & kErrRetrace)

@@ -53,6 +53,14 @@ class Carver {
     size_t off_ = 0;
 };
 
+// Calls whose walks or solves end at one node need a connected graph.
+inline int require_connected(const rwc_csr* g, const char* what) {
+    if (g && g->components > 1)
+        return fail(RWC_ERR_DISCONNECTED, "%s needs a connected graph (this CSR has %d components)", what,
+                    g->components);
+    return RWC_OK;
+}
+
 inline int check_workspace(const void* ws, size_t have, size_t need) {
     if (need > 0 && ws == nullptr) return fail(RWC_ERR_WORKSPACE, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
@@ -84,6 +92,7 @@ enum DeviceError : uint32_t {
     kErrNonFinite = 1u << 12,
     kErrCapacity = 1u << 13,    // a FastChol pool or a column's sort buffer is full
     kErrPivot = 1u << 14,       // a non-positive pivot in the incomplete factorization
+    kErrUncovered = 1u << 16,   // a root set misses a connected component
     kErrWait = 1u << 15,        // a FastChol inverse column outwaited its spin limit
 };
 

@@ -544,6 +544,28 @@ __global__ void uf_hook(int64_t m, const int32_t* __restrict__ src, const int32_
     }
 }
 
+// component[u] = the smallest input id of u's component (the union-find root).
+__global__ void uf_flatten(int32_t n, int32_t* parent, int32_t* __restrict__ component) {
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        component[u] = uf_find(parent, static_cast<int32_t>(u));
+}
+
+// The nodes a breadth-first search from the pivot did not reach (other components), appended
+// to its order in internal order: flags, their exclusive scan, then the scatter.
+__global__ void unreached_flags(int32_t n, const int32_t* __restrict__ dist, uint32_t* __restrict__ flags) {
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u <= n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        flags[u] = (u < n && dist[u] < 0) ? 1u : 0u;
+}
+
+__global__ void append_unreached(int32_t n, uint32_t tail, const int32_t* __restrict__ dist,
+                                 const uint32_t* __restrict__ pos, int32_t* __restrict__ order) {
+    for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        if (dist[u] < 0) order[tail + pos[u]] = static_cast<int32_t>(u);
+}
+
 __global__ void uf_count_roots(int32_t n, const int32_t* __restrict__ parent, BuildScalars* sc) {
     int32_t c = 0;
     for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < n;
@@ -570,6 +592,7 @@ struct BuildLayout {
     int32_t* bfs_order;
     int32_t* node_id;
     int32_t* node_index;
+    int32_t* component;
     uint64_t* sfix;
     BuildScalars* scalars;
     size_t persistent;
@@ -601,6 +624,7 @@ BuildLayout carve_build(void* ws, int32_t n, int64_t m, bool weighted) {
     L.bfs_order = c.take<int32_t>(n);
     L.node_id = c.take<int32_t>(n);
     L.node_index = c.take<int32_t>(n);
+    L.component = c.take<int32_t>(n);
     L.sfix = c.take<uint64_t>(n);
     L.scalars = c.take<BuildScalars>(1);
     L.persistent = c.used();
@@ -653,8 +677,16 @@ extern "C" int rwc_csr_persistent_bytes(int32_t n, int64_t m, int32_t weighted, 
 
 extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const float* w,
                              void* ws, size_t ws_bytes, rwc_csr* out, void* stream) {
+    return rwc_build_csr_ex(n, m, src, dst, w, 0u, ws, ws_bytes, out, stream);
+}
+
+extern "C" int rwc_build_csr_ex(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const float* w,
+                                uint32_t flags, void* ws, size_t ws_bytes, rwc_csr* out, void* stream) {
     clear_error();
     if (!src || !dst || !out) return fail(RWC_ERR_INVALID_ARG, "src, dst and out must not be null");
+    if (flags & ~static_cast<uint32_t>(RWC_BUILD_ALLOW_DISCONNECTED))
+        return fail(RWC_ERR_INVALID_ARG, "unknown build flags 0x%x", flags);
+    const bool allow_disconnected = (flags & RWC_BUILD_ALLOW_DISCONNECTED) != 0;
     RWC_CHECK(check_sizes(n, m));
     const bool weighted = (w != nullptr);
     const size_t need = carve_build(nullptr, n, m, weighted).total;
@@ -751,11 +783,13 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
                        src, dst, L.parent);
     hipLaunchKernelGGL(uf_count_roots, dim3(blocks_for(n, kBlock) < gs ? blocks_for(n, kBlock) : gs), dim3(kBlock), 0,
                        s, n, L.parent, L.scalars);
+    // component ids by input id, before the breadth-first search takes over the union-find scratch
+    hipLaunchKernelGGL(uf_flatten, dim3(gn), dim3(kBlock), 0, s, n, L.parent, L.component);
     RWC_HIP(hipGetLastError());
     RWC_HIP(hipMemcpyAsync(&host, L.scalars, sizeof(host), hipMemcpyDeviceToHost, s));
     RWC_HIP(hipStreamSynchronize(s));
     RWC_CHECK(device_error_to_status(host.status));
-    if (host.nroots != 1)
+    if (host.nroots != 1 && !allow_disconnected)
         return fail(RWC_ERR_DISCONNECTED, "the graph has %d connected components", host.nroots);
 
     // breadth-first start order from the pivot (the union-find scratch holds the distances):
@@ -777,8 +811,17 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
         RWC_HIP(hipMemcpyAsync(&bs, L.bfs, sizeof(bs), hipMemcpyDeviceToHost, s));
         RWC_HIP(hipStreamSynchronize(s));
     }
-    if (bs.tail != static_cast<uint32_t>(n))
-        return fail(RWC_ERR_DISCONNECTED, "breadth-first search stopped at %u of %d nodes", bs.tail, n);
+    if (bs.tail != static_cast<uint32_t>(n)) {
+        if (host.nroots == 1 || !allow_disconnected)
+            return fail(RWC_ERR_DISCONNECTED, "breadth-first search stopped at %u of %d nodes", bs.tail, n);
+        // the other components' nodes follow the pivot's component, in internal order
+        uint32_t* pos = reinterpret_cast<uint32_t*>(L.keys_b);   // n + 1 counters; the sort is done
+        hipLaunchKernelGGL(unreached_flags, dim3(blocks_for(n + 1, kBlock) < gs ? blocks_for(n + 1, kBlock) : gs),
+                           dim3(kBlock), 0, s, n, L.parent, pos);
+        RWC_CHECK(exclusive_scan(pos, pos, static_cast<int64_t>(n) + 1, L.sums, s));
+        hipLaunchKernelGGL(append_unreached, dim3(gn), dim3(kBlock), 0, s, n, bs.tail, L.parent, pos, L.bfs_order);
+        RWC_HIP(hipGetLastError());
+    }
     const int32_t depth = bs.depth;
 
     rwc_csr g{};
@@ -803,6 +846,8 @@ extern "C" int rwc_build_csr(int32_t n, int64_t m, const int32_t* src, const int
     g.node_index = L.node_index;
     g.pivot_index = host.pivot;
     g.internal_order = by_strength ? 1 : 0;
+    g.components = host.nroots;
+    g.component = L.component;
     *out = g;
     return RWC_OK;
 }

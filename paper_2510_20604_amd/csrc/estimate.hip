@@ -14,6 +14,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "roots.hpp"
 #include "device.hpp"
 
 namespace rwc {
@@ -377,6 +378,7 @@ struct EstLayout {
     Scalars* sc;
     uint32_t* gmask;
     int64_t mask_words;
+    uint32_t* cover;   // [n] components holding a root (graphs of several components)
     size_t total;
 };
 
@@ -393,6 +395,7 @@ EstLayout carve_est(void* ws, int32_t n, bool group) {
     L.sc = c.take<Scalars>(1);
     L.mask_words = group ? (static_cast<int64_t>(n) + 31) / 32 : 0;
     L.gmask = group ? c.take<uint32_t>(L.mask_words) : nullptr;
+    L.cover = group ? c.take<uint32_t>(n) : nullptr;
     L.total = c.used();
     return L;
 }
@@ -484,6 +487,7 @@ extern "C" int rwc_estimate(const rwc_csr* g, const uint64_t* counts, const uint
                             void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (!g || !counts || !rwc) return fail(RWC_ERR_INVALID_ARG, "g, counts and rwc must not be null");
+    RWC_CHECK(require_connected(g, "rwc_estimate (the pivot solve)"));
     if (l < 1) return fail(RWC_ERR_INVALID_ARG, "l must be positive");
     if (stderr_out && !counts_sq) return fail(RWC_ERR_INVALID_ARG, "stderr needs counts_sq");
     RWC_CHECK(check_solve_params(sp));
@@ -509,6 +513,7 @@ extern "C" int rwc_estimate_diag(const rwc_csr* g, const double* diag, const rwc
                                  double* hit, int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (!g || !diag || !rwc) return fail(RWC_ERR_INVALID_ARG, "g, diag and rwc must not be null");
+    RWC_CHECK(require_connected(g, "rwc_estimate_diag (the pivot solve)"));
     RWC_CHECK(check_solve_params(sp));
     const int32_t n = g->n;
     RWC_CHECK(check_workspace(ws, ws_bytes, carve_est(nullptr, n, false).total));
@@ -553,6 +558,7 @@ extern "C" int rwc_estimate_group(const rwc_csr* g, const int32_t* roots, int32_
     hipLaunchKernelGGL(clear_words, dim3(blocks_for(L.mask_words, kBlock)), dim3(kBlock), 0, s, L.gmask, L.mask_words);
     hipLaunchKernelGGL(mark_roots, dim3(blocks_for(num_roots, kBlock)), dim3(kBlock), 0, s, roots, num_roots, n,
                        g->node_index, L.gmask, L.header);
+    if (g->components > 1) check_root_cover(*g, roots, num_roots, L.cover, L.gmask, L.header, s);
     if (!(sp && sp->check_every < 0)) {
         // host-checked mode: a bad root set would leave the system singular, so stop here
         WsHeader h{};
@@ -612,6 +618,7 @@ extern "C" int rwc_estimate_static(const rwc_csr* g, const uint64_t* counts, con
                                    int32_t* iters, void* stream) {
     clear_error();
     if (!g) return fail(RWC_ERR_INVALID_ARG, "g must not be null");
+    RWC_CHECK(require_connected(g, "rwc_estimate_static (the pivot solve)"));
     if (sp && sp->check_every < 0)
         return fail(RWC_ERR_INVALID_ARG, "rwc_estimate_static runs the host-checked solve only");
     const size_t need = carve_est(nullptr, g->n, false).total;

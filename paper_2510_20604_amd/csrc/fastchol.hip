@@ -935,6 +935,7 @@ FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense)
 int check_fc(const rwc_csr* g, const rwc_fastchol_params* p) {
     if (!g || !p) return fail(RWC_ERR_INVALID_ARG, "g and p are required");
     if (g->n < 2 || !g->row_ptr || !g->node_id) return fail(RWC_ERR_INVALID_ARG, "g is not a built CSR");
+    RWC_CHECK(require_connected(g, "rwc_fastchol"));
     if (!(p->droptol >= 0.0) || !(p->window >= 1.0) || p->zeta < 0 || !(p->eps_p >= 0.0))
         return fail(RWC_ERR_INVALID_ARG, "droptol and eps_p must be >= 0, window >= 1, zeta >= 0");
     if (p->factor_capacity < g->n - 1 || p->inverse_capacity < 0)

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "roots.hpp"
 #include "device.hpp"
 #include "walk.hpp"
 
@@ -333,6 +334,7 @@ struct SampleLayout {
     uint32_t* queue;
     uint32_t* rootmask;
     int64_t mask_words;
+    uint32_t* cover;   // [n0] components holding a root (graphs of several components)
     size_t total;
 };
 
@@ -365,6 +367,7 @@ SampleLayout carve_sample(void* ws, int32_t G, const Plan& plan, int32_t n0, int
     // root bitmap of graph 0 (an explicit root set is for single-graph calls)
     L.mask_words = (static_cast<int64_t>(n0) + 31) / 32;
     L.rootmask = c.take<uint32_t>(L.mask_words);
+    L.cover = c.take<uint32_t>(n0);
     L.total = c.used();
     return L;
 }
@@ -394,6 +397,11 @@ int validate(const rwc_csr* graphs, int32_t G, const rwc_sample_params* p) {
         return fail(RWC_ERR_INVALID_ARG, "a root set needs roots, a single graph and root = -1");
     if (p->num_roots >= graphs[0].n)
         return fail(RWC_ERR_INVALID_ARG, "the root set must leave at least one node outside it");
+    // a disconnected graph needs a root set (one that meets every component, checked on the device)
+    for (int32_t g = 0; g < G; ++g)
+        if (graphs[g].components > 1 && p->num_roots == 0)
+            return fail(RWC_ERR_DISCONNECTED, "graph %d has %d components: sample it with a root set that meets each",
+                        g, graphs[g].components);
     const int W = p->walkers_per_tree;
     if (W < 0 || W > kWave || (W & (W - 1)) != 0)
         return fail(RWC_ERR_INVALID_ARG, "walkers_per_tree must be 0 (automatic) or a power of two up to 64");
@@ -727,6 +735,8 @@ extern "C" int rwc_sample_forests(const rwc_csr* graphs, int32_t G, const rwc_sa
         if (nroots > 0)
             hipLaunchKernelGGL(build_rootmask, dim3(blocks_for(nroots, 256)), dim3(256), 0, ls, p->roots, nroots,
                                graphs[0].n, graphs[0].node_index, L.rootmask, L.header);
+        if (nroots > 0 && graphs[0].components > 1)
+            check_root_cover(graphs[0], p->roots, nroots, L.cover, L.rootmask, L.header, ls);
         if (p->root >= 0) hipLaunchKernelGGL(resolve_root, dim3(1), dim3(1), 0, ls, L.graphs, graphs[0].node_index, p->root);
         hipLaunchKernelGGL(init_state, dim3(node_blocks), dim3(256), 0, ls, L.graphs, L.node_off, G, plan.total_nodes);
         for (int32_t b = 0; b < plan.batches; ++b) {

@@ -168,6 +168,7 @@ extern "C" int rwc_sample_trap_walks(const rwc_csr* g, const rwc_trap_params* p,
                                      void* stream) {
     clear_error();
     RWC_CHECK(check_trap(g, p));
+    RWC_CHECK(require_connected(g, "rwc_sample_trap_walks"));
     if (!counts) return fail(RWC_ERR_INVALID_ARG, "counts is required");
     RWC_CHECK(check_workspace(ws, ws_bytes, carve_trap(nullptr).total));
     TrapLayout L = carve_trap(ws);

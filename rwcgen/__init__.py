@@ -16,5 +16,6 @@ from .graphs import (  # noqa: F401
     star_graph,
     cycle_graph,
     path_graph,
+    disjoint_union,
     batch_mix,
 )

@@ -201,6 +201,21 @@ def path_graph(n: int) -> EdgeList:
     return EdgeList(n, a, a + 1, None, f"P{n}")
 
 
+def disjoint_union(parts: list[EdgeList], isolated: int = 0) -> EdgeList:
+    """The parts side by side (part k's ids shifted by the sizes of parts 0..k-1), then
+    `isolated` nodes without edges: a graph of len(parts) + isolated connected components
+    (each part connected).  Weights are kept when every part has them, else unit weights."""
+    src, dst, ws, off = [], [], [], 0
+    for g in parts:
+        src.append(g.src.astype(np.int64) + off)
+        dst.append(g.dst.astype(np.int64) + off)
+        ws.append(g.w)
+        off += g.n
+    w = np.concatenate(ws).astype(np.float32) if all(x is not None for x in ws) else None
+    return EdgeList(off + isolated, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32), w,
+                    "+".join(g.name for g in parts) + (f"+{isolated} isolated" if isolated else ""))
+
+
 def batch_mix(count: int, n_lo: float, n_hi: float, seed: int, w_lo: float = 0.5,
               w_hi: float = 2.0) -> list[EdgeList]:
     """`count` graphs of uneven size: n log-uniform in [n_lo, n_hi]; the first half

@@ -242,3 +242,19 @@ def test_fastchol_method_and_dense_workspace():
     assert ws(1001, 3)[0] == -1
     assert ws(1001, -1)[0] == -1
     assert ws((1 << 20) + 2, _lib.RWC_FASTCHOL_DENSE)[0] == -7
+
+
+def test_build_flags_are_checked_before_device_work():
+    """rwc_build_csr_ex: RWC_BUILD_ALLOW_DISCONNECTED matches the header; unknown bits and null
+    inputs are refused before any device call; the CSR's `components` and `component` fields
+    sit where the header puts them."""
+    from paper_2510_20604_amd import _lib
+    lib = _lib.load()
+    hdr = open(os.path.join(ROOT, "include", "rwc.h")).read()
+    assert re.search(rf"#define RWC_BUILD_ALLOW_DISCONNECTED {_lib.RWC_BUILD_ALLOW_DISCONNECTED}u\b", hdr)
+    csr = _lib.RwcCsr()
+    assert lib.rwc_build_csr_ex(10, 5, 8, 8, None, 2, 256, 1 << 20, ctypes.byref(csr), None) == -1
+    assert lib.rwc_build_csr_ex(10, 5, None, None, None, 1, None, 0, ctypes.byref(csr), None) == -1
+    names = [f[0] for f in _lib.RwcCsr._fields_]
+    assert names.index("components") == names.index("bfs_depth") + 1
+    assert names[-1] == "component"

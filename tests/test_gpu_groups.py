@@ -107,3 +107,95 @@ def test_group_estimate_accuracy():
     mre = E.mean_relative_error(exact, got)
     print(f"group marginal MRE at l = {l}: {mre:.4%}")
     assert mre < 0.01
+
+
+# ------------------------------------------------------------ disconnected graphs -------
+def _disconnected():
+    """A weighted BA graph, a weighted grid and a path side by side, and two isolated nodes:
+    five components; the root set holds one node of each (two in the grid)."""
+    ba = G.barabasi_albert(1500, 3, 31)
+    ba = ba.with_weights(G.uniform_weights(ba.m, 0.5, 2.0, 32))
+    grid = G.grid_with_deletions(900, 0.0, 0)
+    grid = grid.with_weights(G.uniform_weights(grid.m, 1.0, 4.0, 33))
+    path = G.path_graph(60).with_weights(np.full(59, 1.5, np.float32))
+    g = G.disjoint_union([ba, grid, path], isolated=2)
+    S = np.array([17, ba.n + 5, ba.n + 800, ba.n + grid.n + 59, g.n - 2, g.n - 1])
+    return g, S, (ba.n, grid.n, path.n)
+
+
+def test_disconnected_build_records_components():
+    g, _, (nb, ng, npth) = _disconnected()
+    with pytest.raises(P.RWCError) as ei:
+        P.Graph(g.n, g.src, g.dst, g.w)
+    assert ei.value.status == -6
+    Gd = P.Graph(g.n, g.src, g.dst, g.w, allow_disconnected=True)
+    assert Gd.components == 5
+    comp = Gd.component().cpu().numpy()
+    want = np.concatenate([np.zeros(nb), np.full(ng, nb), np.full(npth, nb + ng), [g.n - 2, g.n - 1]])
+    np.testing.assert_array_equal(comp, want)
+    order = Gd.bfs_order().cpu().numpy()
+    assert sorted(order.tolist()) == list(range(g.n))          # every node starts a walk once
+    assert order[0] == Gd.csr.pivot_index
+    ids = Gd.node_id().cpu().numpy()[order]
+    first = np.sum(comp[ids] == comp[Gd.pivot])                 # the pivot's component comes first
+    assert (comp[ids[:first]] == comp[Gd.pivot]).all()
+
+
+@pytest.mark.parametrize("walkers", [1, 8, 64])
+def test_disconnected_forests_bit_exact(walkers):
+    g, S, _ = _disconnected()
+    l = 60
+    Gd = P.Graph(g.n, g.src, g.dst, g.w, allow_disconnected=True)
+    o = W.OracleCSR(g.n, g.src, g.dst, g.w)
+    ref = W.fastwalk_sample(o, S, 2003, 0, 0, l, want_parents=True, threads=8)
+    s = P.sample_forests(Gd, l, 2003, roots=S, walkers_per_tree=walkers, dump=[0, l - 1])
+    np.testing.assert_array_equal(P.as_uint64(s["counts"]), ref["visits"])
+    np.testing.assert_array_equal(P.as_uint64(s["counts_sq"]), ref["visits_sq"])
+    np.testing.assert_array_equal(P.as_uint64(s["tree_hash"][0]), ref["hash"])
+    np.testing.assert_array_equal(s["parents"].cpu().numpy(), ref["parents"][[0, l - 1]])
+    assert int(P.as_uint64(s["total_steps"])[0]) == int(ref["steps"].sum())
+
+
+def test_disconnected_group_estimate_matches_oracle():
+    g, S, _ = _disconnected()
+    l = 60
+    Gd = P.Graph(g.n, g.src, g.dst, g.w, allow_disconnected=True)
+    s = P.sample_forests(Gd, l, 2003, roots=S)
+    counts = P.as_uint64(s["counts"]).astype(np.float64)
+    est = P.estimate_group(Gd, S, s["counts"], l)
+    with np.errstate(invalid="ignore", divide="ignore"):   # the isolated roots' rows of P
+        want = E.group_marginal_estimate(g.n, g.src, g.dst, g.w, S, counts / l)
+        hs = E.group_rwc(g.n, g.src, g.dst, g.w, S)
+        hit = E.hitting_times_to_set(g.n, g.src, g.dst, g.w, S)
+    np.testing.assert_allclose(est["marginal"].cpu().numpy(), want, rtol=1e-9)
+    assert float(est["group_rwc"][0]) == pytest.approx(hs, rel=1e-9)
+    np.testing.assert_allclose(est["hit"].cpu().numpy(), hit, rtol=1e-9, atol=1e-9)
+
+
+def test_disconnected_graph_is_refused_where_one_root_is_needed():
+    """Unrooted sampling, the pivot estimate, trap walks, FastChol, the adjoint and the tuner
+    refuse a disconnected CSR on the host; a root set that misses a component is reported by
+    the device (the missed component's nodes join the roots, so the launches still end)."""
+    g, S, _ = _disconnected()
+    Gd = P.Graph(g.n, g.src, g.dst, g.w, allow_disconnected=True)
+    calls = [lambda: P.sample_forests(Gd, 4, 1),
+             lambda: P.sample_trap_walks(Gd, 2, 1),
+             lambda: P.fastchol(Gd),
+             lambda: P.autotune(Gd, 64, 1)]
+    for call in calls:
+        with pytest.raises(P.RWCError) as ei:
+            call()
+        assert ei.value.status == -6
+    counts = P.sample_forests(Gd, 4, 1, roots=S)["counts"]
+    with pytest.raises(P.RWCError) as ei:
+        P.estimate(Gd, counts, 4)
+    assert ei.value.status == -6
+    with pytest.raises(P.RWCError) as ei:
+        P.backward(Gd, torch.ones(g.n, dtype=torch.float64, device=Gd.device))
+    assert ei.value.status == -6
+    missing = S[S != g.n - 1]   # the last isolated node holds no root
+    for fn in (lambda: P.sample_forests(Gd, 4, 1, roots=missing),
+               lambda: P.estimate_group(Gd, missing, counts, 4)):
+        with pytest.raises(P.RWCError) as ei:
+            fn()
+        assert ei.value.status == -6

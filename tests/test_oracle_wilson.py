@@ -371,14 +371,21 @@ def _rooted_forests(n, edges, S):
     return out
 
 
-@pytest.mark.parametrize("case", ["grid3x3", "weighted6", "K5"])
+@pytest.mark.parametrize("case", ["grid3x3", "weighted6", "K5", "disconnected"])
 def test_forest_distribution_matches_matrix_forest_theorem(case):
     """Forests rooted at S: the sum over them of prod w_e is det(L_S) (the matrix-tree theorem
-    with S merged, or the all-minors form), and the sampled forests follow prod w_e (chi^2)."""
+    with S merged, or the all-minors form), and the sampled forests follow prod w_e (chi^2).
+    The disconnected case (K4, a weighted 4-cycle and an isolated node, one root in each
+    component and a second one in the cycle) has one factor of det(L_S) per component."""
     if case == "grid3x3":
         g, S = G.grid_with_deletions(9, 0.0, 0), [0, 8]
     elif case == "K5":
         g, S = G.complete_graph(5), [1, 3]
+    elif case == "disconnected":
+        c4 = G.cycle_graph(4).with_weights(np.array([0.5, 2.0, 1.0, 3.0], np.float32))
+        k4 = G.complete_graph(4).with_weights(np.ones(6, np.float32))
+        g = G.disjoint_union([k4, c4], isolated=1)
+        S = [1, 4, 6, 8]
     else:
         src = np.array([0, 0, 1, 1, 2, 3, 4, 2], dtype=np.int32)
         dst = np.array([1, 2, 2, 3, 4, 4, 5, 5], dtype=np.int32)
@@ -430,6 +437,29 @@ def test_expected_departures_with_a_root_set():
         np.testing.assert_array_equal(one[key], ref[key])
     with pytest.raises(ValueError):
         W.fastwalk_sample(csr, [3, 3], 5, 0, 0, 2)
+
+
+def test_expected_departures_on_a_disconnected_graph():
+    """Three components (a weighted ER graph, a 4 x 4 grid, an isolated node) and a root set
+    with one node in each (two in the grid): L_S is block diagonal and E[departures from u] =
+    d_u (L_S^{-1})_uu holds component by component; the isolated root never departs."""
+    er = G.erdos_renyi_lcc(24, 4, 19)
+    er = er.with_weights(G.uniform_weights(er.m, 0.5, 2.0, 20))
+    grid = G.grid_with_deletions(16, 0.0, 0).with_weights(np.ones(24, np.float32))
+    g = G.disjoint_union([er, grid], isolated=1)
+    csr = W.OracleCSR(g.n, g.src, g.dst, g.w)
+    S = [5, er.n + 3, er.n + 12, g.n - 1]
+    l = 40000
+    r = W.fastwalk_sample(csr, S, 77, 0, 0, l, threads=4)
+    t = E.grounded_inverse_diag_set(g.n, g.src, g.dst, g.w, S)
+    mean = r["visits"].astype(float) / l
+    var = r["visits_sq"].astype(float) / l - mean ** 2
+    mask = ~np.isin(np.arange(g.n), S)
+    z = (mean[mask] - t[mask]) / np.sqrt(var[mask] / l)
+    assert np.max(np.abs(z)) < 5.0
+    assert (r["visits"][S] == 0).all()
+    s = r["steps"].astype(float)
+    assert abs(s.mean() - t.sum()) < 5 * s.std() / np.sqrt(l)
 
 
 # ------------------------------------------------------------ trap walks ---------------
