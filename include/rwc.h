@@ -494,11 +494,12 @@ int rwc_backward(const rwc_csr* g, const double* grad_rwc_dev, const rwc_backwar
  * algorithm's order of floating-point operations.  Feed tau~ to rwc_estimate_diag for RWC.
  * ------------------------------------------------------------------------------------- */
 /* How rwc_fastchol factors calL_v; both give the same factor bit for bit.
- *   RWC_FASTCHOL_DENSE: right-looking on an (n-1) x (n-1) double array in the workspace, one
+ *   RWC_FASTCHOL_DENSE: right-looking on the packed lower triangle of the (n-1) x (n-1) matrix
+ *     ((n-1) n / 2 doubles) in the workspace, one
  *     launch per column, the column's updates spread over the GPU (n - 1 <= 2^20);
  *   RWC_FASTCHOL_CHAIN: left-looking on one wave, sparse throughout (any n; a column may reach
  *     at most 4096 kept entries);
- *   RWC_FASTCHOL_AUTO: DENSE while the array is at most 32 GiB ((n-1) <= 65536), else CHAIN. */
+ *   RWC_FASTCHOL_AUTO: DENSE while that triangle is at most 32 GiB ((n-1) <= 92681), else CHAIN. */
 #define RWC_FASTCHOL_AUTO 0
 #define RWC_FASTCHOL_CHAIN 1
 #define RWC_FASTCHOL_DENSE 2

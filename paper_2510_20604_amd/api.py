@@ -428,7 +428,7 @@ def fastchol(graph: Graph, droptol: float = 1e-4, window: float = 16.0, zeta: in
     """FastChol's tau~ (rwc_fastchol): the estimate of diag(calL_v^{-1}) by input id from the
     threshold incomplete Cholesky factor and its windowed, sparsified inverse (Section 4,
     Algorithm 2).  The pools default to 512 (n - 1) entries each for the factor and for S~, at
-    most a full triangle.  method: "dense" (right-looking IChol on an (n-1)^2 array), "chain"
+    most a full triangle.  method: "dense" (right-looking IChol on the packed (n-1) n / 2 triangle), "chain"
     (left-looking on one wave) or "auto" (dense up to 32 GiB); both give the same bits.  With
     sync=True waits, raises on a device-side error and also returns the number of entries of
     the factor and of S~."""

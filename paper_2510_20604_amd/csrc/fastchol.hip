@@ -16,8 +16,8 @@
 // Both recursions are chains: column j needs every earlier column its row reaches (IChol) and
 // column u the later columns of its window with a factor entry (the inverse).  IChol has two
 // forms with the same result:
-//   - dense (the default while the (n-1)^2 matrix fits): right-looking on an N x N array in
-//     HBM; launch k forms column k + 1 of R on 16 workgroups while the others subtract
+//   - dense (the default while the matrix's packed lower triangle fits): right-looking on that
+//     triangle in HBM; launch k forms column k + 1 of R on 16 workgroups while the others subtract
 //     R(i, k) R(j, k) for step k's kept pairs, one launch per step;
 //   - chain: left-looking on one wave, sparse throughout, for any size.
 // The inverse's columns form a shallow dependency DAG, which eight waves of one workgroup run,
@@ -72,7 +72,8 @@ struct FcArgs {
     double* inv_val;    // the inverse: per wave, kSortCap entries to order a large column in
     int32_t* inv_row;
     double* dmax;
-    double* dense;      // dense IChol: S, N x N column-major (lower triangle used)
+    double* dense;      // dense IChol: the lower triangle of S, packed by columns (column j holds
+                        // rows j .. N - 1 from packed_column(j, N))
     double* colnorm;    // dense IChol: ||A(j:N, j)||_1 per column
     double* xk;         // dense IChol: R(i, j) of the last column j that kept row i ...
     int32_t* xstamp;    // ... and that j (-1 before any)
@@ -427,6 +428,9 @@ constexpr int kFormRows = 4;      // rows per thread in one round of a workgroup
 constexpr int kDenseGrid = 256;   // workgroups of a launch
 constexpr int kDenseItems = 4;    // (column, 64-row chunk) items a wave loads at once
 
+// Offset of column j in the packed lower triangle of an N x N matrix (columns of N - j rows).
+__host__ __device__ __forceinline__ int64_t packed_column(int64_t j, int64_t N) { return j * N - j * (j - 1) / 2; }
+
 __global__ void fc_dense_clear(uint64_t* p, int64_t count) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -444,7 +448,7 @@ __global__ void __launch_bounds__(256) fc_dense_scatter(FcArgs A) {
         const int32_t x = A.node_index[u];
         const double du = A.strength[x];
         const int32_t beg = A.row_ptr[x], end = A.row_ptr[x + 1];
-        double* Sj = A.dense + static_cast<int64_t>(j) * N;
+        double* Sj = A.dense + (packed_column(j, N) - j);   // Sj[i], i >= j
         if (lane == 0) {
             Sj[j] = 1.0;
             A.xstamp[j] = -1;
@@ -482,7 +486,7 @@ __global__ void __launch_bounds__(256) fc_dense_scatter(FcArgs A) {
 __device__ void form_part(const FcArgs& A, int32_t j, int p, uint32_t* counts /* [kFormRows][kDenseWaves] */) {
     const int64_t N = A.N;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    const double* Sj = A.dense + static_cast<int64_t>(j) * N;
+    const double* Sj = A.dense + (packed_column(j, N) - j);   // Sj[i], i >= j
     const int64_t M = N - 1 - j;
     const int64_t R = (M + kFormGroups - 1) / kFormGroups;
     const int64_t lo = j + 1 + p * R;
@@ -658,10 +662,10 @@ __global__ void __launch_bounds__(kDenseBlock) fc_dense_step(FcArgs A, int32_t k
         }
 #pragma unroll
         for (int q = 0; q < kDenseItems; ++q)
-            if (on[q]) sv[q] = A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]];
+            if (on[q]) sv[q] = A.dense[packed_column(rb[q], N) + (ra[q] - rb[q])];
 #pragma unroll
         for (int q = 0; q < kDenseItems; ++q)
-            if (on[q]) A.dense[static_cast<int64_t>(rb[q]) * N + ra[q]] = sv[q] - xa[q] * xb[q];
+            if (on[q]) A.dense[packed_column(rb[q], N) + (ra[q] - rb[q])] = sv[q] - xa[q] * xb[q];
     }
 }
 
@@ -878,8 +882,9 @@ struct FcLayout {
     size_t total;
 };
 
-// Dense IChol needs (n - 1)^2 doubles; the automatic choice takes it up to this many bytes (an
-// eighth of the device's 288 GB; BA(60000, 5)'s 28.8 GB array factors 47x faster than the chain).
+// Dense IChol needs the (n - 1)(n) / 2 doubles of a packed triangle; the automatic choice takes
+// it up to this many bytes (an eighth of the device's 288 GB: n - 1 <= 92681; BA(60000, 5)'s
+// triangle factors 47x faster than the chain).
 constexpr uint64_t kDenseAutoBytes = uint64_t{32} << 30;
 constexpr int64_t kDenseMaxColumns = int64_t{1} << 20;
 
@@ -887,7 +892,7 @@ bool use_dense(const rwc_fastchol_params* p, int32_t n) {
     const uint64_t N = static_cast<uint64_t>(n - 1);
     if (p->method == RWC_FASTCHOL_DENSE) return true;
     if (p->method == RWC_FASTCHOL_CHAIN) return false;
-    return N * N * sizeof(double) <= kDenseAutoBytes;
+    return N * (N + 1) / 2 * sizeof(double) <= kDenseAutoBytes;
 }
 
 FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense) {
@@ -926,7 +931,7 @@ FcLayout carve_fc(void* ws, int32_t n, int64_t r_cap, int64_t s_cap, bool dense)
         L.stage_piv = c.take<double>(2);
         L.stage_first = c.take<int32_t>(2);
         L.stage_cap = static_cast<int64_t>(cap);
-        L.dense = c.take<double>(static_cast<size_t>(N) * static_cast<size_t>(N));
+        L.dense = c.take<double>(static_cast<size_t>(N) * static_cast<size_t>(N + 1) / 2);
     }
     L.total = c.used();
     return L;
@@ -1025,7 +1030,7 @@ extern "C" int rwc_fastchol(const rwc_csr* g, const rwc_fastchol_params* p, doub
     }
     if (dense) {
         const int64_t N = g->n - 1;
-        const int64_t cells = N * N;
+        const int64_t cells = N * (N + 1) / 2;
         hipLaunchKernelGGL(fc_dense_clear, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(cells, 256), 8192))),
                            dim3(256), 0, s, reinterpret_cast<uint64_t*>(L.dense), cells);
         hipLaunchKernelGGL(fc_dense_scatter, dim3(blocks_for(N, 256 / kWave)), dim3(256), 0, s, A);

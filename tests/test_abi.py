@@ -204,7 +204,8 @@ def test_estimate_rejects_bad_modes_before_device_work():
 
 
 def test_fastchol_method_and_dense_workspace():
-    """rwc_fastchol_params.method: AUTO takes the dense form while (n-1)^2 doubles fit 32 GiB,
+    """rwc_fastchol_params.method: AUTO takes the dense form while the (n-1) n / 2 doubles of the
+    packed lower triangle fit 32 GiB,
     DENSE holds that array, three per-column words (norm, kept value, its column) and the
     staging area of two columns (16 parts of ceil((n-2)/16) + 1 entries each, with counts,
     pivots and flags) where CHAIN holds its row lists (first and last entry per row, next entry
@@ -231,13 +232,13 @@ def test_fastchol_method_and_dense_workspace():
     rc, dense = ws(1001, _lib.RWC_FASTCHOL_DENSE)
     assert rc == 0
     N, r_cap, cap = 1000, 64 * 1001, -(-999 // 16) + 1
-    dense_only = N * N * 8 + N * (8 + 8 + 4) + 2 * 16 * cap * (4 + 8) + 2 * 16 * 4 + 2 * 8 + 2 * 4
+    dense_only = N * (N + 1) // 2 * 8 + N * (8 + 8 + 4) + 2 * 16 * cap * (4 + 8) + 2 * 16 * 4 + 2 * 8 + 2 * 4
     chain_only = N * (8 + 8) + r_cap * (8 + 8)
     assert abs((dense - chain) - (dense_only - chain_only)) <= 13 * 256
     assert ws(1001, _lib.RWC_FASTCHOL_AUTO) == (0, dense)
-    big = 65538   # (n-1)^2 doubles just past 32 GiB: AUTO takes the chain
+    big = 92683   # the packed triangle just past 32 GiB: AUTO takes the chain
     assert ws(big, _lib.RWC_FASTCHOL_AUTO) == ws(big, _lib.RWC_FASTCHOL_CHAIN)
-    edge = 65537  # exactly 32 GiB: still dense
+    edge = 92682  # just within 32 GiB: still dense
     assert ws(edge, _lib.RWC_FASTCHOL_AUTO) == ws(edge, _lib.RWC_FASTCHOL_DENSE)
     assert ws(1001, 3)[0] == -1
     assert ws(1001, -1)[0] == -1
