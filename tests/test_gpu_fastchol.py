@@ -81,28 +81,31 @@ def test_dense_matches_oracle_on_ba20k():
     np.testing.assert_array_equal(r["tau"].cpu().numpy(), tau)
 
 
+@pytest.mark.parametrize("method", ["chain", "dense"])
 @pytest.mark.parametrize("name", ["er300", "grid", "ba2000"])
-def test_exact_fastchol_gives_exact_rwc(name):
+def test_exact_fastchol_gives_exact_rwc(name, method):
     """No dropping, a full window, no sparsification: tau~ = diag(calL_v^{-1}) and the assembled
-    RWC (rwc_estimate_diag) is the exact RWC."""
+    RWC (rwc_estimate_diag) is the exact RWC, with either factor."""
     g = _graph(name)
     if g.n > 1000:
         pytest.skip("dense inverse too large for this check")
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     N = g.n - 1
     tri = N * (N + 1) // 2
-    r = P.fastchol(Gd, droptol=0.0, window=float(N), zeta=N, eps_p=0.0, factor_capacity=tri, inverse_capacity=tri)
+    r = P.fastchol(Gd, droptol=0.0, window=float(N), zeta=N, eps_p=0.0, factor_capacity=tri, inverse_capacity=tri,
+                   method=method)
     t = E.grounded_normalized_inverse_diag(g.n, g.src, g.dst, g.w, Gd.pivot)
     np.testing.assert_allclose(r["tau"].cpu().numpy(), t, rtol=1e-9, atol=1e-12)
     rwc = P.estimate_diag(Gd, r["tau"])["rwc"].cpu().numpy()
     np.testing.assert_allclose(rwc, E.rwc_by_hitting_times(g.n, g.src, g.dst, g.w), rtol=1e-8)
 
 
+@pytest.mark.parametrize("method", ["chain", "dense"])
 @pytest.mark.parametrize("name", ["er1000_w", "grid"])
-def test_estimate_diag_matches_oracle_assembly(name):
+def test_estimate_diag_matches_oracle_assembly(name, method):
     g = _graph(name)
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
-    r = P.fastchol(Gd)
+    r = P.fastchol(Gd, method=method)
     tau = r["tau"].cpu().numpy()
     got = P.estimate_diag(Gd, r["tau"])["rwc"].cpu().numpy()
     want = E.apprwc(g.n, g.src, g.dst, g.w, Gd.pivot, tau)
