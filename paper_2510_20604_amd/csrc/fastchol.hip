@@ -89,10 +89,11 @@ struct FcArgs {
 };
 
 // Words one lane writes and another reads later (the dense accumulator, its stamps and the row
-// lists): relaxed atomics.  Each kernel here is a single wave, so their scope is the wavefront,
-// and so is the scope of wave_order(): a wave's vector memory operations are performed in the
-// order it issues them, so ordering them needs no wait for the memory system, only that the
-// compiler keep them in program order.
+// lists): relaxed atomics.  They are used only on memory that one wave alone touches (the chain's
+// kernel is a single wave; each wave of the inverse has its own slices), so their scope is the
+// wavefront, and so is the scope of wave_order(): a wave's vector memory operations are
+// performed in the order it issues them, so ordering them needs no wait for the memory system,
+// only that the compiler keep them in program order.
 template <class T>
 __device__ __forceinline__ T ld(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -114,7 +115,8 @@ __device__ __forceinline__ uint32_t rank_of(bool flag, uint32_t& count) {
     return static_cast<uint32_t>(__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (kWave - lane)))));
 }
 
-// Bitonic sort of len (<= kSortCap) entries in LDS by one wave; less(a, b) a total order.
+// Bitonic sort of len (<= kSortCap) entries, in LDS or in the wave's own global scratch, by one
+// wave; less(a, b) a total order.
 template <class Less>
 __device__ void wave_sort(double* val, int32_t* row, int32_t len, Less less) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -549,7 +551,7 @@ __device__ void form_part(const FcArgs& A, int32_t j, int p, uint32_t* counts /*
                 const int32_t i = static_cast<int32_t>(base + q * kDenseBlock + threadIdx.x);
                 srow[pos] = i;
                 sval[pos] = xv[q];
-                A.xk[i] = xv[q];   // this thread read row i's old mark above
+                A.xk[i] = xv[q];   // this thread read row i's previous xk / xstamp above
                 A.xstamp[i] = j;
             }
         }
