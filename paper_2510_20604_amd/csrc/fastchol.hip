@@ -730,13 +730,26 @@ __global__ void __launch_bounds__(kInvWaves * kWave) fc_inverse(FcArgs A) {
             st(&touched[0], u);
         }
         wave_order();
+        // the window's entries of column u, 64 at a time (lane l: entry p0 + l); their columns of
+        // S~ are waited for together, then added in ascending row order, each a dependent load of
+        // its entries and then of their stamps and accumulators
         bool stop = false;
-        for (int64_t p = c0 + 1; p < c1 && !stop; ++p) {
-            const int32_t i = A.r_row[p];
-            if (i > u + w) break;
-            // column i of S~ is read once its wave has published it
+        for (int64_t p0 = c0 + 1; p0 < c1 && !stop; p0 += kWave) {
+            const int64_t p = p0 + lane;
+            int32_t i = -1;
+            double coef = 0.0;
+            if (p < c1) {
+                const int32_t r = A.r_row[p];
+                if (r <= u + w) {
+                    i = r;
+                    coef = A.r_val[p] / ruu;
+                }
+            }
+            const uint64_t live = __ballot(i >= 0);   // a prefix: rows ascend
+            if (live == 0ull) break;
             int64_t spins = 0;
-            while (__hip_atomic_load(&A.done[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+            while (__ballot(i >= 0 && __hip_atomic_load(&A.done[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) !=
+                   0ull) {
                 if (__hip_atomic_load(&abort_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0 ||
                     ++spins > kInvSpinLimit) {
                     stop = true;
@@ -745,32 +758,40 @@ __global__ void __launch_bounds__(kInvWaves * kWave) fc_inverse(FcArgs A) {
                 __builtin_amdgcn_s_sleep(2);
             }
             if (stop) break;
-            const double coef = A.r_val[p] / ruu;
-            const int64_t s0 = A.s_start[i];
-            const int32_t sl = A.s_len[i];
-            for (int32_t q0 = 0; q0 < sl; q0 += kWave) {
-                const int32_t q = q0 + lane;
-                int32_t r = -1;
-                double sv = 0.0;
-                bool fresh = false;
-                if (q < sl) {
-                    r = A.s_row[s0 + q];
-                    sv = A.s_val[s0 + q];
-                    fresh = ld(&stamps[r]) != stamp;
-                }
-                uint32_t cnt = 0;
-                const uint32_t rk = rank_of(fresh, cnt);
-                double cur = 0.0;
-                if (fresh) {
-                    st(&stamps[r], stamp);
-                    st(&touched[nt + rk], r);   // distinct rows below N
-                } else if (r >= 0) {
-                    cur = ld(&acc[r]);
-                }
-                nt += cnt;
-                if (r >= 0) st(&acc[r], cur - coef * sv);
+            int64_t s0 = 0;
+            int32_t sl = 0;
+            if (i >= 0) {
+                s0 = A.s_start[i];
+                sl = A.s_len[i];
             }
-            wave_order();
+            for (uint64_t bits = live; bits != 0ull; bits &= bits - 1) {
+                const int l = __builtin_ctzll(bits);
+                const double cf = __shfl(coef, l, kWave);
+                const int64_t b0 = __shfl(s0, l, kWave);
+                const int32_t bl = __shfl(sl, l, kWave);
+                for (int32_t q0 = 0; q0 < bl; q0 += kWave) {
+                    const int32_t q = q0 + lane;
+                    int32_t r = -1;
+                    double sv = 0.0;
+                    if (q < bl) {
+                        r = A.s_row[b0 + q];
+                        sv = A.s_val[b0 + q];
+                    }
+                    const int32_t rc = r >= 0 ? r : u;   // a valid address for every lane
+                    const int32_t sg = ld(&stamps[rc]);
+                    const double old = ld(&acc[rc]);
+                    const bool fresh = r >= 0 && sg != stamp;
+                    uint32_t cnt = 0;
+                    const uint32_t rk = rank_of(fresh, cnt);
+                    if (fresh) {
+                        st(&stamps[r], stamp);
+                        st(&touched[nt + rk], r);   // distinct rows below N
+                    }
+                    nt += cnt;
+                    if (r >= 0) st(&acc[r], (fresh ? 0.0 : old) - cf * sv);
+                }
+                wave_order();
+            }
         }
         if (stop) {
             if (__hip_atomic_load(&abort_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
