@@ -107,6 +107,14 @@ __device__ __forceinline__ void wave_order() { __builtin_amdgcn_fence(__ATOMIC_S
 __device__ __forceinline__ int32_t node_of_column(int32_t j, int32_t v) { return j + (j >= v ? 1 : 0); }
 __device__ __forceinline__ int32_t column_of_node(int32_t u, int32_t v) { return u - (u > v ? 1 : 0); }
 
+// Lane l's value of x (l the same in every lane), exactly.
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffull), l));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), l));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // Lanes whose flag is set, in lane order: this lane's rank among them and their number.
 __device__ __forceinline__ uint32_t rank_of(bool flag, uint32_t& count) {
     const uint64_t m = __ballot(flag);
@@ -687,7 +695,6 @@ constexpr int64_t kInvSpinLimit = int64_t{1} << 26;
 __global__ void __launch_bounds__(kInvWaves * kWave) fc_inverse(FcArgs A) {
     __shared__ double lval[kInvWaves][kInvLds];
     __shared__ int32_t lrow[kInvWaves][kInvLds];
-    __shared__ int32_t kept_count[kInvWaves];
     __shared__ int32_t next_col;
     __shared__ unsigned long long pool;
     __shared__ int32_t abort_all;
@@ -839,22 +846,33 @@ __global__ void __launch_bounds__(kInvWaves * kWave) fc_inverse(FcArgs A) {
                 const double a = fabs(va), b = fabs(vb);
                 return a > b || (a == b && ra < rb);
             });
-            // the 1-norm in sorted order, then the tail grown from the smallest entry
-            if (lane == 0) {
-                double l1 = 0.0;
-                for (int32_t k = 0; k < static_cast<int32_t>(nz); ++k) l1 += fabs(val[k]);
-                double tail = 0.0;
-                int32_t k = static_cast<int32_t>(nz);
-                while (k > 0 && tail + fabs(val[k - 1]) <= A.eps_p * l1) {
-                    tail += fabs(val[k - 1]);
+            // the 1-norm in sorted order, then the tail grown from the smallest entry: every lane
+            // adds the same values in the same order, read from the lanes that loaded them
+            double l1 = 0.0;
+            for (int32_t t0 = 0; t0 < static_cast<int32_t>(nz); t0 += kWave) {
+                const int32_t t = t0 + lane;
+                const double a = t < static_cast<int32_t>(nz) ? fabs(val[t]) : 0.0;
+                const int32_t m = static_cast<int32_t>(nz) - t0 < kWave ? static_cast<int32_t>(nz) - t0 : kWave;
+                for (int32_t l = 0; l < m; ++l) l1 += lane_value(a, l);
+            }
+            const double lim = A.eps_p * l1;
+            double tail = 0.0;
+            int32_t k = static_cast<int32_t>(nz);
+            for (bool more = true; more && k > 0;) {
+                const int32_t base = k > kWave ? k - kWave : 0;   // entries [base, k), largest index first
+                const int32_t t = base + lane;
+                const double a = t < k ? fabs(val[t]) : 0.0;
+                for (int32_t l = k - 1 - base; l >= 0; --l) {
+                    const double x = lane_value(a, l);
+                    if (!(tail + x <= lim)) {
+                        more = false;
+                        break;
+                    }
+                    tail += x;
                     --k;
                 }
-                kept_count[wave] = k;   // hand the count to the other lanes through LDS
             }
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_wave_barrier();
-            keep = kept_count[wave];
-            __builtin_amdgcn_wave_barrier();
+            keep = k;
         }
         wave_sort(val, row, keep, [](double, int32_t ra, double, int32_t rb) { return ra < rb; });
         unsigned long long at = 0;
@@ -868,9 +886,17 @@ __global__ void __launch_bounds__(kInvWaves * kWave) fc_inverse(FcArgs A) {
             A.s_row[sp + k] = row[k];
             A.s_val[sp + k] = val[k];
         }
+        double t2 = 0.0;   // ||S~(:, u)||^2 in row order, as above
+        for (int32_t t0 = 0; t0 < keep; t0 += kWave) {
+            const int32_t t = t0 + lane;
+            const double a = t < keep ? val[t] : 0.0;
+            const int32_t m = keep - t0 < kWave ? keep - t0 : kWave;
+            for (int32_t l = 0; l < m; ++l) {
+                const double x = lane_value(a, l);
+                t2 += x * x;
+            }
+        }
         if (lane == 0) {
-            double t2 = 0.0;
-            for (int32_t k = 0; k < keep; ++k) t2 += val[k] * val[k];
             A.s_start[u] = sp;
             A.s_len[u] = keep;
             A.tau[node] = t2;
