@@ -204,7 +204,10 @@ typedef struct rwc_sample_params {
                                     rooted at S, i.e. Algorithm 3 with InTree = S at the start
                                     of each sample.  Ids must be distinct and in [0, n); a
                                     violation is reported by rwc_workspace_status (the
-                                    outputs are then meaningless).  NULL when num_roots = 0  */
+                                    outputs are then meaningless).  On a CSR with several
+                                    components S must meet each one; a miss is reported the
+                                    same way, as RWC_ERR_DISCONNECTED.  NULL when
+                                    num_roots = 0                                            */
     int32_t num_roots;           /* 0: one root (`root`); else 1 .. n - 1                    */
     int32_t reserved2;
     const int32_t* walkers_per_graph; /* HOST [num_graphs] or NULL: walkers per tree of each
@@ -433,7 +436,9 @@ int rwc_estimate_group_workspace(const rwc_csr* g, size_t* bytes);
  *   marginal_dev   double [n] output H_{S + u}
  *   hit_dev        double [n] output hitting times to S, or NULL
  * Modes and synchronisation as rwc_estimate; a bad root set is RWC_ERR_INVALID_ARG or
- * RWC_ERR_NODE_RANGE (host-checked mode), or reported by rwc_workspace_status. */
+ * RWC_ERR_NODE_RANGE (host-checked mode), or reported by rwc_workspace_status.  On a CSR with
+ * several components S must meet each one (else RWC_ERR_DISCONNECTED, reported by
+ * rwc_workspace_status). */
 int rwc_estimate_group(const rwc_csr* g, const int32_t* roots_dev, int32_t num_roots,
                        const uint64_t* counts_dev, int64_t l, const rwc_solve_params* sp,
                        double* group_rwc_dev, double* marginal_dev, double* hit_dev, int32_t* iters,
