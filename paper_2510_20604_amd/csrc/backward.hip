@@ -198,211 +198,317 @@ __device__ __forceinline__ int64_t part_index(int k, int32_t c, int64_t w, int32
 // partials each thread of bpcg_scalars loads at once
 constexpr int kScalarBatch = 8;
 
-// One wave per row (grid-stride), lanes over columns.
+// The residual starts as the right-hand side (zero on row v), X = 0 and P = z = r / d; the
+// partial dots z.r and r.r, and r.P with P as stored.  One thread per (row, column) element
+// as in bpcg_update (the thread count is a multiple of R; thread t keeps column t mod R and
+// fills partial slot t / R).
 __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restrict__ d, double* __restrict__ Y,
-                          double* __restrict__ X, float* __restrict__ P32, double* __restrict__ part) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-    for (int32_t c0 = 0; c0 < R; c0 += kWave) {
-        const int32_t c = c0 + lane;
-        double zr = 0.0, rr = 0.0;
-        for (int64_t u = wave; u < n; u += nw) {
-            if (c >= R) continue;
-            const int64_t i = u * R + c;
-            const double r = (u == v) ? 0.0 : Y[i];
-            const double z = (u == v) ? 0.0 : r / d[u];
-            Y[i] = r;   // Y becomes the residual
-            X[i] = 0.0;
-            P32[p_index(u, c, R, n)] = static_cast<float>(z);
-            zr += z * r;
-            rr += r * r;
-        }
-        if (c < R) {
-            part[part_index(0, c, wave, R, nw)] = zr;
-            part[part_index(1, c, wave, R, nw)] = rr;
-        }
+                          double* __restrict__ X, float* __restrict__ P32, double* __restrict__ part,
+                          double* __restrict__ rp_part) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t rows_step = static_cast<int64_t>(gridDim.x) * blockDim.x / R;
+    const int32_t c = static_cast<int32_t>(t % R);
+    double zr = 0.0, rr = 0.0, rp = 0.0;
+    for (int64_t u = t / R; u < n; u += rows_step) {
+        const int64_t i = u * R + c;
+        const double r = (u == v) ? 0.0 : Y[i];
+        const double z = (u == v) ? 0.0 : r / d[u];
+        Y[i] = r;   // Y becomes the residual
+        X[i] = 0.0;
+        const float p = static_cast<float>(z);
+        P32[p_index(u, c, R, n)] = p;
+        zr += z * r;
+        rr += r * r;
+        rp += r * static_cast<double>(p);
     }
+    const int64_t slot = t / R;
+    part[part_index(0, c, slot, R, rows_step)] = zr;
+    part[part_index(1, c, slot, R, rows_step)] = rr;
+    rp_part[part_index(0, c, slot, R, rows_step)] = rp;
 }
 
-// AP = L_v P (FP32 P promoted, FP64 sums); partial dots r.P and P.AP per column.  Block b
-// owns rows b, b + nb, b + 2 nb, ... (nb blocks), so the hub rows of a power-law graph, which
-// cluster at small ids, land in different blocks; each wave takes one row at a time and a lane
-// holds up to kColPass columns (lane + 64 j), so one pass over a row's entries serves up to
-// 128 columns.  Rows longer than kLongRow are skipped there and then taken, in order, by all
-// waves of the block, which split the entries and add their sums in LDS in wave order.  Row v
-// of P is zero, so its column entries need no test.
+// AP = L_v P (FP32 P promoted, FP64 sums) and the partial dot P.AP per column (r.P comes from
+// the kernel that writes P).
+//
+// The gathers of neighbour rows of P are bound by memory latency, so a wave keeps kChunk of
+// them in flight at every step, whatever rows their entries belong to.  The CSR entries are
+// cut into one contiguous segment per wave, balanced on the cost nnz + kRowCost n (a wave
+// runs one round per kChunk entries or per kQueue row ends, whichever comes first).  A wave
+// walks its segment in rounds: the round's entries, up to kChunk of them, have their rows of P
+// gathered together and added in entry order to the running sum of the row they belong to.
+// A row that ends in a round leaves its sum in a small per-wave LDS queue, and is finished
+// (AP row, dots) in the next round while that round's gathers are in flight.  A row cut by a
+// segment boundary leaves the sum of its entries in each segment in a slot: the head slot of
+// a segment that starts inside the row, the tail slot of the segment the row starts in;
+// spmm_fixup adds them in segment order and finishes the row.  Lane l holds the columns
+// c0 + l + 64 j (j < kColPass), so one pass over the entries serves up to 128 columns.  Every
+// row has an entry (the adjoint needs a connected graph of two or more nodes), and row v of P
+// is zero, so its column entries need no test.
 constexpr int kColPass = 2;
-constexpr int kLongRow = 4 * kWave;
+constexpr int kChunk = 16;     // gathers in flight per wave
+constexpr int kQueue = 8;      // finished rows a wave holds before writing them out
+constexpr int kRowCost = 10;    // the cost of a row, in entries, for the segment balance
+constexpr int kSegMinCost = 64;   // the least cost of a segment (small graphs use fewer waves)
 
-// sum[j] += w_k * P[col_k, c_j] for the B entries k, k + step, ..., k + (B - 1) step, added in
-// that order; all their loads are issued before the first product.
-template <int B>
-__device__ __forceinline__ void gather_batch(int32_t k, int32_t step, const int32_t* __restrict__ col,
-                                             const float* __restrict__ weight, const float* __restrict__ P32,
-                                             int32_t R, int64_t n, int32_t cbase, double* sum) {
-    int32_t w[B];
-    float t[B];
+// Segments the CSR is cut into: at most `waves`, each of cost at least kSegMinCost.
+int32_t spmm_segments(int64_t nnz, int32_t n, int64_t waves) {
+    const int64_t by_cost = (nnz + static_cast<int64_t>(kRowCost) * n) / kSegMinCost;
+    const int64_t s = by_cost < waves ? by_cost : waves;
+    return static_cast<int32_t>(s < 1 ? 1 : s);
+}
+
+// Segment s of W starts at entry seg_k[s], in row seg_row[s] (s = W: nnz and n).  The cost of
+// the rows before r and of the entries before k in row r is row_ptr[r] + kRowCost (r + 1) +
+// (k - row_ptr[r]) (a row's cost comes before its entries); segment s starts where it reaches
+// s (nnz + kRowCost n) / W.
+__global__ void spmm_bounds(int32_t n, int32_t nnz, int32_t W, const int32_t* __restrict__ row_ptr,
+                            int32_t* __restrict__ seg_k, int32_t* __restrict__ seg_row) {
+    const int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (s > W) return;
+    const int64_t total = static_cast<int64_t>(nnz) + static_cast<int64_t>(kRowCost) * n;
+    const int64_t T = total * s / W;
+    int32_t lo = 0, hi = n;   // largest r with row_ptr[r] + kRowCost r <= T
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] + static_cast<int64_t>(kRowCost) * mid <= T)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    int32_t k = nnz, r = n;
+    if (lo < n) {
+        const int64_t into = T - row_ptr[lo] - static_cast<int64_t>(kRowCost) * (lo + 1);
+        k = row_ptr[lo] + static_cast<int32_t>(into > 0 ? into : 0);
+        if (k > row_ptr[lo + 1]) k = row_ptr[lo + 1];
+        r = lo;
+        while (r < n && row_ptr[r + 1] <= k) ++r;   // the row that holds entry k
+    }
+    seg_k[s] = k;
+    seg_row[s] = r;
+}
+
+// End of row x (row_ptr[x + 1]), or past every entry for x >= n.
+__device__ __forceinline__ int32_t row_end(const int32_t* __restrict__ row_ptr, int32_t n, int64_t x) {
+    return x < n ? row_ptr[x + 1] : INT32_MAX;
+}
+
+__device__ __forceinline__ int32_t lane_int(int32_t x, int32_t l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float lane_float(float x, int32_t l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_double(double x, int32_t l) {
+    const int64_t b = __double_as_longlong(x);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(b), l));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(b >> 32), l));
+    return __longlong_as_double(static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// Finishes row u from its neighbour sums s (this lane's columns c0 + lane + 64 j): AP row and
+// the dot P.AP.
+struct RowFinish {
+    int32_t n, v, R, c0, lane;
+    const double* __restrict__ d;
+    const float* __restrict__ P32;
+    double* __restrict__ AP;
+};
+
+// Writes out the rows q0 .. q0 + qn - 1 (qn <= kQueue) whose sums the queue holds, in order;
+// their own inputs are all loaded before the first is finished.
+__device__ __forceinline__ void finish_queued(const RowFinish& f, int32_t q0, int32_t qn,
+                                              const double (*queue)[kColPass * kWave], double* pap) {
+    // lane i < qn holds d of row q0 + i
+    const double dv = f.d[q0 + (f.lane < qn ? f.lane : qn - 1)];
+    float pu[kQueue][kColPass];
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-        w[i] = col[k + i * step];
-        t[i] = weight[k + i * step];
+    for (int i = 0; i < kQueue; ++i) {
+        if (i >= qn) continue;
+        const int64_t u = q0 + i;
+#pragma unroll
+        for (int j = 0; j < kColPass; ++j) {
+            // lanes past column R - 1 load column R - 1 (unused), so no load is predicated
+            const int32_t c = f.c0 + f.lane + j * kWave < f.R ? f.c0 + f.lane + j * kWave : f.R - 1;
+            pu[i][j] = f.P32[p_index(u, c, f.R, f.n)];
+        }
     }
 #pragma unroll
-    for (int j = 0; j < kColPass; ++j) {
-        const int32_t c = cbase + j * kWave;
-        if (c < R) {
-            // column c lies in block c / 64 (the same block for the whole wave)
-            const int32_t blk = c / kWave;
-            const int64_t stride = p_block_width(blk, R);
-            const float* __restrict__ Pb = P32 + p_block_base(blk, n) + (c - blk * kWave);
-            float a[B];
+    for (int i = 0; i < kQueue; ++i) {
+        if (i >= qn) continue;
+        const int64_t u = q0 + i;
 #pragma unroll
-            for (int i = 0; i < B; ++i) a[i] = Pb[static_cast<int64_t>(w[i]) * stride];
-#pragma unroll
-            for (int i = 0; i < B; ++i) sum[j] += static_cast<double>(t[i]) * static_cast<double>(a[i]);
+        for (int j = 0; j < kColPass; ++j) {
+            const int32_t c = f.c0 + f.lane + j * kWave;
+            if (c >= f.R) continue;
+            const double p = static_cast<double>(pu[i][j]);
+            const double y = (u == f.v) ? 0.0 : lane_double(dv, i) * p - queue[i][f.lane + j * kWave];
+            f.AP[u * f.R + c] = y;
+            pap[j] += p * y;
         }
     }
 }
 
-// The entries k = beg, beg + step, ... < end of a row, in order.  The gathers are bound by
-// memory latency, so a wave keeps 16 rows of P in flight (R-MAT scale 23: 31 % faster than 4).
-__device__ __forceinline__ void gather_rows(int32_t beg, int32_t end, int32_t step, const int32_t* __restrict__ col,
-                                            const float* __restrict__ weight, const float* __restrict__ P32,
-                                            int32_t R, int64_t n, int32_t cbase, double* sum) {
-    int32_t k = beg;
-    for (; k + 15 * step < end; k += 16 * step) gather_batch<16>(k, step, col, weight, P32, R, n, cbase, sum);
-    if (k + 7 * step < end) {
-        gather_batch<8>(k, step, col, weight, P32, R, n, cbase, sum);
-        k += 8 * step;
-    }
-    if (k + 3 * step < end) {
-        gather_batch<4>(k, step, col, weight, P32, R, n, cbase, sum);
-        k += 4 * step;
-    }
-    for (; k < end; k += step) gather_batch<1>(k, step, col, weight, P32, R, n, cbase, sum);
-}
-
-__global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, const int32_t* __restrict__ row_ptr,
-                          const int32_t* __restrict__ col, const float* __restrict__ weight,
-                          const double* __restrict__ d, const float* __restrict__ P32, const double* __restrict__ Rr,
-                          double* __restrict__ AP, double* __restrict__ part) {
-    __shared__ double lds[kWavesPerBlock][kColPass * kWave];
-    __shared__ uint64_t long_mask[kWavesPerBlock];
+__global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, int32_t nnz, int32_t W,
+                          const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                          const float* __restrict__ weight, const double* __restrict__ d,
+                          const float* __restrict__ P32, const int32_t* __restrict__ seg_k,
+                          const int32_t* __restrict__ seg_row, double* __restrict__ AP, double* __restrict__ cut,
+                          double* __restrict__ part) {
+    __shared__ double queue_all[kWavesPerBlock][kQueue][kColPass * kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wib = threadIdx.x / kWave;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // uniform: the segment walk is scalar
     const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib;
-    const int64_t b = blockIdx.x, nb = gridDim.x;
-    const int64_t nw = nb * kWavesPerBlock;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    double (*queue)[kColPass * kWave] = queue_all[wib];
     for (int32_t c0 = 0; c0 < R; c0 += kColPass * kWave) {
-        double rp[kColPass], pap[kColPass];
+        double pap[kColPass];
 #pragma unroll
-        for (int j = 0; j < kColPass; ++j) rp[j] = pap[j] = 0.0;
-        // what one lane needs of row u itself to finish it: its P entries, residuals and d[u]
-        struct RowIn {
-            float pu[kColPass];
-            double rr[kColPass];
-            double du;
-        };
-        auto load_row = [&](int64_t u, RowIn& in) {
-            in.du = d[u];
-#pragma unroll
-            for (int j = 0; j < kColPass; ++j) {
-                const int32_t c = c0 + lane + j * kWave;
-                in.pu[j] = (c < R) ? P32[p_index(u, c, R, n)] : 0.0f;
-                in.rr[j] = (c < R) ? Rr[u * R + c] : 0.0;
+        for (int j = 0; j < kColPass; ++j) pap[j] = 0.0;
+        const RowFinish f{n, v, R, c0, lane, d, P32, AP};
+        if (wave < W) {
+            const int32_t k0 = seg_k[wave], k1 = seg_k[wave + 1];
+            int32_t r = seg_row[wave];                     // the row holding entry k0
+            int32_t rstart = r < n ? row_ptr[r] : k1;      // first entry of row r
+            bool head = rstart < k0;                       // row r began in an earlier segment
+            // row ends: lane l of `win` holds the end of row rw + l, `ahead` the next 64 rows
+            int32_t rw = r;
+            int32_t win = row_end(row_ptr, n, static_cast<int64_t>(rw) + lane);
+            int32_t ahead = row_end(row_ptr, n, static_cast<int64_t>(rw) + kWave + lane);
+            // lanes l < kChunk: column index and weight of entry k + l of the coming round
+            int32_t cw_col = 0;
+            float cw_w = 0.0f;
+            if (lane < kChunk && k0 + lane < nnz) {
+                cw_col = col[k0 + lane];
+                cw_w = weight[k0 + lane];
             }
-        };
-        // finishes row u from its neighbour sums (one lane, its columns)
-        auto finish_row = [&](int64_t u, const double* sum, const RowIn& in) {
+            double sum[kColPass];
 #pragma unroll
-            for (int j = 0; j < kColPass; ++j) {
-                const int32_t c = c0 + lane + j * kWave;
-                if (c >= R) continue;
-                const double pu = static_cast<double>(in.pu[j]);
-                const double y = (u == v) ? 0.0 : in.du * pu - sum[j];
-                AP[u * R + c] = y;
-                rp[j] += in.rr[j] * pu;
-                pap[j] += pu * y;
-            }
-        };
-        auto finish = [&](int64_t u, const double* sum) {
-            RowIn in;
-            load_row(u, in);
-            finish_row(u, sum, in);
-        };
-        // A row's loads form a chain (row bounds, then entries, then gathers); the next row's
-        // bounds and this row's own inputs are loaded before this row's gathers, so their
-        // latency overlaps the chain instead of adding to it.
-        const int64_t ustep = static_cast<int64_t>(kWavesPerBlock) * nb;
-        int64_t u = b + wib * nb;
-        int32_t beg = 0, end = 0;
-        if (u < n) {
-            beg = row_ptr[u];
-            end = row_ptr[u + 1];
-        }
-        while (u < n) {
-            const int64_t un = u + ustep;
-            int32_t nbeg = 0, nend = 0;
-            if (un < n) {
-                nbeg = row_ptr[un];
-                nend = row_ptr[un + 1];
-            }
-            if (end - beg <= kLongRow) {
-                RowIn in;
-                load_row(u, in);
-                double sum[kColPass];
-#pragma unroll
-                for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
-                gather_rows(beg, end, 1, col, weight, P32, R, n, c0 + lane, sum);
-                finish_row(u, sum, in);
-            }
-            u = un;
-            beg = nbeg;
-            end = nend;
-        }
-        for (int64_t base = b; base < n; base += kBlock * nb) {
-            const int64_t u = base + threadIdx.x * nb;
-            const bool is_long = u < n && row_ptr[u + 1] - row_ptr[u] > kLongRow;
-            const uint64_t m = __ballot(is_long);
-            if (lane == 0) long_mask[wib] = m;
-            __syncthreads();
-            for (int wv = 0; wv < kWavesPerBlock; ++wv) {
-                uint64_t bits = long_mask[wv];
-                while (bits) {
-                    const int bit = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    const int64_t r = base + (wv * kWave + bit) * nb;
-                    const int32_t beg = row_ptr[r], end = row_ptr[r + 1];
-                    double sum[kColPass];
-#pragma unroll
-                    for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
-                    gather_rows(beg + wib, end, kWavesPerBlock, col, weight, P32, R, n, c0 + lane, sum);
-#pragma unroll
-                    for (int j = 0; j < kColPass; ++j) lds[wib][lane + j * kWave] = sum[j];
-                    __syncthreads();
-                    if (wib == 0) {
-#pragma unroll
-                        for (int j = 0; j < kColPass; ++j) {
-                            double t = 0.0;
-                            for (int q = 0; q < kWavesPerBlock; ++q) t += lds[q][lane + j * kWave];
-                            sum[j] = t;
-                        }
-                        finish(r, sum);
+            for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
+            int32_t q0 = 0, qn = 0;   // rows q0 .. q0 + qn - 1 wait in the queue
+            for (int32_t k = k0; k < k1;) {
+                // (a) the rows that end in this round, at most kQueue: bit i of `ends` marks entry
+                // k + i as the last of its row; the round stops at the kQueue-th end
+                int32_t cnt = (k1 - k) < kChunk ? (k1 - k) : kChunk;
+                uint32_t ends = 0;
+                int32_t m = 0;
+                for (int32_t rho = r;; ++rho) {
+                    if (rho - rw == kWave) {
+                        rw += kWave;
+                        win = ahead;
+                        ahead = row_end(row_ptr, n, static_cast<int64_t>(rw) + kWave + lane);
                     }
-                    __syncthreads();
+                    const int32_t e = lane_int(win, rho - rw);
+                    if (e > k + cnt) break;
+                    ends |= 1u << (e - 1 - k);
+                    if (++m == kQueue) {
+                        cnt = e - k;
+                        break;
+                    }
+                }
+                // (b) gather the round's rows of P (entries past the round repeat entry k)
+                const int32_t cur_col = cw_col;
+                const float cur_w = cw_w;
+                float a[kChunk][kColPass];
+#pragma unroll
+                for (int j = 0; j < kColPass; ++j) {
+                    // columns c0 + 64 j .. lie in block blk (uniform); each row's base is uniform
+                    // and the lane adds its own offset
+                    const int32_t blk = (c0 + j * kWave) / kWave;
+                    const int64_t stride = p_block_width(blk, R);
+                    const float* __restrict__ Pb = P32 + p_block_base(blk, n);
+                    // lanes past column R - 1 read the row's first entry (their sums are never
+                    // stored), so every load is issued unconditionally
+                    const uint32_t off = c0 + lane + j * kWave < R ? static_cast<uint32_t>(lane) * 4u : 0u;
+#pragma unroll
+                    for (int i = 0; i < kChunk; ++i) {
+                        const int32_t wi = lane_int(cur_col, i < cnt ? i : 0);
+                        const char* row = reinterpret_cast<const char*>(Pb + static_cast<int64_t>(wi) * stride);
+                        a[i][j] = *reinterpret_cast<const float*>(row + off);
+                    }
+                }
+                // the next round's entries
+                const int32_t kn = k + cnt;
+                if (lane < kChunk && kn + lane < nnz) {
+                    cw_col = col[kn + lane];
+                    cw_w = weight[kn + lane];
+                }
+                // (c) finish the rows queued in the last round
+                if (qn > 0) finish_queued(f, q0, qn, queue, pap);
+                qn = 0;
+                // (d) add the round's entries to their rows, in entry order
+#pragma unroll
+                for (int i = 0; i < kChunk; ++i) {
+                    if (i < cnt) {
+                    const double ti = static_cast<double>(lane_float(cur_w, i));
+#pragma unroll
+                    for (int j = 0; j < kColPass; ++j) sum[j] += ti * static_cast<double>(a[i][j]);
+                    if ((ends >> i) & 1u) {   // row r ends at entry k + i
+                        if (head) {
+#pragma unroll
+                            for (int j = 0; j < kColPass; ++j) {
+                                const int32_t c = c0 + lane + j * kWave;
+                                if (c < R) cut[(2 * wave) * R + c] = sum[j];
+                            }
+                            head = false;
+                        } else {
+                            if (qn == 0) q0 = r;
+#pragma unroll
+                            for (int j = 0; j < kColPass; ++j) queue[qn][lane + j * kWave] = sum[j];
+                            ++qn;
+                        }
+#pragma unroll
+                        for (int j = 0; j < kColPass; ++j) sum[j] = 0.0;
+                        ++r;
+                        rstart = k + i + 1;
+                    }
+                    }
+                }
+                k += cnt;
+            }
+            if (qn > 0) finish_queued(f, q0, qn, queue, pap);
+            // the row open at the segment's end, cut by the boundary: its part to a slot
+            if (head || rstart < k1) {
+                const int64_t slot = 2 * wave + (head ? 0 : 1);
+#pragma unroll
+                for (int j = 0; j < kColPass; ++j) {
+                    const int32_t c = c0 + lane + j * kWave;
+                    if (c < R) cut[slot * R + c] = sum[j];
                 }
             }
-            __syncthreads();
         }
 #pragma unroll
         for (int j = 0; j < kColPass; ++j) {
             const int32_t c = c0 + lane + j * kWave;
-            if (c < R) {
-                part[part_index(0, c, wave, R, nw)] = rp[j];
-                part[part_index(1, c, wave, R, nw)] = pap[j];
-            }
+            if (c < R) part[part_index(1, c, wave, R, nw)] = pap[j];
         }
+    }
+}
+
+// The rows cut by segment boundaries.  Wave s (1 <= s < W) takes the row r holding entry
+// seg_k[s] when r began in segment s - 1 (the first boundary inside r): its sum is the tail
+// slot of s - 1 plus the head slots of s, s + 1, ... (every segment that starts inside r), in
+// that order.  Its P.AP is added to the partial of wave s - 1, after that wave's own.
+__global__ void spmm_fixup(int32_t n, int32_t v, int32_t R, int32_t W, const int32_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ seg_k, const int32_t* __restrict__ seg_row,
+                           const double* __restrict__ d, const float* __restrict__ P32,
+                           const double* __restrict__ cut, double* __restrict__ AP, double* __restrict__ part,
+                           int32_t nw) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t s = 1 + (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+    if (s >= W) return;
+    const int32_t r = seg_row[s];
+    if (r >= n) return;
+    const int32_t start = row_ptr[r];
+    if (!(start < seg_k[s] && start >= seg_k[s - 1])) return;
+    int64_t last = s;
+    while (last + 1 < W && seg_row[last + 1] == r) ++last;
+    const double du = d[r];
+    for (int32_t c = lane; c < R; c += kWave) {
+        double sum = cut[(2 * (s - 1) + 1) * R + c];
+        for (int64_t q = s; q <= last; ++q) sum += cut[(2 * q) * R + c];
+        const double p = static_cast<double>(P32[p_index(r, c, R, n)]);
+        const double y = (r == v) ? 0.0 : du * p - sum;
+        AP[static_cast<int64_t>(r) * R + c] = y;
+        const int64_t i1 = part_index(1, c, s - 1, R, nw);
+        part[i1] = part[i1] + p * y;
     }
 }
 
@@ -448,53 +554,63 @@ __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* _
     part[part_index(2, c, slot, R, rows_step)] = rr;
 }
 
+// P = z + beta P (z = r / d), and the partial dot r.P with P as stored; element layout and
+// partial slots as bpcg_update.
 __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
-                               const double* __restrict__ d, const double* __restrict__ Rr, float* __restrict__ P32) {
-    const int64_t total = static_cast<int64_t>(n) * R;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t u = i / R;
+                               const double* __restrict__ d, const double* __restrict__ Rr, float* __restrict__ P32,
+                               double* __restrict__ rp_part) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t rows_step = static_cast<int64_t>(gridDim.x) * blockDim.x / R;
+    const int32_t c = static_cast<int32_t>(t % R);
+    const double beta = sc[c].beta;
+    double rp = 0.0;
+    for (int64_t u = t / R; u < n; u += rows_step) {
         if (u == v) continue;
-        const int32_t c = static_cast<int32_t>(i - u * R);
-        const double z = Rr[i] / d[u];
+        const int64_t i = u * R + c;
+        const double r = Rr[i];
         const int64_t pi = p_index(u, c, R, n);
-        P32[pi] = static_cast<float>(z + sc[c].beta * static_cast<double>(P32[pi]));
+        const float p = static_cast<float>(r / d[u] + beta * static_cast<double>(P32[pi]));
+        P32[pi] = p;
+        rp += r * static_cast<double>(p);
     }
+    rp_part[part_index(0, c, t / R, R, rows_step)] = rp;
 }
 
-// Per-column scalar steps; block c sums column c's per-wave partials (thread t takes waves
-// t, t + 256, ...; then a fixed tree over the threads).
-//   mode 0: after init (zr, rr0)   mode 1: after spmm (alpha)   mode 2: after update (beta)
-__global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict__ part, ColScalars* sc, int mode,
-                             double tol2) {
+// Sum of q[0 .. count) by the block's threads, thread t over t, t + kBlock, ... with
+// kScalarBatch loads in flight (one at a time leaves the kernel waiting on memory latency once
+// per partial); each thread's sum keeps the order of a plain strided loop.
+__device__ double strided_sum(const double* __restrict__ q, int32_t count) {
+    double a = 0.0;
+    int32_t w = threadIdx.x;
+    for (; w + (kScalarBatch - 1) * kBlock < count; w += kScalarBatch * kBlock) {
+        double va[kScalarBatch];
+#pragma unroll
+        for (int j = 0; j < kScalarBatch; ++j) va[j] = q[w + j * kBlock];
+#pragma unroll
+        for (int j = 0; j < kScalarBatch; ++j) a += va[j];
+    }
+    for (; w < count; w += kBlock) a += q[w];
+    return a;
+}
+
+// Per-column scalar steps; block c sums column c's partials (strided_sum, then a fixed tree
+// over the threads).
+//   mode 0: after init (zr, rr0 from `part`)
+//   mode 1: after spmm (alpha = r.P / P.AP: r.P from `rp_part`, P.AP from `part`)
+//   mode 2: after update (beta from z.r, z.r_old, r.r in `part`)
+// `part` holds `nwaves` slots per value, `rp_part` `rp_slots`.
+__global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict__ part, int32_t rp_slots,
+                             const double* __restrict__ rp_part, ColScalars* sc, int mode, double tol2) {
     __shared__ double la[kBlock], lb[kBlock], le[kBlock];
     const int32_t c = blockIdx.x;
-    const double* qa = part + part_index(0, c, 0, R, nwaves);
-    const double* qb = part + part_index(1, c, 0, R, nwaves);
-    const double* qe = part + part_index(2, c, 0, R, nwaves);
-    double a = 0.0, b = 0.0, e = 0.0;
-    // kScalarBatch loads in flight per thread (one at a time leaves this kernel waiting on
-    // memory latency once per partial); the sums keep the order of a plain strided loop
-    int32_t w = threadIdx.x;
-    for (; w + (kScalarBatch - 1) * kBlock < nwaves; w += kScalarBatch * kBlock) {
-        double va[kScalarBatch], vb[kScalarBatch], ve[kScalarBatch];
-#pragma unroll
-        for (int j = 0; j < kScalarBatch; ++j) {
-            va[j] = qa[w + j * kBlock];
-            vb[j] = qb[w + j * kBlock];
-            ve[j] = (mode == 2) ? qe[w + j * kBlock] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kScalarBatch; ++j) {
-            a += va[j];
-            b += vb[j];
-            if (mode == 2) e += ve[j];
-        }
-    }
-    for (; w < nwaves; w += kBlock) {
-        a += qa[w];
-        b += qb[w];
-        if (mode == 2) e += qe[w];
+    double a, b, e = 0.0;
+    if (mode == 1) {
+        a = strided_sum(rp_part + part_index(0, c, 0, R, rp_slots), rp_slots);
+        b = strided_sum(part + part_index(1, c, 0, R, nwaves), nwaves);
+    } else {
+        a = strided_sum(part + part_index(0, c, 0, R, nwaves), nwaves);
+        b = strided_sum(part + part_index(1, c, 0, R, nwaves), nwaves);
+        if (mode == 2) e = strided_sum(part + part_index(2, c, 0, R, nwaves), nwaves);
     }
     la[threadIdx.x] = a;
     lb[threadIdx.x] = b;
@@ -670,20 +786,23 @@ __global__ void edge_gradient(int32_t n, int64_t nnz, int32_t R, const int32_t* 
 
 struct BwdLayout {
     WsHeader* header;
-    double *Y, *X, *AP, *part, *colmean, *coef;
+    double *Y, *X, *AP, *part, *rp_part, *cut, *colmean, *coef;
     float* P32;
     ColScalars* sc;
     EdgeScalars* es;
     GPart* gpart;
     int32_t* gbase;
     int32_t* rank;
+    int32_t *seg_k, *seg_row;
     size_t total;
 };
 
 constexpr int32_t kRowBlocks = 2048;   // blocks of the row-range passes over g
 
-BwdLayout carve_bwd(void* ws, int32_t n, int32_t R) {
+// The SpMM's head and tail slots are sized for the most segments the graph can be cut into.
+BwdLayout carve_bwd(void* ws, int32_t n, int64_t nnz, int32_t R) {
     Carver c(ws);
+    const size_t wmax = static_cast<size_t>(spmm_segments(nnz, n, kMaxWaves));
     BwdLayout L{};
     const size_t nr = static_cast<size_t>(n) * R;
     L.header = c.take<WsHeader>(kHeaderBytes / sizeof(WsHeader));
@@ -692,6 +811,8 @@ BwdLayout carve_bwd(void* ws, int32_t n, int32_t R) {
     L.AP = c.take<double>(nr);
     L.P32 = c.take<float>(nr);
     L.part = c.take<double>(static_cast<size_t>(kMaxWaves) * R * 3);
+    L.rp_part = c.take<double>(static_cast<size_t>(kUpdateSlots) * R);
+    L.cut = c.take<double>(2 * wmax * R);
     L.colmean = c.take<double>(R);
     L.coef = c.take<double>(R);
     L.sc = c.take<ColScalars>(R);
@@ -699,6 +820,8 @@ BwdLayout carve_bwd(void* ws, int32_t n, int32_t R) {
     L.gpart = c.take<GPart>(kRowBlocks);
     L.gbase = c.take<int32_t>(kRowBlocks);
     L.rank = c.take<int32_t>(n);
+    L.seg_k = c.take<int32_t>(wmax + 1);
+    L.seg_row = c.take<int32_t>(wmax + 1);
     L.total = c.used();
     return L;
 }
@@ -734,7 +857,7 @@ extern "C" int rwc_backward_workspace(const rwc_csr* g, const rwc_backward_param
     clear_error();
     if (!bytes) return fail(RWC_ERR_INVALID_ARG, "bytes is required");
     RWC_CHECK(check_params(g, bp));
-    *bytes = carve_bwd(nullptr, g->n, static_cast<int32_t>(workspace_columns(bp))).total;
+    *bytes = carve_bwd(nullptr, g->n, g->nnz, static_cast<int32_t>(workspace_columns(bp))).total;
     return RWC_OK;
 }
 
@@ -746,7 +869,7 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     RWC_CHECK(require_connected(g, "rwc_backward"));
     const int32_t n = g->n, v = g->pivot_index, k = bp->k;
     const int32_t Rmax = static_cast<int32_t>(workspace_columns(bp));
-    RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, Rmax).total));
+    RWC_CHECK(check_workspace(ws, ws_bytes, carve_bwd(nullptr, n, g->nnz, Rmax).total));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double tol = bp->tol > 0 ? bp->tol : 1e-10;
     const int max_iter = bp->max_iter > 0 ? bp->max_iter : 20000;
@@ -754,7 +877,7 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
 
     // 1. The support of g: counts per sign and the sum, per row block, read back once.  The
     // number of solve columns depends on them.
-    BwdLayout L = carve_bwd(ws, n, Rmax);
+    BwdLayout L = carve_bwd(ws, n, g->nnz, Rmax);
     const int32_t rblocks = static_cast<int32_t>(blocks_for(n, 1) < kRowBlocks ? blocks_for(n, 1) : kRowBlocks);
     const int32_t rpb = static_cast<int32_t>((static_cast<int64_t>(n) + rblocks - 1) / rblocks);
     hipLaunchKernelGGL(header_start, dim3(1), dim3(1), 0, s, L.header);
@@ -789,7 +912,7 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
                     bp->max_support);
     const int32_t R = static_cast<int32_t>(2 + (k == 0 ? nz : static_cast<int64_t>(k) * ((npos > 0) + (nneg > 0))));
     // the layout of this call (R columns) fits inside the workspace sized for Rmax
-    L = carve_bwd(ws, n, R);
+    L = carve_bwd(ws, n, g->nnz, R);
     ProbeSpec ps{k, npos > 0 ? 1 : 0, static_cast<uint32_t>(bp->seed), static_cast<uint32_t>(bp->seed >> 32)};
     std::vector<double> coef(R, 0.0);
     if (k > 0) {
@@ -811,9 +934,9 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     hipLaunchKernelGGL(rhs_fill, dim3(flat), dim3(kBlock), 0, s, n, R, ps, grad_rwc, g->node_id, g->strength, L.rank,
                        L.Y);
 
-    // one wave per row up to what the device holds at once: the SpMM is bound by the latency
-    // of its row gathers, so every resident wave slot should hold one (4096 -> 6144 waves:
-    // 8 % faster on R-MAT scale 23)
+    // one wave per row up to what the device holds at once; the SpMM's segments (one per wave,
+    // the waves past them idle) fill every resident wave slot on large graphs, since the
+    // gathers are bound by memory latency
     int64_t nwaves = n;
     if (nwaves > spmm_resident_waves()) nwaves = spmm_resident_waves();
     const unsigned wave_blocks = static_cast<unsigned>((nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -821,6 +944,11 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     const int32_t nw = static_cast<int32_t>(nwaves);
     const int32_t rows_per_block = static_cast<int32_t>((static_cast<int64_t>(n) + wave_blocks - 1) / wave_blocks);
     // (the partial arrays hold kMaxWaves * R * 3 doubles >= wave_blocks * R)
+    const int32_t nseg = spmm_segments(g->nnz, n, nwaves);
+    const int32_t nnz = static_cast<int32_t>(g->nnz);
+    hipLaunchKernelGGL(spmm_bounds, dim3(blocks_for(static_cast<int64_t>(nseg) + 1, kBlock)), dim3(kBlock), 0, s, n,
+                       nnz, nseg, g->row_ptr, L.seg_k, L.seg_row);
+    const unsigned fix_blocks = blocks_for(nseg > 1 ? nseg - 1 : 1, kWavesPerBlock);
     hipLaunchKernelGGL(column_partials, dim3(wave_blocks), dim3(kBlock), 0, s, n, R, rows_per_block, L.Y, L.part);
     hipLaunchKernelGGL(column_finish, dim3(R), dim3(kBlock), 0, s, static_cast<int32_t>(wave_blocks), L.part,
                        L.colmean, 1.0 / n);
@@ -834,9 +962,10 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     const unsigned upd_blocks = static_cast<unsigned>(upd_m * R);
     const int32_t upd_nw = static_cast<int32_t>(upd_m * kBlock);
     const double tol2 = tol * tol;
-    hipLaunchKernelGGL(bpcg_init, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
-                       L.part);
-    hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 0, tol2);
+    hipLaunchKernelGGL(bpcg_init, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
+                       L.part, L.rp_part);
+    hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, upd_nw, L.rp_part, L.sc, 0,
+                       tol2);
     RWC_HIP(hipGetLastError());
     std::vector<ColScalars> host(R);
     int it = 0;
@@ -844,13 +973,19 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     while (!converged && it < max_iter) {
         const int chunk = (max_iter - it) < check ? (max_iter - it) : check;
         for (int c = 0; c < chunk; ++c) {
-            hipLaunchKernelGGL(bpcg_spmm, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, g->row_ptr, g->col,
-                               g->weight, g->strength, L.P32, L.Y, L.AP, L.part);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, L.sc, 1, tol2);
+            hipLaunchKernelGGL(bpcg_spmm, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, nnz, nseg, g->row_ptr,
+                               g->col, g->weight, g->strength, L.P32, L.seg_k, L.seg_row, L.AP, L.cut, L.part);
+            if (nseg > 1)
+                hipLaunchKernelGGL(spmm_fixup, dim3(fix_blocks), dim3(kBlock), 0, s, n, v, R, nseg, g->row_ptr,
+                                   L.seg_k, L.seg_row, g->strength, L.P32, L.cut, L.AP, L.part, nw);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, upd_nw, L.rp_part, L.sc, 1,
+                               tol2);
             hipLaunchKernelGGL(bpcg_update, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
                                L.Y, L.P32, L.AP, L.part);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, L.sc, 2, tol2);
-            hipLaunchKernelGGL(bpcg_direction, dim3(flat), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y, L.P32);
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, upd_nw, L.rp_part, L.sc,
+                               2, tol2);
+            hipLaunchKernelGGL(bpcg_direction, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y,
+                               L.P32, L.rp_part);
         }
         RWC_HIP(hipGetLastError());
         it += chunk;
