@@ -556,6 +556,7 @@ __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* _
 
 // P = z + beta P (z = r / d), and the partial dot r.P with P as stored; element layout and
 // partial slots as bpcg_update.
+constexpr int kDirRows = 8;
 __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
                                const double* __restrict__ d, const double* __restrict__ Rr, float* __restrict__ P32,
                                double* __restrict__ rp_part) {
@@ -564,10 +565,31 @@ __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars
     const int32_t c = static_cast<int32_t>(t % R);
     const double beta = sc[c].beta;
     double rp = 0.0;
-    for (int64_t u = t / R; u < n; u += rows_step) {
+    // kDirRows rows' loads in flight per thread (one row at a time leaves the kernel waiting on
+    // memory latency); the dot keeps the row order
+    int64_t u = t / R;
+    for (; u + (kDirRows - 1) * rows_step < n; u += kDirRows * rows_step) {
+        double r[kDirRows], du[kDirRows];
+        float p_old[kDirRows];
+#pragma unroll
+        for (int q = 0; q < kDirRows; ++q) {
+            const int64_t uq = u + q * rows_step;
+            r[q] = Rr[uq * R + c];
+            du[q] = d[uq];
+            p_old[q] = P32[p_index(uq, c, R, n)];
+        }
+#pragma unroll
+        for (int q = 0; q < kDirRows; ++q) {
+            const int64_t uq = u + q * rows_step;
+            if (uq == v) continue;
+            const float p = static_cast<float>(r[q] / du[q] + beta * static_cast<double>(p_old[q]));
+            P32[p_index(uq, c, R, n)] = p;
+            rp += r[q] * static_cast<double>(p);
+        }
+    }
+    for (; u < n; u += rows_step) {
         if (u == v) continue;
-        const int64_t i = u * R + c;
-        const double r = Rr[i];
+        const double r = Rr[u * R + c];
         const int64_t pi = p_index(u, c, R, n);
         const float p = static_cast<float>(r / d[u] + beta * static_cast<double>(P32[pi]));
         P32[pi] = p;
