@@ -139,3 +139,72 @@ def test_ba2000_gradient_against_central_differences_on_50_edges():
         h = 1e-4 * w0[e]
         fd.append((loss_perturbed(e, h) - loss_perturbed(e, -h)) / (2.0 * h))
     _close(got[edges], np.array(fd), 1e-6)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_smallest_graphs_match_dense_gradient(n):
+    """Paths of two to four nodes, every node a target (exact mode): the adjoint's SpMM cuts
+    the CSR into a single segment, with no boundary for the fix-up to join.  With one edge the
+    gradient is zero (RWC does not change when every weight is scaled, so w dl/dw = 0)."""
+    g = G.path_graph(n)
+    g = g.with_weights(G.uniform_weights(g.m, 0.5, 2.0, 40 + n))
+    t = np.arange(n, dtype=np.int32)
+    gv = np.linspace(1.0, 2.0, n)
+    gd = np.zeros(n)
+    gd[t] = gv
+    want = GR.grad_exact(n, g.src, g.dst, g.w, gd)
+    Gd = P.Graph(n, g.src, g.dst, g.w)
+    got = P.backward(Gd, P.dense_g(n, t, gv, "cuda"), k=0, tol=1e-13)["grad_w"].cpu().numpy()
+    if n == 2:
+        assert abs(got[0]) <= 1e-12 and abs(want[0]) <= 1e-12
+    else:
+        _close(got, want, 1e-7)
+
+
+def test_rows_spanning_many_segments_match_dense_gradient():
+    """Two hubs joined by an edge, with 2400 and 1800 leaves: the SpMM's segments hold about
+    64 units of work, so each hub row is cut by dozens of segment boundaries and summed by the
+    fix-up over every segment it spans.  The second hub is not the pivot, so its cut row
+    reaches the solution; targets on both hubs and on leaves of each."""
+    a, b = 2400, 1800
+    n = a + b + 2
+    src = np.concatenate([[0], np.zeros(a, np.int64), np.ones(b, np.int64)])
+    dst = np.concatenate([[1], 2 + np.arange(a), 2 + a + np.arange(b)])
+    w = G.uniform_weights(len(src), 0.5, 2.0, 61)
+    t = np.array([0, 1, 2, 3, a + 2, a + 3, n - 1], dtype=np.int32)
+    gv = np.array([1.0, 2.0, 0.5, 1.5, 0.75, 1.25, 1.0])
+    gd = np.zeros(n)
+    gd[t] = gv
+    want = GR.grad_exact(n, src, dst, w, gd)
+    Gd = P.Graph(n, src, dst, w)
+    got = P.backward(Gd, P.dense_g(n, t, gv, "cuda"), k=0, tol=1e-13)["grad_w"].cpu().numpy()
+    _close(got, want, 1e-7)
+    assert abs(np.dot(w, got)) <= 1e-8 * np.abs(w * got).sum()
+
+
+def test_more_than_128_columns_match_dense_gradient():
+    """Exact mode with 140 targets: 142 solve columns, so the SpMM runs a second pass over its
+    segments for columns 128 .. 141 (a 14-column block of P)."""
+    g = _graph(1500, 3, 71)
+    t, gv = _targets(g.n, 140, 9, signed=True)
+    gd = np.zeros(g.n)
+    gd[t] = gv
+    want = GR.grad_exact(g.n, g.src, g.dst, g.w, gd)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    got = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=0, tol=1e-12)["grad_w"].cpu().numpy()
+    _close(got, want, 1e-7)
+
+
+def test_two_full_column_blocks_match_oracle_probes():
+    """Sketch mode with 63 probes per sign class and both classes present: 128 columns, two
+    full 64-column blocks of P and no remainder."""
+    g = _graph(700, 3, 83)
+    t, gv = _targets(g.n, 30, 10, signed=True)
+    gd = np.zeros(g.n)
+    gd[t] = gv
+    k, seed = 63, 777
+    cols = GR.probe_columns(g.n, t, gv, k, seed)
+    want = GR.grad_from_probes(g.n, g.src, g.dst, g.w, gd, cols)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    got = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=k, seed=seed, tol=1e-12)["grad_w"].cpu().numpy()
+    _close(got, want, 1e-7)
