@@ -375,7 +375,7 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, int32_t nnz, int32_t 
             // lanes l < kChunk: column index and weight of entry k + l of the coming round
             int32_t cw_col = 0;
             float cw_w = 0.0f;
-            if (lane < kChunk && k0 + lane < nnz) {
+            if (lane < kChunk && static_cast<int64_t>(k0) + lane < nnz) {
                 cw_col = col[k0 + lane];
                 cw_w = weight[k0 + lane];
             }
@@ -426,7 +426,7 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, int32_t nnz, int32_t 
                 }
                 // the next round's entries
                 const int32_t kn = k + cnt;
-                if (lane < kChunk && kn + lane < nnz) {
+                if (lane < kChunk && static_cast<int64_t>(kn) + lane < nnz) {
                     cw_col = col[kn + lane];
                     cw_w = weight[kn + lane];
                 }
