@@ -35,6 +35,7 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxWaves = 8192;   // bound of the per-wave partial arrays
 constexpr int kUpdateSlots = 2048;   // partial slots per column of bpcg_update (<= kMaxWaves)
+constexpr int kDirSlots = 8192;      // partial slots per column of bpcg_init and bpcg_direction (<= kMaxWaves)
 
 __global__ void header_start(WsHeader* header) { header_begin(header); }
 
@@ -833,7 +834,7 @@ BwdLayout carve_bwd(void* ws, int32_t n, int64_t nnz, int32_t R) {
     L.AP = c.take<double>(nr);
     L.P32 = c.take<float>(nr);
     L.part = c.take<double>(static_cast<size_t>(kMaxWaves) * R * 3);
-    L.rp_part = c.take<double>(static_cast<size_t>(kUpdateSlots) * R);
+    L.rp_part = c.take<double>(static_cast<size_t>(kDirSlots) * R);
     L.cut = c.take<double>(2 * wmax * R);
     L.colmean = c.take<double>(R);
     L.coef = c.take<double>(R);
@@ -983,10 +984,14 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     const int64_t upd_m = blocks_for(n, kBlock) < kUpdateSlots / kBlock ? blocks_for(n, kBlock) : kUpdateSlots / kBlock;
     const unsigned upd_blocks = static_cast<unsigned>(upd_m * R);
     const int32_t upd_nw = static_cast<int32_t>(upd_m * kBlock);
+    // bpcg_init and bpcg_direction (the r.P partials) on a grid of their own, same layout
+    const int64_t dir_m = blocks_for(n, kBlock) < kDirSlots / kBlock ? blocks_for(n, kBlock) : kDirSlots / kBlock;
+    const unsigned dir_blocks = static_cast<unsigned>(dir_m * R);
+    const int32_t dir_nw = static_cast<int32_t>(dir_m * kBlock);
     const double tol2 = tol * tol;
-    hipLaunchKernelGGL(bpcg_init, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
+    hipLaunchKernelGGL(bpcg_init, dim3(dir_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
                        L.part, L.rp_part);
-    hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, upd_nw, L.rp_part, L.sc, 0,
+    hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, dir_nw, L.part, dir_nw, L.rp_part, L.sc, 0,
                        tol2);
     RWC_HIP(hipGetLastError());
     std::vector<ColScalars> host(R);
@@ -1000,13 +1005,13 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
             if (nseg > 1)
                 hipLaunchKernelGGL(spmm_fixup, dim3(fix_blocks), dim3(kBlock), 0, s, n, v, R, nseg, g->row_ptr,
                                    L.seg_k, L.seg_row, g->strength, L.P32, L.cut, L.AP, L.part, nw);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, upd_nw, L.rp_part, L.sc, 1,
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, dir_nw, L.rp_part, L.sc, 1,
                                tol2);
             hipLaunchKernelGGL(bpcg_update, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
                                L.Y, L.P32, L.AP, L.part);
-            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, upd_nw, L.rp_part, L.sc,
+            hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, dir_nw, L.rp_part, L.sc,
                                2, tol2);
-            hipLaunchKernelGGL(bpcg_direction, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y,
+            hipLaunchKernelGGL(bpcg_direction, dim3(dir_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y,
                                L.P32, L.rp_part);
         }
         RWC_HIP(hipGetLastError());
