@@ -775,6 +775,7 @@ __global__ void edge_scalars(int32_t nparts, const double* __restrict__ part, Ed
 
 // One thread per CSR entry (u, w) with u < w, i.e. per undirected edge; the row u of entry
 // k is found by binary search, so hub rows spread over the whole grid.
+constexpr int kEdgeCols = 16;
 __global__ void edge_gradient(int32_t n, int64_t nnz, int32_t R, const int32_t* __restrict__ row_ptr,
                               const int32_t* __restrict__ col, const int32_t* __restrict__ edge_id,
                               const double* __restrict__ Z, const double* __restrict__ coef,
@@ -797,8 +798,25 @@ __global__ void edge_gradient(int32_t n, int64_t nnz, int32_t R, const int32_t* 
         const double* zb = Z + w * R;
         const double dA = za[0] - zb[0], sA = za[0] + zb[0];
         const double dB = za[1] - zb[1], sB = za[1] + zb[1];
+        // kEdgeCols columns' loads in flight at a time (one pair at a time leaves the thread
+        // waiting on memory once per column); q keeps the column order
         double q = 0.0;
-        for (int32_t c = 2; c < R; ++c) {
+        int32_t c = 2;
+        for (; c + kEdgeCols <= R; c += kEdgeCols) {
+            double a[kEdgeCols], b[kEdgeCols], f[kEdgeCols];
+#pragma unroll
+            for (int i = 0; i < kEdgeCols; ++i) {
+                a[i] = za[c + i];
+                b[i] = zb[c + i];
+                f[i] = coef[c + i];
+            }
+#pragma unroll
+            for (int i = 0; i < kEdgeCols; ++i) {
+                const double t = a[i] - b[i];
+                q += f[i] * (t * t);
+            }
+        }
+        for (; c < R; ++c) {
             const double t = za[c] - zb[c];
             q += coef[c] * (t * t);
         }
