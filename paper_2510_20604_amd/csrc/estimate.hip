@@ -78,10 +78,10 @@ __global__ void pcg_init(int32_t n, int32_t v, const uint32_t* __restrict__ gmas
 
 // y = L_v p on the grounded system (row and column v removed, p_v kept at zero).  Block b owns
 // rows b, b + nb, b + 2 nb, ... (nb blocks), so hub rows, which cluster at small ids in
-// power-law graphs, land in different blocks.  Eight lanes share a short row (strided over its
+// power-law graphs, land in different blocks.  kRowLanes lanes share a short row (strided over its
 // entries, then a shuffle reduction); rows longer than kLongRow are left out of that pass and
 // then taken one at a time, in order, by the whole block.
-constexpr int kRowLanes = 8;
+constexpr int kRowLanes = 16;
 constexpr int kLongRow = 16 * kRowLanes;
 
 __global__ void spmv_dot(int32_t n, int32_t v, const uint32_t* __restrict__ gmask, const Scalars* __restrict__ sc,
