@@ -459,35 +459,109 @@ __global__ void pivot_input_id(const int32_t* __restrict__ node_id, BuildScalars
 // The frontier bounds live on the device, so that levels can be launched back to back without a
 // host round trip each: the current level expands order[lo, hi); bfs_advance then moves to the
 // nodes appended meanwhile and stops the search (done) once a level adds nothing.
+constexpr int32_t kBfsLongRow = 4096;   // frontier rows longer than this are shared by every wave
+constexpr int kBfsLongRows = 256;       // such rows one level defers (any more expand in place)
+
 struct BfsState {
     uint32_t tail;    // nodes in the queue so far
     uint32_t lo, hi;  // the current level's frontier
     int32_t level;    // its distance from the pivot
     int32_t done;     // no frontier left: further launches return at once
     int32_t depth;    // largest distance reached
+    uint32_t nlong;   // long frontier rows deferred to bfs_long this level
+    int32_t long_rows[kBfsLongRows];
 };
 
-// One wave per frontier node, lanes over its neighbours (hub rows do not serialise a lane).
+// Newly reached nodes collect in a per-wave LDS buffer of kBfsBuf entries, which goes to the
+// queue with one atomic on its tail when it cannot take another 64 (and when the wave ends).
+constexpr int kBfsBuf = 512;
+
+struct BfsBuffer {
+    int32_t* buf;   // this wave's kBfsBuf entries in LDS
+    int32_t count;  // entries held (wave-uniform)
+};
+
+__device__ __forceinline__ void bfs_flush(BfsBuffer& b, int lane, int32_t* __restrict__ order, BfsState* st) {
+    if (b.count == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&st->tail, static_cast<uint32_t>(b.count));
+    base = __shfl(base, 0, kWave);
+    for (int32_t i = lane; i < b.count; i += kWave) order[base + i] = b.buf[i];
+    b.count = 0;
+}
+
+// Expands entries k0 + lane of the row (k0 wave-uniform, entries from `end` on ignored): a
+// neighbour still unreached is claimed for the next level and buffered for the queue.
+__device__ __forceinline__ void bfs_expand(int32_t k0, int32_t end, int lane, int32_t level,
+                                           const int32_t* __restrict__ col, int32_t* __restrict__ dist,
+                                           int32_t* __restrict__ order, BfsState* st, BfsBuffer& b) {
+    const int32_t k = k0 + lane;
+    int32_t w = 0;
+    bool found = false;
+    if (k < end) {
+        w = col[k];
+        found = dist[w] == -1 && atomicCAS(&dist[w], -1, level + 1) == -1;
+    }
+    const uint64_t m = __ballot(found);
+    if (m == 0) return;
+    if (b.count > kBfsBuf - kWave) bfs_flush(b, lane, order, st);
+    if (found) b.buf[b.count + __popcll(m & ((1ull << lane) - 1))] = w;
+    b.count += __popcll(m);
+}
+
+// One wave per frontier node, lanes over its neighbours; rows longer than kBfsLongRow go to
+// bfs_long (up to kBfsLongRows of them), so a hub's row does not hold the level on one wave.
 __global__ void bfs_level(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                           int32_t* __restrict__ dist, int32_t* __restrict__ order, BfsState* st) {
     if (st->done) return;
     const uint32_t lo = st->lo, hi = st->hi;
     const int32_t level = st->level;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+    __shared__ int32_t lds[kBlock / kWave][kBfsBuf];
+    BfsBuffer b{lds[threadIdx.x / kWave], 0};
     for (int64_t i = lo + wave; i < hi; i += nw) {
         const int32_t u = order[i];
-        const int32_t end = row_ptr[u + 1];
-        for (int32_t k = row_ptr[u] + lane; k < end; k += kWave) {
-            const int32_t w = col[k];
-            if (dist[w] == -1 && atomicCAS(&dist[w], -1, level + 1) == -1) order[atomicAdd(&st->tail, 1u)] = w;
+        const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+        if (end - beg > kBfsLongRow) {
+            uint32_t slot = 0;
+            if (lane == 0) {
+                slot = atomicAdd(&st->nlong, 1u);
+                if (slot < kBfsLongRows) st->long_rows[slot] = u;
+            }
+            if (__shfl(slot, 0, kWave) < kBfsLongRows) continue;
         }
+        for (int32_t k0 = beg; k0 < end; k0 += kWave) bfs_expand(k0, end, lane, level, col, dist, order, st, b);
     }
+    bfs_flush(b, lane, order, st);
+}
+
+// The level's long rows, every wave taking every nw-th 64-entry chunk of each.
+__global__ void bfs_long(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                         int32_t* __restrict__ dist, int32_t* __restrict__ order, BfsState* st) {
+    if (st->done) return;
+    const uint32_t nl = st->nlong < kBfsLongRows ? st->nlong : kBfsLongRows;
+    const int32_t level = st->level;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+    __shared__ int32_t lds[kBlock / kWave][kBfsBuf];
+    BfsBuffer b{lds[threadIdx.x / kWave], 0};
+    for (uint32_t j = 0; j < nl; ++j) {
+        const int32_t u = st->long_rows[j];
+        const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+        for (int64_t k0 = beg + wave * kWave; k0 < end; k0 += nw * kWave)
+            bfs_expand(static_cast<int32_t>(k0), end, lane, level, col, dist, order, st, b);
+    }
+    bfs_flush(b, lane, order, st);
 }
 
 __global__ void bfs_advance(BfsState* st) {
     if (st->done) return;
+    st->nlong = 0;
     const uint32_t t = st->tail;
     if (t == st->hi) {
         st->done = 1;
@@ -506,7 +580,13 @@ __global__ void bfs_init(int32_t n, int32_t pivot, int32_t* __restrict__ dist, i
         dist[u] = (u == pivot) ? 0 : -1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         order[0] = pivot;
-        *st = BfsState{1u, 0u, 1u, 0, 0, 0};
+        st->tail = 1u;
+        st->lo = 0u;
+        st->hi = 1u;
+        st->level = 0;
+        st->done = 0;
+        st->depth = 0;
+        st->nlong = 0u;
     }
 }
 
@@ -805,6 +885,7 @@ extern "C" int rwc_build_csr_ex(int32_t n, int64_t m, const int32_t* src, const 
         if (launched > n) return fail(RWC_ERR_HIP, "breadth-first search did not finish in %d levels", n);
         for (int c = 0; c < kBfsChunk; ++c) {
             hipLaunchKernelGGL(bfs_level, dim3(gs), dim3(kBlock), 0, s, L.row_ptr, L.col, L.parent, L.bfs_order, L.bfs);
+            hipLaunchKernelGGL(bfs_long, dim3(gs), dim3(kBlock), 0, s, L.row_ptr, L.col, L.parent, L.bfs_order, L.bfs);
             hipLaunchKernelGGL(bfs_advance, dim3(1), dim3(1), 0, s, L.bfs);
         }
         RWC_HIP(hipGetLastError());

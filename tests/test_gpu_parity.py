@@ -404,3 +404,32 @@ def test_csr_rejects_fixed_point_overflow(shape):
     with pytest.raises(P.RWCError) as ei:
         P.Graph(n, src, dst, w)
     assert ei.value.status == -5
+
+
+def test_breadth_first_order_with_long_frontier_rows():
+    """A hub of 5000 leaves, 300 of which are hubs of 4100 leaves each: rows longer than 4096
+    entries are shared by every wave of a level, and the second level has more of them (300)
+    than one level defers (256), so the rest are expanded in place.  The start order is a
+    permutation from the pivot with non-decreasing distance, and the depth is the pivot's
+    eccentricity."""
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as csg
+    hubs, leaves, sub = 5000, 300, 4100
+    src = [np.zeros(hubs, np.int64)]
+    dst = [1 + np.arange(hubs)]
+    nxt = 1 + hubs
+    for h in range(leaves):
+        src.append(np.full(sub, 1 + h, np.int64))
+        dst.append(nxt + np.arange(sub))
+        nxt += sub
+    src, dst, n = np.concatenate(src), np.concatenate(dst), nxt
+    Gd = P.Graph(n, src, dst)
+    order = Gd.bfs_order().cpu().numpy()
+    nid = Gd.node_id().cpu().numpy()
+    np.testing.assert_array_equal(np.sort(order), np.arange(n))
+    assert nid[order[0]] == Gd.pivot
+    A = sp.csr_matrix((np.ones(2 * len(src)), (np.concatenate([src, dst]), np.concatenate([dst, src]))),
+                      shape=(n, n))
+    dist = csg.shortest_path(A, unweighted=True, indices=Gd.pivot)
+    assert np.all(np.diff(dist[nid[order]]) >= 0)
+    assert Gd.csr.bfs_depth == int(dist.max())
