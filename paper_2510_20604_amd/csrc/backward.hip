@@ -51,6 +51,13 @@ struct ColScalars {
     int32_t pad;
 };
 
+// Batched-PCG progress: columns converged so far, and iterations run.  Once every column is
+// done, the iteration's kernels return at once (the host looks only every few iterations).
+struct BpcgState {
+    int32_t ndone;
+    int32_t iters;
+};
+
 // ----------------------------------------------------------------- RHS ---------------
 // The right-hand sides are built on the device from the dense g: column 0 is g, column 1 is d,
 // columns 2.. are the probe columns y_i, then every column is centred.
@@ -205,8 +212,9 @@ constexpr int kScalarBatch = 8;
 // fills partial slot t / R).
 __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restrict__ d, double* __restrict__ Y,
                           double* __restrict__ X, float* __restrict__ P32, double* __restrict__ part,
-                          double* __restrict__ rp_part) {
+                          double* __restrict__ rp_part, BpcgState* __restrict__ st) {
     const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (t == 0) *st = BpcgState{0, 0};
     const int64_t rows_step = static_cast<int64_t>(gridDim.x) * blockDim.x / R;
     const int32_t c = static_cast<int32_t>(t % R);
     double zr = 0.0, rr = 0.0, rp = 0.0;
@@ -352,8 +360,9 @@ __global__ void bpcg_spmm(int32_t n, int32_t v, int32_t R, int32_t nnz, int32_t 
                           const float* __restrict__ weight, const double* __restrict__ d,
                           const float* __restrict__ P32, const int32_t* __restrict__ seg_k,
                           const int32_t* __restrict__ seg_row, double* __restrict__ AP, double* __restrict__ cut,
-                          double* __restrict__ part) {
+                          double* __restrict__ part, const BpcgState* __restrict__ st) {
     __shared__ double queue_all[kWavesPerBlock][kQueue][kColPass * kWave];
+    if (st->ndone == R) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // uniform: the segment walk is scalar
     const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib;
@@ -491,7 +500,8 @@ __global__ void spmm_fixup(int32_t n, int32_t v, int32_t R, int32_t W, const int
                            const int32_t* __restrict__ seg_k, const int32_t* __restrict__ seg_row,
                            const double* __restrict__ d, const float* __restrict__ P32,
                            const double* __restrict__ cut, double* __restrict__ AP, double* __restrict__ part,
-                           int32_t nw) {
+                           int32_t nw, const BpcgState* __restrict__ st) {
+    if (st->ndone == R) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t s = 1 + (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
     if (s >= W) return;
@@ -530,7 +540,9 @@ int64_t spmm_resident_waves() {
 // (virtual wave t / R of the column-partial layout).
 __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
                             const double* __restrict__ d, double* __restrict__ X, double* __restrict__ Rr,
-                            const float* __restrict__ P32, const double* __restrict__ AP, double* __restrict__ part) {
+                            const float* __restrict__ P32, const double* __restrict__ AP, double* __restrict__ part,
+                            const BpcgState* __restrict__ st) {
+    if (st->ndone == R) return;
     const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int64_t rows_step = static_cast<int64_t>(gridDim.x) * blockDim.x / R;
     const int32_t c = static_cast<int32_t>(t % R);
@@ -560,7 +572,8 @@ __global__ void bpcg_update(int32_t n, int32_t v, int32_t R, const ColScalars* _
 constexpr int kDirRows = 8;
 __global__ void bpcg_direction(int32_t n, int32_t v, int32_t R, const ColScalars* __restrict__ sc,
                                const double* __restrict__ d, const double* __restrict__ Rr, float* __restrict__ P32,
-                               double* __restrict__ rp_part) {
+                               double* __restrict__ rp_part, const BpcgState* __restrict__ st) {
+    if (st->ndone == R) return;
     const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int64_t rows_step = static_cast<int64_t>(gridDim.x) * blockDim.x / R;
     const int32_t c = static_cast<int32_t>(t % R);
@@ -623,9 +636,14 @@ __device__ double strided_sum(const double* __restrict__ q, int32_t count) {
 //   mode 2: after update (beta from z.r, z.r_old, r.r in `part`)
 // `part` holds `nwaves` slots per value, `rp_part` `rp_slots`.
 __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict__ part, int32_t rp_slots,
-                             const double* __restrict__ rp_part, ColScalars* sc, int mode, double tol2) {
+                             const double* __restrict__ rp_part, ColScalars* sc, int mode, double tol2,
+                             BpcgState* __restrict__ st) {
     __shared__ double la[kBlock], lb[kBlock], le[kBlock];
     const int32_t c = blockIdx.x;
+    // every column done: the iteration is not run (ndone only grows, so the whole iteration
+    // sees the same answer)
+    if (mode != 0 && st->ndone == R) return;
+    if (mode == 1 && c == 0 && threadIdx.x == 0) st->iters += 1;
     double a, b, e = 0.0;
     if (mode == 1) {
         a = strided_sum(rp_part + part_index(0, c, 0, R, rp_slots), rp_slots);
@@ -659,6 +677,7 @@ __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict
         s.done = (b == 0.0) ? 1 : 0;
         s.alpha = 0.0;
         s.beta = 0.0;
+        if (s.done) atomicAdd(&st->ndone, 1);
     } else if (mode == 1) {
         s.rp = a;
         s.pap = b;
@@ -667,7 +686,10 @@ __global__ void bpcg_scalars(int32_t R, int32_t nwaves, const double* __restrict
         s.rr = e;
         s.beta = (s.done || s.zr == 0.0) ? 0.0 : (a - b) / s.zr;
         s.zr = a;
-        if (e <= tol2 * s.rr0) s.done = 1;
+        if (!s.done && e <= tol2 * s.rr0) {
+            s.done = 1;
+            atomicAdd(&st->ndone, 1);
+        }
     }
     sc[c] = s;
 }
@@ -830,6 +852,7 @@ struct BwdLayout {
     double *Y, *X, *AP, *part, *rp_part, *cut, *colmean, *coef;
     float* P32;
     ColScalars* sc;
+    BpcgState* bst;
     EdgeScalars* es;
     GPart* gpart;
     int32_t* gbase;
@@ -857,6 +880,7 @@ BwdLayout carve_bwd(void* ws, int32_t n, int64_t nnz, int32_t R) {
     L.colmean = c.take<double>(R);
     L.coef = c.take<double>(R);
     L.sc = c.take<ColScalars>(R);
+    L.bst = c.take<BpcgState>(1);
     L.es = c.take<EdgeScalars>(1);
     L.gpart = c.take<GPart>(kRowBlocks);
     L.gbase = c.take<int32_t>(kRowBlocks);
@@ -1008,38 +1032,41 @@ extern "C" int rwc_backward(const rwc_csr* g, const double* grad_rwc, const rwc_
     const int32_t dir_nw = static_cast<int32_t>(dir_m * kBlock);
     const double tol2 = tol * tol;
     hipLaunchKernelGGL(bpcg_init, dim3(dir_blocks), dim3(kBlock), 0, s, n, v, R, g->strength, L.Y, L.X, L.P32,
-                       L.part, L.rp_part);
+                       L.part, L.rp_part, L.bst);
     hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, dir_nw, L.part, dir_nw, L.rp_part, L.sc, 0,
-                       tol2);
+                       tol2, L.bst);
     RWC_HIP(hipGetLastError());
     std::vector<ColScalars> host(R);
+    BpcgState progress{};
     int it = 0;
     bool converged = false;
     while (!converged && it < max_iter) {
         const int chunk = (max_iter - it) < check ? (max_iter - it) : check;
         for (int c = 0; c < chunk; ++c) {
             hipLaunchKernelGGL(bpcg_spmm, dim3(wave_blocks), dim3(kBlock), 0, s, n, v, R, nnz, nseg, g->row_ptr,
-                               g->col, g->weight, g->strength, L.P32, L.seg_k, L.seg_row, L.AP, L.cut, L.part);
+                               g->col, g->weight, g->strength, L.P32, L.seg_k, L.seg_row, L.AP, L.cut, L.part, L.bst);
             if (nseg > 1)
                 hipLaunchKernelGGL(spmm_fixup, dim3(fix_blocks), dim3(kBlock), 0, s, n, v, R, nseg, g->row_ptr,
-                                   L.seg_k, L.seg_row, g->strength, L.P32, L.cut, L.AP, L.part, nw);
+                                   L.seg_k, L.seg_row, g->strength, L.P32, L.cut, L.AP, L.part, nw, L.bst);
             hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, nw, L.part, dir_nw, L.rp_part, L.sc, 1,
-                               tol2);
+                               tol2, L.bst);
             hipLaunchKernelGGL(bpcg_update, dim3(upd_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.X,
-                               L.Y, L.P32, L.AP, L.part);
+                               L.Y, L.P32, L.AP, L.part, L.bst);
             hipLaunchKernelGGL(bpcg_scalars, dim3(R), dim3(kBlock), 0, s, R, upd_nw, L.part, dir_nw, L.rp_part, L.sc,
-                               2, tol2);
+                               2, tol2, L.bst);
             hipLaunchKernelGGL(bpcg_direction, dim3(dir_blocks), dim3(kBlock), 0, s, n, v, R, L.sc, g->strength, L.Y,
-                               L.P32, L.rp_part);
+                               L.P32, L.rp_part, L.bst);
         }
         RWC_HIP(hipGetLastError());
         it += chunk;
         RWC_HIP(hipMemcpyAsync(host.data(), L.sc, sizeof(ColScalars) * R, hipMemcpyDeviceToHost, s));
+        RWC_HIP(hipMemcpyAsync(&progress, L.bst, sizeof(BpcgState), hipMemcpyDeviceToHost, s));
         RWC_HIP(hipStreamSynchronize(s));
         converged = true;
         for (int32_t c = 0; c < R; ++c) converged = converged && host[c].done;
     }
-    if (iters) *iters = it;
+    // iterations run: the launches past the one where the last column converged return at once
+    if (iters) *iters = progress.iters;
     if (!converged) {
         double worst = 0.0;
         for (int32_t c = 0; c < R; ++c)
