@@ -239,14 +239,14 @@ __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restr
 // AP = L_v P (FP32 P promoted, FP64 sums) and the partial dot P.AP per column (r.P comes from
 // the kernel that writes P).
 //
-// The gathers of neighbour rows of P are bound by memory latency, so a wave keeps kChunk of
-// them in flight at every step, whatever rows their entries belong to.  The CSR entries are
+// The gathers of neighbour rows of P reach HBM bandwidth only with many of them in flight, so a
+// wave keeps kChunk of them in flight at every step, whatever rows their entries belong to.  The CSR entries are
 // cut into one contiguous segment per wave, balanced on the cost nnz + kRowCost n (a wave
 // runs one round per kChunk entries or per kQueue row ends, whichever comes first).  A wave
 // walks its segment in rounds: the round's entries, up to kChunk of them, have their rows of P
 // gathered together and added in entry order to the running sum of the row they belong to.
 // A row that ends in a round leaves its sum in a small per-wave LDS queue, and is finished
-// (AP row, dots) in the next round while that round's gathers are in flight.  A row cut by a
+// (AP row, P.AP) in the next round while that round's gathers are in flight.  A row cut by a
 // segment boundary leaves the sum of its entries in each segment in a slot: the head slot of
 // a segment that starts inside the row, the tail slot of the segment the row starts in;
 // spmm_fixup adds them in segment order and finishes the row.  Lane l holds the columns
@@ -256,7 +256,7 @@ __global__ void bpcg_init(int32_t n, int32_t v, int32_t R, const double* __restr
 constexpr int kColPass = 2;
 constexpr int kChunk = 16;     // gathers in flight per wave
 constexpr int kQueue = 8;      // finished rows a wave holds before writing them out
-constexpr int kRowCost = 10;    // the cost of a row, in entries, for the segment balance
+constexpr int kRowCost = 10;   // the cost of a row, in entries, for the segment balance
 constexpr int kSegMinCost = 64;   // the least cost of a segment (small graphs use fewer waves)
 
 // Segments the CSR is cut into: at most `waves`, each of cost at least kSegMinCost.
