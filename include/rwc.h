@@ -452,7 +452,9 @@ typedef struct rwc_backward_params {
                             Philox4x32-10 on the counter (i, u, 0, 2^32 - 1); probes of the
                             negative class are numbered k .. 2k-1                          */
     double tol;          /* relative residual of every solve column; 0 = 1e-10            */
-    int32_t check_every; /* iterations between host convergence checks; 0 = 16            */
+    int32_t check_every; /* iterations between host convergence checks; 0 = 16.  Iterations
+                            launched past the last column's convergence return at once,
+                            so the result and `iters` do not depend on it              */
     int32_t max_support; /* exact mode (k = 0): the most nonzeros g may have (the workspace
                             holds 2 + max_support solve columns); ignored when k > 0       */
 } rwc_backward_params;
@@ -476,7 +478,8 @@ int rwc_backward_workspace(const rwc_csr* g, const rwc_backward_params* bp, size
  *                 (exact mode) more than max_support nonzeros; if it is zero everywhere the
  *                 gradient is zero
  *   grad_w_dev    double [m] output in input-edge order (device)
- *   iters         HOST int32 output: CG iterations used, or NULL
+ *   iters         HOST int32 output: CG iterations run (up to the last column's
+ *                 convergence), or NULL
  * Synchronises `stream` (it reads back the support counts, then checks convergence every
  * check_every iterations). */
 int rwc_backward(const rwc_csr* g, const double* grad_rwc_dev, const rwc_backward_params* bp,

@@ -488,20 +488,22 @@ def dense_g(n: int, targets, gvals, device) -> torch.Tensor:
 
 
 def backward(graph: Graph, g: torch.Tensor, k: int = 0, seed: int = 0, tol: float = 1e-10,
-             max_iter: int = 0, max_support: int | None = None) -> dict:
+             max_iter: int = 0, max_support: int | None = None, check_every: int = 0) -> dict:
     """Gradient of sum_j g_j RWC_j with respect to the edge weights (rwc_backward).
 
     g: float64 [n] device tensor (the upstream gradient).  k = 0 solves one column per nonzero
     of g (exact; the workspace is sized for max_support nonzeros, by default the count of g's
-    nonzeros, read once); k > 0 uses k Rademacher probes per sign class of g.
-    Returns grad_w (float64 [m] on the device, input-edge order) and the CG iterations."""
+    nonzeros, read once); k > 0 uses k Rademacher probes per sign class of g.  check_every: the
+    host looks at convergence every that many iterations (0: 16); iterations launched past it
+    return at once, so the result does not depend on it.
+    Returns grad_w (float64 [m] on the device, input-edge order) and the CG iterations run."""
     L = _lib.lib()
     gt = _dev_tensor(g, torch.float64, graph.device)
     if gt.numel() != graph.n:
         raise ValueError(f"g must have n = {graph.n} entries, not {gt.numel()}")
     if k == 0 and max_support is None:
         max_support = int(torch.count_nonzero(gt))
-    bp = BackwardParams(k=k, max_iter=max_iter, seed=seed, tol=tol, check_every=0,
+    bp = BackwardParams(k=k, max_iter=max_iter, seed=seed, tol=tol, check_every=check_every,
                         max_support=max_support if k == 0 else 0)
     size = ctypes.c_size_t()
     check(L.rwc_backward_workspace(ctypes.byref(graph.csr), ctypes.byref(bp), ctypes.byref(size)),

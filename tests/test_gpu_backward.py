@@ -208,3 +208,19 @@ def test_two_full_column_blocks_match_oracle_probes():
     Gd = P.Graph(g.n, g.src, g.dst, g.w)
     got = P.backward(Gd, P.dense_g(g.n, t, gv, "cuda"), k=k, seed=seed, tol=1e-12)["grad_w"].cpu().numpy()
     _close(got, want, 1e-7)
+
+
+def test_iterations_past_convergence_change_nothing():
+    """The host looks at the columns' convergence every `check_every` iterations; the ones
+    launched past the last column's convergence return at once.  Looking after every
+    iteration, every 7 or every 16 gives the same iteration count (the one run) and the same
+    gradient bit for bit."""
+    g = _graph(2000, 4, 75)
+    t, gv = _targets(g.n, 12, 11, signed=True)
+    Gd = P.Graph(g.n, g.src, g.dst, g.w)
+    gd = P.dense_g(g.n, t, gv, "cuda")
+    runs = [P.backward(Gd, gd, k=16, seed=5, tol=1e-10, check_every=c) for c in (1, 7, 16)]
+    iters = [r["iters"] for r in runs]
+    assert iters[0] == iters[1] == iters[2], iters
+    for r in runs[1:]:
+        assert torch.equal(r["grad_w"], runs[0]["grad_w"])
